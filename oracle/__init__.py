@@ -1,0 +1,268 @@
+"""FP64 CPU oracle for image-based glint lighting (Kneiphof & Klein, EGSR 2025).
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, ``__graft_entry__.smoke()``
+and the ``cpu_baseline`` leg of ``bench.py``, never by the product path.  It
+shares no code with the HIP library.  The arithmetic lives in
+``glint_oracle.c`` (plain loops, double precision); this module only marshals
+numpy arrays into it and chains its steps in the paper's order:
+
+* Sec. 5, "Discrete Radiance Levels" / "Fuzzy Indicator Functions"
+  -> :func:`partition`
+* Sec. 5, "Integrated NDF", Eq. (rtiblndf) with the kernel of Sec. 3.4
+  -> :func:`mipchain`, :func:`prefilter`
+* Sec. 5 (visible reflecting facet area) and Sec. 3.4 (split sum)
+  -> :func:`luts`
+* Sec. 3.2 (N_P), Sec. 4 Eq. (probhk) and Eq. (iblglints:fin), Sec. 6 and
+  Alg. "Dual-gated Gaussian" -> :func:`shade`
+
+Pins (tests/test_oracle_*.py): every step is checked against closed forms,
+invariants, library routines or brute force, except the per-footprint hash
+(pcg4d, Jarzynski & Olano 2020), for which no published test vectors are at
+hand: its values are *parity unpinned* (checked only for exactness of the
+float mapping and chi^2 uniformity); the GPU path implements the same
+published definition independently.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from .build import build_oracle, library_path
+
+_LIB = None
+LUT_N = 64
+
+
+def lib():
+    global _LIB
+    if _LIB is None:
+        path = library_path()
+        if not os.path.exists(path):
+            build_oracle()
+        _LIB = C.CDLL(path)
+        _declare(_LIB)
+    return _LIB
+
+
+def _p(a, ctype):
+    return a.ctypes.data_as(C.POINTER(ctype))
+
+
+def _declare(L):
+    f32p, f64p = C.POINTER(C.c_float), C.POINTER(C.c_double)
+    u8p, i64p = C.POINTER(C.c_uint8), C.POINTER(C.c_int64)
+    L.orc_partition.argtypes = [f32p, C.c_int, C.c_int, C.c_double, C.c_int, C.c_int, f64p, u8p, f32p]
+    L.orc_mipchain.argtypes = [f32p, u8p, f32p, C.c_int, C.c_int, C.c_int, f32p]
+    L.orc_prefilter_texels.argtypes = [f32p, u8p, f32p, f32p, C.c_int, C.c_int, C.c_int, C.c_int, i64p,
+                                       C.c_int64, f64p, C.c_int]
+    L.orc_lut_cells.argtypes = [C.POINTER(C.c_int), C.c_int64, f64p, f64p, f64p, C.c_int]
+    L.orc_ppnd16.argtypes = [C.c_double]
+    L.orc_ppnd16.restype = C.c_double
+    L.orc_hash_xi.argtypes = [C.c_uint32, C.c_uint32, C.c_int32, C.c_int64, C.c_int64, C.c_int,
+                              f32p, f32p]
+    L.orc_shade_pixels.argtypes = [C.POINTER(f32p), f32p, f32p, f64p, f32p, f32p, C.c_int, C.c_int, C.c_int,
+                                   C.c_uint32, C.c_int, i64p, C.c_int64, f64p, f64p, u8p, f64p, u8p, C.c_int]
+    L.orc_gate_probs.argtypes = [C.c_float, C.c_float, f32p]
+    L.orc_dual_gated.argtypes = [C.c_double, C.c_double, C.c_float, C.c_float, f64p, f64p, u8p]
+    L.orc_face_dir.argtypes = [C.c_int, C.c_double, C.c_double, f64p]
+    L.orc_dir_face.argtypes = [f64p, f64p]
+    L.orc_dir_face.restype = C.c_int
+    L.orc_lattice_level.argtypes = [C.c_double, f64p]
+    L.orc_lattice_level.restype = C.c_int
+    L.orc_taps.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, f64p]
+
+
+def threads_default():
+    return int(os.environ.get("GLINT_ORACLE_THREADS", os.cpu_count() or 1))
+
+
+def pyramid_texels(R: int, M: int) -> int:
+    return sum(6 * (R >> m) ** 2 for m in range(M))
+
+
+def level_offset(R: int, m: int) -> int:
+    return sum(6 * (R >> s) ** 2 for s in range(m))
+
+
+def partition(env: np.ndarray, K: int, ell: float = 1e-3, level_mode: int = 0, weight_space: int = 0):
+    """Radiance levels and fuzzy indicators (Sec. 5).  env: [6,R,R,3] float32.
+
+    Returns (levels [K] f64, ind_j [6,R,R] u8, ind_t [6,R,R] f32).
+    Pinned by closed forms in tests/test_oracle_env.py.
+    """
+    env = np.ascontiguousarray(env, dtype=np.float32)
+    R = env.shape[1]
+    levels = np.zeros(K, np.float64)
+    ind_j = np.zeros((6, R, R), np.uint8)
+    ind_t = np.zeros((6, R, R), np.float32)
+    rc = lib().orc_partition(_p(env, C.c_float), R, K, ell, level_mode, weight_space, _p(levels, C.c_double),
+                             _p(ind_j, C.c_uint8), _p(ind_t, C.c_float))
+    if rc:
+        raise ValueError("orc_partition rejected its arguments")
+    return levels, ind_j, ind_t
+
+
+def mipchain(env, ind_j, ind_t, K: int, M: int) -> np.ndarray:
+    """Source mip chain levels 1..M-1, float32, flat [texels, K+3]."""
+    R = env.shape[1]
+    n = level_offset(R, M) - 6 * R * R
+    chain = np.zeros((max(n, 1), K + 3), np.float32)
+    rc = lib().orc_mipchain(_p(env, C.c_float), _p(ind_j, C.c_uint8), _p(ind_t, C.c_float), R, K, M,
+                            _p(chain, C.c_float))
+    if rc:
+        raise ValueError("orc_mipchain rejected its arguments")
+    return chain
+
+
+def prefilter(env, ind_j, ind_t, chain, K: int, M: int, T: int = 64, texel_ids=None, threads=None):
+    """Prefiltered pyramid values (double) [n, K+3] for the given mip-major texel
+    ids (all texels when None).  Channels: K indicators, then RGB."""
+    env = np.ascontiguousarray(env, dtype=np.float32)
+    R = env.shape[1]
+    if texel_ids is None:
+        texel_ids = np.arange(pyramid_texels(R, M), dtype=np.int64)
+    texel_ids = np.ascontiguousarray(texel_ids, dtype=np.int64)
+    out = np.zeros((len(texel_ids), K + 3), np.float64)
+    rc = lib().orc_prefilter_texels(_p(env, C.c_float), _p(ind_j, C.c_uint8), _p(ind_t, C.c_float),
+                                    _p(chain, C.c_float), R, K, M, T, _p(texel_ids, C.c_int64),
+                                    len(texel_ids), _p(out, C.c_double), threads or threads_default())
+    if rc:
+        raise ValueError("orc_prefilter_texels rejected its arguments")
+    return out
+
+
+def split_pyramid(values: np.ndarray, K: int):
+    """[n, K+3] double -> (ind [n,K] float32, rgb [n,4] float32) as stored."""
+    ind = values[:, :K].astype(np.float32)
+    rgb = np.zeros((len(values), 4), np.float32)
+    rgb[:, :3] = values[:, K:K + 3].astype(np.float32)
+    return ind, rgb
+
+
+def luts(cells=None, threads=None):
+    """S = E_D / D_H and split-sum (A, B) on the 64x64 (sqrt(alpha), mu) grid.
+
+    Returns (S [n] f64, A [n], B [n]) for cells = ia*64+im (all when None)."""
+    if cells is None:
+        cells = np.arange(LUT_N * LUT_N, dtype=np.int32)
+    cells = np.ascontiguousarray(cells, dtype=np.int32)
+    S = np.zeros(len(cells)); A = np.zeros(len(cells)); B = np.zeros(len(cells))
+    rc = lib().orc_lut_cells(_p(cells, C.c_int), len(cells), _p(S, C.c_double), _p(A, C.c_double),
+                             _p(B, C.c_double), threads or threads_default())
+    if rc:
+        raise ValueError("orc_lut_cells rejected its arguments")
+    return S, A, B
+
+
+def lut_tables(threads=None):
+    """Full LUTs as stored (float32): S [64,64], E [64,64,2]."""
+    S, A, B = luts(threads=threads)
+    lut_S = S.astype(np.float32).reshape(LUT_N, LUT_N)
+    lut_E = np.stack([A, B], axis=-1).astype(np.float32).reshape(LUT_N, LUT_N, 2)
+    return lut_S, lut_E
+
+
+GBUF_FIELDS = ("nx", "ny", "nz", "vx", "vy", "vz", "u", "v", "area", "ax", "ay", "density",
+               "f0r", "f0g", "f0b", "surf_id")
+
+
+def shade(gbuf: dict, ind_pyr, rgb_pyr, levels, lut_S, lut_E, R: int, K: int, M: int, seed: int,
+          vertices: int = 1, pixels=None, threads=None):
+    """Glint radiance of the requested pixels (all when None).
+
+    gbuf: dict of flat float32 arrays (surf_id uint32).  ind_pyr [texels,K]
+    float32 and rgb_pyr [texels,4] float32 are the stored pyramids.
+    Returns dict(radiance [n,3] f64, counts [n,V,K] f64, codes [n,V,K-1] u8,
+    probs [n,K] f64, flags [n] u8).
+    """
+    fields = [np.ascontiguousarray(gbuf[k], dtype=np.uint32 if k == "surf_id" else np.float32)
+              for k in GBUF_FIELDS]
+    P = len(fields[0])
+    if pixels is None:
+        pixels = np.arange(P, dtype=np.int64)
+    pixels = np.ascontiguousarray(pixels, dtype=np.int64)
+    n = len(pixels)
+    arr = (C.POINTER(C.c_float) * 16)(*[f.ctypes.data_as(C.POINTER(C.c_float)) for f in fields])
+    ind_pyr = np.ascontiguousarray(ind_pyr, dtype=np.float32)
+    rgb_pyr = np.ascontiguousarray(rgb_pyr, dtype=np.float32)
+    levels = np.ascontiguousarray(levels, dtype=np.float64)
+    lut_S = np.ascontiguousarray(lut_S, dtype=np.float32)
+    lut_E = np.ascontiguousarray(lut_E, dtype=np.float32)
+    out = dict(radiance=np.zeros((n, 3)), counts=np.zeros((n, vertices, K)),
+               codes=np.zeros((n, vertices, K - 1), np.uint8), probs=np.zeros((n, K)),
+               flags=np.zeros(n, np.uint8))
+    rc = lib().orc_shade_pixels(arr, _p(ind_pyr, C.c_float), _p(rgb_pyr, C.c_float), _p(levels, C.c_double),
+                                _p(lut_S, C.c_float), _p(lut_E, C.c_float), R, K, M, seed, vertices,
+                                _p(pixels, C.c_int64), n, _p(out["radiance"], C.c_double),
+                                _p(out["counts"], C.c_double), _p(out["codes"], C.c_uint8),
+                                _p(out["probs"], C.c_double), _p(out["flags"], C.c_uint8),
+                                threads or threads_default())
+    if rc:
+        raise ValueError("orc_shade_pixels rejected its arguments")
+    return out
+
+
+def frame(env, gbuf, K, M, T=64, ell=1e-3, seed=1, vertices=1, level_mode=0, weight_space=0, pixels=None,
+          threads=None, lut=None):
+    """Whole hot path on the CPU: partition -> mip chain -> prefilter -> LUTs ->
+    shade.  Returns a dict with every intermediate."""
+    levels, ind_j, ind_t = partition(env, K, ell, level_mode, weight_space)
+    chain = mipchain(env, ind_j, ind_t, K, M)
+    pyr = prefilter(env, ind_j, ind_t, chain, K, M, T, threads=threads)
+    ind_pyr, rgb_pyr = split_pyramid(pyr, K)
+    lut_S, lut_E = lut if lut is not None else lut_tables(threads)
+    R = env.shape[1]
+    sh = shade(gbuf, ind_pyr, rgb_pyr, levels, lut_S, lut_E, R, K, M, seed, vertices, pixels, threads)
+    return dict(levels=levels, ind_j=ind_j, ind_t=ind_t, chain=chain, pyramid=pyr, ind_pyr=ind_pyr,
+                rgb_pyr=rgb_pyr, lut_S=lut_S, lut_E=lut_E, **sh)
+
+
+# --- small pieces, exposed for the definition tests --------------------------
+
+def ppnd16(p: float) -> float:
+    return lib().orc_ppnd16(float(p))
+
+
+def hash_xi(seed, surf, level, a, b, node):
+    x1, x2 = C.c_float(), C.c_float()
+    lib().orc_hash_xi(seed, surf, level, a, b, node, C.byref(x1), C.byref(x2))
+    return x1.value, x2.value
+
+
+def gate_probs(N: float, p: float):
+    out = np.zeros(4, np.float32)
+    lib().orc_gate_probs(N, p, _p(out, C.c_float))
+    return out  # P(n=N), P(n=1), P(nb=N), P(nb=1)
+
+
+def dual_gated(N: float, p: float, xi1: float, xi2: float):
+    n, nb, code = C.c_double(), C.c_double(), C.c_uint8()
+    lib().orc_dual_gated(N, p, xi1, xi2, C.byref(n), C.byref(nb), C.byref(code))
+    return n.value, nb.value, code.value
+
+
+def face_dir(face, s, t):
+    d = np.zeros(3)
+    lib().orc_face_dir(face, s, t, _p(d, C.c_double))
+    return d
+
+
+def dir_face(d):
+    d = np.ascontiguousarray(d, dtype=np.float64)
+    st = np.zeros(2)
+    f = lib().orc_dir_face(_p(d, C.c_double), _p(st, C.c_double))
+    return f, st[0], st[1]
+
+
+def lattice_level(area):
+    fr = C.c_double()
+    l0 = lib().orc_lattice_level(float(area), C.byref(fr))
+    return l0, fr.value
+
+
+def taps(m, M, T, R):
+    out = np.zeros((T, 5))
+    lib().orc_taps(m, M, T, R, _p(out, C.c_double))
+    return out
