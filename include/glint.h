@@ -1,0 +1,234 @@
+/*
+ * glint.h -- C ABI of the MI355X (gfx950) glint hot path.
+ *
+ * Real-time image-based lighting of glints (Kneiphof & Klein, EGSR 2025):
+ *   per frame, the environment map is split into K area lights of constant
+ *   radiance and each light's (fuzzy) indicator is filtered with the IBL
+ *   kernel into a roughness pyramid (Sec. 5); per pixel, the footprint's
+ *   microfacet count N_P (Sec. 3.2), the K reflection probabilities (Sec. 4,
+ *   Eq. (probhk) with Eq. (rtiblndf)) and a hierarchical multinomial of
+ *   dual-gated Gaussian binomials (Sec. 6, Alg. "Dual-gated Gaussian") give
+ *   the glint radiance of Eq. (iblglints:fin).
+ *
+ * Conventions for every entry point:
+ *   - Returns GLINT_OK (0) or a positive error code; nothing is thrown.
+ *     glint_last_error() returns a message for the calling thread.
+ *   - Pointers marked "device" are HIP device pointers (e.g. torch CUDA
+ *     tensors' data_ptr()); the caller owns every buffer.  Entry points that
+ *     take a stream never allocate device memory and never synchronise:
+ *     work is enqueued on `stream` (a hipStream_t; NULL = default stream).
+ *     Device faults surface on a later call or on glint_sync().
+ *   - Arguments are validated on the host before anything is launched; a
+ *     rejected call launches nothing and leaves every output untouched.
+ *   - Concurrent calls on different streams must not share output buffers
+ *     or workspaces.
+ *
+ * Cube-map layout: env[face][y][x][3] float32 RGB radiance, faces
+ * +X,-X,+Y,-Y,+Z,-Z, texel centre s = 2(x+1/2)/R - 1, t = 2(y+1/2)/R - 1,
+ * direction +X:(1,-t,-s) -X:(-1,-t,s) +Y:(s,1,t) -Y:(s,-1,-t) +Z:(s,-t,1)
+ * -Z:(-s,-t,-1).  Pyramids are mip-major: mip m (face size R >> m) starts at
+ * texel offset sum_{s<m} 6 (R>>s)^2, then [face][y][x].
+ */
+#ifndef GLINT_H
+#define GLINT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GLINT_VERSION 1
+
+enum glint_status {
+    GLINT_OK = 0,
+    GLINT_EINVAL = 1,       /* invalid argument (size, null pointer, option) */
+    GLINT_EUNSUPPORTED = 2, /* valid but not implemented (option value) */
+    GLINT_EDEVICE = 3,      /* HIP runtime error (launch, device query) */
+    GLINT_ENOMEM = 4        /* host allocation failed (context only) */
+};
+
+typedef enum glint_dtype {
+    GLINT_F32 = 0,    /* 32-bit float */
+    GLINT_F16 = 1,    /* IEEE half, round to nearest even */
+    GLINT_BF16 = 2,   /* bfloat16, round to nearest even */
+    GLINT_UNORM16 = 3 /* 16-bit unsigned normalised: round(v * 65535) */
+} glint_dtype;
+
+typedef struct glint_ctx_s *glint_ctx;
+
+/* Library version (GLINT_VERSION of the build). */
+int glint_version(void);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *glint_last_error(void);
+
+/* Creates a context bound to HIP device `device` (queries its properties).
+ * *out receives the context.  GLINT_EINVAL for a bad device index or a null
+ * out pointer; GLINT_EDEVICE if the device cannot be queried. */
+int glint_create(int device, glint_ctx *out);
+void glint_destroy(glint_ctx ctx);
+
+/* Waits for all work on the context's device; reports device faults. */
+int glint_sync(glint_ctx ctx);
+
+/* ------------------------------------------------------------------------
+ * Environment partition (Sec. 5, "Discrete Radiance Levels", "Fuzzy
+ * Indicator Functions", Eq. (wkdefpractice)).
+ *
+ * Brightness of a texel is Rec. 709 luminance of its RGB (non-finite or
+ * negative channels count as 0).  With Lmin = max(ell, min Y) and
+ * Lmax = max Y: levels[0] = 0 and, for k >= 1,
+ * levels[k] = min(Lmax, exp(lerp(ln Lmin, ln Lmax, k/(K-1)))) with
+ * levels[K-1] = Lmax (level_mode 0, the paper's; level_mode 2 uses
+ * (k-1)/(K-2) so that levels[1] = Lmin).  Each texel stores the interval
+ * index j (largest j <= K-2 with levels[j] <= min(Y, Lmax)) and the lerp
+ * factor t in [0,1] (linear space, weight_space 0, the paper's choice; log
+ * space for j >= 1 with weight_space 1); the fuzzy indicator weights are
+ * w_j = 1 - t, w_{j+1} = t.  t = 1 when levels[j+1] == levels[j].
+ * ------------------------------------------------------------------------ */
+typedef struct glint_partition_params {
+    int K;            /* number of radiance levels, 2..16 */
+    double ell;       /* lower clip of the minimum radiance (> 0), e.g. 1e-3 */
+    int level_mode;   /* 0 (paper) or 2 */
+    int weight_space; /* 0 linear (paper) or 1 log */
+} glint_partition_params;
+
+/* Device workspace (bytes) glint_partition_env needs for a face size R. */
+size_t glint_partition_workspace_bytes(int R);
+
+/* env: device [6][R][R][3] float32.  workspace: device, at least
+ * glint_partition_workspace_bytes(R) bytes, 8-byte aligned, no initial
+ * contents required.  Outputs (device): levels [K] double,
+ * ind_j [6][R][R] uint8, ind_t [6][R][R] float32.
+ * GLINT_EINVAL: R not a power of two in [1, 4096], K outside 2..16,
+ * ell <= 0, an option out of range, or a null pointer. */
+int glint_partition_env(glint_ctx ctx, const float *env, int R, const glint_partition_params *params,
+                        void *workspace, double *levels, uint8_t *ind_j, float *ind_t, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Prefilter (Sec. 5 "Integrated NDF", Eq. (rtiblndf) with the real-time IBL
+ * kernel of Sec. 3.4, Eq. (rtibl), assuming n = v = r).  The K indicator
+ * channels and RGB are filtered with the same kernel.
+ *
+ * Source: a mip chain of the dense indicator weights + RGB (level 0 exact,
+ * level s+1 the float-stored 2x2 mean of level s).  Mip m of the output
+ * (roughness alpha_m = (m/(M-1))^2; mip 0 is the unfiltered level) is
+ *   F(r) = sum_j W_j v(l_j, lod_j) / sum_j W_j
+ * over T GGX-importance-sampled Hammersley taps around r (tap j: azimuth
+ * 2 pi j/T, cos^2 theta = (1-u)/(1+(alpha^2-1)u) with u the base-2 radical
+ * inverse of j), l_j the mirror of r about the tap's half vector,
+ * W_j = <r,l_j>+, lod_j = clamp(log2(Omega_s/Omega_p)/2 + 1, 0, M-1) with
+ * Omega_s = 4/(T D(h_j)) and Omega_p = 4 pi/(6 R^2) (filtered importance
+ * sampling), v a trilinear lookup of the chain.  Lookups across a face edge
+ * take the nearest texel of the face that owns the texel's direction.
+ * Sums run in double; results are rounded once to the stored type.
+ * ------------------------------------------------------------------------ */
+typedef struct glint_prefilter_params {
+    int num_mips;      /* M, 1 <= M <= log2(R) + 1 */
+    int taps;          /* T, 1..1024 (never tuned: it changes results) */
+    glint_dtype dtype; /* storage type of the indicator pyramid */
+} glint_prefilter_params;
+
+/* Texels of an M-level pyramid of face size R: sum_m 6 (R>>m)^2. */
+int64_t glint_pyramid_texels(int R, int num_mips);
+
+/* Device workspace (bytes) for the source mip chain. */
+size_t glint_prefilter_workspace_bytes(int R, int K, const glint_prefilter_params *params);
+
+/* env: device [6][R][R][3] float32; ind_j, ind_t: device, as written by
+ * glint_partition_env.  workspace: device, >= glint_prefilter_workspace_bytes,
+ * 16-byte aligned.  Outputs (device): ind_pyr [texels][K] of params->dtype;
+ * rgb_pyr [texels][4] float32 (RGB, 4th channel 0).
+ * GLINT_EINVAL: bad R, K, M, T or dtype, or a null pointer. */
+int glint_prefilter(glint_ctx ctx, const float *env, const uint8_t *ind_j, const float *ind_t, int R, int K,
+                    const glint_prefilter_params *params, void *workspace, void *ind_pyr, float *rgb_pyr,
+                    void *stream);
+
+/* ------------------------------------------------------------------------
+ * Lookup tables, once per BRDF model (isotropic GGX, Schlick Fresnel,
+ * height-correlated Smith), on a 64 x 64 cell-centred grid over
+ * (sqrt(alpha) rows, mu_o = <n,v> columns):
+ *   lut_S[a][m]      = E_D / D_H, the visible reflecting facet area of
+ *                      Sec. 5 over the total facet area of Sec. 3.2;
+ *   lut_E[a][m][0,1] = split-sum albedo E_rho = F0 * [0] + [1] (Sec. 3.4).
+ * Midpoint quadrature in GGX half-vector coordinates (double), stored float.
+ * Outputs: device float32 arrays [64][64] and [64][64][2].
+ * ------------------------------------------------------------------------ */
+int glint_build_luts(glint_ctx ctx, float *lut_S, float *lut_E, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Per-pixel glint shading (Sec. 3.2, Sec. 3.3 Eq. (anisogrid), Sec. 4
+ * Eq. (probhk) and Eq. (iblglints:fin), Sec. 6 Alg. "Dual-gated Gaussian").
+ *
+ * Per pixel: N_P = density * area (stratified count); w_r = 2<n,v>n - v;
+ * alpha = sqrt(alpha_x alpha_y); F = trilinear pyramid lookup at (w_r,
+ * lod = sqrt(alpha)(M-1)); p_k = S F_k / sum F for k >= 1 and
+ * p_0 = 1 - sum_{k>=1} p_k (level 0 has zero radiance and absorbs facets
+ * that reflect nothing); L_o = (F0 A + B) RGB(w_r, lod).
+ * Counts: a balanced binary tree over the K bins (K a power of two, nodes
+ * in breadth-first order), node probability S_left / S_node, the left child
+ * receiving the positive count n and the right child the negative count
+ * nbar of the dual-gated Gaussian.  Gating probabilities and masks are
+ * evaluated in float with the bias c = max(1, eps/p), eps = 10^-3.54
+ * (Sec. 6 "Numeric Gating Issues"); the Gaussian quantile (AS 241) and all
+ * other arithmetic in double.  Random numbers per (surface, lattice vertex,
+ * node) from the pcg4d hash (Jarzynski & Olano 2020).
+ * Lattice (the footprint grid of Sec. 3.3, used as a black box by the
+ * paper): level l0 = floor(log2(area)/2) on the uv plane, spacing 2^l0.
+ * vertices = 1: the nearest vertex; vertices = 6: the 3 vertices of the uv
+ * triangle containing the point at levels l0 and l0+1, barycentric weights
+ * times (1-f, f), f = log2(area)/2 - l0.  Each vertex draws with N_i = N_P;
+ * the counts are blended with the weights.
+ * Radiance = L_o * sum_k L_k M_k / (N_P sum_k L_k p_k) (0 if either sum is 0).
+ * ------------------------------------------------------------------------ */
+#define GLINT_NO_SURFACE 0xFFFFFFFFu
+
+typedef struct glint_gbuffer {
+    /* device float32 arrays of num_pixels entries each (structure of arrays) */
+    const float *nx, *ny, *nz; /* unit surface normal */
+    const float *vx, *vy, *vz; /* unit vector towards the viewer */
+    const float *u, *v;        /* surface uv (lattice coordinates) */
+    const float *area;         /* footprint area |P| (> 0) */
+    const float *ax, *ay;      /* GGX roughness alpha_x, alpha_y */
+    const float *density;      /* microfacets per unit area N */
+    const float *f0r, *f0g, *f0b; /* Fresnel reflectance at normal incidence */
+    const uint32_t *surf_id;   /* surface id (hash input); GLINT_NO_SURFACE = background */
+} glint_gbuffer;
+
+typedef struct glint_env {
+    const void *ind_pyr;   /* device [texels][K], dtype below (from glint_prefilter) */
+    const float *rgb_pyr;  /* device [texels][4] float32 */
+    const double *levels;  /* device [K] (from glint_partition_env) */
+    const float *lut_S;    /* device [64][64] */
+    const float *lut_E;    /* device [64][64][2] */
+    int R, K, num_mips;
+    glint_dtype dtype;
+} glint_env;
+
+typedef struct glint_shade_params {
+    uint32_t seed; /* material seed mixed into the hash */
+    int vertices;  /* 1 or 6 */
+} glint_shade_params;
+
+/* Optional per-pixel outputs for verification (each pointer may be NULL). */
+typedef struct glint_shade_debug {
+    double *counts; /* device [P][vertices][K]: multinomial counts per vertex */
+    uint8_t *codes; /* device [P][vertices][K-1]: gating mask bits per node:
+                       1 n=N, 2 n in {1,N}, 4 nbar=N, 8 nbar in {1,N}, 16 Gaussian */
+    double *probs;  /* device [P][K]: reflection probabilities p_k */
+} glint_shade_debug;
+
+/* radiance: device [P][3] float32 (background pixels get 0).  debug may be
+ * NULL.  GLINT_EINVAL: P < 0, K not in {2,4,8,16}, bad R/M/dtype/vertices or
+ * a null pointer (P = 0 is a no-op). */
+int glint_shade(glint_ctx ctx, const glint_gbuffer *gbuf, int64_t num_pixels, const glint_env *env,
+                const glint_shade_params *params, float *radiance, const glint_shade_debug *debug,
+                void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GLINT_H */

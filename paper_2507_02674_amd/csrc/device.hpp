@@ -1,0 +1,211 @@
+// Device-side building blocks of the glint kernels (gfx950).
+//
+// Cube addressing, seam handling, the pcg4d hash, the AS 241 inverse normal
+// CDF and the float gating probabilities of the dual-gated Gaussian.  Every
+// routine is evaluated in double except the gating (float, the precision the
+// paper tunes its bias constant for, Sec. 6 "Numeric Gating Issues").
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace glint {
+
+constexpr int kLutN = 64;
+
+struct d3 {
+    double x, y, z;
+};
+
+// Direction of face coordinates (s, t) in [-1,1]^2 (unnormalised).
+__device__ __forceinline__ d3 face_dir(int face, double s, double t)
+{
+    switch (face) {
+    case 0: return {1.0, -t, -s};
+    case 1: return {-1.0, -t, s};
+    case 2: return {s, 1.0, t};
+    case 3: return {s, -1.0, -t};
+    case 4: return {s, -t, 1.0};
+    default: return {-s, -t, -1.0};
+    }
+}
+
+// Owning face of d (largest |component|, ties to x then y) and its face
+// coordinates.  Divisions are IEEE (correctly rounded) double divisions.
+__device__ __forceinline__ int dir_face(const d3 &d, double &s, double &t)
+{
+    const double ax = fabs(d.x), ay = fabs(d.y), az = fabs(d.z);
+    if (ax >= ay && ax >= az) {
+        if (d.x >= 0.0) { s = -d.z / ax; t = -d.y / ax; return 0; }
+        s = d.z / ax; t = -d.y / ax; return 1;
+    }
+    if (ay >= az) {
+        if (d.y >= 0.0) { s = d.x / ay; t = d.z / ay; return 2; }
+        s = d.x / ay; t = -d.z / ay; return 3;
+    }
+    if (d.z >= 0.0) { s = d.x / az; t = -d.y / az; return 4; }
+    s = -d.x / az; t = -d.y / az; return 5;
+}
+
+__host__ __device__ __forceinline__ int64_t level_offset(int R, int level)
+{
+    int64_t off = 0;
+    for (int s = 0; s < level; ++s) {
+        const int64_t n = R >> s;
+        off += 6 * n * n;
+    }
+    return off;
+}
+
+// A texel index off the face (x or y in {-1, n}) is re-projected through
+// the 3-D direction of its extended centre to the nearest texel of the
+// owning face.  Returns the flat index within the level.
+__device__ __forceinline__ int64_t texel_index(int face, int x, int y, int n)
+{
+    if (x < 0 || x >= n || y < 0 || y >= n) {
+        const double inv = 1.0 / (double)n;
+        const d3 d = face_dir(face, 2.0 * ((double)x + 0.5) * inv - 1.0, 2.0 * ((double)y + 0.5) * inv - 1.0);
+        double s, t;
+        face = dir_face(d, s, t);
+        x = (int)floor((s + 1.0) * 0.5 * (double)n);
+        y = (int)floor((t + 1.0) * 0.5 * (double)n);
+        x = x < 0 ? 0 : (x > n - 1 ? n - 1 : x);
+        y = y < 0 ? 0 : (y > n - 1 ? n - 1 : y);
+    }
+    return ((int64_t)face * n + y) * n + x;
+}
+
+// Bilinear footprint of direction d on a level of face size n: the four
+// texel indices (within the level) and their weights.
+struct bilin4 {
+    int64_t idx[4];
+    double w[4];
+};
+
+__device__ __forceinline__ bilin4 bilinear_taps(const d3 &d, int n)
+{
+    double s, t;
+    const int face = dir_face(d, s, t);
+    const double x = (s + 1.0) * 0.5 * (double)n - 0.5;
+    const double y = (t + 1.0) * 0.5 * (double)n - 0.5;
+    const double x0 = floor(x), y0 = floor(y);
+    const double fx = x - x0, fy = y - y0;
+    const int ix = (int)x0, iy = (int)y0;
+    bilin4 b;
+    b.idx[0] = texel_index(face, ix, iy, n);
+    b.idx[1] = texel_index(face, ix + 1, iy, n);
+    b.idx[2] = texel_index(face, ix, iy + 1, n);
+    b.idx[3] = texel_index(face, ix + 1, iy + 1, n);
+    b.w[0] = (1.0 - fy) * (1.0 - fx);
+    b.w[1] = (1.0 - fy) * fx;
+    b.w[2] = fy * (1.0 - fx);
+    b.w[3] = fy * fx;
+    return b;
+}
+
+// Base-2 radical inverse of a 32-bit index (exact in double).
+__device__ __forceinline__ double radical_inverse(uint32_t j)
+{
+    return (double)__builtin_bitreverse32(j) * 2.3283064365386963e-10;
+}
+
+// ---------------------------------------------------------------------------
+// pcg4d (Jarzynski & Olano, "Hash Functions for GPU Rendering", JCGT 2020).
+// ---------------------------------------------------------------------------
+struct u4 {
+    uint32_t x, y, z, w;
+};
+
+__device__ __forceinline__ u4 pcg4d(u4 v)
+{
+    v.x = v.x * 1664525u + 1013904223u;
+    v.y = v.y * 1664525u + 1013904223u;
+    v.z = v.z * 1664525u + 1013904223u;
+    v.w = v.w * 1664525u + 1013904223u;
+    v.x += v.y * v.w; v.y += v.z * v.x; v.z += v.x * v.y; v.w += v.y * v.z;
+    v.x ^= v.x >> 16; v.y ^= v.y >> 16; v.z ^= v.z >> 16; v.w ^= v.w >> 16;
+    v.x += v.y * v.w; v.y += v.z * v.x; v.z += v.x * v.y; v.w += v.y * v.z;
+    return v;
+}
+
+// (h >> 9 + 1/2) 2^-23: exact float in (0, 1).
+__device__ __forceinline__ float hash_unit(uint32_t h)
+{
+    return ((float)(h >> 9) + 0.5f) * 1.1920928955078125e-07f;
+}
+
+// ---------------------------------------------------------------------------
+// Inverse standard normal CDF, AS 241 PPND16 (Wichura 1988), double.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double ppnd16(double p)
+{
+    const double q = p - 0.5;
+    if (fabs(q) <= 0.425) {
+        const double r = 0.180625 - q * q;
+        const double num = (((((((r * 2509.0809287301226727 + 33430.575583588128105) * r + 67265.770927008700853) * r
+                                + 45921.953931549871457) * r + 13731.693765509461125) * r + 1971.5909503065514427) * r
+                             + 133.14166789178437745) * r + 3.387132872796366608);
+        const double den = (((((((r * 5226.495278852545925 + 28729.085735721942674) * r + 39307.89580009271061) * r
+                                + 21213.794301586595867) * r + 5394.1960214247511077) * r + 687.1870074920579083) * r
+                             + 42.313330701600911252) * r + 1.0);
+        return q * num / den;
+    }
+    double r = q < 0.0 ? p : 1.0 - p;
+    r = sqrt(-log(r));
+    double num, den;
+    if (r <= 5.0) {
+        r -= 1.6;
+        num = (((((((r * 7.7454501427834140764e-4 + 0.0227238449892691845833) * r + 0.24178072517745061177) * r
+                   + 1.27045825245236838258) * r + 3.64784832476320460504) * r + 5.7694972214606914055) * r
+                + 4.6303378461565452959) * r + 1.42343711074968357734);
+        den = (((((((r * 1.05075007164441684324e-9 + 5.475938084995344946e-4) * r + 0.0151986665636164571966) * r
+                   + 0.14810397642748007459) * r + 0.68976733498510000455) * r + 1.6763848301838038494) * r
+                + 2.05319162663775882187) * r + 1.0);
+    } else {
+        r -= 5.0;
+        num = (((((((r * 2.01033439929228813265e-7 + 2.71155556874348757815e-5) * r + 0.0012426609473880784386) * r
+                   + 0.026532189526576123093) * r + 0.29656057182850489123) * r + 1.7848265399172913358) * r
+                + 5.4637849111641143699) * r + 6.6579046435011037772);
+        den = (((((((r * 2.04426310338993978564e-15 + 1.4215117583164458887e-7) * r + 1.8463183175100546818e-5) * r
+                   + 7.868691311456132591e-4) * r + 0.0148753612908506148525) * r + 0.13692988092273580531) * r
+                + 0.59983220655588793769) * r + 1.0);
+    }
+    const double val = num / den;
+    return q < 0.0 ? -val : val;
+}
+
+// ---------------------------------------------------------------------------
+// Float gating thresholds of the dual-gated Gaussian.  With c = max(1, eps/p)
+// the biased power (1 - c p)^(N2/c) equals (1 - max(p, eps))^(N2 min(1, p/eps)),
+// a form that is also defined at p = 0.  Contraction is off so each
+// operation rounds as written.
+// ---------------------------------------------------------------------------
+struct gate_f {
+    float th_nN;   // P(n = N)
+    float th_n1N;  // P(n = N) + P(n = 1)
+    float th_nbN;  // 1 - P(nbar = N)
+    float th_nb1N; // (1 - P(nbar = N)) - P(nbar = 1)
+};
+
+__device__ __forceinline__ gate_f gate_thresholds(float Nf, float pf)
+{
+#pragma clang fp contract(off)
+    const float eps = 2.8840315031266055e-04f; // 10^-3.54
+    const float N2 = fmaxf(2.0f, Nf);
+    const float cN = fminf(fmaxf(Nf - 1.0f, 0.0f), 1.0f);
+    const float cp = fmaxf(pf, eps);
+    const float ex = N2 * fminf(1.0f, pf / eps);
+    const float d1 = fmaxf(0.0f, 1.0f - fabsf(1.0f - Nf));
+    const float P_nN = cN * powf(pf, N2);
+    const float P_nbN = cN * powf(1.0f - cp, ex);
+    const float P_n1 = d1 * pf;
+    const float P_nb1 = d1 * (1.0f - pf);
+    gate_f g;
+    g.th_nN = P_nN;
+    g.th_n1N = P_nN + P_n1;
+    g.th_nbN = 1.0f - P_nbN;
+    g.th_nb1N = (1.0f - P_nbN) - P_nb1;
+    return g;
+}
+
+} // namespace glint

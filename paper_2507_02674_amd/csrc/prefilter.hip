@@ -1,0 +1,349 @@
+// Environment prefilter of the K indicator channels and RGB (Sec. 5,
+// "Integrated NDF", Eq. (rtiblndf), with the real-time IBL kernel of
+// Sec. 3.4, Eq. (rtibl), n = v = r).
+//
+// Source mip chain: level 0 is virtual (dense weights 1-t, t expanded from
+// the packed indicator plus RGB from the map); levels >= 1 are stored float,
+// [texel][CP] with CP = K+3 rounded up to 4 (16-byte texel records).
+//
+//   k_chain_level   one launch per chain level: 2x2 mean of the level above,
+//                   summed in double in a fixed order, stored float;
+//   k_pyr_level0    mip 0 of the output pyramid (alpha = 0): the dense level;
+//   k_prefilter     mips >= 1: a group of G = 8 lanes per output texel splits
+//                   the T taps, accumulates in double, reduces across the
+//                   group with cross-lane shuffles; the tap table of the
+//                   block's mip lives in LDS.  Blocks are mip-homogeneous and
+//                   remapped so consecutive tiles share an XCD's L2.
+#include "device.hpp"
+#include "internal.hpp"
+
+namespace glint {
+
+constexpr int kChainThreads = 256;
+constexpr int kFilterThreads = 256;
+constexpr int kGroup = 8; // lanes per output texel
+
+__host__ __device__ constexpr int chain_stride(int K) { return (K + 3 + 3) & ~3; }
+
+// ---------------------------------------------------------------------------
+// storage types of the indicator pyramid
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint16_t f32_to_bf16(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7F800000u) == 0x7F800000u && (u & 0x7FFFFFu)) return (uint16_t)((u >> 16) | 0x40u);
+    u += 0x7FFFu + ((u >> 16) & 1u); // round to nearest even
+    return (uint16_t)(u >> 16);
+}
+
+template <int DT>
+__device__ __forceinline__ void store_value(void *base, int64_t i, double v);
+
+template <>
+__device__ __forceinline__ void store_value<0>(void *base, int64_t i, double v)
+{
+    static_cast<float *>(base)[i] = (float)v;
+}
+template <>
+__device__ __forceinline__ void store_value<1>(void *base, int64_t i, double v)
+{
+    static_cast<_Float16 *>(base)[i] = (_Float16)v;
+}
+template <>
+__device__ __forceinline__ void store_value<2>(void *base, int64_t i, double v)
+{
+    static_cast<uint16_t *>(base)[i] = f32_to_bf16((float)v);
+}
+template <>
+__device__ __forceinline__ void store_value<3>(void *base, int64_t i, double v)
+{
+    double c = v < 0.0 ? 0.0 : (v > 1.0 ? 1.0 : v);
+    static_cast<uint16_t *>(base)[i] = (uint16_t)rint(c * 65535.0);
+}
+
+// ---------------------------------------------------------------------------
+// level-0 texel: dense weights + RGB
+// ---------------------------------------------------------------------------
+template <int K>
+struct Level0 {
+    const float *env;
+    const uint8_t *ind_j;
+    const float *ind_t;
+
+    __device__ __forceinline__ void load(int64_t i, double (&v)[K + 3]) const
+    {
+        const int j = ind_j[i];
+        const double t = (double)ind_t[i];
+        const double omt = 1.0 - t;
+#pragma unroll
+        for (int k = 0; k < K; ++k) v[k] = k == j ? omt : (k == j + 1 ? t : 0.0);
+        const float *e = env + 3 * i;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const float x = e[c];
+            v[K + c] = (__builtin_isfinite(x) && x > 0.0f) ? (double)x : 0.0;
+        }
+    }
+};
+
+template <int K>
+__device__ __forceinline__ void load_chain(const float *__restrict__ lvl, int64_t i, double (&v)[K + 3])
+{
+    constexpr int CP = chain_stride(K);
+    const float4 *p = reinterpret_cast<const float4 *>(lvl + i * CP);
+    float buf[CP];
+#pragma unroll
+    for (int q = 0; q < CP / 4; ++q) {
+        const float4 f = p[q];
+        buf[4 * q] = f.x; buf[4 * q + 1] = f.y; buf[4 * q + 2] = f.z; buf[4 * q + 3] = f.w;
+    }
+#pragma unroll
+    for (int k = 0; k < K + 3; ++k) v[k] = (double)buf[k];
+}
+
+// ---------------------------------------------------------------------------
+// chain level s (>= 1) from level s-1
+// ---------------------------------------------------------------------------
+template <int K>
+__global__ void __launch_bounds__(kChainThreads) k_chain_level(Level0<K> l0, const float *__restrict__ src,
+                                                                float *__restrict__ dst, int n)
+{
+    constexpr int C = K + 3, CP = chain_stride(K);
+    const int64_t total = 6LL * n * n;
+    const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= total) return;
+    const int x = (int)(o % n), y = (int)((o / n) % n), f = (int)(o / ((int64_t)n * n));
+    const int m = 2 * n;
+    const int64_t c00 = ((int64_t)f * m + 2 * y) * m + 2 * x;
+    const int64_t idx[4] = {c00, c00 + 1, c00 + m, c00 + m + 1};
+    double a[C], b[C], c[C], d[C];
+    if (src == nullptr) {
+        l0.load(idx[0], a); l0.load(idx[1], b); l0.load(idx[2], c); l0.load(idx[3], d);
+    } else {
+        load_chain<K>(src, idx[0], a); load_chain<K>(src, idx[1], b);
+        load_chain<K>(src, idx[2], c); load_chain<K>(src, idx[3], d);
+    }
+    float out[CP];
+    {
+#pragma clang fp contract(off)
+#pragma unroll
+        for (int k = 0; k < C; ++k) out[k] = (float)(((a[k] + b[k]) + (c[k] + d[k])) * 0.25);
+    }
+#pragma unroll
+    for (int k = C; k < CP; ++k) out[k] = 0.0f;
+    float4 *q = reinterpret_cast<float4 *>(dst + o * CP);
+#pragma unroll
+    for (int i = 0; i < CP / 4; ++i) q[i] = make_float4(out[4 * i], out[4 * i + 1], out[4 * i + 2], out[4 * i + 3]);
+}
+
+// ---------------------------------------------------------------------------
+// pyramid mip 0
+// ---------------------------------------------------------------------------
+template <int K, int DT>
+__global__ void __launch_bounds__(kChainThreads) k_pyr_level0(Level0<K> l0, int64_t n, void *__restrict__ ind_pyr,
+                                                               float *__restrict__ rgb_pyr)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double v[K + 3];
+    l0.load(i, v);
+#pragma unroll
+    for (int k = 0; k < K; ++k) store_value<DT>(ind_pyr, i * K + k, v[k]);
+    reinterpret_cast<float4 *>(rgb_pyr)[i] = make_float4((float)v[K], (float)v[K + 1], (float)v[K + 2], 0.0f);
+}
+
+// ---------------------------------------------------------------------------
+// filtered mips
+// ---------------------------------------------------------------------------
+struct Tap {
+    double hx, hy, hz, w, lod;
+};
+
+struct FilterLaunch {
+    int R, M, T;
+    int nmips;              // filtered mips (M - 1)
+    int block_start[16];    // first logical block of mip 1 + q; block_start[nmips] = total
+    int texels[16];         // output texels of mip 1 + q
+    int xcd_chunk;          // logical blocks per XCD (grid = 8 * xcd_chunk)
+};
+
+__device__ __forceinline__ void make_tap(int j, int m, int M, int T, int R, Tap &tp)
+{
+    const double a = (double)m / (double)(M - 1);
+    const double alpha = a * a;
+    const double a2 = alpha * alpha;
+    const double uphi = (double)j / (double)T;
+    const double uth = radical_inverse((uint32_t)j);
+    const double c2 = (1.0 - uth) / (1.0 + (a2 - 1.0) * uth);
+    const double ct = sqrt(c2);
+    const double st = sqrt(fmax(0.0, 1.0 - c2));
+    double sp, cp;
+    sincospi(2.0 * uphi, &sp, &cp);
+    tp.hx = st * cp;
+    tp.hy = st * sp;
+    tp.hz = ct;
+    tp.w = fmax(0.0, 2.0 * c2 - 1.0);
+    const double den = 1.0 + (a2 - 1.0) * c2;
+    const double D = a2 / (3.14159265358979323846 * den * den);
+    const double omega_s = 4.0 / ((double)T * D);
+    const double omega_p = 4.0 * 3.14159265358979323846 / (6.0 * (double)R * (double)R);
+    double lod = 0.5 * log2(omega_s / omega_p) + 1.0;
+    lod = lod < 0.0 ? 0.0 : (lod > (double)(M - 1) ? (double)(M - 1) : lod);
+    tp.lod = lod;
+}
+
+template <int K, int DT>
+__global__ void __launch_bounds__(kFilterThreads) k_prefilter(FilterLaunch fl, Level0<K> l0,
+                                                               const float *__restrict__ chain,
+                                                               void *__restrict__ ind_pyr,
+                                                               float *__restrict__ rgb_pyr)
+{
+    constexpr int C = K + 3, CP = chain_stride(K);
+    extern __shared__ Tap s_taps[];
+    __shared__ double s_wsum;
+
+    // XCD-aware remap: hardware dispatches block b to XCD b % 8; give each
+    // XCD a contiguous range of logical blocks (neighbouring texels share
+    // source texels in that XCD's L2).
+    // The grid is padded to 8 * xcd_chunk blocks, so this is a bijection;
+    // padding blocks land past the last mip's texels and stay inactive.
+    const int b = (int)blockIdx.x;
+    const int lb = (b % 8) * fl.xcd_chunk + b / 8;
+    int q = 0;
+    while (q + 1 < fl.nmips && lb >= fl.block_start[q + 1]) ++q;
+    const int m = q + 1;
+    for (int j = threadIdx.x; j < fl.T; j += blockDim.x) make_tap(j, m, fl.M, fl.T, fl.R, s_taps[j]);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double ws = 0.0;
+        for (int j = 0; j < fl.T; ++j)
+            if (s_taps[j].w > 0.0) ws += s_taps[j].w;
+        s_wsum = ws;
+    }
+    __syncthreads();
+
+    const int n = fl.R >> m;
+    const int64_t texel = (int64_t)(lb - fl.block_start[q]) * (kFilterThreads / kGroup) + threadIdx.x / kGroup;
+    const int sub = threadIdx.x % kGroup;
+    const bool active = texel < fl.texels[q];
+    double acc[C];
+#pragma unroll
+    for (int k = 0; k < C; ++k) acc[k] = 0.0;
+
+    if (active) {
+        const int x = (int)(texel % n), y = (int)((texel / n) % n), f = (int)(texel / ((int64_t)n * n));
+        const double inv = 1.0 / (double)n;
+        d3 r = face_dir(f, 2.0 * ((double)x + 0.5) * inv - 1.0, 2.0 * ((double)y + 0.5) * inv - 1.0);
+        const double len = sqrt(r.x * r.x + r.y * r.y + r.z * r.z);
+        r.x /= len; r.y /= len; r.z /= len;
+        // orthonormal basis around r (Duff et al. 2017)
+        const double sgn = copysign(1.0, r.z);
+        const double ea = -1.0 / (sgn + r.z);
+        const double eb = r.x * r.y * ea;
+        const d3 t1 = {1.0 + sgn * r.x * r.x * ea, sgn * eb, -sgn * r.x};
+        const d3 t2 = {eb, sgn + r.y * r.y * ea, -r.y};
+
+        for (int j = sub; j < fl.T; j += kGroup) {
+            const Tap tp = s_taps[j];
+            if (!(tp.w > 0.0)) continue;
+            const d3 h = {tp.hx * t1.x + tp.hy * t2.x + tp.hz * r.x, tp.hx * t1.y + tp.hy * t2.y + tp.hz * r.y,
+                          tp.hx * t1.z + tp.hy * t2.z + tp.hz * r.z};
+            const d3 l = {2.0 * tp.hz * h.x - r.x, 2.0 * tp.hz * h.y - r.y, 2.0 * tp.hz * h.z - r.z};
+            const double l0f = floor(tp.lod);
+            const int s0 = (int)l0f;
+            const int s1 = s0 + 1 < fl.M ? s0 + 1 : fl.M - 1;
+            const double fr = tp.lod - l0f;
+            const int nlev = fr > 0.0 ? 2 : 1;
+            for (int li = 0; li < nlev; ++li) {
+                const int s = li == 0 ? s0 : s1;
+                const double lw = tp.w * (li == 0 ? 1.0 - fr : fr);
+                const bilin4 bl = bilinear_taps(l, fl.R >> s);
+                const float *lvl = s == 0 ? nullptr : chain + (level_offset(fl.R, s) - 6LL * fl.R * fl.R) * CP;
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    double v[C];
+                    if (s == 0) l0.load(bl.idx[c], v);
+                    else load_chain<K>(lvl, bl.idx[c], v);
+                    const double w = lw * bl.w[c];
+#pragma unroll
+                    for (int k = 0; k < C; ++k) acc[k] += w * v[k];
+                }
+            }
+        }
+    }
+    // reduce over the group's lanes
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+#pragma unroll
+        for (int o = kGroup / 2; o >= 1; o >>= 1) acc[k] += __shfl_xor(acc[k], o, kGroup);
+    }
+    if (active && sub == 0) {
+        const double ws = s_wsum;
+        const int64_t out = level_offset(fl.R, m) + texel;
+#pragma unroll
+        for (int k = 0; k < K; ++k) store_value<DT>(ind_pyr, out * K + k, acc[k] / ws);
+        reinterpret_cast<float4 *>(rgb_pyr)[out] =
+            make_float4((float)(acc[K] / ws), (float)(acc[K + 1] / ws), (float)(acc[K + 2] / ws), 0.0f);
+    }
+}
+
+size_t chain_bytes(int R, int K, int M)
+{
+    return (size_t)(level_offset(R, M) - 6LL * R * R) * chain_stride(K) * sizeof(float);
+}
+
+template <int K, int DT>
+static hipError_t launch_prefilter_t(const float *env, const uint8_t *ind_j, const float *ind_t, int R, int M,
+                                     int T, float *chain, void *ind_pyr, float *rgb_pyr, hipStream_t stream)
+{
+    Level0<K> l0{env, ind_j, ind_t};
+    // chain levels 1..M-1
+    for (int s = 1; s < M; ++s) {
+        const int n = R >> s;
+        const int64_t total = 6LL * n * n;
+        const float *src = s == 1 ? nullptr : chain + (level_offset(R, s - 1) - 6LL * R * R) * chain_stride(K);
+        float *dst = chain + (level_offset(R, s) - 6LL * R * R) * chain_stride(K);
+        hipLaunchKernelGGL(k_chain_level<K>, dim3((unsigned)((total + kChainThreads - 1) / kChainThreads)),
+                           dim3(kChainThreads), 0, stream, l0, src, dst, n);
+    }
+    const int64_t n0 = 6LL * R * R;
+    hipLaunchKernelGGL((k_pyr_level0<K, DT>), dim3((unsigned)((n0 + kChainThreads - 1) / kChainThreads)),
+                       dim3(kChainThreads), 0, stream, l0, n0, ind_pyr, rgb_pyr);
+    if (M > 1) {
+        FilterLaunch fl{};
+        fl.R = R; fl.M = M; fl.T = T; fl.nmips = M - 1;
+        const int per_block = kFilterThreads / kGroup;
+        int total = 0;
+        for (int q = 0; q < M - 1; ++q) {
+            const int n = R >> (q + 1);
+            fl.texels[q] = 6 * n * n;
+            fl.block_start[q] = total;
+            total += (fl.texels[q] + per_block - 1) / per_block;
+        }
+        fl.block_start[M - 1] = total;
+        fl.xcd_chunk = (total + 7) / 8;
+        const size_t shm = sizeof(Tap) * (size_t)T;
+        hipLaunchKernelGGL((k_prefilter<K, DT>), dim3(8 * fl.xcd_chunk), dim3(kFilterThreads), shm, stream, fl, l0,
+                           chain, ind_pyr, rgb_pyr);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_prefilter(const float *env, const uint8_t *ind_j, const float *ind_t, int R, int K, int M, int T,
+                            int dtype, void *workspace, void *ind_pyr, float *rgb_pyr, hipStream_t stream)
+{
+    float *chain = static_cast<float *>(workspace);
+#define GLINT_PF(KK, DD)                                                                                     \
+    if (K == KK && dtype == DD)                                                                              \
+        return launch_prefilter_t<KK, DD>(env, ind_j, ind_t, R, M, T, chain, ind_pyr, rgb_pyr, stream);
+#define GLINT_PF_K(KK) GLINT_PF(KK, 0) GLINT_PF(KK, 1) GLINT_PF(KK, 2) GLINT_PF(KK, 3)
+    GLINT_PF_K(2)
+    GLINT_PF_K(4)
+    GLINT_PF_K(8)
+    GLINT_PF_K(16)
+#undef GLINT_PF_K
+#undef GLINT_PF
+    return hipErrorInvalidValue;
+}
+
+} // namespace glint

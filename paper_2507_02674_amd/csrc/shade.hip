@@ -1,0 +1,315 @@
+// Per-pixel glint shading (Sec. 3.2, Sec. 3.3 Eq. (anisogrid), Sec. 4
+// Eq. (probhk) and Eq. (iblglints:fin), Sec. 6 Alg. "Dual-gated Gaussian").
+//
+// One thread per pixel.  The footprint count, the reflection probabilities
+// (trilinear pyramid lookup), the tree probabilities and the Gaussian draw
+// are double; the gating thresholds and masks are float, as the paper's bias
+// constant assumes.  The multinomial tree is walked depth by depth in place
+// over a register array of K counts (compile-time K, static indices).
+#include "device.hpp"
+#include "internal.hpp"
+
+namespace glint {
+
+constexpr int kShadeThreads = 256;
+
+template <int DT>
+__device__ __forceinline__ double load_value(const void *base, int64_t i);
+
+template <>
+__device__ __forceinline__ double load_value<0>(const void *base, int64_t i)
+{
+    return (double)static_cast<const float *>(base)[i];
+}
+template <>
+__device__ __forceinline__ double load_value<1>(const void *base, int64_t i)
+{
+    return (double)static_cast<const _Float16 *>(base)[i];
+}
+template <>
+__device__ __forceinline__ double load_value<2>(const void *base, int64_t i)
+{
+    return (double)__uint_as_float((uint32_t)static_cast<const uint16_t *>(base)[i] << 16);
+}
+template <>
+__device__ __forceinline__ double load_value<3>(const void *base, int64_t i)
+{
+    return (double)static_cast<const uint16_t *>(base)[i] / 65535.0;
+}
+
+__device__ __forceinline__ double lut_bilinear(const float *__restrict__ lut, int stride, int comp, double mu,
+                                               double sa)
+{
+    double x = mu * kLutN - 0.5, y = sa * kLutN - 0.5;
+    x = x < 0.0 ? 0.0 : (x > kLutN - 1 ? kLutN - 1 : x);
+    y = y < 0.0 ? 0.0 : (y > kLutN - 1 ? kLutN - 1 : y);
+    double x0 = floor(x), y0 = floor(y);
+    x0 = x0 > kLutN - 2 ? kLutN - 2 : x0;
+    y0 = y0 > kLutN - 2 ? kLutN - 2 : y0;
+    const double fx = x - x0, fy = y - y0;
+    const int ix = (int)x0, iy = (int)y0;
+    const double v00 = lut[(iy * kLutN + ix) * stride + comp];
+    const double v01 = lut[(iy * kLutN + ix + 1) * stride + comp];
+    const double v10 = lut[((iy + 1) * kLutN + ix) * stride + comp];
+    const double v11 = lut[((iy + 1) * kLutN + ix + 1) * stride + comp];
+    const double top = (1.0 - fx) * v00 + fx * v01;
+    const double bot = (1.0 - fx) * v10 + fx * v11;
+    return (1.0 - fy) * top + fy * bot;
+}
+
+struct ShadeArgs {
+    glint_gbuffer g;
+    int64_t P;
+    const void *ind_pyr;
+    const float *rgb_pyr;
+    const double *levels;
+    const float *lut_S;
+    const float *lut_E;
+    int R, M;
+    uint32_t seed;
+    float *radiance;
+    double *counts;
+    uint8_t *codes;
+    double *probs;
+};
+
+// One dual-gated Gaussian draw (Alg. "Dual-gated Gaussian").
+__device__ __forceinline__ void dual_gated(double N, double p, float xi1, float xi2, double &n, double &nb,
+                                           uint32_t &code)
+{
+    const gate_f g = gate_thresholds((float)N, (float)p);
+    const bool BnN = xi1 < g.th_nN;
+    const bool Bn1N = xi1 < g.th_n1N;
+    const bool BnbN = g.th_nbN <= xi1;
+    const bool Bnb1N = g.th_nb1N <= xi1;
+    const bool BG = ((float)N > 1.0f) && !Bn1N && !Bnb1N;
+    const double N2 = N > 2.0 ? N : 2.0;
+    double G = 0.0, Gb = 0.0;
+    if (BG) {
+        const double mu = 1.0 + (N2 - 2.0) * p;
+        const double sig = sqrt((N2 - 2.0) * p * (1.0 - p));
+        const double x = mu + sig * ppnd16((double)xi2);
+        G = x < 1.0 ? 1.0 : (x > N2 - 1.0 ? N2 - 1.0 : x);
+        Gb = N2 - G;
+    }
+    n = (BnN ? N2 - 1.0 : 0.0) + (Bn1N ? 1.0 : 0.0) + (BG ? G : 0.0);
+    nb = (BnbN ? N2 - 1.0 : 0.0) + (Bnb1N ? 1.0 : 0.0) + (BG ? Gb : 0.0);
+    code = (uint32_t)BnN | ((uint32_t)Bn1N << 1) | ((uint32_t)BnbN << 2) | ((uint32_t)Bnb1N << 3) |
+           ((uint32_t)BG << 4);
+}
+
+// Hierarchical multinomial over K bins (balanced binary tree, breadth-first
+// node numbering; left child gets n, right child gets nbar).
+template <int K>
+__device__ __forceinline__ void multinomial(double NP, const double (&p)[K], uint32_t seed_mix, int lev, int64_t a,
+                                            int64_t b, double (&cnt)[K], uint8_t *codes)
+{
+    cnt[0] = NP;
+#pragma unroll
+    for (int k = 1; k < K; ++k) cnt[k] = 0.0;
+#pragma unroll
+    for (int d = 0, width = K; width > 1; ++d, width >>= 1) {
+#pragma unroll
+        for (int j = (1 << d) - 1; j >= 0; --j) {
+            const int lo = j * width, mid = lo + width / 2, hi = lo + width;
+            double sl = 0.0, sr = 0.0;
+#pragma unroll
+            for (int k = lo; k < mid; ++k) sl += p[k];
+#pragma unroll
+            for (int k = mid; k < hi; ++k) sr += p[k];
+            const double st = sl + sr;
+            double pn = st > 0.0 ? sl / st : 0.0;
+            pn = pn > 1.0 ? 1.0 : pn;
+            const int node = (1 << d) - 1 + j;
+            const u4 h = pcg4d({(uint32_t)a, (uint32_t)b, (((uint32_t)lev & 0xFFFFu) << 16) | (uint32_t)node,
+                                seed_mix});
+            double n, nb;
+            uint32_t code;
+            dual_gated(cnt[j], pn, hash_unit(h.x), hash_unit(h.y), n, nb, code);
+            if (codes) codes[node] = (uint8_t)code;
+            cnt[2 * j] = n;
+            cnt[2 * j + 1] = nb;
+        }
+    }
+}
+
+template <int K, int DT, int V>
+__global__ void __launch_bounds__(kShadeThreads) k_shade(ShadeArgs A)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= A.P) return;
+    const uint32_t surf = A.g.surf_id[i];
+    if (surf == GLINT_NO_SURFACE) {
+        A.radiance[3 * i] = 0.0f; A.radiance[3 * i + 1] = 0.0f; A.radiance[3 * i + 2] = 0.0f;
+        if (A.counts) for (int k = 0; k < V * K; ++k) A.counts[i * V * K + k] = 0.0;
+        if (A.codes) for (int k = 0; k < V * (K - 1); ++k) A.codes[i * V * (K - 1) + k] = 0;
+        if (A.probs) for (int k = 0; k < K; ++k) A.probs[i * K + k] = 0.0;
+        return;
+    }
+    const double area = (double)A.g.area[i];
+    const double NP = (double)A.g.density[i] * area; // Sec. 3.2: stratified count
+    const d3 n = {(double)A.g.nx[i], (double)A.g.ny[i], (double)A.g.nz[i]};
+    const d3 v = {(double)A.g.vx[i], (double)A.g.vy[i], (double)A.g.vz[i]};
+    const double mu = n.x * v.x + n.y * v.y + n.z * v.z;
+    const d3 wr = {2.0 * mu * n.x - v.x, 2.0 * mu * n.y - v.y, 2.0 * mu * n.z - v.z};
+    const double aeff = sqrt((double)A.g.ax[i] * (double)A.g.ay[i]);
+    const double sa = sqrt(aeff);
+    double lod = sa * (double)(A.M - 1);
+    lod = lod < 0.0 ? 0.0 : (lod > (double)(A.M - 1) ? (double)(A.M - 1) : lod);
+
+    // trilinear pyramid lookup of the K indicator channels and RGB
+    const double l0f = floor(lod);
+    const int s0 = (int)l0f;
+    const int s1 = s0 + 1 < A.M ? s0 + 1 : A.M - 1;
+    const double fr = lod - l0f;
+    double F[K], rgb[3];
+#pragma unroll
+    for (int k = 0; k < K; ++k) F[k] = 0.0;
+    rgb[0] = rgb[1] = rgb[2] = 0.0;
+#pragma unroll
+    for (int li = 0; li < 2; ++li) {
+        const int s = li == 0 ? s0 : s1;
+        const double lw = li == 0 ? 1.0 - fr : fr;
+        const bilin4 bl = bilinear_taps(wr, A.R >> s);
+        const int64_t base = level_offset(A.R, s);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int64_t t = base + bl.idx[c];
+            const double w = lw * bl.w[c];
+#pragma unroll
+            for (int k = 0; k < K; ++k) F[k] += w * load_value<DT>(A.ind_pyr, t * K + k);
+            const float4 q = reinterpret_cast<const float4 *>(A.rgb_pyr)[t];
+            rgb[0] += w * (double)q.x;
+            rgb[1] += w * (double)q.y;
+            rgb[2] += w * (double)q.z;
+        }
+    }
+
+    // Sec. 4 Eq. (probhk) with Sec. 5 Eq. (rtiblndf)
+    double sumF = 0.0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) sumF += F[k];
+    const double S = lut_bilinear(A.lut_S, 1, 0, mu, sa);
+    const double EA = lut_bilinear(A.lut_E, 2, 0, mu, sa);
+    const double EB = lut_bilinear(A.lut_E, 2, 1, mu, sa);
+    double p[K];
+    double rest = 0.0;
+#pragma unroll
+    for (int k = 1; k < K; ++k) {
+        p[k] = sumF > 0.0 ? S * F[k] / sumF : 0.0;
+        rest += p[k];
+    }
+    p[0] = 1.0 - rest;
+    if (A.probs) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) A.probs[i * K + k] = p[k];
+    }
+
+    // footprint lattice: level l0 = floor(log2(area)/2) from the exponent
+    int e;
+    (void)frexp(area, &e);
+    const int l0 = (e - 1) >= 0 ? (e - 1) / 2 : -((-(e - 1) + 1) / 2);
+    double lt = 0.5 * log2(area) - (double)l0;
+    lt = lt < 0.0 ? 0.0 : (lt > 1.0 ? 1.0 : lt);
+    const uint32_t seed_mix = A.seed ^ (surf * 0x9E3779B9u);
+    const double uu = (double)A.g.u[i], vv = (double)A.g.v[i];
+
+    double Msum[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) Msum[k] = 0.0;
+#pragma unroll
+    for (int vi = 0; vi < V; ++vi) {
+        int lev;
+        int64_t a, b;
+        double w;
+        if (V == 1) {
+            lev = l0;
+            a = (int64_t)floor(ldexp(uu, -lev) + 0.5);
+            b = (int64_t)floor(ldexp(vv, -lev) + 0.5);
+            w = 1.0;
+        } else {
+            const int side = vi / 3, corner = vi % 3;
+            lev = l0 + side;
+            const double x = ldexp(uu, -lev), y = ldexp(vv, -lev);
+            const double fxl = floor(x), fyl = floor(y);
+            const double fx = x - fxl, fy = y - fyl;
+            const int64_t ix = (int64_t)fxl, iy = (int64_t)fyl;
+            double bw;
+            if (fx >= fy) {
+                if (corner == 0) { a = ix; b = iy; bw = 1.0 - fx; }
+                else if (corner == 1) { a = ix + 1; b = iy; bw = fx - fy; }
+                else { a = ix + 1; b = iy + 1; bw = fy; }
+            } else {
+                if (corner == 0) { a = ix; b = iy; bw = 1.0 - fy; }
+                else if (corner == 1) { a = ix; b = iy + 1; bw = fy - fx; }
+                else { a = ix + 1; b = iy + 1; bw = fx; }
+            }
+            w = (side == 0 ? 1.0 - lt : lt) * bw;
+        }
+        double Mv[K];
+        uint8_t *cod = A.codes ? A.codes + (i * V + vi) * (K - 1) : nullptr;
+        multinomial<K>(NP, p, seed_mix, lev, a, b, Mv, cod);
+#pragma unroll
+        for (int k = 0; k < K; ++k) Msum[k] += w * Mv[k];
+        if (A.counts) {
+#pragma unroll
+            for (int k = 0; k < K; ++k) A.counts[(i * V + vi) * K + k] = Mv[k];
+        }
+    }
+
+    // Sec. 4 Eq. (iblglints:fin)
+    double num = 0.0, den = 0.0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const double L = A.levels[k];
+        num += L * Msum[k];
+        den += L * p[k];
+    }
+    den *= NP;
+    const double gmod = (num > 0.0 && den > 0.0) ? num / den : 0.0;
+    const double f0[3] = {(double)A.g.f0r[i], (double)A.g.f0g[i], (double)A.g.f0b[i]};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) A.radiance[3 * i + c] = (float)((f0[c] * EA + EB) * rgb[c] * gmod);
+}
+
+template <int K, int DT>
+static hipError_t launch_shade_kd(const ShadeArgs &a, int V, hipStream_t stream)
+{
+    const unsigned blocks = (unsigned)((a.P + kShadeThreads - 1) / kShadeThreads);
+    if (V == 1) hipLaunchKernelGGL((k_shade<K, DT, 1>), dim3(blocks), dim3(kShadeThreads), 0, stream, a);
+    else hipLaunchKernelGGL((k_shade<K, DT, 6>), dim3(blocks), dim3(kShadeThreads), 0, stream, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_shade(const glint_gbuffer &g, int64_t P, const glint_env &env, const glint_shade_params &sp,
+                        float *radiance, const glint_shade_debug *dbg, hipStream_t stream)
+{
+    ShadeArgs a;
+    a.g = g;
+    a.P = P;
+    a.ind_pyr = env.ind_pyr;
+    a.rgb_pyr = env.rgb_pyr;
+    a.levels = env.levels;
+    a.lut_S = env.lut_S;
+    a.lut_E = env.lut_E;
+    a.R = env.R;
+    a.M = env.num_mips;
+    a.seed = sp.seed;
+    a.radiance = radiance;
+    a.counts = dbg ? dbg->counts : nullptr;
+    a.codes = dbg ? dbg->codes : nullptr;
+    a.probs = dbg ? dbg->probs : nullptr;
+    const int K = env.K, DT = (int)env.dtype, V = sp.vertices;
+#define GLINT_SH(KK, DD)                                                                                     \
+    if (K == KK && DT == DD) return launch_shade_kd<KK, DD>(a, V, stream);
+#define GLINT_SH_K(KK) GLINT_SH(KK, 0) GLINT_SH(KK, 1) GLINT_SH(KK, 2) GLINT_SH(KK, 3)
+    GLINT_SH_K(2)
+    GLINT_SH_K(4)
+    GLINT_SH_K(8)
+    GLINT_SH_K(16)
+#undef GLINT_SH_K
+#undef GLINT_SH
+    return hipErrorInvalidValue;
+}
+
+} // namespace glint

@@ -1,0 +1,194 @@
+"""Thin Python binding of libglint.so (the C ABI in include/glint.h).
+
+Argument marshalling only: torch tensors are passed as device pointers and
+torch's current HIP stream as the stream; every step of the hot path runs in
+the library's HIP kernels.  There is no CPU fallback: if the library is
+missing or no GPU is present, calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+from . import build as _build
+
+GLINT_OK, GLINT_EINVAL, GLINT_EUNSUPPORTED, GLINT_EDEVICE, GLINT_ENOMEM = 0, 1, 2, 3, 4
+GLINT_F32, GLINT_F16, GLINT_BF16, GLINT_UNORM16 = 0, 1, 2, 3
+GLINT_NO_SURFACE = 0xFFFFFFFF
+LUT_N = 64
+
+GBUF_FIELDS = ("nx", "ny", "nz", "vx", "vy", "vz", "u", "v", "area", "ax", "ay", "density",
+               "f0r", "f0g", "f0b", "surf_id")
+
+
+class GlintError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"glint error {code}: {msg}")
+        self.code = code
+
+
+class PartitionParams(C.Structure):
+    _fields_ = [("K", C.c_int), ("ell", C.c_double), ("level_mode", C.c_int), ("weight_space", C.c_int)]
+
+
+class PrefilterParams(C.Structure):
+    _fields_ = [("num_mips", C.c_int), ("taps", C.c_int), ("dtype", C.c_int)]
+
+
+class GBuffer(C.Structure):
+    _fields_ = [(k, C.c_void_p) for k in GBUF_FIELDS]
+
+
+class Env(C.Structure):
+    _fields_ = [("ind_pyr", C.c_void_p), ("rgb_pyr", C.c_void_p), ("levels", C.c_void_p),
+                ("lut_S", C.c_void_p), ("lut_E", C.c_void_p), ("R", C.c_int), ("K", C.c_int),
+                ("num_mips", C.c_int), ("dtype", C.c_int)]
+
+
+class ShadeParams(C.Structure):
+    _fields_ = [("seed", C.c_uint32), ("vertices", C.c_int)]
+
+
+class ShadeDebug(C.Structure):
+    _fields_ = [("counts", C.c_void_p), ("codes", C.c_void_p), ("probs", C.c_void_p)]
+
+
+_LIB = None
+
+EXPORTS = {
+    "glint_version": ([], C.c_int),
+    "glint_last_error": ([], C.c_char_p),
+    "glint_create": ([C.c_int, C.POINTER(C.c_void_p)], C.c_int),
+    "glint_destroy": ([C.c_void_p], None),
+    "glint_sync": ([C.c_void_p], C.c_int),
+    "glint_partition_workspace_bytes": ([C.c_int], C.c_size_t),
+    "glint_partition_env": ([C.c_void_p, C.c_void_p, C.c_int, C.POINTER(PartitionParams), C.c_void_p, C.c_void_p,
+                             C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
+    "glint_pyramid_texels": ([C.c_int, C.c_int], C.c_int64),
+    "glint_prefilter_workspace_bytes": ([C.c_int, C.c_int, C.POINTER(PrefilterParams)], C.c_size_t),
+    "glint_prefilter": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_int,
+                         C.POINTER(PrefilterParams), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
+    "glint_build_luts": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
+    "glint_shade": ([C.c_void_p, C.POINTER(GBuffer), C.c_int64, C.POINTER(Env), C.POINTER(ShadeParams),
+                     C.c_void_p, C.POINTER(ShadeDebug), C.c_void_p], C.c_int),
+}
+
+
+def lib():
+    """Loads the in-tree libglint.so (building it once if it was never built)."""
+    global _LIB
+    if _LIB is None:
+        path = _build.library_path()
+        if not os.path.exists(path):
+            _build.build_library()
+        L = C.CDLL(path)
+        for name, (args, res) in EXPORTS.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _LIB = L
+    return _LIB
+
+
+def library_path() -> str:
+    return _build.library_path()
+
+
+def _check(rc):
+    if rc != GLINT_OK:
+        raise GlintError(rc, lib().glint_last_error().decode())
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return C.c_void_p(stream)
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _require_cuda(*tensors):
+    for t in tensors:
+        if t is not None and not t.is_cuda:
+            raise GlintError(GLINT_EINVAL, "tensor arguments must live on the GPU")
+
+
+# --- C ABI, one function per entry point ------------------------------------------
+
+def glint_version() -> int:
+    return lib().glint_version()
+
+
+def glint_create(device: int = 0) -> C.c_void_p:
+    h = C.c_void_p()
+    _check(lib().glint_create(device, C.byref(h)))
+    return h
+
+
+def glint_destroy(ctx) -> None:
+    lib().glint_destroy(ctx)
+
+
+def glint_sync(ctx) -> None:
+    _check(lib().glint_sync(ctx))
+
+
+def glint_partition_workspace_bytes(R: int) -> int:
+    return lib().glint_partition_workspace_bytes(R)
+
+
+def glint_partition_env(ctx, env, R, params: PartitionParams, workspace, levels, ind_j, ind_t, stream=None):
+    _require_cuda(env, workspace, levels, ind_j, ind_t)
+    _check(lib().glint_partition_env(ctx, _ptr(env), R, C.byref(params), _ptr(workspace), _ptr(levels),
+                                     _ptr(ind_j), _ptr(ind_t), _stream(stream)))
+
+
+def glint_pyramid_texels(R: int, num_mips: int) -> int:
+    return lib().glint_pyramid_texels(R, num_mips)
+
+
+def glint_prefilter_workspace_bytes(R: int, K: int, params: PrefilterParams) -> int:
+    return lib().glint_prefilter_workspace_bytes(R, K, C.byref(params))
+
+
+def glint_prefilter(ctx, env, ind_j, ind_t, R, K, params: PrefilterParams, workspace, ind_pyr, rgb_pyr,
+                    stream=None):
+    _require_cuda(env, ind_j, ind_t, workspace, ind_pyr, rgb_pyr)
+    _check(lib().glint_prefilter(ctx, _ptr(env), _ptr(ind_j), _ptr(ind_t), R, K, C.byref(params),
+                                 _ptr(workspace), _ptr(ind_pyr), _ptr(rgb_pyr), _stream(stream)))
+
+
+def glint_build_luts(ctx, lut_S, lut_E, stream=None):
+    _require_cuda(lut_S, lut_E)
+    _check(lib().glint_build_luts(ctx, _ptr(lut_S), _ptr(lut_E), _stream(stream)))
+
+
+def make_gbuffer(fields: dict) -> GBuffer:
+    """Maps a dict of device tensors (one per G-buffer field) to the C struct."""
+    _require_cuda(*fields.values())
+    return GBuffer(*[fields[k].data_ptr() for k in GBUF_FIELDS])
+
+
+def make_env(ind_pyr, rgb_pyr, levels, lut_S, lut_E, R, K, num_mips, dtype) -> Env:
+    _require_cuda(ind_pyr, rgb_pyr, levels, lut_S, lut_E)
+    return Env(ind_pyr.data_ptr(), rgb_pyr.data_ptr(), levels.data_ptr(), lut_S.data_ptr(), lut_E.data_ptr(),
+               R, K, num_mips, dtype)
+
+
+def glint_shade(ctx, gbuf: GBuffer, num_pixels: int, env: Env, params: ShadeParams, radiance, debug=None,
+                stream=None):
+    _require_cuda(radiance)
+    dbg = None
+    if debug is not None:
+        _require_cuda(*[t for t in debug.values() if t is not None])
+        dbg = ShadeDebug(*[debug.get(k).data_ptr() if debug.get(k) is not None else None
+                           for k in ("counts", "codes", "probs")])
+    _check(lib().glint_shade(ctx, C.byref(gbuf), num_pixels, C.byref(env), C.byref(params), _ptr(radiance),
+                             C.byref(dbg) if dbg is not None else None, _stream(stream)))

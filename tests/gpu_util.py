@@ -1,0 +1,118 @@
+"""Helpers for the GPU parity tests: run one library entry point on numpy
+inputs and return numpy outputs (all compute in libglint's kernels)."""
+import numpy as np
+import torch
+
+from paper_2507_02674_amd import glint as G
+
+STORAGE = {G.GLINT_F32: (torch.float32, np.float32), G.GLINT_F16: (torch.float16, np.float16),
+           G.GLINT_BF16: (torch.int16, np.uint16), G.GLINT_UNORM16: (torch.int16, np.uint16)}
+
+
+def log(*args):
+    print("[gpu]", *args, flush=True)
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def partition(ctx, env, K, ell=1e-3, level_mode=0, weight_space=0):
+    R = env.shape[1]
+    e = dev(env)
+    ws = torch.empty(max(G.glint_partition_workspace_bytes(R) // 8, 1), dtype=torch.float64, device="cuda")
+    levels = torch.empty(K, dtype=torch.float64, device="cuda")
+    ind_j = torch.empty((6, R, R), dtype=torch.uint8, device="cuda")
+    ind_t = torch.empty((6, R, R), dtype=torch.float32, device="cuda")
+    G.glint_partition_env(ctx, e, R, G.PartitionParams(K, ell, level_mode, weight_space), ws, levels, ind_j, ind_t)
+    return host(levels), host(ind_j), host(ind_t)
+
+
+def prefilter(ctx, env, ind_j, ind_t, K, M, T=64, dtype=G.GLINT_F32):
+    R = env.shape[1]
+    fp = G.PrefilterParams(M, T, dtype)
+    ws = torch.empty(max(G.glint_prefilter_workspace_bytes(R, K, fp) // 4, 4), dtype=torch.float32, device="cuda")
+    n = G.glint_pyramid_texels(R, M)
+    tdt, ndt = STORAGE[dtype]
+    ind_pyr = torch.empty((n, K), dtype=tdt, device="cuda")
+    rgb_pyr = torch.empty((n, 4), dtype=torch.float32, device="cuda")
+    G.glint_prefilter(ctx, dev(env), dev(ind_j), dev(ind_t), R, K, fp, ws, ind_pyr, rgb_pyr)
+    raw = host(ind_pyr).view(ndt) if ndt == np.uint16 else host(ind_pyr)
+    CP = (K + 3 + 3) & ~3
+    chain = host(ws)[: (n - 6 * R * R) * CP].reshape(-1, CP)[:, : K + 3]
+    return raw, host(rgb_pyr), chain
+
+
+def decode(raw, dtype):
+    if dtype == G.GLINT_F32:
+        return raw.astype(np.float32)
+    if dtype == G.GLINT_F16:
+        return raw.astype(np.float32)
+    if dtype == G.GLINT_BF16:
+        return (raw.astype(np.uint32) << 16).view(np.float32)
+    return raw.astype(np.float64) / 65535.0
+
+
+def encode(values, dtype):
+    """Rounds float64 values to the stored type (reference rounding)."""
+    if dtype == G.GLINT_F32:
+        return values.astype(np.float32)
+    if dtype == G.GLINT_F16:
+        return values.astype(np.float16)
+    if dtype == G.GLINT_BF16:
+        f = values.astype(np.float32).view(np.uint32).astype(np.uint64)
+        f = (f + 0x7FFF + ((f >> 16) & 1)) >> 16
+        return f.astype(np.uint16)
+    return np.rint(np.clip(values, 0, 1) * 65535.0).astype(np.uint16)
+
+
+def luts(ctx):
+    S = torch.empty((64, 64), dtype=torch.float32, device="cuda")
+    E = torch.empty((64, 64, 2), dtype=torch.float32, device="cuda")
+    G.glint_build_luts(ctx, S, E)
+    return host(S), host(E)
+
+
+def gbuf_to_device(gbuf):
+    out = {}
+    for k in G.GBUF_FIELDS:
+        a = np.ascontiguousarray(gbuf[k])
+        if k == "surf_id":
+            a = a.view(np.int32)
+        out[k] = dev(a)
+    return out
+
+
+def shade(ctx, gbuf, ind_raw, rgb, levels, lut_S, lut_E, R, K, M, dtype=G.GLINT_F32, seed=1, vertices=1,
+          debug=True, num_pixels=None):
+    fields = gbuf_to_device(gbuf)
+    P = len(gbuf["nx"]) if num_pixels is None else num_pixels
+    tdt, ndt = STORAGE[dtype]
+    ind = torch.from_numpy(np.ascontiguousarray(ind_raw).view(np.int16) if ndt == np.uint16 else
+                           np.ascontiguousarray(ind_raw)).cuda()
+    rgb_t, lev_t, S_t, E_t = dev(rgb), dev(levels), dev(lut_S), dev(lut_E)
+    env = G.make_env(ind, rgb_t, lev_t, S_t, E_t, R, K, M, dtype)
+    rad = torch.full((max(P, 1), 3), -1.0, dtype=torch.float32, device="cuda")
+    dbg = None
+    if debug:
+        dbg = dict(counts=torch.empty((max(P, 1), vertices, K), dtype=torch.float64, device="cuda"),
+                   codes=torch.empty((max(P, 1), vertices, K - 1), dtype=torch.uint8, device="cuda"),
+                   probs=torch.empty((max(P, 1), K), dtype=torch.float64, device="cuda"))
+    G.glint_shade(ctx, G.make_gbuffer(fields), P, env, G.ShadeParams(seed, vertices), rad, dbg)
+    out = dict(radiance=host(rad)[:P])
+    if debug:
+        for k, v in dbg.items():
+            out[k] = host(v)[:P]
+    return out
+
+
+def ulp_diff(a, b):
+    """Distance in float32 units in the last place (same-sign finite values)."""
+    a = np.ascontiguousarray(a, dtype=np.float32).view(np.int32).astype(np.int64)
+    b = np.ascontiguousarray(b, dtype=np.float32).view(np.int32).astype(np.int64)
+    return np.abs(a - b)

@@ -1,0 +1,64 @@
+"""The C-ABI library loads and exports every entry point include/glint.h declares
+(host-only checks: no kernel is launched here)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2507_02674_amd import glint as G
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "glint.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(glint_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_hot_path():
+    names = declared_functions()
+    for required in ("glint_partition_env", "glint_prefilter", "glint_build_luts", "glint_shade",
+                     "glint_create", "glint_destroy", "glint_last_error"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = C.CDLL(G.library_path())
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    assert set(declared_functions()) <= set(G.EXPORTS)
+
+
+def test_host_side_queries():
+    assert G.glint_version() == 1
+    assert G.glint_pyramid_texels(256, 8) == sum(6 * (256 >> m) ** 2 for m in range(8)) == 524280
+    assert G.glint_pyramid_texels(32, 6) == 8190
+    assert G.glint_pyramid_texels(3, 1) == 0  # not a power of two
+    assert G.glint_pyramid_texels(32, 7) == 0  # too many mips
+    fp = G.PrefilterParams(8, 64, G.GLINT_F32)
+    # chain levels 1..7, K+3 = 11 channels padded to 12 floats
+    assert G.glint_prefilter_workspace_bytes(256, 8, fp) == (524280 - 6 * 256 * 256) * 12 * 4
+    assert G.glint_partition_workspace_bytes(256) > 0
+    assert G.glint_partition_workspace_bytes(100) == 0
+
+
+def test_struct_layouts_match_header():
+    # field order and sizes as declared in include/glint.h (LP64)
+    assert C.sizeof(G.PartitionParams) == 24
+    assert G.PartitionParams.ell.offset == 8
+    assert C.sizeof(G.GBuffer) == 16 * 8
+    assert C.sizeof(G.Env) == 5 * 8 + 4 * 4
+    assert C.sizeof(G.ShadeParams) == 8
+    assert C.sizeof(G.ShadeDebug) == 24
+
+
+def test_calls_validate_before_touching_the_device():
+    lib = G.lib()
+    # a null context is rejected with EINVAL, not a crash
+    rc = lib.glint_partition_env(None, None, 32, None, None, None, None, None, None)
+    assert rc == G.GLINT_EINVAL
+    assert "context" in lib.glint_last_error().decode()
+    rc = lib.glint_shade(None, None, 10, None, None, None, None, None)
+    assert rc == G.GLINT_EINVAL
