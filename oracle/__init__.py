@@ -72,6 +72,7 @@ def _declare(L):
     L.orc_lattice_level.argtypes = [C.c_double, f64p]
     L.orc_lattice_level.restype = C.c_int
     L.orc_taps.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, f64p]
+    L.orc_pyramid_lookup.argtypes = [f32p, C.c_int, C.c_int, C.c_int, f64p, f64p, C.c_int64, f64p]
 
 
 def threads_default():
@@ -265,4 +266,16 @@ def lattice_level(area):
 def taps(m, M, T, R):
     out = np.zeros((T, 5))
     lib().orc_taps(m, M, T, R, _p(out, C.c_double))
+    return out
+
+
+def pyramid_lookup(pyr, R, M, dirs, lods):
+    """Trilinear seamless lookup of a float pyramid [texels, C] at dirs [n,3]."""
+    pyr = np.ascontiguousarray(pyr, dtype=np.float32)
+    dirs = np.ascontiguousarray(dirs, dtype=np.float64).reshape(-1, 3)
+    lods = np.ascontiguousarray(np.broadcast_to(lods, (len(dirs),)), dtype=np.float64)
+    Cn = pyr.shape[1]
+    out = np.zeros((len(dirs), Cn))
+    lib().orc_pyramid_lookup(_p(pyr, C.c_float), R, M, Cn, _p(dirs, C.c_double), _p(lods, C.c_double), len(dirs),
+                             _p(out, C.c_double))
     return out

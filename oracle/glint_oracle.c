@@ -208,23 +208,51 @@ int orc_mipchain(const float *env, const uint8_t *ind_j, const float *ind_t, int
     return ORC_OK;
 }
 
-/* Texel lookup with seams: a texel index off the face is re-projected
- * through the 3-D direction of its (extended) centre to the nearest texel of
- * the owning face. */
+/* Seams.  A bilinear footprint reaches at most one texel beyond a face.
+ * A texel off one edge of the face is re-projected through the 3-D
+ * direction of its (extended) centre to the nearest texel of the face that
+ * owns that direction -- the adjacent texel across the edge.  The texel off
+ * two edges (beyond a cube corner) has no single neighbour: it takes the
+ * mean of the three texels that meet at that cube corner.  With this rule
+ * the bilinear lookup is continuous across edges and corners, so it does
+ * not depend on which face a direction lying on an edge is assigned to. */
+static void reproject_one(int face, int x, int y, int n, int *f2, int *x2, int *y2)
+{
+    double d[3], s, t;
+    face_to_dir(face, 2.0 * (x + 0.5) / n - 1.0, 2.0 * (y + 0.5) / n - 1.0, d);
+    *f2 = dir_to_face(d, &s, &t);
+    int a = (int)floor((s + 1.0) * 0.5 * n);
+    int b = (int)floor((t + 1.0) * 0.5 * n);
+    *x2 = a < 0 ? 0 : (a > n - 1 ? n - 1 : a);
+    *y2 = b < 0 ? 0 : (b > n - 1 ? n - 1 : b);
+}
+
+/* Resolves texel (x, y) of `face` (x, y in [-1, n]) to 1 or 3 in-face
+ * texels; returns the count. */
+static int resolve_texel(int face, int x, int y, int n, int fo[3], int xo[3], int yo[3])
+{
+    int xin = x >= 0 && x < n, yin = y >= 0 && y < n;
+    if (xin && yin) { fo[0] = face; xo[0] = x; yo[0] = y; return 1; }
+    int xc = x < 0 ? 0 : (x > n - 1 ? n - 1 : x);
+    int yc = y < 0 ? 0 : (y > n - 1 ? n - 1 : y);
+    if (xin || yin) { reproject_one(face, x, y, n, &fo[0], &xo[0], &yo[0]); return 1; }
+    fo[0] = face; xo[0] = xc; yo[0] = yc;
+    reproject_one(face, x, yc, n, &fo[1], &xo[1], &yo[1]);
+    reproject_one(face, xc, y, n, &fo[2], &xo[2], &yo[2]);
+    return 3;
+}
+
 static void chain_texel_seamless(const src_chain *c, int level, int face, int x, int y, double *out)
 {
     int n = c->R >> level;
-    if (x >= 0 && x < n && y >= 0 && y < n) { chain_texel(c, level, face, x, y, out); return; }
-    double d[3], s, t;
-    face_to_dir(face, 2.0 * (x + 0.5) / n - 1.0, 2.0 * (y + 0.5) / n - 1.0, d);
-    int f2 = dir_to_face(d, &s, &t);
-    int x2 = (int)floor((s + 1.0) * 0.5 * n);
-    int y2 = (int)floor((t + 1.0) * 0.5 * n);
-    if (x2 < 0) x2 = 0;
-    if (x2 > n - 1) x2 = n - 1;
-    if (y2 < 0) y2 = 0;
-    if (y2 > n - 1) y2 = n - 1;
-    chain_texel(c, level, f2, x2, y2, out);
+    int fo[3], xo[3], yo[3];
+    int cnt = resolve_texel(face, x, y, n, fo, xo, yo);
+    if (cnt == 1) { chain_texel(c, level, fo[0], xo[0], yo[0], out); return; }
+    double a[20], b[20], d[20];
+    chain_texel(c, level, fo[0], xo[0], yo[0], a);
+    chain_texel(c, level, fo[1], xo[1], yo[1], b);
+    chain_texel(c, level, fo[2], xo[2], yo[2], d);
+    for (int k = 0; k < c->K + 3; ++k) out[k] = ((a[k] + b[k]) + d[k]) / 3.0;
 }
 
 typedef void (*texel_fn)(const void *src, int level, int face, int x, int y, double *out);
@@ -709,23 +737,25 @@ typedef struct {
     int R, C;
 } pyr_src;
 
+static void pyr_texel_at(const pyr_src *src, int level, int face, int x, int y, double *out)
+{
+    int n = src->R >> level;
+    const float *p = src->pyr + (level_offset(src->R, level) + ((int64_t)face * n + y) * n + x) * src->C;
+    for (int k = 0; k < src->C; ++k) out[k] = (double)p[k];
+}
+
 static void pyr_texel(const void *srcv, int level, int face, int x, int y, double *out)
 {
     const pyr_src *src = (const pyr_src *)srcv;
     int n = src->R >> level;
-    if (!(x >= 0 && x < n && y >= 0 && y < n)) {
-        double d[3], s, t;
-        face_to_dir(face, 2.0 * (x + 0.5) / n - 1.0, 2.0 * (y + 0.5) / n - 1.0, d);
-        face = dir_to_face(d, &s, &t);
-        x = (int)floor((s + 1.0) * 0.5 * n);
-        y = (int)floor((t + 1.0) * 0.5 * n);
-        if (x < 0) x = 0;
-        if (x > n - 1) x = n - 1;
-        if (y < 0) y = 0;
-        if (y > n - 1) y = n - 1;
-    }
-    const float *p = src->pyr + (level_offset(src->R, level) + ((int64_t)face * n + y) * n + x) * src->C;
-    for (int k = 0; k < src->C; ++k) out[k] = (double)p[k];
+    int fo[3], xo[3], yo[3];
+    int cnt = resolve_texel(face, x, y, n, fo, xo, yo);
+    if (cnt == 1) { pyr_texel_at(src, level, fo[0], xo[0], yo[0], out); return; }
+    double a[20], b[20], d[20];
+    pyr_texel_at(src, level, fo[0], xo[0], yo[0], a);
+    pyr_texel_at(src, level, fo[1], xo[1], yo[1], b);
+    pyr_texel_at(src, level, fo[2], xo[2], yo[2], d);
+    for (int k = 0; k < src->C; ++k) out[k] = ((a[k] + b[k]) + d[k]) / 3.0;
 }
 
 static double lut_bilinear(const float *lut, int stride, int comp, double mu, double sa)
@@ -923,4 +953,14 @@ void orc_taps(int m, int M, int T, int R, double *out5)
         out5[5 * j + 3] = t[j].w; out5[5 * j + 4] = t[j].lod;
     }
     free(t);
+}
+
+/* Trilinear lookup of a float pyramid (mip-major, C channels per texel) at
+ * the given directions and lods: the addressing used by the filter's taps
+ * and by shading.  out: [count][C]. */
+void orc_pyramid_lookup(const float *pyr, int R, int M, int C, const double *dirs, const double *lods,
+                        int64_t count, double *out)
+{
+    pyr_src ps = {pyr, R, C};
+    for (int64_t q = 0; q < count; ++q) trilinear(pyr_texel, &ps, R, M, C, dirs + 3 * q, lods[q], out + q * C);
 }

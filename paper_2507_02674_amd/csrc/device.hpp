@@ -57,49 +57,74 @@ __host__ __device__ __forceinline__ int64_t level_offset(int R, int level)
     return off;
 }
 
-// A texel index off the face (x or y in {-1, n}) is re-projected through
-// the 3-D direction of its extended centre to the nearest texel of the
-// owning face.  Returns the flat index within the level.
-__device__ __forceinline__ int64_t texel_index(int face, int x, int y, int n)
+// Seams.  A bilinear footprint reaches at most one texel beyond a face.  A
+// texel off one edge is re-projected through the 3-D direction of its
+// extended centre to the nearest texel of the owning face (the adjacent
+// texel across the edge); the texel off two edges (beyond a cube corner)
+// is the mean of the three texels meeting at that corner.  This keeps the
+// lookup continuous across edges and corners.
+__device__ __forceinline__ int64_t reproject_one(int face, int x, int y, int n)
 {
-    if (x < 0 || x >= n || y < 0 || y >= n) {
-        const double inv = 1.0 / (double)n;
-        const d3 d = face_dir(face, 2.0 * ((double)x + 0.5) * inv - 1.0, 2.0 * ((double)y + 0.5) * inv - 1.0);
-        double s, t;
-        face = dir_face(d, s, t);
-        x = (int)floor((s + 1.0) * 0.5 * (double)n);
-        y = (int)floor((t + 1.0) * 0.5 * (double)n);
-        x = x < 0 ? 0 : (x > n - 1 ? n - 1 : x);
-        y = y < 0 ? 0 : (y > n - 1 ? n - 1 : y);
-    }
-    return ((int64_t)face * n + y) * n + x;
+    const double inv = 1.0 / (double)n;
+    const d3 d = face_dir(face, 2.0 * ((double)x + 0.5) * inv - 1.0, 2.0 * ((double)y + 0.5) * inv - 1.0);
+    double s, t;
+    const int f2 = dir_face(d, s, t);
+    int a = (int)floor((s + 1.0) * 0.5 * (double)n);
+    int b = (int)floor((t + 1.0) * 0.5 * (double)n);
+    a = a < 0 ? 0 : (a > n - 1 ? n - 1 : a);
+    b = b < 0 ? 0 : (b > n - 1 ? n - 1 : b);
+    return ((int64_t)f2 * n + b) * n + a;
 }
 
-// Bilinear footprint of direction d on a level of face size n: the four
-// texel indices (within the level) and their weights.
-struct bilin4 {
-    int64_t idx[4];
-    double w[4];
+// Resolves texel (x, y), x and y in [-1, n], of `face` to 1 or 3 flat
+// indices within the level; returns the count.
+__device__ __forceinline__ int resolve_texel(int face, int x, int y, int n, int64_t (&idx)[3])
+{
+    const bool xin = (unsigned)x < (unsigned)n, yin = (unsigned)y < (unsigned)n;
+    if (xin && yin) {
+        idx[0] = ((int64_t)face * n + y) * n + x;
+        return 1;
+    }
+    if (xin || yin) {
+        idx[0] = reproject_one(face, x, y, n);
+        return 1;
+    }
+    const int xc = x < 0 ? 0 : n - 1, yc = y < 0 ? 0 : n - 1;
+    idx[0] = ((int64_t)face * n + yc) * n + xc;
+    idx[1] = reproject_one(face, x, yc, n);
+    idx[2] = reproject_one(face, xc, y, n);
+    return 3;
+}
+
+// Footprint of a direction on one level: face coordinates are computed once
+// per direction (dir_face) and shared by every level.
+struct face_st {
+    int face;
+    double s, t;
 };
 
-__device__ __forceinline__ bilin4 bilinear_taps(const d3 &d, int n)
+__device__ __forceinline__ face_st locate(const d3 &d)
 {
-    double s, t;
-    const int face = dir_face(d, s, t);
-    const double x = (s + 1.0) * 0.5 * (double)n - 0.5;
-    const double y = (t + 1.0) * 0.5 * (double)n - 0.5;
+    face_st f;
+    f.face = dir_face(d, f.s, f.t);
+    return f;
+}
+
+struct bilin {
+    int x0, y0;
+    double fx, fy;
+};
+
+__device__ __forceinline__ bilin bilinear_at(const face_st &f, int n)
+{
+    const double x = (f.s + 1.0) * 0.5 * (double)n - 0.5;
+    const double y = (f.t + 1.0) * 0.5 * (double)n - 0.5;
     const double x0 = floor(x), y0 = floor(y);
-    const double fx = x - x0, fy = y - y0;
-    const int ix = (int)x0, iy = (int)y0;
-    bilin4 b;
-    b.idx[0] = texel_index(face, ix, iy, n);
-    b.idx[1] = texel_index(face, ix + 1, iy, n);
-    b.idx[2] = texel_index(face, ix, iy + 1, n);
-    b.idx[3] = texel_index(face, ix + 1, iy + 1, n);
-    b.w[0] = (1.0 - fy) * (1.0 - fx);
-    b.w[1] = (1.0 - fy) * fx;
-    b.w[2] = fy * (1.0 - fx);
-    b.w[3] = fy * fx;
+    bilin b;
+    b.x0 = (int)x0;
+    b.y0 = (int)y0;
+    b.fx = x - x0;
+    b.fy = y - y0;
     return b;
 }
 

@@ -101,6 +101,36 @@ __device__ __forceinline__ void load_chain(const float *__restrict__ lvl, int64_
     for (int k = 0; k < K + 3; ++k) v[k] = (double)buf[k];
 }
 
+// Adds w * (value of texel (x, y) of `face` on chain level s) to acc, with
+// the seam rule (mean of three texels beyond a cube corner).
+template <int K>
+__device__ __forceinline__ void fetch_texel(const Level0<K> &l0, const float *__restrict__ lvl, int s, int64_t i,
+                                            double (&v)[K + 3])
+{
+    if (s == 0) l0.load(i, v);
+    else load_chain<K>(lvl, i, v);
+}
+
+template <int K>
+__device__ __forceinline__ void accumulate_texel(const Level0<K> &l0, const float *__restrict__ lvl, int s, int face,
+                                                 int x, int y, int n, double w, double (&acc)[K + 3])
+{
+    constexpr int C = K + 3;
+    int64_t idx[3];
+    const int cnt = resolve_texel(face, x, y, n, idx);
+    double v[C];
+    fetch_texel<K>(l0, lvl, s, idx[0], v);
+    if (cnt == 3) {
+        double b[C], c[C];
+        fetch_texel<K>(l0, lvl, s, idx[1], b);
+        fetch_texel<K>(l0, lvl, s, idx[2], c);
+#pragma unroll
+        for (int k = 0; k < C; ++k) v[k] = ((v[k] + b[k]) + c[k]) / 3.0;
+    }
+#pragma unroll
+    for (int k = 0; k < C; ++k) acc[k] += w * v[k];
+}
+
 // ---------------------------------------------------------------------------
 // chain level s (>= 1) from level s-1
 // ---------------------------------------------------------------------------
@@ -201,18 +231,22 @@ __global__ void __launch_bounds__(kFilterThreads) k_prefilter(FilterLaunch fl, L
     constexpr int C = K + 3, CP = chain_stride(K);
     extern __shared__ Tap s_taps[];
     __shared__ double s_wsum;
+    __shared__ const float *s_lvl[16];
 
     // XCD-aware remap: hardware dispatches block b to XCD b % 8; give each
     // XCD a contiguous range of logical blocks (neighbouring texels share
-    // source texels in that XCD's L2).
-    // The grid is padded to 8 * xcd_chunk blocks, so this is a bijection;
-    // padding blocks land past the last mip's texels and stay inactive.
+    // source texels in that XCD's L2).  The grid is padded to 8 * xcd_chunk
+    // blocks, so this is a bijection; padding blocks land past the last
+    // mip's texels and stay inactive.
     const int b = (int)blockIdx.x;
     const int lb = (b % 8) * fl.xcd_chunk + b / 8;
     int q = 0;
     while (q + 1 < fl.nmips && lb >= fl.block_start[q + 1]) ++q;
     const int m = q + 1;
     for (int j = threadIdx.x; j < fl.T; j += blockDim.x) make_tap(j, m, fl.M, fl.T, fl.R, s_taps[j]);
+    if (threadIdx.x < fl.M)
+        s_lvl[threadIdx.x] = threadIdx.x == 0 ? nullptr
+                                              : chain + (level_offset(fl.R, threadIdx.x) - 6LL * fl.R * fl.R) * CP;
     __syncthreads();
     if (threadIdx.x == 0) {
         double ws = 0.0;
@@ -249,25 +283,21 @@ __global__ void __launch_bounds__(kFilterThreads) k_prefilter(FilterLaunch fl, L
             const d3 h = {tp.hx * t1.x + tp.hy * t2.x + tp.hz * r.x, tp.hx * t1.y + tp.hy * t2.y + tp.hz * r.y,
                           tp.hx * t1.z + tp.hy * t2.z + tp.hz * r.z};
             const d3 l = {2.0 * tp.hz * h.x - r.x, 2.0 * tp.hz * h.y - r.y, 2.0 * tp.hz * h.z - r.z};
+            const face_st fs = locate(l);
             const double l0f = floor(tp.lod);
             const int s0 = (int)l0f;
-            const int s1 = s0 + 1 < fl.M ? s0 + 1 : fl.M - 1;
             const double fr = tp.lod - l0f;
             const int nlev = fr > 0.0 ? 2 : 1;
             for (int li = 0; li < nlev; ++li) {
-                const int s = li == 0 ? s0 : s1;
+                const int s = s0 + li; // fr > 0 implies s0 + 1 <= M - 1
                 const double lw = tp.w * (li == 0 ? 1.0 - fr : fr);
-                const bilin4 bl = bilinear_taps(l, fl.R >> s);
-                const float *lvl = s == 0 ? nullptr : chain + (level_offset(fl.R, s) - 6LL * fl.R * fl.R) * CP;
-#pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    double v[C];
-                    if (s == 0) l0.load(bl.idx[c], v);
-                    else load_chain<K>(lvl, bl.idx[c], v);
-                    const double w = lw * bl.w[c];
-#pragma unroll
-                    for (int k = 0; k < C; ++k) acc[k] += w * v[k];
-                }
+                const int ns = fl.R >> s;
+                const bilin bl = bilinear_at(fs, ns);
+                const float *lvl = s_lvl[s];
+                accumulate_texel<K>(l0, lvl, s, fs.face, bl.x0, bl.y0, ns, lw * ((1.0 - bl.fy) * (1.0 - bl.fx)), acc);
+                accumulate_texel<K>(l0, lvl, s, fs.face, bl.x0 + 1, bl.y0, ns, lw * ((1.0 - bl.fy) * bl.fx), acc);
+                accumulate_texel<K>(l0, lvl, s, fs.face, bl.x0, bl.y0 + 1, ns, lw * (bl.fy * (1.0 - bl.fx)), acc);
+                accumulate_texel<K>(l0, lvl, s, fs.face, bl.x0 + 1, bl.y0 + 1, ns, lw * (bl.fy * bl.fx), acc);
             }
         }
     }

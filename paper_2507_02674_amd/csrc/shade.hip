@@ -37,6 +37,65 @@ __device__ __forceinline__ double load_value<3>(const void *base, int64_t i)
     return (double)static_cast<const uint16_t *>(base)[i] / 65535.0;
 }
 
+// One pyramid texel: K indicator channels (stored type DT) and RGB, as double.
+template <int K, int DT>
+__device__ __forceinline__ void load_texel(const void *__restrict__ ind, const float *__restrict__ rgb, int64_t t,
+                                           double (&v)[K + 3])
+{
+    if constexpr (DT == 0 && K % 4 == 0) {
+        const float4 *p = reinterpret_cast<const float4 *>(static_cast<const float *>(ind) + t * K);
+#pragma unroll
+        for (int q = 0; q < K / 4; ++q) {
+            const float4 f = p[q];
+            v[4 * q] = f.x; v[4 * q + 1] = f.y; v[4 * q + 2] = f.z; v[4 * q + 3] = f.w;
+        }
+    } else if constexpr (DT != 0 && K % 8 == 0) {
+        const uint4 *p = reinterpret_cast<const uint4 *>(static_cast<const uint16_t *>(ind) + t * K);
+#pragma unroll
+        for (int q = 0; q < K / 8; ++q) {
+            const uint4 u = p[q];
+            const uint32_t w[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const uint16_t h = (uint16_t)(w[e / 2] >> (16 * (e % 2)));
+                double val;
+                if constexpr (DT == 1) val = (double)__builtin_bit_cast(_Float16, h);
+                else if constexpr (DT == 2) val = (double)__uint_as_float((uint32_t)h << 16);
+                else val = (double)h / 65535.0;
+                v[8 * q + e] = val;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < K; ++k) v[k] = load_value<DT>(ind, t * K + k);
+    }
+    const float4 c = reinterpret_cast<const float4 *>(rgb)[t];
+    v[K] = c.x; v[K + 1] = c.y; v[K + 2] = c.z;
+}
+
+// Adds w * texel (x, y) of `face` on pyramid level `base` (seam rule: the
+// texel beyond a cube corner is the mean of the three corner texels).
+template <int K, int DT>
+__device__ __forceinline__ void accumulate_pyr(const void *__restrict__ ind, const float *__restrict__ rgb,
+                                               int64_t base, int face, int x, int y, int n, double w,
+                                               double (&acc)[K + 3])
+{
+    constexpr int C = K + 3;
+    int64_t idx[3];
+    const int cnt = resolve_texel(face, x, y, n, idx);
+    double v[C];
+    load_texel<K, DT>(ind, rgb, base + idx[0], v);
+    if (cnt == 3) {
+        double b[C], c[C];
+        load_texel<K, DT>(ind, rgb, base + idx[1], b);
+        load_texel<K, DT>(ind, rgb, base + idx[2], c);
+#pragma unroll
+        for (int k = 0; k < C; ++k) v[k] = ((v[k] + b[k]) + c[k]) / 3.0;
+    }
+#pragma unroll
+    for (int k = 0; k < C; ++k) acc[k] += w * v[k];
+}
+
 __device__ __forceinline__ double lut_bilinear(const float *__restrict__ lut, int stride, int comp, double mu,
                                                double sa)
 {
@@ -162,28 +221,25 @@ __global__ void __launch_bounds__(kShadeThreads) k_shade(ShadeArgs A)
     const int s0 = (int)l0f;
     const int s1 = s0 + 1 < A.M ? s0 + 1 : A.M - 1;
     const double fr = lod - l0f;
-    double F[K], rgb[3];
+    double acc[K + 3];
 #pragma unroll
-    for (int k = 0; k < K; ++k) F[k] = 0.0;
-    rgb[0] = rgb[1] = rgb[2] = 0.0;
+    for (int k = 0; k < K + 3; ++k) acc[k] = 0.0;
+    const face_st fs = locate(wr);
 #pragma unroll
     for (int li = 0; li < 2; ++li) {
         const int s = li == 0 ? s0 : s1;
         const double lw = li == 0 ? 1.0 - fr : fr;
-        const bilin4 bl = bilinear_taps(wr, A.R >> s);
+        if (li == 1 && !(fr > 0.0)) break;
+        const int ns = A.R >> s;
+        const bilin bl = bilinear_at(fs, ns);
         const int64_t base = level_offset(A.R, s);
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const int64_t t = base + bl.idx[c];
-            const double w = lw * bl.w[c];
-#pragma unroll
-            for (int k = 0; k < K; ++k) F[k] += w * load_value<DT>(A.ind_pyr, t * K + k);
-            const float4 q = reinterpret_cast<const float4 *>(A.rgb_pyr)[t];
-            rgb[0] += w * (double)q.x;
-            rgb[1] += w * (double)q.y;
-            rgb[2] += w * (double)q.z;
-        }
+        accumulate_pyr<K, DT>(A.ind_pyr, A.rgb_pyr, base, fs.face, bl.x0, bl.y0, ns, lw * ((1.0 - bl.fy) * (1.0 - bl.fx)), acc);
+        accumulate_pyr<K, DT>(A.ind_pyr, A.rgb_pyr, base, fs.face, bl.x0 + 1, bl.y0, ns, lw * ((1.0 - bl.fy) * bl.fx), acc);
+        accumulate_pyr<K, DT>(A.ind_pyr, A.rgb_pyr, base, fs.face, bl.x0, bl.y0 + 1, ns, lw * (bl.fy * (1.0 - bl.fx)), acc);
+        accumulate_pyr<K, DT>(A.ind_pyr, A.rgb_pyr, base, fs.face, bl.x0 + 1, bl.y0 + 1, ns, lw * (bl.fy * bl.fx), acc);
     }
+    const double *F = acc;
+    const double rgb[3] = {acc[K], acc[K + 1], acc[K + 2]};
 
     // Sec. 4 Eq. (probhk) with Sec. 5 Eq. (rtiblndf)
     double sumF = 0.0;

@@ -237,3 +237,51 @@ def test_lut_limits():
     assert np.allclose(B[0, 16:], fc[16:], atol=2e-3)
     # roughness reduces the visible reflecting area
     assert np.all(np.diff(S[:, 40]) <= 1e-9)
+
+
+@pytest.mark.parametrize("R,M", [(4, 3), (16, 5)])
+def test_lookup_continuous_across_edges_and_corners(R, M):
+    """A seamless cube lookup is a continuous function of direction: on face
+    edges (|x| = |y| etc.) and at cube corners a tiny perturbation of the
+    direction may change the owning face but not the value."""
+    rng = np.random.default_rng(5)
+    n_tex = oracle.pyramid_texels(R, M)
+    pyr = rng.random((n_tex, 3)).astype(np.float32)
+    dirs = []
+    for _ in range(300):
+        a, b = rng.uniform(0.2, 1.0, 2)
+        sx, sy, sz = rng.choice([-1.0, 1.0], 3)
+        kind = rng.integers(4)
+        if kind == 0:
+            d = np.array([sx * a, sy * a, sz * b * a])      # |x| = |y|
+        elif kind == 1:
+            d = np.array([sx * a, sy * b * a, sz * a])      # |x| = |z|
+        elif kind == 2:
+            d = np.array([sx * b * a, sy * a, sz * a])      # |y| = |z|
+        else:
+            d = np.array([sx, sy, sz]) * a                 # cube corner
+        dirs.append(d)
+    dirs = np.array(dirs)
+    for lod in (0.0, 0.5, float(M - 1)):
+        base = oracle.pyramid_lookup(pyr, R, M, dirs, lod)
+        for eps in (1e-12, -1e-12):
+            for axis in range(3):
+                p = dirs.copy()
+                p[:, axis] *= 1 + eps
+                got = oracle.pyramid_lookup(pyr, R, M, p, lod)
+                assert np.abs(got - base).max() < 1e-9
+
+
+def test_lookup_interpolates_texel_centres():
+    """At a texel centre of level s the lookup returns that texel exactly."""
+    R, M = 8, 4
+    rng = np.random.default_rng(6)
+    pyr = rng.random((oracle.pyramid_texels(R, M), 2)).astype(np.float32)
+    for s in range(M):
+        n = R >> s
+        for f in range(6):
+            for (x, y) in ((0, 0), (n - 1, 0), (n // 2, n - 1)):
+                d = oracle.face_dir(f, 2 * (x + 0.5) / n - 1, 2 * (y + 0.5) / n - 1)
+                got = oracle.pyramid_lookup(pyr, R, M, d[None], float(s))[0]
+                want = pyr[oracle.level_offset(R, s) + (f * n + y) * n + x]
+                assert np.allclose(got, want, atol=1e-7)
