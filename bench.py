@@ -51,7 +51,22 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=float, default=1.0 / 48.0,
                     help="fraction of pyramid texels and glint pixels the oracle times")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (calibrates HBM byte counters)")
     return ap.parse_args()
+
+
+def copy_probe(mib: int) -> None:
+    """A plain device-to-device copy of known size, to scale the FETCH_SIZE /
+    WRITE_SIZE counters of the same profiler pass."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_mib": mib, "launches": 3}), flush=True)
 
 
 def cpu_baseline(w, env, gbuf, glint_pixels, frac, shade_inputs):
@@ -86,6 +101,9 @@ def cpu_baseline(w, env, gbuf, glint_pixels, frac, shade_inputs):
 
 def main():
     a = parse()
+    if a.copy_probe:
+        copy_probe(a.copy_probe)
+        return
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it",
                           "n_gpus": a.gpus}))

@@ -31,20 +31,33 @@ __device__ __forceinline__ d3 face_dir(int face, double s, double t)
 }
 
 // Owning face of d (largest |component|, ties to x then y) and its face
-// coordinates.  Divisions are IEEE (correctly rounded) double divisions.
+// coordinates.  The major axis is chosen first so only two (IEEE, correctly
+// rounded) double divisions are emitted; negation is exact, so the
+// quotients equal the per-face formulas.
 __device__ __forceinline__ int dir_face(const d3 &d, double &s, double &t)
 {
     const double ax = fabs(d.x), ay = fabs(d.y), az = fabs(d.z);
+    int face;
+    double ma, sc, tc;
     if (ax >= ay && ax >= az) {
-        if (d.x >= 0.0) { s = -d.z / ax; t = -d.y / ax; return 0; }
-        s = d.z / ax; t = -d.y / ax; return 1;
+        face = d.x >= 0.0 ? 0 : 1;
+        ma = ax;
+        sc = d.x >= 0.0 ? -d.z : d.z;
+        tc = -d.y;
+    } else if (ay >= az) {
+        face = d.y >= 0.0 ? 2 : 3;
+        ma = ay;
+        sc = d.x;
+        tc = d.y >= 0.0 ? d.z : -d.z;
+    } else {
+        face = d.z >= 0.0 ? 4 : 5;
+        ma = az;
+        sc = d.z >= 0.0 ? d.x : -d.x;
+        tc = -d.y;
     }
-    if (ay >= az) {
-        if (d.y >= 0.0) { s = d.x / ay; t = d.z / ay; return 2; }
-        s = d.x / ay; t = -d.z / ay; return 3;
-    }
-    if (d.z >= 0.0) { s = d.x / az; t = -d.y / az; return 4; }
-    s = -d.x / az; t = -d.y / az; return 5;
+    s = sc / ma;
+    t = tc / ma;
+    return face;
 }
 
 __host__ __device__ __forceinline__ int64_t level_offset(int R, int level)
@@ -65,7 +78,7 @@ __host__ __device__ __forceinline__ int64_t level_offset(int R, int level)
 // lookup continuous across edges and corners.
 __device__ __forceinline__ int64_t reproject_one(int face, int x, int y, int n)
 {
-    const double inv = 1.0 / (double)n;
+    const double inv = ldexp(1.0, -__builtin_ctz((unsigned)n)); // 1/n, exact for n a power of two
     const d3 d = face_dir(face, 2.0 * ((double)x + 0.5) * inv - 1.0, 2.0 * ((double)y + 0.5) * inv - 1.0);
     double s, t;
     const int f2 = dir_face(d, s, t);

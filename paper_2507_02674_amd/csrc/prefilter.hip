@@ -6,9 +6,13 @@
 // the packed indicator plus RGB from the map); levels >= 1 are stored float,
 // [texel][CP] with CP = K+3 rounded up to 4 (16-byte texel records).
 //
-//   k_chain_level   one launch per chain level: 2x2 mean of the level above,
-//                   summed in double in a fixed order, stored float;
-//   k_pyr_level0    mip 0 of the output pyramid (alpha = 0): the dense level;
+//   k_chain_tiles   per 32x32 tile of level 0: mip 0 of the output pyramid
+//                   (alpha = 0, the dense level) and chain levels 1..5 via
+//                   LDS, each level the float-rounded 2x2 mean (double sums
+//                   in a fixed order) of the one above;
+//   k_chain_faces   the coarser levels of each face through LDS;
+//   k_chain_level   one level per launch (only for faces larger than 32
+//                   texels that the tiles did not reach, R >= 2048);
 //   k_prefilter     mips >= 1: a group of G = 8 lanes per output texel splits
 //                   the T taps, accumulates in double, reduces across the
 //                   group with cross-lane shuffles; the tap table of the
@@ -84,6 +88,22 @@ struct Level0 {
             v[K + c] = (__builtin_isfinite(x) && x > 0.0f) ? (double)x : 0.0;
         }
     }
+
+    // acc += w * (dense texel i), without materialising the dense texel
+    __device__ __forceinline__ void add(int64_t i, double w, double (&acc)[K + 3]) const
+    {
+        const int j = ind_j[i];
+        const double t = (double)ind_t[i];
+        const double wt = w * t, wo = w * (1.0 - t);
+#pragma unroll
+        for (int k = 0; k < K; ++k) acc[k] += k == j ? wo : (k == j + 1 ? wt : 0.0);
+        const float *e = env + 3 * i;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const float x = e[c];
+            acc[K + c] += w * ((__builtin_isfinite(x) && x > 0.0f) ? (double)x : 0.0);
+        }
+    }
 };
 
 template <int K>
@@ -101,34 +121,39 @@ __device__ __forceinline__ void load_chain(const float *__restrict__ lvl, int64_
     for (int k = 0; k < K + 3; ++k) v[k] = (double)buf[k];
 }
 
-// Adds w * (value of texel (x, y) of `face` on chain level s) to acc, with
-// the seam rule (mean of three texels beyond a cube corner).
+// acc += w * texel i of chain level s (level 0 expanded on the fly).
 template <int K>
-__device__ __forceinline__ void fetch_texel(const Level0<K> &l0, const float *__restrict__ lvl, int s, int64_t i,
-                                            double (&v)[K + 3])
+__device__ __forceinline__ void add_texel(const Level0<K> &l0, const float *__restrict__ lvl, int s, int64_t i,
+                                          double w, double (&acc)[K + 3])
 {
-    if (s == 0) l0.load(i, v);
-    else load_chain<K>(lvl, i, v);
+    constexpr int CP = chain_stride(K);
+    if (s == 0) {
+        l0.add(i, w, acc);
+    } else {
+        const float4 *q = reinterpret_cast<const float4 *>(lvl + i * CP);
+#pragma unroll
+        for (int q4 = 0; q4 < CP / 4; ++q4) {
+            const float4 f = q[q4];
+            const float fv[4] = {f.x, f.y, f.z, f.w};
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                if (4 * q4 + e < K + 3) acc[4 * q4 + e] += w * (double)fv[e];
+        }
+    }
 }
 
+// acc += w * (texel (x, y) of `face` on level s) with the seam rule: beyond a
+// cube corner the texel is the mean of the three texels meeting there,
+// added as three terms of weight w/3.
 template <int K>
 __device__ __forceinline__ void accumulate_texel(const Level0<K> &l0, const float *__restrict__ lvl, int s, int face,
                                                  int x, int y, int n, double w, double (&acc)[K + 3])
 {
-    constexpr int C = K + 3;
     int64_t idx[3];
     const int cnt = resolve_texel(face, x, y, n, idx);
-    double v[C];
-    fetch_texel<K>(l0, lvl, s, idx[0], v);
-    if (cnt == 3) {
-        double b[C], c[C];
-        fetch_texel<K>(l0, lvl, s, idx[1], b);
-        fetch_texel<K>(l0, lvl, s, idx[2], c);
-#pragma unroll
-        for (int k = 0; k < C; ++k) v[k] = ((v[k] + b[k]) + c[k]) / 3.0;
-    }
-#pragma unroll
-    for (int k = 0; k < C; ++k) acc[k] += w * v[k];
+    const double wc = cnt == 3 ? w / 3.0 : w;
+#pragma unroll 1
+    for (int e = 0; e < cnt; ++e) add_texel<K>(l0, lvl, s, e == 0 ? idx[0] : (e == 1 ? idx[1] : idx[2]), wc, acc);
 }
 
 // ---------------------------------------------------------------------------
@@ -167,19 +192,134 @@ __global__ void __launch_bounds__(kChainThreads) k_chain_level(Level0<K> l0, con
 }
 
 // ---------------------------------------------------------------------------
-// pyramid mip 0
+// fused chain: a block owns a T x T tile of level 0 (T = min(32, R)); it
+// writes mip 0 of the output pyramid for the tile and builds chain levels
+// 1..log2(T) through LDS (each level rounded to float before the next, sums
+// in double in a fixed order).  A second launch builds the coarser levels of
+// each face the same way from the last tile level.
 // ---------------------------------------------------------------------------
-template <int K, int DT>
-__global__ void __launch_bounds__(kChainThreads) k_pyr_level0(Level0<K> l0, int64_t n, void *__restrict__ ind_pyr,
-                                                               float *__restrict__ rgb_pyr)
+constexpr int kTile = 32;
+
+template <int K>
+__device__ __forceinline__ void mean4_store(const double (&a)[K + 3], const double (&b)[K + 3],
+                                            const double (&c)[K + 3], const double (&d)[K + 3], float *lds_out,
+                                            float *__restrict__ gl_out)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    double v[K + 3];
-    l0.load(i, v);
+    constexpr int C = K + 3, CP = chain_stride(K);
+    float out[CP];
+    {
+#pragma clang fp contract(off)
 #pragma unroll
-    for (int k = 0; k < K; ++k) store_value<DT>(ind_pyr, i * K + k, v[k]);
-    reinterpret_cast<float4 *>(rgb_pyr)[i] = make_float4((float)v[K], (float)v[K + 1], (float)v[K + 2], 0.0f);
+        for (int k = 0; k < C; ++k) out[k] = (float)(((a[k] + b[k]) + (c[k] + d[k])) * 0.25);
+    }
+#pragma unroll
+    for (int k = C; k < CP; ++k) out[k] = 0.0f;
+#pragma unroll
+    for (int k = 0; k < CP; ++k) lds_out[k] = out[k];
+    float4 *q = reinterpret_cast<float4 *>(gl_out);
+#pragma unroll
+    for (int i = 0; i < CP / 4; ++i) q[i] = make_float4(out[4 * i], out[4 * i + 1], out[4 * i + 2], out[4 * i + 3]);
+}
+
+template <int K>
+__device__ __forceinline__ void lds_texel(const float *p, double (&v)[K + 3])
+{
+#pragma unroll
+    for (int k = 0; k < K + 3; ++k) v[k] = (double)p[k];
+}
+
+// Reduces a square LDS level of side `side` (records of CP floats) into the
+// next level (side/2), storing it to LDS `dst` and to the chain level whose
+// face-local origin is (ox, oy) with face size n.
+template <int K>
+__device__ __forceinline__ void reduce_lds_level(const float *src, float *dst, int side, int face, int ox, int oy,
+                                                 int n, float *__restrict__ level_base)
+{
+    constexpr int CP = chain_stride(K);
+    const int half = side / 2;
+    for (int o = threadIdx.x; o < half * half; o += blockDim.x) {
+        const int x = o % half, y = o / half;
+        double a[K + 3], b[K + 3], c[K + 3], d[K + 3];
+        lds_texel<K>(src + ((2 * y) * side + 2 * x) * CP, a);
+        lds_texel<K>(src + ((2 * y) * side + 2 * x + 1) * CP, b);
+        lds_texel<K>(src + ((2 * y + 1) * side + 2 * x) * CP, c);
+        lds_texel<K>(src + ((2 * y + 1) * side + 2 * x + 1) * CP, d);
+        const int64_t gi = ((int64_t)face * n + oy + y) * n + ox + x;
+        mean4_store<K>(a, b, c, d, dst + o * CP, level_base + gi * CP);
+    }
+}
+
+template <int K, int DT>
+__global__ void __launch_bounds__(256) k_chain_tiles(Level0<K> l0, int R, int M, float *__restrict__ chain,
+                                                     void *__restrict__ ind_pyr, float *__restrict__ rgb_pyr)
+{
+    constexpr int CP = chain_stride(K);
+    __shared__ float s_a[(kTile / 2) * (kTile / 2) * CP];
+    __shared__ float s_b[(kTile / 4) * (kTile / 4) * CP];
+    const int T = R < kTile ? R : kTile;
+    const int tiles = R / T;
+    const int face = blockIdx.x / (tiles * tiles);
+    const int tx = blockIdx.x % tiles, ty = (blockIdx.x / tiles) % tiles;
+    // mip 0 of the pyramid: the dense level, T*T texels of this tile
+    for (int o = threadIdx.x; o < T * T; o += blockDim.x) {
+        const int x = tx * T + o % T, y = ty * T + o / T;
+        const int64_t i = ((int64_t)face * R + y) * R + x;
+        double v[K + 3];
+        l0.load(i, v);
+#pragma unroll
+        for (int k = 0; k < K; ++k) store_value<DT>(ind_pyr, i * K + k, v[k]);
+        reinterpret_cast<float4 *>(rgb_pyr)[i] = make_float4((float)v[K], (float)v[K + 1], (float)v[K + 2], 0.0f);
+    }
+    if (M < 2 || T < 2) return;
+    // level 1 from level 0
+    {
+        const int half = T / 2, n1 = R / 2;
+        float *base1 = chain; // level 1 starts the chain
+        for (int o = threadIdx.x; o < half * half; o += blockDim.x) {
+            const int x = o % half, y = o / half;
+            const int gx = tx * T + 2 * x, gy = ty * T + 2 * y;
+            const int64_t c00 = ((int64_t)face * R + gy) * R + gx;
+            double a[K + 3], b[K + 3], c[K + 3], d[K + 3];
+            l0.load(c00, a); l0.load(c00 + 1, b); l0.load(c00 + R, c); l0.load(c00 + R + 1, d);
+            const int64_t gi = ((int64_t)face * n1 + ty * half + y) * n1 + tx * half + x;
+            mean4_store<K>(a, b, c, d, s_a + o * CP, base1 + gi * CP);
+        }
+    }
+    __syncthreads();
+    // levels 2.. within the tile, ping-ponging between the two LDS buffers
+    int side = T / 2;
+    float *src = s_a, *dst = s_b;
+    for (int s = 2; s < M && side >= 2; ++s) {
+        const int n = R >> s, half = side / 2;
+        float *lvl = chain + (level_offset(R, s) - 6LL * R * R) * CP;
+        reduce_lds_level<K>(src, dst, side, face, tx * half, ty * half, n, lvl);
+        __syncthreads();
+        float *t = src; src = dst; dst = t;
+        side = half;
+    }
+}
+
+// Coarse levels: one block per face, from the last level the tiles built.
+template <int K>
+__global__ void __launch_bounds__(256) k_chain_faces(int R, int M, int first, float *__restrict__ chain)
+{
+    constexpr int CP = chain_stride(K);
+    extern __shared__ float s_dyn[];
+    const int face = blockIdx.x;
+    const int n0 = R >> (first - 1); // face size of the level the tiles finished
+    float *src = s_dyn, *dst = s_dyn + n0 * n0 * CP;
+    const float *lvl0 = chain + (level_offset(R, first - 1) - 6LL * R * R) * CP;
+    for (int o = threadIdx.x; o < n0 * n0 * CP; o += blockDim.x) src[o] = lvl0[(int64_t)face * n0 * n0 * CP + o];
+    __syncthreads();
+    int side = n0;
+    for (int s = first; s < M; ++s) {
+        const int half = side / 2;
+        float *lvl = chain + (level_offset(R, s) - 6LL * R * R) * CP;
+        reduce_lds_level<K>(src, dst, side, face, 0, 0, half, lvl);
+        __syncthreads();
+        float *t = src; src = dst; dst = t;
+        side = half;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -277,6 +417,7 @@ __global__ void __launch_bounds__(kFilterThreads) k_prefilter(FilterLaunch fl, L
         const d3 t1 = {1.0 + sgn * r.x * r.x * ea, sgn * eb, -sgn * r.x};
         const d3 t2 = {eb, sgn + r.y * r.y * ea, -r.y};
 
+#pragma unroll 1
         for (int j = sub; j < fl.T; j += kGroup) {
             const Tap tp = s_taps[j];
             if (!(tp.w > 0.0)) continue;
@@ -287,17 +428,44 @@ __global__ void __launch_bounds__(kFilterThreads) k_prefilter(FilterLaunch fl, L
             const double l0f = floor(tp.lod);
             const int s0 = (int)l0f;
             const double fr = tp.lod - l0f;
-            const int nlev = fr > 0.0 ? 2 : 1;
+            const int nlev = fr > 0.0 ? 2 : 1; // fr > 0 implies s0 + 1 <= M - 1
+#pragma unroll 1
             for (int li = 0; li < nlev; ++li) {
-                const int s = s0 + li; // fr > 0 implies s0 + 1 <= M - 1
-                const double lw = tp.w * (li == 0 ? 1.0 - fr : fr);
+                const int s = s0 + li;
                 const int ns = fl.R >> s;
                 const bilin bl = bilinear_at(fs, ns);
+                const double lw = tp.w * (li ? fr : 1.0 - fr);
+                const double w4[4] = {lw * ((1.0 - bl.fy) * (1.0 - bl.fx)), lw * ((1.0 - bl.fy) * bl.fx),
+                                      lw * (bl.fy * (1.0 - bl.fx)), lw * (bl.fy * bl.fx)};
                 const float *lvl = s_lvl[s];
-                accumulate_texel<K>(l0, lvl, s, fs.face, bl.x0, bl.y0, ns, lw * ((1.0 - bl.fy) * (1.0 - bl.fx)), acc);
-                accumulate_texel<K>(l0, lvl, s, fs.face, bl.x0 + 1, bl.y0, ns, lw * ((1.0 - bl.fy) * bl.fx), acc);
-                accumulate_texel<K>(l0, lvl, s, fs.face, bl.x0, bl.y0 + 1, ns, lw * (bl.fy * (1.0 - bl.fx)), acc);
-                accumulate_texel<K>(l0, lvl, s, fs.face, bl.x0 + 1, bl.y0 + 1, ns, lw * (bl.fy * bl.fx), acc);
+                if (bl.x0 >= 0 && bl.x0 + 1 < ns && bl.y0 >= 0 && bl.y0 + 1 < ns) {
+                    // footprint inside the face: four loads in flight
+                    const int64_t t0 = ((int64_t)fs.face * ns + bl.y0) * ns + bl.x0;
+                    const int64_t tt[4] = {t0, t0 + 1, t0 + ns, t0 + ns + 1};
+                    if (s == 0) {
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) l0.add(tt[c], w4[c], acc);
+                    } else {
+                        float4 raw[4][CP / 4];
+#pragma unroll
+                        for (int c = 0; c < 4; ++c)
+#pragma unroll
+                            for (int q4 = 0; q4 < CP / 4; ++q4)
+                                raw[c][q4] = reinterpret_cast<const float4 *>(lvl + tt[c] * CP)[q4];
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) {
+                            const float *f = reinterpret_cast<const float *>(raw[c]);
+#pragma unroll
+                            for (int k = 0; k < C; ++k) acc[k] += w4[c] * (double)f[k];
+                        }
+                    }
+                } else {
+                    // across a seam: one copy of the seam rule
+#pragma unroll 1
+                    for (int c = 0; c < 4; ++c)
+                        accumulate_texel<K>(l0, lvl, s, fs.face, bl.x0 + (c & 1), bl.y0 + (c >> 1), ns,
+                                            c == 0 ? w4[0] : (c == 1 ? w4[1] : (c == 2 ? w4[2] : w4[3])), acc);
+                }
             }
         }
     }
@@ -327,18 +495,31 @@ static hipError_t launch_prefilter_t(const float *env, const uint8_t *ind_j, con
                                      int T, float *chain, void *ind_pyr, float *rgb_pyr, hipStream_t stream)
 {
     Level0<K> l0{env, ind_j, ind_t};
-    // chain levels 1..M-1
-    for (int s = 1; s < M; ++s) {
+    // mip 0 of the pyramid and chain levels 1..log2(T) per tile, then the
+    // coarser chain levels per face
+    const int tile = R < kTile ? R : kTile;
+    const int tiles = R / tile;
+    hipLaunchKernelGGL((k_chain_tiles<K, DT>), dim3(6 * tiles * tiles), dim3(256), 0, stream, l0, R, M, chain,
+                       ind_pyr, rgb_pyr);
+    int tile_levels = 0;
+    while ((1 << (tile_levels + 1)) <= tile) ++tile_levels; // log2(tile)
+    // levels the tiles did not build: per-level launches while the parent
+    // face is larger than a tile, then one per-face launch through LDS
+    for (int s = tile_levels + 1; s < M; ++s) {
+        const int parent = R >> (s - 1);
+        if (parent <= 16) { // (16^2 + 8^2) records of <= 20 floats: < 64 KB of LDS
+            const size_t shm =
+                sizeof(float) * (size_t)chain_stride(K) * (size_t)(parent * parent + (parent / 2) * (parent / 2));
+            hipLaunchKernelGGL(k_chain_faces<K>, dim3(6), dim3(256), shm, stream, R, M, s, chain);
+            break;
+        }
         const int n = R >> s;
         const int64_t total = 6LL * n * n;
-        const float *src = s == 1 ? nullptr : chain + (level_offset(R, s - 1) - 6LL * R * R) * chain_stride(K);
+        const float *src = chain + (level_offset(R, s - 1) - 6LL * R * R) * chain_stride(K);
         float *dst = chain + (level_offset(R, s) - 6LL * R * R) * chain_stride(K);
         hipLaunchKernelGGL(k_chain_level<K>, dim3((unsigned)((total + kChainThreads - 1) / kChainThreads)),
                            dim3(kChainThreads), 0, stream, l0, src, dst, n);
     }
-    const int64_t n0 = 6LL * R * R;
-    hipLaunchKernelGGL((k_pyr_level0<K, DT>), dim3((unsigned)((n0 + kChainThreads - 1) / kChainThreads)),
-                       dim3(kChainThreads), 0, stream, l0, n0, ind_pyr, rgb_pyr);
     if (M > 1) {
         FilterLaunch fl{};
         fl.R = R; fl.M = M; fl.T = T; fl.nmips = M - 1;

@@ -73,27 +73,24 @@ __device__ __forceinline__ void load_texel(const void *__restrict__ ind, const f
     v[K] = c.x; v[K + 1] = c.y; v[K + 2] = c.z;
 }
 
-// Adds w * texel (x, y) of `face` on pyramid level `base` (seam rule: the
-// texel beyond a cube corner is the mean of the three corner texels).
+// acc += w * (texel (x, y) of `face` on the pyramid level at `base`) with the
+// seam rule: beyond a cube corner the texel is the mean of the three texels
+// meeting there, added as three terms of weight w/3.
 template <int K, int DT>
 __device__ __forceinline__ void accumulate_pyr(const void *__restrict__ ind, const float *__restrict__ rgb,
                                                int64_t base, int face, int x, int y, int n, double w,
                                                double (&acc)[K + 3])
 {
-    constexpr int C = K + 3;
     int64_t idx[3];
     const int cnt = resolve_texel(face, x, y, n, idx);
-    double v[C];
-    load_texel<K, DT>(ind, rgb, base + idx[0], v);
-    if (cnt == 3) {
-        double b[C], c[C];
-        load_texel<K, DT>(ind, rgb, base + idx[1], b);
-        load_texel<K, DT>(ind, rgb, base + idx[2], c);
+    const double wc = cnt == 3 ? w / 3.0 : w;
+#pragma unroll 1
+    for (int e = 0; e < cnt; ++e) {
+        double v[K + 3];
+        load_texel<K, DT>(ind, rgb, base + (e == 0 ? idx[0] : (e == 1 ? idx[1] : idx[2])), v);
 #pragma unroll
-        for (int k = 0; k < C; ++k) v[k] = ((v[k] + b[k]) + c[k]) / 3.0;
+        for (int k = 0; k < K + 3; ++k) acc[k] += wc * v[k];
     }
-#pragma unroll
-    for (int k = 0; k < C; ++k) acc[k] += w * v[k];
 }
 
 __device__ __forceinline__ double lut_bilinear(const float *__restrict__ lut, int stride, int comp, double mu,
@@ -157,19 +154,30 @@ __device__ __forceinline__ void dual_gated(double N, double p, float xi1, float 
            ((uint32_t)BG << 4);
 }
 
-// Hierarchical multinomial over K bins (balanced binary tree, breadth-first
-// node numbering; left child gets n, right child gets nbar).
+// Hierarchical multinomial over K bins: balanced binary tree, nodes in
+// breadth-first (heap) order; node i covers a contiguous run of bins, its
+// probability is S_left / S_node, its left child 2i+1 receives the positive
+// count n and its right child 2i+2 the negative count nbar.
+//
+// Code shape: the depth loop is unrolled (log2 K copies of the sampler); the
+// nodes of one depth run in a loop that is not unrolled.  The loop consumes
+// its inputs from the front of small register queues and appends the two
+// child counts at the back, shifting with static indices, so no register
+// array is indexed dynamically.
 template <int K>
 __device__ __forceinline__ void multinomial(double NP, const double (&p)[K], uint32_t seed_mix, int lev, int64_t a,
-                                            int64_t b, double (&cnt)[K], uint8_t *codes)
+                                            int64_t b, double (&leaf)[K], uint8_t *codes)
 {
-    cnt[0] = NP;
+    double Q[K]; // counts of the current depth, in node order
+    Q[0] = NP;
 #pragma unroll
-    for (int k = 1; k < K; ++k) cnt[k] = 0.0;
+    for (int k = 1; k < K; ++k) Q[k] = 0.0;
 #pragma unroll
-    for (int d = 0, width = K; width > 1; ++d, width >>= 1) {
+    for (int d = 0; (1 << d) < K; ++d) {
+        const int nd = 1 << d, width = K >> d;
+        double P[K / 2]; // node probabilities of this depth, in node order
 #pragma unroll
-        for (int j = (1 << d) - 1; j >= 0; --j) {
+        for (int j = 0; j < nd; ++j) {
             const int lo = j * width, mid = lo + width / 2, hi = lo + width;
             double sl = 0.0, sr = 0.0;
 #pragma unroll
@@ -177,19 +185,33 @@ __device__ __forceinline__ void multinomial(double NP, const double (&p)[K], uin
 #pragma unroll
             for (int k = mid; k < hi; ++k) sr += p[k];
             const double st = sl + sr;
-            double pn = st > 0.0 ? sl / st : 0.0;
-            pn = pn > 1.0 ? 1.0 : pn;
-            const int node = (1 << d) - 1 + j;
-            const u4 h = pcg4d({(uint32_t)a, (uint32_t)b, (((uint32_t)lev & 0xFFFFu) << 16) | (uint32_t)node,
-                                seed_mix});
+            const double q = st > 0.0 ? sl / st : 0.0;
+            P[j] = q > 1.0 ? 1.0 : q;
+        }
+        double Rq[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) Rq[k] = 0.0;
+#pragma unroll 1
+        for (int j = 0; j < nd; ++j) {
+            const double N = Q[0], pj = P[0];
+#pragma unroll
+            for (int k = 0; k + 1 < nd; ++k) { Q[k] = Q[k + 1]; P[k] = P[k + 1]; }
+            const int node = nd - 1 + j;
+            const u4 h = pcg4d({(uint32_t)a, (uint32_t)b, (((uint32_t)lev & 0xFFFFu) << 16) | (uint32_t)node, seed_mix});
             double n, nb;
             uint32_t code;
-            dual_gated(cnt[j], pn, hash_unit(h.x), hash_unit(h.y), n, nb, code);
+            dual_gated(N, pj, hash_unit(h.x), hash_unit(h.y), n, nb, code);
             if (codes) codes[node] = (uint8_t)code;
-            cnt[2 * j] = n;
-            cnt[2 * j + 1] = nb;
+#pragma unroll
+            for (int k = 0; k + 2 < 2 * nd; ++k) Rq[k] = Rq[k + 2];
+            Rq[2 * nd - 2] = n;
+            Rq[2 * nd - 1] = nb;
         }
+#pragma unroll
+        for (int k = 0; k < 2 * nd; ++k) Q[k] = Rq[k];
     }
+#pragma unroll
+    for (int k = 0; k < K; ++k) leaf[k] = Q[k];
 }
 
 template <int K, int DT, int V>
@@ -225,18 +247,34 @@ __global__ void __launch_bounds__(kShadeThreads) k_shade(ShadeArgs A)
 #pragma unroll
     for (int k = 0; k < K + 3; ++k) acc[k] = 0.0;
     const face_st fs = locate(wr);
-#pragma unroll
-    for (int li = 0; li < 2; ++li) {
+    const int nlev = fr > 0.0 ? 2 : 1;
+#pragma unroll 1
+    for (int li = 0; li < nlev; ++li) {
         const int s = li == 0 ? s0 : s1;
         const double lw = li == 0 ? 1.0 - fr : fr;
-        if (li == 1 && !(fr > 0.0)) break;
         const int ns = A.R >> s;
         const bilin bl = bilinear_at(fs, ns);
         const int64_t base = level_offset(A.R, s);
-        accumulate_pyr<K, DT>(A.ind_pyr, A.rgb_pyr, base, fs.face, bl.x0, bl.y0, ns, lw * ((1.0 - bl.fy) * (1.0 - bl.fx)), acc);
-        accumulate_pyr<K, DT>(A.ind_pyr, A.rgb_pyr, base, fs.face, bl.x0 + 1, bl.y0, ns, lw * ((1.0 - bl.fy) * bl.fx), acc);
-        accumulate_pyr<K, DT>(A.ind_pyr, A.rgb_pyr, base, fs.face, bl.x0, bl.y0 + 1, ns, lw * (bl.fy * (1.0 - bl.fx)), acc);
-        accumulate_pyr<K, DT>(A.ind_pyr, A.rgb_pyr, base, fs.face, bl.x0 + 1, bl.y0 + 1, ns, lw * (bl.fy * bl.fx), acc);
+        const double w4[4] = {lw * ((1.0 - bl.fy) * (1.0 - bl.fx)), lw * ((1.0 - bl.fy) * bl.fx),
+                              lw * (bl.fy * (1.0 - bl.fx)), lw * (bl.fy * bl.fx)};
+        if (bl.x0 >= 0 && bl.x0 + 1 < ns && bl.y0 >= 0 && bl.y0 + 1 < ns) {
+            // footprint inside the face: four loads in flight
+            const int64_t t0 = base + ((int64_t)fs.face * ns + bl.y0) * ns + bl.x0;
+            const int64_t tt[4] = {t0, t0 + 1, t0 + ns, t0 + ns + 1};
+            double v[4][K + 3];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) load_texel<K, DT>(A.ind_pyr, A.rgb_pyr, tt[c], v[c]);
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+#pragma unroll
+                for (int k = 0; k < K + 3; ++k) acc[k] += w4[c] * v[c][k];
+        } else {
+            // across a seam: one copy of the seam rule
+#pragma unroll 1
+            for (int c = 0; c < 4; ++c)
+                accumulate_pyr<K, DT>(A.ind_pyr, A.rgb_pyr, base, fs.face, bl.x0 + (c & 1), bl.y0 + (c >> 1), ns,
+                                      c == 0 ? w4[0] : (c == 1 ? w4[1] : (c == 2 ? w4[2] : w4[3])), acc);
+        }
     }
     const double *F = acc;
     const double rgb[3] = {acc[K], acc[K + 1], acc[K + 2]};
@@ -250,9 +288,10 @@ __global__ void __launch_bounds__(kShadeThreads) k_shade(ShadeArgs A)
     const double EB = lut_bilinear(A.lut_E, 2, 1, mu, sa);
     double p[K];
     double rest = 0.0;
+    const double scale = sumF > 0.0 ? S / sumF : 0.0;
 #pragma unroll
     for (int k = 1; k < K; ++k) {
-        p[k] = sumF > 0.0 ? S * F[k] / sumF : 0.0;
+        p[k] = scale * F[k];
         rest += p[k];
     }
     p[0] = 1.0 - rest;
