@@ -121,9 +121,12 @@ int glint_partition_env(glint_ctx ctx, const float *env, int R, const glint_part
  * inverse of j), l_j the mirror of r about the tap's half vector,
  * W_j = <r,l_j>+, lod_j = clamp(log2(Omega_s/Omega_p)/2 + 1, 0, M-1) with
  * Omega_s = 4/(T D(h_j)) and Omega_p = 4 pi/(6 R^2) (filtered importance
- * sampling), v a trilinear lookup of the chain.  Lookups across a face edge
- * take the nearest texel of the face that owns the texel's direction.
- * Sums run in double; results are rounded once to the stored type.
+ * sampling), v a trilinear lookup of the chain.  Seams: a texel one step
+ * beyond a face edge is the nearest texel of the face that owns its centre's
+ * direction (the adjacent texel); the texel beyond a cube corner is the mean
+ * of the three texels meeting there, so lookups are continuous.  Shading
+ * reads the pyramid with the same rule.  Sums run in double; results are
+ * rounded once to the stored type.
  * ------------------------------------------------------------------------ */
 typedef struct glint_prefilter_params {
     int num_mips;      /* M, 1 <= M <= log2(R) + 1 */
@@ -226,6 +229,64 @@ typedef struct glint_shade_debug {
 int glint_shade(glint_ctx ctx, const glint_gbuffer *gbuf, int64_t num_pixels, const glint_env *env,
                 const glint_shade_params *params, float *radiance, const glint_shade_debug *debug,
                 void *stream);
+
+/* ------------------------------------------------------------------------
+ * Batched frame: several environment maps and many views of uneven size,
+ * with mixed K, materials and vertex counts, in one graph launch.  The
+ * result is defined as glint_partition_env + glint_prefilter for every
+ * environment followed by glint_shade for every view (no debug outputs);
+ * outputs are bit-identical to those calls.
+ *
+ * The first call for a given argument set (compared byte-wise, including
+ * the pointers) is a set-up call: it times the shading launch for each
+ * candidate tile size (pixels per workgroup: 64, 128, 256, 512; results do
+ * not depend on the choice) and keeps the fastest per (K, dtype, vertices,
+ * size class) in the context, uploads the view descriptors into
+ * `workspace`, and captures the frame into a HIP graph: one branch per
+ * environment on the context's side streams (the maps are filtered
+ * concurrently), joined before one shading launch per (K, vertices) group
+ * that covers all views of the group.  The set-up call synchronises the
+ * stream and lets the HIP runtime allocate graph objects.  Later calls with
+ * the same arguments enqueue exactly one hipGraphLaunch and allocate
+ * nothing.  Every environment's outputs and every view's radiance must be
+ * distinct buffers; env_index selects the environment a view is lit by.
+ * ------------------------------------------------------------------------ */
+typedef struct glint_env_task {
+    const float *env;               /* device [6][R][R][3] */
+    int R;
+    glint_partition_params partition;
+    glint_prefilter_params prefilter;
+    void *partition_workspace;      /* device, >= glint_partition_workspace_bytes(R) */
+    void *prefilter_workspace;      /* device, >= glint_prefilter_workspace_bytes(R, K, &prefilter) */
+    double *levels;                 /* outputs, as glint_partition_env / glint_prefilter */
+    uint8_t *ind_j;
+    float *ind_t;
+    void *ind_pyr;
+    float *rgb_pyr;
+    const float *lut_S, *lut_E;     /* device LUTs from glint_build_luts */
+} glint_env_task;
+
+typedef struct glint_view {
+    glint_gbuffer gbuf;
+    int64_t num_pixels;
+    int env_index;                  /* 0 .. n_env-1 */
+    glint_shade_params shade;
+    float *radiance;                /* device [num_pixels][3] */
+} glint_view;
+
+/* Device workspace (bytes, 16-byte aligned) for n_views views. */
+size_t glint_batched_workspace_bytes(int n_views);
+
+/* GLINT_EINVAL for null pointers, n_env outside 1..64, n_views outside
+ * 1..4096, an env_index out of range, or any per-environment or per-view
+ * argument glint_partition_env / glint_prefilter / glint_shade would
+ * reject.  All environments in one call share one pyramid dtype. */
+int glint_frame_batched(glint_ctx ctx, const glint_env_task *envs, int n_env, const glint_view *views,
+                        int n_views, void *workspace, void *stream);
+
+/* Tile size (pixels per workgroup) the autotuner chose for the largest
+ * (K, vertices) group of the most recent set-up call; 0 before any. */
+int glint_batched_tile_px(glint_ctx ctx);
 
 #ifdef __cplusplus
 }

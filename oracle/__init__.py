@@ -73,6 +73,8 @@ def _declare(L):
     L.orc_lattice_level.restype = C.c_int
     L.orc_taps.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, f64p]
     L.orc_pyramid_lookup.argtypes = [f32p, C.c_int, C.c_int, C.c_int, f64p, f64p, C.c_int64, f64p]
+    L.orc_sample_filter.argtypes = [f32p, u8p, f32p, f32p, C.c_int, C.c_int, C.c_int, C.c_int, f64p, f64p,
+                                    C.c_int64, f64p, C.c_int]
 
 
 def threads_default():
@@ -278,4 +280,19 @@ def pyramid_lookup(pyr, R, M, dirs, lods):
     out = np.zeros((len(dirs), Cn))
     lib().orc_pyramid_lookup(_p(pyr, C.c_float), R, M, Cn, _p(dirs, C.c_double), _p(lods, C.c_double), len(dirs),
                              _p(out, C.c_double))
+    return out
+
+
+def sample_filter(env, ind_j, ind_t, chain, K, M, T, dirs, alphas, threads=None):
+    """The prefilter's quadrature at arbitrary (direction, alpha): [n, K+3] double."""
+    env = np.ascontiguousarray(env, dtype=np.float32)
+    R = env.shape[1]
+    dirs = np.ascontiguousarray(dirs, dtype=np.float64).reshape(-1, 3)
+    alphas = np.ascontiguousarray(np.broadcast_to(alphas, (len(dirs),)), dtype=np.float64)
+    out = np.zeros((len(dirs), K + 3))
+    rc = lib().orc_sample_filter(_p(env, C.c_float), _p(ind_j, C.c_uint8), _p(ind_t, C.c_float),
+                                 _p(chain, C.c_float), R, K, M, T, _p(dirs, C.c_double), _p(alphas, C.c_double),
+                                 len(dirs), _p(out, C.c_double), threads or threads_default())
+    if rc:
+        raise ValueError("orc_sample_filter rejected its arguments")
     return out

@@ -321,10 +321,10 @@ static double radical_inverse(uint32_t j)
 
 typedef struct { double hx, hy, hz, w, lod; } tap_t;
 
-static void make_taps(int m, int M, int T, int R, tap_t *taps)
+/* Tap table for roughness alpha (the prefilter uses alpha_m = (m/(M-1))^2;
+ * the filter sampled at an arbitrary alpha uses the same construction). */
+static void make_taps_alpha(double alpha, int M, int T, int R, tap_t *taps)
 {
-    double a = (double)m / (double)(M - 1);
-    double alpha = a * a;
     double a2 = alpha * alpha;
     double omega_p = 4.0 * M_PI / (6.0 * (double)R * (double)R);
     for (int j = 0; j < T; ++j) {
@@ -348,6 +348,12 @@ static void make_taps(int m, int M, int T, int R, tap_t *taps)
     }
 }
 
+static void make_taps(int m, int M, int T, int R, tap_t *taps)
+{
+    double a = (double)m / (double)(M - 1);
+    make_taps_alpha(a * a, M, T, R, taps);
+}
+
 /* Orthonormal basis around r (Duff et al. 2017, branchless construction). */
 static void onb(const double r[3], double t1[3], double t2[3])
 {
@@ -358,16 +364,10 @@ static void onb(const double r[3], double t1[3], double t2[3])
     t2[0] = b; t2[1] = sgn + r[1] * r[1] * a; t2[2] = -r[1];
 }
 
-/* Filter one output texel (mip m >= 1) of all K+3 channels. */
-static void filter_texel(const src_chain *c, int T, int m, int face, int x, int y, const tap_t *taps,
-                         double *out)
+/* Filter all K+3 channels around the unit direction r with a tap table. */
+static void filter_dir(const src_chain *c, int T, const double r[3], const tap_t *taps, double *out)
 {
     int C = c->K + 3;
-    int n = c->R >> m;
-    double r[3];
-    face_to_dir(face, 2.0 * (x + 0.5) / n - 1.0, 2.0 * (y + 0.5) / n - 1.0, r);
-    double len = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
-    r[0] /= len; r[1] /= len; r[2] /= len;
     double t1[3], t2[3];
     onb(r, t1, t2);
     double acc[20] = {0}, wsum = 0.0, v[20];
@@ -381,6 +381,18 @@ static void filter_texel(const src_chain *c, int T, int m, int face, int x, int 
         wsum += taps[j].w;
     }
     for (int k = 0; k < C; ++k) out[k] = acc[k] / wsum;
+}
+
+/* Filter one output texel (mip m >= 1): its centre direction, normalised. */
+static void filter_texel(const src_chain *c, int T, int m, int face, int x, int y, const tap_t *taps,
+                         double *out)
+{
+    int n = c->R >> m;
+    double r[3];
+    face_to_dir(face, 2.0 * (x + 0.5) / n - 1.0, 2.0 * (y + 0.5) / n - 1.0, r);
+    double len = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+    r[0] /= len; r[1] /= len; r[2] /= len;
+    filter_dir(c, T, r, taps, out);
 }
 
 /* Prefiltered pyramid values (double, K indicator channels then RGB) of the
@@ -963,4 +975,33 @@ void orc_pyramid_lookup(const float *pyr, int R, int M, int C, const double *dir
 {
     pyr_src ps = {pyr, R, C};
     for (int64_t q = 0; q < count; ++q) trilinear(pyr_texel, &ps, R, M, C, dirs + 3 * q, lods[q], out + q * C);
+}
+
+/* The filter of Eq. (rtiblndf) evaluated at arbitrary (direction, alpha):
+ * the same quadrature as the pyramid's mips, at a continuous roughness.
+ * Training targets of the learned surrogate and the reference its error and
+ * the pyramid's interpolation error are measured against.  out: [n][K+3]. */
+int orc_sample_filter(const float *env, const uint8_t *ind_j, const float *ind_t, const float *chain, int R, int K,
+                      int M, int T, const double *dirs, const double *alphas, int64_t count, double *out, int threads)
+{
+    if (R < 1 || K < 2 || K > 16 || M < 1 || (R >> (M - 1)) < 1 || T < 1) return ORC_EINVAL;
+    src_chain c = {env, ind_j, ind_t, chain, R, K, M};
+    int C = K + 3;
+    int bad = 0;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 16) num_threads(threads > 0 ? threads : 1) reduction(| : bad)
+#endif
+    for (int64_t q = 0; q < count; ++q) {
+        double alpha = alphas[q];
+        if (!(alpha > 0.0)) { bad = 1; continue; }
+        tap_t taps[1024];
+        if (T > 1024) { bad = 1; continue; }
+        make_taps_alpha(alpha, M, T, R, taps);
+        double r[3] = {dirs[3 * q], dirs[3 * q + 1], dirs[3 * q + 2]};
+        double len = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+        r[0] /= len; r[1] /= len; r[2] /= len;
+        filter_dir(&c, T, r, taps, out + q * C);
+    }
+    (void)threads;
+    return bad ? ORC_EINVAL : ORC_OK;
 }

@@ -116,10 +116,33 @@ struct face_st {
     double s, t;
 };
 
+// Same face choice as dir_face, with one reciprocal instead of two
+// divisions (s and t may differ from the quotients by an ulp of double; the
+// seamless bilinear lookup is continuous, so lookups move by ~1e-16).
 __device__ __forceinline__ face_st locate(const d3 &d)
 {
+    const double ax = fabs(d.x), ay = fabs(d.y), az = fabs(d.z);
     face_st f;
-    f.face = dir_face(d, f.s, f.t);
+    double ma, sc, tc;
+    if (ax >= ay && ax >= az) {
+        f.face = d.x >= 0.0 ? 0 : 1;
+        ma = ax;
+        sc = d.x >= 0.0 ? -d.z : d.z;
+        tc = -d.y;
+    } else if (ay >= az) {
+        f.face = d.y >= 0.0 ? 2 : 3;
+        ma = ay;
+        sc = d.x;
+        tc = d.y >= 0.0 ? d.z : -d.z;
+    } else {
+        f.face = d.z >= 0.0 ? 4 : 5;
+        ma = az;
+        sc = d.z >= 0.0 ? d.x : -d.x;
+        tc = -d.y;
+    }
+    const double inv = 1.0 / ma;
+    f.s = sc * inv;
+    f.t = tc * inv;
     return f;
 }
 

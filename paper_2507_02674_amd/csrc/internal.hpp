@@ -23,4 +23,12 @@ hipError_t launch_luts(float *lut_S, float *lut_E, hipStream_t stream);
 hipError_t launch_shade(const glint_gbuffer &g, int64_t P, const glint_env &env, const glint_shade_params &sp,
                         float *radiance, const glint_shade_debug *dbg, hipStream_t stream);
 
+// batched shading: per-view descriptors (device copies of make_shade_args
+// output) and the first tile of each view
+size_t shade_args_bytes();
+void make_shade_args(void *out, const glint_gbuffer &g, int64_t P, const glint_env &env,
+                     const glint_shade_params &sp, float *radiance);
+hipError_t launch_shade_views(int K, int dtype, int V, const void *views, const int64_t *tile0, int n_views,
+                              int64_t tiles, int tile_px, hipStream_t stream);
+
 } // namespace glint

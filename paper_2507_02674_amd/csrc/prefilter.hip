@@ -371,7 +371,7 @@ __global__ void __launch_bounds__(kFilterThreads) k_prefilter(FilterLaunch fl, L
     constexpr int C = K + 3, CP = chain_stride(K);
     extern __shared__ Tap s_taps[];
     __shared__ double s_wsum;
-    __shared__ const float *s_lvl[16];
+    __shared__ int64_t s_lvl[16]; // float offset of each chain level (0 for level 0)
 
     // XCD-aware remap: hardware dispatches block b to XCD b % 8; give each
     // XCD a contiguous range of logical blocks (neighbouring texels share
@@ -385,8 +385,7 @@ __global__ void __launch_bounds__(kFilterThreads) k_prefilter(FilterLaunch fl, L
     const int m = q + 1;
     for (int j = threadIdx.x; j < fl.T; j += blockDim.x) make_tap(j, m, fl.M, fl.T, fl.R, s_taps[j]);
     if (threadIdx.x < fl.M)
-        s_lvl[threadIdx.x] = threadIdx.x == 0 ? nullptr
-                                              : chain + (level_offset(fl.R, threadIdx.x) - 6LL * fl.R * fl.R) * CP;
+        s_lvl[threadIdx.x] = threadIdx.x == 0 ? 0 : (level_offset(fl.R, threadIdx.x) - 6LL * fl.R * fl.R) * CP;
     __syncthreads();
     if (threadIdx.x == 0) {
         double ws = 0.0;
@@ -437,7 +436,7 @@ __global__ void __launch_bounds__(kFilterThreads) k_prefilter(FilterLaunch fl, L
                 const double lw = tp.w * (li ? fr : 1.0 - fr);
                 const double w4[4] = {lw * ((1.0 - bl.fy) * (1.0 - bl.fx)), lw * ((1.0 - bl.fy) * bl.fx),
                                       lw * (bl.fy * (1.0 - bl.fx)), lw * (bl.fy * bl.fx)};
-                const float *lvl = s_lvl[s];
+                const float *lvl = chain + s_lvl[s]; // global pointer arithmetic: global loads
                 if (bl.x0 >= 0 && bl.x0 + 1 < ns && bl.y0 >= 0 && bl.y0 + 1 < ns) {
                     // footprint inside the face: four loads in flight
                     const int64_t t0 = ((int64_t)fs.face * ns + bl.y0) * ns + bl.x0;

@@ -214,11 +214,10 @@ __device__ __forceinline__ void multinomial(double NP, const double (&p)[K], uin
     for (int k = 0; k < K; ++k) leaf[k] = Q[k];
 }
 
+// Shades pixel i of the view described by A (all of rows b1-b5).
 template <int K, int DT, int V>
-__global__ void __launch_bounds__(kShadeThreads) k_shade(ShadeArgs A)
+__device__ __forceinline__ void shade_pixel(const ShadeArgs &A, int64_t i)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= A.P) return;
     const uint32_t surf = A.g.surf_id[i];
     if (surf == GLINT_NO_SURFACE) {
         A.radiance[3 * i] = 0.0f; A.radiance[3 * i + 1] = 0.0f; A.radiance[3 * i + 2] = 0.0f;
@@ -367,6 +366,35 @@ __global__ void __launch_bounds__(kShadeThreads) k_shade(ShadeArgs A)
     for (int c = 0; c < 3; ++c) A.radiance[3 * i + c] = (float)((f0[c] * EA + EB) * rgb[c] * gmod);
 }
 
+template <int K, int DT, int V>
+__global__ void __launch_bounds__(kShadeThreads) k_shade(ShadeArgs A)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= A.P) return;
+    shade_pixel<K, DT, V>(A, i);
+}
+
+// All views of one (K, V) group in one launch: block b shades tile b of the
+// concatenated views (tile = blockDim.x pixels); tile0[v] is the first tile
+// of view v (ascending), so the view is found by a scan of <= n_views entries.
+template <int K, int DT, int V>
+__global__ void __launch_bounds__(512) k_shade_views(const ShadeArgs *__restrict__ views,
+                                                     const int64_t *__restrict__ tile0, int n_views)
+{
+    __shared__ int s_view;
+    const int64_t b = blockIdx.x;
+    if (threadIdx.x == 0) {
+        int v = 0;
+        while (v + 1 < n_views && tile0[v + 1] <= b) ++v;
+        s_view = v;
+    }
+    __syncthreads();
+    const ShadeArgs A = views[s_view];
+    const int64_t i = (b - tile0[s_view]) * blockDim.x + threadIdx.x;
+    if (i >= A.P) return;
+    shade_pixel<K, DT, V>(A, i);
+}
+
 template <int K, int DT>
 static hipError_t launch_shade_kd(const ShadeArgs &a, int V, hipStream_t stream)
 {
@@ -374,6 +402,51 @@ static hipError_t launch_shade_kd(const ShadeArgs &a, int V, hipStream_t stream)
     if (V == 1) hipLaunchKernelGGL((k_shade<K, DT, 1>), dim3(blocks), dim3(kShadeThreads), 0, stream, a);
     else hipLaunchKernelGGL((k_shade<K, DT, 6>), dim3(blocks), dim3(kShadeThreads), 0, stream, a);
     return hipGetLastError();
+}
+
+size_t shade_args_bytes() { return sizeof(ShadeArgs); }
+
+// Fills the device-side descriptor of one view (host memory, copied later).
+void make_shade_args(void *out, const glint_gbuffer &g, int64_t P, const glint_env &env,
+                     const glint_shade_params &sp, float *radiance)
+{
+    ShadeArgs a;
+    a.g = g;
+    a.P = P;
+    a.ind_pyr = env.ind_pyr;
+    a.rgb_pyr = env.rgb_pyr;
+    a.levels = env.levels;
+    a.lut_S = env.lut_S;
+    a.lut_E = env.lut_E;
+    a.R = env.R;
+    a.M = env.num_mips;
+    a.seed = sp.seed;
+    a.radiance = radiance;
+    a.counts = nullptr;
+    a.codes = nullptr;
+    a.probs = nullptr;
+    *static_cast<ShadeArgs *>(out) = a;
+}
+
+hipError_t launch_shade_views(int K, int dtype, int V, const void *views, const int64_t *tile0, int n_views,
+                              int64_t tiles, int tile_px, hipStream_t stream)
+{
+    const ShadeArgs *va = static_cast<const ShadeArgs *>(views);
+#define GLINT_SV(KK, DD, VV)                                                                                 \
+    if (K == KK && dtype == DD && V == VV) {                                                                 \
+        hipLaunchKernelGGL((k_shade_views<KK, DD, VV>), dim3((unsigned)tiles), dim3(tile_px), 0, stream, va, \
+                           tile0, n_views);                                                                  \
+        return hipGetLastError();                                                                            \
+    }
+#define GLINT_SV_K(KK) GLINT_SV(KK, 0, 1) GLINT_SV(KK, 1, 1) GLINT_SV(KK, 2, 1) GLINT_SV(KK, 3, 1) \
+    GLINT_SV(KK, 0, 6) GLINT_SV(KK, 1, 6) GLINT_SV(KK, 2, 6) GLINT_SV(KK, 3, 6)
+    GLINT_SV_K(2)
+    GLINT_SV_K(4)
+    GLINT_SV_K(8)
+    GLINT_SV_K(16)
+#undef GLINT_SV_K
+#undef GLINT_SV
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_shade(const glint_gbuffer &g, int64_t P, const glint_env &env, const glint_shade_params &sp,

@@ -53,6 +53,18 @@ class ShadeDebug(C.Structure):
     _fields_ = [("counts", C.c_void_p), ("codes", C.c_void_p), ("probs", C.c_void_p)]
 
 
+class EnvTask(C.Structure):
+    _fields_ = [("env", C.c_void_p), ("R", C.c_int), ("partition", PartitionParams), ("prefilter", PrefilterParams),
+                ("partition_workspace", C.c_void_p), ("prefilter_workspace", C.c_void_p), ("levels", C.c_void_p),
+                ("ind_j", C.c_void_p), ("ind_t", C.c_void_p), ("ind_pyr", C.c_void_p), ("rgb_pyr", C.c_void_p),
+                ("lut_S", C.c_void_p), ("lut_E", C.c_void_p)]
+
+
+class View(C.Structure):
+    _fields_ = [("gbuf", GBuffer), ("num_pixels", C.c_int64), ("env_index", C.c_int), ("shade", ShadeParams),
+                ("radiance", C.c_void_p)]
+
+
 _LIB = None
 
 EXPORTS = {
@@ -71,6 +83,10 @@ EXPORTS = {
     "glint_build_luts": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     "glint_shade": ([C.c_void_p, C.POINTER(GBuffer), C.c_int64, C.POINTER(Env), C.POINTER(ShadeParams),
                      C.c_void_p, C.POINTER(ShadeDebug), C.c_void_p], C.c_int),
+    "glint_batched_workspace_bytes": ([C.c_int], C.c_size_t),
+    "glint_frame_batched": ([C.c_void_p, C.POINTER(EnvTask), C.c_int, C.POINTER(View), C.c_int, C.c_void_p,
+                             C.c_void_p], C.c_int),
+    "glint_batched_tile_px": ([C.c_void_p], C.c_int),
 }
 
 
@@ -192,3 +208,19 @@ def glint_shade(ctx, gbuf: GBuffer, num_pixels: int, env: Env, params: ShadePara
                            for k in ("counts", "codes", "probs")])
     _check(lib().glint_shade(ctx, C.byref(gbuf), num_pixels, C.byref(env), C.byref(params), _ptr(radiance),
                              C.byref(dbg) if dbg is not None else None, _stream(stream)))
+
+
+def glint_batched_workspace_bytes(n_views: int) -> int:
+    return lib().glint_batched_workspace_bytes(n_views)
+
+
+def glint_frame_batched(ctx, envs, views, workspace, stream=None):
+    """envs: sequence of EnvTask, views: sequence of View (C structs)."""
+    _require_cuda(workspace)
+    ea = (EnvTask * len(envs))(*envs)
+    va = (View * len(views))(*views)
+    _check(lib().glint_frame_batched(ctx, ea, len(envs), va, len(views), _ptr(workspace), _stream(stream)))
+
+
+def glint_batched_tile_px(ctx) -> int:
+    return lib().glint_batched_tile_px(ctx)

@@ -74,3 +74,42 @@ class Shader:
 
     def run(self, env: G.Env, stream=None, debug=None):
         G.glint_shade(self.ctx, self.gb, self.P, env, self.sp, self.radiance, debug, stream)
+
+
+class BatchedFrame:
+    """Many environments and views in one graph launch (glint_frame_batched).
+
+    envs: list of (env tensor [6,R,R,3], K, M, T); views: list of
+    (gbuf dict, env_index, seed, vertices).  Allocates every buffer once."""
+
+    def __init__(self, ctx, envs, views, dtype=G.GLINT_F32, ell=1e-3, device="cuda"):
+        self.ctx = ctx
+        self.pipes, self.env_tensors = [], []
+        for (env, K, M, T) in envs:
+            R = int(env.shape[1])
+            pipe = EnvPipeline(ctx, R, K, M, T, dtype, ell, device=device)
+            pipe.build_luts()
+            self.pipes.append(pipe)
+            self.env_tensors.append(env)
+        self.shaders = [Shader(ctx, gb, seed=seed, vertices=V, device=device) for (gb, _, seed, V) in views]
+        self.env_index = [e for (_, e, _, _) in views]
+        self.tasks = []
+        for pipe, env in zip(self.pipes, self.env_tensors):
+            self.tasks.append(G.EnvTask(env.data_ptr(), pipe.R, pipe.pp, pipe.fp, pipe.part_ws.data_ptr(),
+                                        pipe.filt_ws.data_ptr(), pipe.levels.data_ptr(), pipe.ind_j.data_ptr(),
+                                        pipe.ind_t.data_ptr(), pipe.ind_pyr.data_ptr(), pipe.rgb_pyr.data_ptr(),
+                                        pipe.lut_S.data_ptr(), pipe.lut_E.data_ptr()))
+        self.view_structs = [G.View(sh.gb, sh.P, e, sh.sp, sh.radiance.data_ptr())
+                             for sh, e in zip(self.shaders, self.env_index)]
+        nbytes = G.glint_batched_workspace_bytes(len(views))
+        self.workspace = torch.empty(nbytes // 8 + 64, dtype=torch.float64, device=device)
+        # 256-byte aligned view into the workspace
+        off = (-self.workspace.data_ptr()) % 256 // 8
+        self.ws = self.workspace[off:]
+
+    @property
+    def total_pixels(self):
+        return sum(sh.P for sh in self.shaders)
+
+    def run(self, stream=None):
+        G.glint_frame_batched(self.ctx, self.tasks, self.view_structs, self.ws, stream)

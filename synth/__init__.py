@@ -253,3 +253,29 @@ WORKLOADS = {
     "precision": Workload("precision", R=512, M=9, K=8, T=64, W=2560, H=1440, env_seed=3, scene="frame",
                           density_decades=(6.0, 10.0)),
 }
+
+
+def batched_views(n_views: int = 64, seed: int = 11, max_pixels: int = 1920 * 1080, min_pixels: int = 256 * 256,
+                  n_env: int = 4):
+    """Views of uneven size for the batched frame: pixel counts log-uniform in
+    [min_pixels, max_pixels], aspect ratios 1, 4:3 or 16:9, cameras on seeded
+    orbits around the sphere+plane scene, per-view density decades.
+    Returns a list of (gbuf, env_index, hash_seed, vertices)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for v in range(n_views):
+        px = math.exp(rng.uniform(math.log(min_pixels), math.log(max_pixels)))
+        aspect = [1.0, 4.0 / 3.0, 16.0 / 9.0][rng.integers(3)]
+        H = max(16, int(round(math.sqrt(px / aspect))))
+        W = max(16, int(round(H * aspect)))
+        az = rng.uniform(0, 2 * math.pi)
+        dist = rng.uniform(3.0, 6.0)
+        eye = (dist * math.sin(az), rng.uniform(0.2, 1.5), dist * math.cos(az))
+        lo = rng.uniform(4.0, 7.0)
+        gb = scene_frame(W, H, seed=100 + v, density_decades=(lo, lo + rng.uniform(1.0, 3.0)), eye=eye,
+                         target=(0.0, -0.3, 0.0))
+        out.append((gb, v % n_env, 1000 + v, 1))
+    return out
+
+
+BATCHED_ENVS = ((101, 4), (102, 8), (103, 16), (104, 8))  # (seed, K); each map 6x256x256, 8 mips

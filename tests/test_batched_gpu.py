@@ -1,0 +1,96 @@
+"""Batched frame (glint_frame_batched): several environments and views of
+uneven size, mixed K and vertex counts, in one captured graph.  Its outputs
+must equal the per-call path bit for bit, on the set-up call and on every
+replay."""
+import numpy as np
+import pytest
+
+import synth
+from paper_2507_02674_amd import glint as G
+from paper_2507_02674_amd.pipeline import BatchedFrame, EnvPipeline, Shader
+from tests import gpu_util as U
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU; the library has no CPU fallback")
+    c = G.glint_create(0)
+    yield c
+    G.glint_destroy(c)
+
+
+def small_setup():
+    import torch
+    env_specs = [(32, 4, 6, 1), (16, 16, 5, 2), (64, 8, 7, 3)]  # (R, K, M, seed)
+    envs = [(torch.from_numpy(synth.make_env(R, seed)).cuda(), K, M, 64) for (R, K, M, seed) in env_specs]
+    sizes = [(40, 30), (64, 64), (100, 57), (17, 13), (128, 72), (33, 33), (90, 50)]
+    views = []
+    for v, (W, H) in enumerate(sizes):
+        gb = synth.scene_frame(W, H, seed=200 + v, density_decades=(3.0, 8.0),
+                               eye=(3.0 * np.sin(v), 0.8, 3.0 * np.cos(v)), target=(0.0, -0.3, 0.0))
+        views.append((gb, v % len(envs), 500 + v, 6 if v in (2, 5) else 1))
+    return envs, views
+
+
+def reference(ctx, envs, views):
+    """Per-call path: partition + prefilter per environment, shade per view."""
+    pipes = []
+    for (env, K, M, T) in envs:
+        p = EnvPipeline(ctx, int(env.shape[1]), K, M, T)
+        p.build_luts()
+        p.run(env)
+        pipes.append(p)
+    outs = []
+    for (gb, e, seed, V) in views:
+        sh = Shader(ctx, gb, seed=seed, vertices=V)
+        sh.run(pipes[e].env_struct())
+        outs.append(U.host(sh.radiance))
+    return pipes, outs
+
+
+def test_batched_equals_per_call_path_and_replays(ctx):
+    import torch
+    U.log("batched: 3 envs (K=4,16,8), 7 views (V=1/6)")
+    envs, views = small_setup()
+    bf = BatchedFrame(ctx, envs, views)
+    bf.run()  # set-up call: autotune, upload, capture, launch
+    first = [U.host(sh.radiance) for sh in bf.shaders]
+    pipes, ref = reference(ctx, envs, views)
+    for v, (a, b) in enumerate(zip(first, ref)):
+        assert np.array_equal(a, b), f"view {v}"
+    for e, (bp, rp) in enumerate(zip(bf.pipes, pipes)):
+        for name in ("levels", "ind_j", "ind_t", "ind_pyr", "rgb_pyr"):
+            assert torch.equal(getattr(bp, name), getattr(rp, name)), (e, name)
+    assert G.glint_batched_tile_px(ctx) in (64, 128, 256, 512)
+    # replays: one graph launch each, with eager work and syncs in between
+    for rep in range(3):
+        for sh in bf.shaders:
+            sh.radiance.fill_(-1.0)
+        _ = torch.ones(1000, device="cuda").sum().item()
+        bf.run()
+        torch.cuda.synchronize()
+        for v, sh in enumerate(bf.shaders):
+            assert np.array_equal(U.host(sh.radiance), ref[v]), (rep, v)
+    U.log(f"  tile px chosen: {G.glint_batched_tile_px(ctx)}")
+
+
+def test_batched_rejects_bad_arguments(ctx):
+    envs, views = small_setup()
+    bf = BatchedFrame(ctx, envs, views[:2])
+    bad = G.View(bf.view_structs[0].gbuf, bf.view_structs[0].num_pixels, 7, bf.view_structs[0].shade,
+                 bf.view_structs[0].radiance)
+    with pytest.raises(G.GlintError) as e:
+        G.glint_frame_batched(ctx, bf.tasks, [bad], bf.ws)
+    assert e.value.code == G.GLINT_EINVAL
+    t = bf.tasks[1]
+    odd = G.EnvTask(t.env, t.R, t.partition, G.PrefilterParams(t.prefilter.num_mips, t.prefilter.taps, G.GLINT_F16),
+                    t.partition_workspace, t.prefilter_workspace, t.levels, t.ind_j, t.ind_t, t.ind_pyr, t.rgb_pyr,
+                    t.lut_S, t.lut_E)
+    with pytest.raises(G.GlintError):
+        G.glint_frame_batched(ctx, [bf.tasks[0], odd], bf.view_structs, bf.ws)
+    with pytest.raises(G.GlintError):
+        G.glint_frame_batched(ctx, bf.tasks, [], bf.ws)

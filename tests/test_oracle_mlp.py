@@ -1,0 +1,64 @@
+"""Pins of the surrogate's FP64 definition (oracle/mlp.py): finite-difference
+gradients, softmax/cross-entropy identities, layout round trip, Adam."""
+import numpy as np
+import pytest
+
+from oracle import mlp
+
+
+def test_layout_and_parameter_count():
+    assert mlp.real_params(8) == 9224
+    rng = np.random.default_rng(0)
+    w = rng.normal(size=mlp.N_PARAMS)
+    p = mlp.unpack(w, 8)
+    back = mlp.pack(p, 8)
+    keep = back != 0
+    assert np.array_equal(back[keep], w[keep])
+    assert np.count_nonzero(back) == mlp.real_params(8)
+
+
+@pytest.mark.parametrize("K", [4, 8])
+def test_gradient_matches_finite_differences(K):
+    rng = np.random.default_rng(1)
+    w = mlp.init(K, seed=3).astype(np.float64)
+    w += rng.normal(scale=0.05, size=w.shape) * (mlp.pack(mlp.unpack(np.ones(mlp.N_PARAMS), K), K) != 0)
+    x = rng.normal(size=(16, 5))
+    t = rng.dirichlet(np.ones(K), size=16)
+    loss, g = mlp.loss_and_grad(w, x, t, K)
+    idx = np.nonzero(g)[0]
+    pick = rng.choice(idx, 60, replace=False)
+    h = 1e-6
+    for i in pick:
+        wp, wm = w.copy(), w.copy()
+        wp[i] += h
+        wm[i] -= h
+        fd = (mlp.loss_and_grad(wp, x, t, K)[0] - mlp.loss_and_grad(wm, x, t, K)[0]) / (2 * h)
+        assert fd == pytest.approx(g[i], rel=1e-5, abs=1e-9)
+
+
+def test_softmax_cross_entropy_identities():
+    K = 8
+    rng = np.random.default_rng(2)
+    w = mlp.init(K).astype(np.float64)
+    x = rng.normal(size=(32, 5))
+    y, _ = mlp.forward(w, x, K)
+    assert np.allclose(y.sum(1), 1.0) and np.all(y > 0)
+    # cross-entropy against its own output is the entropy; the gradient of the
+    # logits vanishes there
+    loss, g = mlp.loss_and_grad(w, x, y, K)
+    assert loss == pytest.approx(-np.mean(np.sum(y * np.log(y), 1)), rel=1e-12)
+    assert np.abs(g).max() < 1e-12
+
+
+def test_adam_first_step_moves_by_lr():
+    g = np.array([1e-3, -2.0, 5.0])
+    w, m, v = mlp.adam(np.zeros(3), np.zeros(3), np.zeros(3), g, 1, 1e-3)
+    assert np.allclose(w, -1e-3 * np.sign(g), rtol=1e-4)
+
+
+def test_bf16_rounding():
+    assert mlp.bf16(1.0) == 1.0
+    assert mlp.bf16(1.0 + 2 ** -9) == 1.0          # tie to even
+    assert mlp.bf16(1.0 + 3 * 2 ** -9) == 1.0 + 2 ** -7
+    x = np.random.default_rng(3).normal(size=1000)
+    assert np.all(np.abs(mlp.bf16(x) - x) <= 2 ** -8 * np.abs(x))
