@@ -150,6 +150,87 @@ int glint_prefilter(glint_ctx ctx, const float *env, const uint8_t *ind_j, const
                     void *stream);
 
 /* ------------------------------------------------------------------------
+ * The filter of Sec. 5 at arbitrary (direction, roughness): the same
+ * quadrature as glint_prefilter (tap table built for the given alpha rather
+ * than alpha_m = (m/(M-1))^2, trilinear lookups of the source chain), for
+ * checking the pyramid and for producing training targets of the learned
+ * surrogate.  workspace: the prefilter workspace that the most recent
+ * glint_prefilter call for the same env, R, K and params filled (it holds
+ * the source mip chain); it is only read.  dirs: device [n][3] float32
+ * directions (normalised here, need not be unit).
+ * ------------------------------------------------------------------------ */
+
+/* alphas: device [n] float32 GGX roughness in (0, 1].  out: device
+ * [n][K+3] float32, the K filtered indicator values then RGB.
+ * GLINT_EINVAL: bad R, K, M, T, n < 0 or a null pointer (n = 0: no-op). */
+int glint_sample_filter(glint_ctx ctx, const float *env, const uint8_t *ind_j, const float *ind_t, int R, int K,
+                        const glint_prefilter_params *params, const void *workspace, const float *dirs,
+                        const float *alphas, int64_t n, float *out, void *stream);
+
+/* Training pairs of the learned surrogate (see below): for each sample the
+ * filter at alpha = sqrt(alpha_x alpha_y) (the isotropic roughness that
+ * shading uses), x [n][5] = surrogate inputs of (dir, alpha_x, alpha_y)
+ * and target [n][K] = F_k / sum F (1/K each if sum F = 0).  ax, ay: device
+ * [n] float32 in (0, 1].  The caller draws dirs, ax and ay (e.g. dirs
+ * uniform on the sphere, ln alpha uniform in [ln 0.02, ln 0.5]). */
+int glint_surrogate_samples(glint_ctx ctx, const float *env, const uint8_t *ind_j, const float *ind_t, int R,
+                            int K, const glint_prefilter_params *params, const void *workspace, const float *dirs,
+                            const float *ax, const float *ay, int64_t n, float *x, float *target, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Learned surrogate of the indicator lookup (an extension, not the
+ * paper's method).  An MLP maps x = (w_x, w_y, w_z, (ln alpha_x - c)/h,
+ * (ln alpha_y - c)/h), c and h mapping [ln 0.02, ln 0.5] onto [-1, 1], to
+ * softmax probabilities that stand in for F_k / sum F in Eq. (probhk):
+ * 5 -> 64 -> 64 -> 64 -> K, SiLU hidden units.  The dense layers run on
+ * the matrix cores with bfloat16 weights and activations (round to nearest
+ * even) and float32 accumulation; biases, softmax and the error signals'
+ * scaling are float32.
+ *
+ * Parameters: a flat float32 master of glint_surrogate_params() entries,
+ * padded for 32 x 32 x 16 matrix tiles:
+ *   W1 [64][16] (columns 5..15 zero), b1 [64], W2 [64][64], b2 [64],
+ *   W3 [64][64], b3 [64], W4 [32][64] (rows K..31 zero), b4 [32] (K.. zero)
+ * and a bfloat16 copy (uint16_t bit patterns, same layout, 16-byte aligned)
+ * that the matrix cores read.  Loss: mean over the batch of the soft-label
+ * cross-entropy -sum_k t_k ln y_k.
+ * ------------------------------------------------------------------------ */
+
+/* Entries of the padded parameter layout (11488). */
+int glint_surrogate_params(void);
+
+/* Device workspace (bytes) of glint_surrogate_gradient and
+ * glint_surrogate_train_step for a batch of B samples (per-block partial
+ * gradients); 0 if B is outside 1..2^20. */
+size_t glint_surrogate_workspace_bytes(int batch);
+
+/* Zeroes the pad entries of the master w (device) and writes the bfloat16
+ * copy w_bf16 (device).  Call after writing or loading w. */
+int glint_surrogate_prepare(glint_ctx ctx, int K, float *w, uint16_t *w_bf16, void *stream);
+
+/* Forward pass: x device [B][5] float32 -> probs device [B][K] float32.
+ * K in 2..32; GLINT_EINVAL for bad sizes or null pointers. */
+int glint_surrogate_forward(glint_ctx ctx, int K, const float *w, const uint16_t *w_bf16, const float *x,
+                            int64_t B, float *probs, void *stream);
+
+/* Gradient of the mean loss over the batch: grad device [params] float32
+ * (pad entries 0), loss device float32 scalar.  x [B][5], target [B][K];
+ * workspace device, >= glint_surrogate_workspace_bytes(B), 16-byte aligned.
+ * The per-block partial gradients are summed in a fixed order, so results
+ * are deterministic. */
+int glint_surrogate_gradient(glint_ctx ctx, int K, const float *w, const uint16_t *w_bf16, const float *x,
+                             const float *target, int B, void *workspace, float *grad, float *loss, void *stream);
+
+/* One training step: the gradient as above, then Adam (beta1 0.9, beta2
+ * 0.999, eps 1e-8, bias correction with step >= 1) on the master w with
+ * moments m, v (device [params] float32, zero before step 1), then the
+ * bfloat16 copy is refreshed.  loss receives the batch loss before the
+ * update.  lr: the step's learning rate (schedules are the caller's). */
+int glint_surrogate_train_step(glint_ctx ctx, int K, float *w, uint16_t *w_bf16, float *m, float *v, int step,
+                               float lr, const float *x, const float *target, int B, void *workspace, float *loss,
+                               void *stream);
+
+/* ------------------------------------------------------------------------
  * Lookup tables, once per BRDF model (isotropic GGX, Schlick Fresnel,
  * height-correlated Smith), on a 64 x 64 cell-centred grid over
  * (sqrt(alpha) rows, mu_o = <n,v> columns):
@@ -229,6 +310,21 @@ typedef struct glint_shade_debug {
 int glint_shade(glint_ctx ctx, const glint_gbuffer *gbuf, int64_t num_pixels, const glint_env *env,
                 const glint_shade_params *params, float *radiance, const glint_shade_debug *debug,
                 void *stream);
+
+/* Device workspace (bytes) of glint_shade_surrogate: the surrogate's
+ * outputs for num_pixels pixels ([P][K] float32). */
+size_t glint_shade_surrogate_workspace_bytes(int64_t num_pixels, int K);
+
+/* Surrogate form of glint_shade: F_k / sum F of each surface pixel comes
+ * from the network at (w_r, alpha_x, alpha_y) instead of the indicator
+ * pyramid, which is not read (env->ind_pyr may be NULL; env->dtype is
+ * ignored); RGB, S and E_rho are read as in glint_shade and the rest of
+ * the pixel's arithmetic is unchanged.  w, w_bf16: parameters for env->K.
+ * workspace: device, >= glint_shade_surrogate_workspace_bytes, 16-byte
+ * aligned.  Errors as glint_shade. */
+int glint_shade_surrogate(glint_ctx ctx, const glint_gbuffer *gbuf, int64_t num_pixels, const glint_env *env,
+                          const float *w, const uint16_t *w_bf16, const glint_shade_params *params,
+                          void *workspace, float *radiance, const glint_shade_debug *debug, void *stream);
 
 /* ------------------------------------------------------------------------
  * Batched frame: several environment maps and many views of uneven size,

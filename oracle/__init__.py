@@ -64,6 +64,9 @@ def _declare(L):
                               f32p, f32p]
     L.orc_shade_pixels.argtypes = [C.POINTER(f32p), f32p, f32p, f64p, f32p, f32p, C.c_int, C.c_int, C.c_int,
                                    C.c_uint32, C.c_int, i64p, C.c_int64, f64p, f64p, u8p, f64p, u8p, C.c_int]
+    L.orc_shade_pixels_given_F.argtypes = [C.POINTER(f32p), f64p, f32p, f64p, f32p, f32p, C.c_int, C.c_int,
+                                           C.c_int, C.c_uint32, C.c_int, i64p, C.c_int64, f64p, f64p, u8p, f64p,
+                                           u8p, C.c_int]
     L.orc_gate_probs.argtypes = [C.c_float, C.c_float, f32p]
     L.orc_dual_gated.argtypes = [C.c_double, C.c_double, C.c_float, C.c_float, f64p, f64p, u8p]
     L.orc_face_dir.argtypes = [C.c_int, C.c_double, C.c_double, f64p]
@@ -172,11 +175,13 @@ GBUF_FIELDS = ("nx", "ny", "nz", "vx", "vy", "vz", "u", "v", "area", "ax", "ay",
 
 
 def shade(gbuf: dict, ind_pyr, rgb_pyr, levels, lut_S, lut_E, R: int, K: int, M: int, seed: int,
-          vertices: int = 1, pixels=None, threads=None):
+          vertices: int = 1, pixels=None, threads=None, F=None):
     """Glint radiance of the requested pixels (all when None).
 
     gbuf: dict of flat float32 arrays (surf_id uint32).  ind_pyr [texels,K]
-    float32 and rgb_pyr [texels,4] float32 are the stored pyramids.
+    float32 and rgb_pyr [texels,4] float32 are the stored pyramids.  With F
+    ([n,K], one row per requested pixel) the filtered indicator values are
+    taken from F instead of the indicator pyramid (ind_pyr is then unused).
     Returns dict(radiance [n,3] f64, counts [n,V,K] f64, codes [n,V,K-1] u8,
     probs [n,K] f64, flags [n] u8).
     """
@@ -188,7 +193,7 @@ def shade(gbuf: dict, ind_pyr, rgb_pyr, levels, lut_S, lut_E, R: int, K: int, M:
     pixels = np.ascontiguousarray(pixels, dtype=np.int64)
     n = len(pixels)
     arr = (C.POINTER(C.c_float) * 16)(*[f.ctypes.data_as(C.POINTER(C.c_float)) for f in fields])
-    ind_pyr = np.ascontiguousarray(ind_pyr, dtype=np.float32)
+    ind_pyr = np.ascontiguousarray(ind_pyr if F is None else np.zeros(1), dtype=np.float32)
     rgb_pyr = np.ascontiguousarray(rgb_pyr, dtype=np.float32)
     levels = np.ascontiguousarray(levels, dtype=np.float64)
     lut_S = np.ascontiguousarray(lut_S, dtype=np.float32)
@@ -196,6 +201,17 @@ def shade(gbuf: dict, ind_pyr, rgb_pyr, levels, lut_S, lut_E, R: int, K: int, M:
     out = dict(radiance=np.zeros((n, 3)), counts=np.zeros((n, vertices, K)),
                codes=np.zeros((n, vertices, K - 1), np.uint8), probs=np.zeros((n, K)),
                flags=np.zeros(n, np.uint8))
+    if F is not None:
+        F = np.ascontiguousarray(F, dtype=np.float64).reshape(n, K)
+        rc = lib().orc_shade_pixels_given_F(arr, _p(F, C.c_double), _p(rgb_pyr, C.c_float), _p(levels, C.c_double),
+                                            _p(lut_S, C.c_float), _p(lut_E, C.c_float), R, K, M, seed, vertices,
+                                            _p(pixels, C.c_int64), n, _p(out["radiance"], C.c_double),
+                                            _p(out["counts"], C.c_double), _p(out["codes"], C.c_uint8),
+                                            _p(out["probs"], C.c_double), _p(out["flags"], C.c_uint8),
+                                            threads or threads_default())
+        if rc:
+            raise ValueError("orc_shade_pixels_given_F rejected its arguments")
+        return out
     rc = lib().orc_shade_pixels(arr, _p(ind_pyr, C.c_float), _p(rgb_pyr, C.c_float), _p(levels, C.c_double),
                                 _p(lut_S, C.c_float), _p(lut_E, C.c_float), R, K, M, seed, vertices,
                                 _p(pixels, C.c_int64), n, _p(out["radiance"], C.c_double),

@@ -818,10 +818,10 @@ typedef struct {
  * float gating threshold, 2 = a node probability on a float rounding
  * boundary, 4 = a node count on a float rounding boundary, 8 = a sampled
  * count within 1e-5 of an integer (without being one). */
-int orc_shade_pixels(const float *const *gb, const float *ind_pyr, const float *rgb_pyr, const double *levels,
-                     const float *lut_S, const float *lut_E, int R, int K, int M, uint32_t seed, int V,
-                     const int64_t *pix, int64_t count, double *radiance, double *counts, uint8_t *codes,
-                     double *probs, uint8_t *flags, int threads)
+static int shade_impl(const float *const *gb, const float *ind_pyr, const float *rgb_pyr, const double *levels,
+                      const float *lut_S, const float *lut_E, int R, int K, int M, uint32_t seed, int V,
+                      const int64_t *pix, int64_t count, const double *Fext, double *radiance, double *counts,
+                      uint8_t *codes, double *probs, uint8_t *flags, int threads)
 {
     if (R < 1 || K < 2 || K > 16 || (K & (K - 1)) || M < 1 || (R >> (M - 1)) < 1 || (V != 1 && V != 6))
         return ORC_EINVAL;
@@ -857,7 +857,10 @@ int orc_shade_pixels(const float *const *gb, const float *ind_pyr, const float *
         /* Sec. 4 Eq. (probhk) with Sec. 5 Eq. (rtiblndf): p_k = S F_k / sum F for
          * k >= 2 (one-based); the zero-radiance bin absorbs the rest. */
         double F[20], rgb[4];
-        trilinear(pyr_texel, &ps_ind, R, M, K, wr, lod, F);
+        if (Fext)
+            for (int k = 0; k < K; ++k) F[k] = Fext[q * K + k];
+        else
+            trilinear(pyr_texel, &ps_ind, R, M, K, wr, lod, F);
         trilinear(pyr_texel, &ps_rgb, R, M, 4, wr, lod, rgb);
         double sumF = 0.0;
         for (int k = 0; k < K; ++k) sumF += F[k];
@@ -931,6 +934,29 @@ int orc_shade_pixels(const float *const *gb, const float *ind_pyr, const float *
     }
     (void)threads;
     return ORC_OK;
+}
+
+int orc_shade_pixels(const float *const *gb, const float *ind_pyr, const float *rgb_pyr, const double *levels,
+                     const float *lut_S, const float *lut_E, int R, int K, int M, uint32_t seed, int V,
+                     const int64_t *pix, int64_t count, double *radiance, double *counts, uint8_t *codes,
+                     double *probs, uint8_t *flags, int threads)
+{
+    return shade_impl(gb, ind_pyr, rgb_pyr, levels, lut_S, lut_E, R, K, M, seed, V, pix, count, NULL, radiance,
+                      counts, codes, probs, flags, threads);
+}
+
+/* As orc_shade_pixels, with the K filtered indicator values of each requested
+ * pixel given (F [count][K], e.g. a learned surrogate's output) instead of
+ * read from the indicator pyramid; RGB still comes from the RGB pyramid.
+ * ind_pyr is not read. */
+int orc_shade_pixels_given_F(const float *const *gb, const double *F, const float *rgb_pyr, const double *levels,
+                             const float *lut_S, const float *lut_E, int R, int K, int M, uint32_t seed, int V,
+                             const int64_t *pix, int64_t count, double *radiance, double *counts, uint8_t *codes,
+                             double *probs, uint8_t *flags, int threads)
+{
+    if (!F) return ORC_EINVAL;
+    return shade_impl(gb, NULL, rgb_pyr, levels, lut_S, lut_E, R, K, M, seed, V, pix, count, F, radiance, counts,
+                      codes, probs, flags, threads);
 }
 
 /* Exposed pieces for the definition tests. */

@@ -127,6 +127,29 @@ int check_gbuffer(const glint_gbuffer *g)
     return GLINT_OK;
 }
 
+int check_surrogate(int K, const void *w, const void *w_bf16)
+{
+    if (K < 2 || K > 32) return fail(GLINT_EINVAL, "surrogate K=%d must be in [2, 32]", K);
+    if (!w || !w_bf16) return fail(GLINT_EINVAL, "null surrogate parameters");
+    if (reinterpret_cast<uintptr_t>(w_bf16) % 16 || reinterpret_cast<uintptr_t>(w) % 4)
+        return fail(GLINT_EINVAL, "w_bf16 must be 16-byte aligned");
+    return GLINT_OK;
+}
+
+int check_batch(int B, const float *x, const float *target, const void *workspace)
+{
+    if (B < 1 || B > (1 << 20)) return fail(GLINT_EINVAL, "batch size %d must be in [1, 2^20]", B);
+    if (!x || !target || !workspace) return fail(GLINT_EINVAL, "null pointer argument");
+    if (reinterpret_cast<uintptr_t>(workspace) % 16) return fail(GLINT_EINVAL, "workspace must be 16-byte aligned");
+    return GLINT_OK;
+}
+
+// Bytes of the per-block partial gradients (a multiple of 256).
+size_t surrogate_partial_bytes(size_t blocks)
+{
+    return (blocks * (size_t)glint::mlp_params() * sizeof(float) + 255) & ~(size_t)255;
+}
+
 } // namespace
 
 extern "C" {
@@ -225,8 +248,141 @@ int glint_shade(glint_ctx ctx, const glint_gbuffer *g, int64_t P, const glint_en
     if (int rc = check_gbuffer(g)) return rc;
     if (reinterpret_cast<uintptr_t>(env->rgb_pyr) % 16) return fail(GLINT_EINVAL, "rgb_pyr must be 16-byte aligned");
     if (P > ((int64_t)1 << 40)) return fail(GLINT_EINVAL, "num_pixels too large");
-    return device_status(glint::launch_shade(*g, P, *env, *sp, radiance, dbg, (hipStream_t)stream),
+    return device_status(glint::launch_shade(*g, P, *env, *sp, nullptr, radiance, dbg, (hipStream_t)stream),
                          "glint_shade launch");
+}
+
+int glint_sample_filter(glint_ctx ctx, const float *env, const uint8_t *ind_j, const float *ind_t, int R, int K,
+                        const glint_prefilter_params *fp, const void *workspace, const float *dirs,
+                        const float *alphas, int64_t n, float *out, void *stream)
+{
+    if (int rc = check_ctx(ctx)) return rc;
+    if (!fp || !env || !ind_j || !ind_t || !workspace) return fail(GLINT_EINVAL, "null pointer argument");
+    if (int rc = check_R(R)) return rc;
+    if (int rc = check_tree_K(K)) return rc;
+    if (int rc = check_mips(R, fp->num_mips)) return rc;
+    if (fp->taps < 1 || fp->taps > 1024) return fail(GLINT_EINVAL, "taps=%d must be in [1, 1024]", fp->taps);
+    if (n < 0 || n > ((int64_t)1 << 36)) return fail(GLINT_EINVAL, "bad sample count %lld", (long long)n);
+    if (reinterpret_cast<uintptr_t>(workspace) % 16) return fail(GLINT_EINVAL, "workspace must be 16-byte aligned");
+    if (n == 0) return ok();
+    if (!dirs || !alphas || !out) return fail(GLINT_EINVAL, "null pointer argument");
+    return device_status(glint::launch_sample_filter(env, ind_j, ind_t, workspace, R, K, fp->num_mips, fp->taps, 0,
+                                                     dirs, alphas, nullptr, n, out, nullptr, (hipStream_t)stream),
+                         "glint_sample_filter launch");
+}
+
+int glint_surrogate_samples(glint_ctx ctx, const float *env, const uint8_t *ind_j, const float *ind_t, int R,
+                            int K, const glint_prefilter_params *fp, const void *workspace, const float *dirs,
+                            const float *ax, const float *ay, int64_t n, float *x, float *target, void *stream)
+{
+    if (int rc = check_ctx(ctx)) return rc;
+    if (!fp || !env || !ind_j || !ind_t || !workspace) return fail(GLINT_EINVAL, "null pointer argument");
+    if (int rc = check_R(R)) return rc;
+    if (int rc = check_tree_K(K)) return rc;
+    if (int rc = check_mips(R, fp->num_mips)) return rc;
+    if (fp->taps < 1 || fp->taps > 1024) return fail(GLINT_EINVAL, "taps=%d must be in [1, 1024]", fp->taps);
+    if (n < 0 || n > ((int64_t)1 << 36)) return fail(GLINT_EINVAL, "bad sample count %lld", (long long)n);
+    if (reinterpret_cast<uintptr_t>(workspace) % 16) return fail(GLINT_EINVAL, "workspace must be 16-byte aligned");
+    if (n == 0) return ok();
+    if (!dirs || !ax || !ay || !x || !target) return fail(GLINT_EINVAL, "null pointer argument");
+    return device_status(glint::launch_sample_filter(env, ind_j, ind_t, workspace, R, K, fp->num_mips, fp->taps, 1,
+                                                     dirs, ax, ay, n, x, target, (hipStream_t)stream),
+                         "glint_surrogate_samples launch");
+}
+
+int glint_surrogate_params(void) { return glint::mlp_params(); }
+
+size_t glint_surrogate_workspace_bytes(int batch)
+{
+    if (batch < 1 || batch > (1 << 20)) return 0;
+    const size_t blocks = (size_t)(batch + 31) / 32;
+    return surrogate_partial_bytes(blocks) + ((blocks * sizeof(float) + 255) & ~(size_t)255);
+}
+
+int glint_surrogate_prepare(glint_ctx ctx, int K, float *w, uint16_t *w_bf16, void *stream)
+{
+    if (int rc = check_ctx(ctx)) return rc;
+    if (int rc = check_surrogate(K, w, w_bf16)) return rc;
+    return device_status(glint::launch_mlp_prepare(w, w_bf16, K, (hipStream_t)stream),
+                         "glint_surrogate_prepare launch");
+}
+
+int glint_surrogate_forward(glint_ctx ctx, int K, const float *w, const uint16_t *w_bf16, const float *x,
+                            int64_t B, float *probs, void *stream)
+{
+    if (int rc = check_ctx(ctx)) return rc;
+    if (int rc = check_surrogate(K, w, w_bf16)) return rc;
+    if (B < 0 || B > ((int64_t)1 << 36)) return fail(GLINT_EINVAL, "bad batch size %lld", (long long)B);
+    if (B == 0) return ok();
+    if (!x || !probs) return fail(GLINT_EINVAL, "null pointer argument");
+    return device_status(glint::launch_mlp_forward(x, B, K, w, w_bf16, probs, (hipStream_t)stream),
+                         "glint_surrogate_forward launch");
+}
+
+int glint_surrogate_gradient(glint_ctx ctx, int K, const float *w, const uint16_t *w_bf16, const float *x,
+                             const float *target, int B, void *workspace, float *grad, float *loss, void *stream)
+{
+    if (int rc = check_ctx(ctx)) return rc;
+    if (int rc = check_surrogate(K, w, w_bf16)) return rc;
+    if (int rc = check_batch(B, x, target, workspace)) return rc;
+    if (!grad || !loss) return fail(GLINT_EINVAL, "null pointer argument");
+    const size_t blocks = (size_t)(B + 31) / 32;
+    float *partial = static_cast<float *>(workspace);
+    float *loss_partial = reinterpret_cast<float *>(static_cast<char *>(workspace) + surrogate_partial_bytes(blocks));
+    return device_status(glint::launch_mlp_gradient(x, target, B, K, w, w_bf16, partial, loss_partial, grad, loss,
+                                                    (hipStream_t)stream),
+                         "glint_surrogate_gradient launch");
+}
+
+int glint_surrogate_train_step(glint_ctx ctx, int K, float *w, uint16_t *w_bf16, float *m, float *v, int step,
+                               float lr, const float *x, const float *target, int B, void *workspace, float *loss,
+                               void *stream)
+{
+    if (int rc = check_ctx(ctx)) return rc;
+    if (int rc = check_surrogate(K, w, w_bf16)) return rc;
+    if (int rc = check_batch(B, x, target, workspace)) return rc;
+    if (!m || !v || !loss) return fail(GLINT_EINVAL, "null pointer argument");
+    if (step < 1) return fail(GLINT_EINVAL, "step must be >= 1");
+    if (!(lr >= 0.0f) || !(lr < 1.0f)) return fail(GLINT_EINVAL, "learning rate must be in [0, 1)");
+    const size_t blocks = (size_t)(B + 31) / 32;
+    float *partial = static_cast<float *>(workspace);
+    float *loss_partial = reinterpret_cast<float *>(static_cast<char *>(workspace) + surrogate_partial_bytes(blocks));
+    return device_status(glint::launch_mlp_grad_step(x, target, B, K, w, w_bf16, m, v, step, lr, partial,
+                                                     loss_partial, loss, (hipStream_t)stream),
+                         "glint_surrogate_train_step launch");
+}
+
+size_t glint_shade_surrogate_workspace_bytes(int64_t P, int K)
+{
+    if (P < 0 || P > ((int64_t)1 << 40) || K < 2 || K > 16) return 0;
+    const size_t b = (size_t)P * (size_t)K * sizeof(float);
+    return b < 256 ? 256 : (b + 255) & ~(size_t)255;
+}
+
+int glint_shade_surrogate(glint_ctx ctx, const glint_gbuffer *g, int64_t P, const glint_env *env, const float *w,
+                          const uint16_t *w_bf16, const glint_shade_params *sp, void *workspace, float *radiance,
+                          const glint_shade_debug *dbg, void *stream)
+{
+    if (int rc = check_ctx(ctx)) return rc;
+    if (!g || !env || !sp) return fail(GLINT_EINVAL, "null pointer argument");
+    if (P < 0) return fail(GLINT_EINVAL, "num_pixels must be >= 0");
+    if (int rc = check_R(env->R)) return rc;
+    if (int rc = check_tree_K(env->K)) return rc;
+    if (int rc = check_mips(env->R, env->num_mips)) return rc;
+    if (int rc = check_surrogate(env->K, w, w_bf16)) return rc;
+    if (sp->vertices != 1 && sp->vertices != 6) return fail(GLINT_EINVAL, "vertices must be 1 or 6");
+    if (P == 0) return ok();
+    if (!radiance || !workspace || !env->rgb_pyr || !env->levels || !env->lut_S || !env->lut_E)
+        return fail(GLINT_EINVAL, "null pointer argument");
+    if (int rc = check_gbuffer(g)) return rc;
+    if (reinterpret_cast<uintptr_t>(env->rgb_pyr) % 16 || reinterpret_cast<uintptr_t>(workspace) % 16)
+        return fail(GLINT_EINVAL, "rgb_pyr and workspace must be 16-byte aligned");
+    if (P > ((int64_t)1 << 40)) return fail(GLINT_EINVAL, "num_pixels too large");
+    float *F = static_cast<float *>(workspace);
+    hipError_t e = glint::launch_mlp_lookup(*g, P, env->K, w, w_bf16, F, (hipStream_t)stream);
+    if (e != hipSuccess) return device_status(e, "glint_shade_surrogate network launch");
+    return device_status(glint::launch_shade(*g, P, *env, *sp, F, radiance, dbg, (hipStream_t)stream),
+                         "glint_shade_surrogate launch");
 }
 
 size_t glint_batched_workspace_bytes(int n_views)

@@ -269,4 +269,18 @@ __device__ __forceinline__ gate_f gate_thresholds(float Nf, float pf)
     return g;
 }
 
+// Learned-surrogate inputs of a lookup (the project's extension, not the
+// paper's): the reflection direction, then (ln alpha - c) / h for alpha_x
+// and alpha_y, where c and h map [ln 0.02, ln 0.5] onto [-1, 1].
+__device__ __forceinline__ void surrogate_features(double wx, double wy, double wz, double ax, double ay, float *out)
+{
+    const double lo = -3.912023005428146, hi = -0.6931471805599453; // ln 0.02, ln 0.5
+    const double c = 0.5 * (lo + hi), h = 0.5 * (hi - lo);
+    out[0] = (float)wx;
+    out[1] = (float)wy;
+    out[2] = (float)wz;
+    out[3] = (float)((log(ax) - c) / h);
+    out[4] = (float)((log(ay) - c) / h);
+}
+
 } // namespace glint

@@ -18,10 +18,31 @@ size_t chain_bytes(int R, int K, int M);
 hipError_t launch_prefilter(const float *env, const uint8_t *ind_j, const float *ind_t, int R, int K, int M, int T,
                             int dtype, void *workspace, void *ind_pyr, float *rgb_pyr, hipStream_t stream);
 
+// mode 0: filter at alpha = a0 -> out0 [n][K+3]; mode 1: training pairs at
+// alpha = sqrt(a0 a1) -> out0 features [n][5], out1 targets [n][K].
+hipError_t launch_sample_filter(const float *env, const uint8_t *ind_j, const float *ind_t, const void *workspace,
+                                int R, int K, int M, int T, int mode, const float *dirs, const float *a0,
+                                const float *a1, int64_t n, float *out0, float *out1, hipStream_t stream);
+
 hipError_t launch_luts(float *lut_S, float *lut_E, hipStream_t stream);
 
+// learned surrogate
+int mlp_params();
+hipError_t launch_mlp_prepare(float *w, uint16_t *wb, int K, hipStream_t stream);
+hipError_t launch_mlp_grad_step(const float *x, const float *target, int B, int K, float *w, uint16_t *wb,
+                                float *m, float *v, int step, float lr, float *partial, float *loss_partial,
+                                float *loss_out, hipStream_t stream);
+hipError_t launch_mlp_gradient(const float *x, const float *target, int B, int K, const float *w,
+                               const uint16_t *wb, float *partial, float *loss_partial, float *grad, float *loss_out,
+                               hipStream_t stream);
+hipError_t launch_mlp_forward(const float *x, int64_t B, int K, const float *w, const uint16_t *wb, float *probs,
+                              hipStream_t stream);
+hipError_t launch_mlp_lookup(const glint_gbuffer &g, int64_t P, int K, const float *w, const uint16_t *wb, float *F,
+                             hipStream_t stream);
+
+// F: null for the plain form; else the surrogate's filtered indicator values [P][K].
 hipError_t launch_shade(const glint_gbuffer &g, int64_t P, const glint_env &env, const glint_shade_params &sp,
-                        float *radiance, const glint_shade_debug *dbg, hipStream_t stream);
+                        const float *F, float *radiance, const glint_shade_debug *dbg, hipStream_t stream);
 
 // batched shading: per-view descriptors (device copies of make_shade_args
 // output) and the first tile of each view

@@ -1,0 +1,523 @@
+// Learned surrogate of the indicator pyramid lookup (not from the paper: the
+// project's own extension).  A small MLP maps (reflection direction,
+// scaled ln alpha_x, ln alpha_y) to the K normalised filtered indicator
+// values F_k / sum F; the plain filter provides its training targets.
+//
+// Network 5 -> 64 -> 64 -> 64 -> K, SiLU hidden units, softmax output.
+// Dense layers run on the matrix cores (v_mfma_f32_32x32x16_bf16): bfloat16
+// weights and activations, float32 accumulation.  One wave computes a tile
+// of 32 rows (samples or pixels) through all layers out of LDS.
+//
+// Parameter layout (flat float32 master, bfloat16 copy, padded for the
+// 32x32x16 tiles): W1 [64][16] (inputs 5..15 zero), b1 [64], W2 [64][64],
+// b2 [64], W3 [64][64], b3 [64], W4 [32][64] (rows K..31 zero), b4 [32].
+#include "device.hpp"
+#include "internal.hpp"
+
+namespace glint {
+
+namespace {
+
+typedef __attribute__((__vector_size__(8 * sizeof(short)))) short bf16x8;
+typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
+
+constexpr int kH = 64, kIn = 16, kOut = 32;
+constexpr int oW1 = 0, ob1 = oW1 + kH * kIn, oW2 = ob1 + kH, ob2 = oW2 + kH * kH, oW3 = ob2 + kH,
+              ob3 = oW3 + kH * kH, oW4 = ob3 + kH, ob4 = oW4 + kOut * kH, kParams = ob4 + kOut;
+
+// LDS row strides (bf16 elements).  Rows are read as 16-byte vectors by 32
+// lanes; strides of 24, 40 and 72 elements (12, 20, 36 dwords) put any 16
+// consecutive rows on disjoint banks.
+constexpr int kLdW1 = 24, kLdX = 40, kLdH = 72, kLdO = 40;
+constexpr int sW1 = 0, sW2 = sW1 + kH * kLdW1, sW3 = sW2 + kH * kLdH, sW4 = sW3 + kH * kLdH,
+              kWLds = sW4 + kOut * kLdH; // bf16 weights staged in LDS (no biases)
+
+constexpr int kInferWaves = 4;     // waves per block of the inference kernels
+constexpr int kInferMaxBlocks = 1024;
+
+__device__ __forceinline__ uint16_t to_bf16(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7F800000u) == 0x7F800000u && (u & 0x7FFFFFu)) return (uint16_t)((u >> 16) | 0x40u);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float from_bf16(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+__device__ __forceinline__ float silu(float z) { return z / (1.0f + __expf(-z)); }
+
+__device__ __forceinline__ float dsilu(float z)
+{
+    const float s = 1.0f / (1.0f + __expf(-z));
+    return s * (1.0f + z * (1.0f - s));
+}
+
+// acc (32 x 32 tile) += A[r][k] B[k][c] over k in [0, Kd), Kd a multiple of
+// 16; A(r, k) = a[r * ars + k * acs], B(k, c) = b[k * brs + c * bcs] (bf16
+// bit patterns in LDS).  Lane l supplies A[l%32][8(l/32)+j] and
+// B[8(l/32)+j][l%32], j < 8.  AV / BV: the eight values are contiguous
+// (acs == 1 / brs == 1, 16-byte aligned) and are read as one vector.
+template <bool AV, bool BV>
+__device__ __forceinline__ void tile_mma(const uint16_t *a, int ars, int acs, const uint16_t *b, int brs, int bcs,
+                                         int Kd, f32x16 &acc)
+{
+    const int l = threadIdx.x & 63, r = l & 31, kg = (l >> 5) * 8;
+    for (int k0 = 0; k0 < Kd; k0 += 16) {
+        bf16x8 av, bv;
+        if constexpr (AV) {
+            av = *reinterpret_cast<const bf16x8 *>(a + r * ars + k0 + kg);
+        } else {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) av[j] = (short)a[r * ars + (k0 + kg + j) * acs];
+        }
+        if constexpr (BV) {
+            bv = *reinterpret_cast<const bf16x8 *>(b + r * bcs + k0 + kg);
+        } else {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) bv[j] = (short)b[(k0 + kg + j) * brs + r * bcs];
+        }
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
+    }
+}
+
+// Row / column of accumulator i of this lane in the 32 x 32 tile.
+__device__ __forceinline__ int acc_row(int i) { return 8 * (i >> 2) + 4 * ((threadIdx.x & 63) >> 5) + (i & 3); }
+__device__ __forceinline__ int acc_col() { return threadIdx.x & 31; }
+
+__device__ __forceinline__ void zero(f32x16 &acc)
+{
+#pragma unroll
+    for (int i = 0; i < 16; ++i) acc[i] = 0.0f;
+}
+
+// Stages the bf16 weights (16-byte chunks) into LDS; all threads of the block.
+__device__ __forceinline__ void stage_weights(const uint16_t *__restrict__ wb, uint16_t *s_w)
+{
+    constexpr int c1 = kH * kIn / 8, c2 = c1 + kH * kH / 8, c3 = c2 + kH * kH / 8, c4 = c3 + kOut * kH / 8;
+    for (int c = threadIdx.x; c < c4; c += blockDim.x) {
+        int src, dst;
+        if (c < c1) {
+            const int n = c >> 1, q = c & 1;
+            src = oW1 + n * kIn + 8 * q;
+            dst = sW1 + n * kLdW1 + 8 * q;
+        } else if (c < c2) {
+            const int e = c - c1, n = e >> 3, q = e & 7;
+            src = oW2 + n * kH + 8 * q;
+            dst = sW2 + n * kLdH + 8 * q;
+        } else if (c < c3) {
+            const int e = c - c2, n = e >> 3, q = e & 7;
+            src = oW3 + n * kH + 8 * q;
+            dst = sW3 + n * kLdH + 8 * q;
+        } else {
+            const int e = c - c3, n = e >> 3, q = e & 7;
+            src = oW4 + n * kH + 8 * q;
+            dst = sW4 + n * kLdH + 8 * q;
+        }
+        *reinterpret_cast<uint4 *>(s_w + dst) = *reinterpret_cast<const uint4 *>(wb + src);
+    }
+}
+
+// out[r][n] = bf16(silu(in[r][:Kd] . W[n][:Kd] + bias[n])) for the 32 rows
+// and 64 units; z[r][n] keeps the float pre-activation when z is non-null.
+__device__ __forceinline__ void dense_silu(const uint16_t *in, int ldi, int Kd, const uint16_t *W, int ldw,
+                                           const float *__restrict__ bias, uint16_t *out, float *z)
+{
+#pragma unroll 1
+    for (int n0 = 0; n0 < kH; n0 += 32) {
+        f32x16 acc;
+        zero(acc);
+        tile_mma<true, true>(in, ldi, 1, W + n0 * ldw, 1, ldw, Kd, acc);
+        const int n = n0 + acc_col();
+        const float bn = bias[n];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int r = acc_row(i);
+            const float zz = acc[i] + bn;
+            if (z) z[r * kH + n] = zz;
+            out[r * kLdH + n] = to_bf16(silu(zz));
+        }
+    }
+}
+
+// logit[r][n] = h[r][:] . W4[n][:] + b4[n] for n < 32 (float, [32][32]).
+__device__ __forceinline__ void dense_out(const uint16_t *h, const uint16_t *W4, const float *__restrict__ b4,
+                                          float *logit)
+{
+    f32x16 acc;
+    zero(acc);
+    tile_mma<true, true>(h, kLdH, 1, W4, 1, kLdH, kH, acc);
+    const int n = acc_col();
+    const float bn = b4[n];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) logit[acc_row(i) * kOut + n] = acc[i] + bn;
+}
+
+// Softmax of row r's first K logits: y_k = exp(logit_k - mx) * inv.
+__device__ __forceinline__ void softmax_stats(const float *logit, int r, int K, float &mx, float &inv)
+{
+    mx = -3.4e38f;
+    for (int k = 0; k < K; ++k) mx = fmaxf(mx, logit[r * kOut + k]);
+    float se = 0.0f;
+    for (int k = 0; k < K; ++k) se += __expf(logit[r * kOut + k] - mx);
+    inv = 1.0f / se;
+}
+
+// Per-wave LDS of the inference kernels: inputs and two ping-pong hidden
+// buffers; the float logits reuse the second hidden buffer.
+struct InferTile {
+    uint16_t x[32 * kLdX];
+    uint16_t h[2][32 * kLdH];
+};
+static_assert(32 * kOut * sizeof(float) <= sizeof(uint16_t) * 32 * kLdH, "logits fit a hidden buffer");
+
+// Per-wave LDS of the training kernel (one wave per block).
+struct TrainTile {
+    uint16_t x[32 * kLdX];    // inputs, bf16 (cols 5.. zero)
+    uint16_t h[3][32 * kLdH]; // h1..h3, bf16
+    float z[3][32 * kH];      // z1..z3, float
+    float logit[32 * kOut];   // output logits, float
+    uint16_t dz[2][32 * kLdH]; // hidden error signals (ping-pong), bf16
+    uint16_t dz4[32 * kLdO];  // output error signal, bf16 (cols K.. zero)
+};
+
+} // namespace
+
+// ---------------------------------------------------------------------------
+// training: one wave per 32 samples; per-block partial gradients
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(64) k_mlp_grad(const float *__restrict__ x, const float *__restrict__ target,
+                                                 int B, int K, const float *__restrict__ w,
+                                                 const uint16_t *__restrict__ wb, float *__restrict__ partial,
+                                                 float *__restrict__ loss_partial)
+{
+    __shared__ __attribute__((aligned(16))) uint16_t s_w[kWLds];
+    __shared__ __attribute__((aligned(16))) TrainTile t;
+    const int lane = threadIdx.x;
+    const int row0 = blockIdx.x * 32;
+    stage_weights(wb, s_w);
+    for (int i = lane; i < 32 * kLdX; i += 64) {
+        const int r = i / kLdX, c = i % kLdX;
+        t.x[i] = (c < 5 && row0 + r < B) ? to_bf16(x[(int64_t)(row0 + r) * 5 + c]) : (uint16_t)0;
+    }
+    __syncthreads();
+    const uint16_t *W1 = s_w + sW1, *W2 = s_w + sW2, *W3 = s_w + sW3, *W4 = s_w + sW4;
+    dense_silu(t.x, kLdX, kIn, W1, kLdW1, w + ob1, t.h[0], t.z[0]);
+    __syncthreads(); // one-wave block: orders the LDS writes before the next layer reads them
+    dense_silu(t.h[0], kLdH, kH, W2, kLdH, w + ob2, t.h[1], t.z[1]);
+    __syncthreads();
+    dense_silu(t.h[1], kLdH, kH, W3, kLdH, w + ob3, t.h[2], t.z[2]);
+    __syncthreads();
+    dense_out(t.h[2], W4, w + ob4, t.logit);
+    __syncthreads();
+
+    // softmax, loss and the output error signal (y - t) / B; one row per lane
+    float loss = 0.0f;
+    if (lane < 32) {
+        const int r = lane;
+        const bool valid = row0 + r < B;
+        float mx, inv;
+        softmax_stats(t.logit, r, K, mx, inv);
+        for (int k = 0; k < kOut; ++k) {
+            float d = 0.0f;
+            if (k < K && valid) {
+                const float y = __expf(t.logit[r * kOut + k] - mx) * inv;
+                const float tk = target[(int64_t)(row0 + r) * K + k];
+                d = (y - tk) / (float)B;
+                loss -= tk * logf(fmaxf(y, 1e-30f));
+            }
+            t.dz4[r * kLdO + k] = to_bf16(d);
+        }
+    }
+    __syncthreads();
+    float *P = partial + (int64_t)blockIdx.x * kParams;
+
+    // output layer: dW4[n][k] = sum_r dz4[r][n] h3[r][k]; db4[n] = sum_r dz4[r][n]
+#pragma unroll 1
+    for (int k0 = 0; k0 < kH; k0 += 32) {
+        f32x16 acc;
+        zero(acc);
+        tile_mma<false, false>(t.dz4, 1, kLdO, t.h[2] + k0, kLdH, 1, 32, acc);
+#pragma unroll
+        for (int i = 0; i < 16; ++i) P[oW4 + acc_row(i) * kH + k0 + acc_col()] = acc[i];
+    }
+    if (lane < kOut) {
+        float s = 0.0f;
+        for (int r = 0; r < 32; ++r) s += from_bf16(t.dz4[r * kLdO + lane]);
+        P[ob4 + lane] = s;
+    }
+    // dz3 = (dz4 W4) * silu'(z3)
+#pragma unroll 1
+    for (int n0 = 0; n0 < kH; n0 += 32) {
+        f32x16 acc;
+        zero(acc);
+        tile_mma<true, false>(t.dz4, kLdO, 1, W4 + n0, kLdH, 1, kOut, acc);
+        const int n = n0 + acc_col();
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int r = acc_row(i);
+            t.dz[0][r * kLdH + n] = to_bf16(acc[i] * dsilu(t.z[2][r * kH + n]));
+        }
+    }
+    __syncthreads();
+    // hidden layers 3, 2, 1
+    const uint16_t *Wl[3] = {W1, W2, W3};
+    const int ldw[3] = {kLdW1, kLdH, kLdH};
+    const int oW[3] = {oW1, oW2, oW3}, ob[3] = {ob1, ob2, ob3};
+    int cur = 0;
+#pragma unroll 1
+    for (int layer = 2; layer >= 0; --layer) {
+        const uint16_t *dzl = t.dz[cur];
+        const uint16_t *in = layer == 0 ? t.x : t.h[layer - 1];
+        const int in_ld = layer == 0 ? kLdX : kLdH;
+        const int in_n = layer == 0 ? kIn : kH; // columns of W_layer
+        // dW[n][k] = sum_r dz[r][n] in[r][k]
+#pragma unroll 1
+        for (int m0 = 0; m0 < kH; m0 += 32) {
+#pragma unroll 1
+            for (int k0 = 0; k0 < in_n; k0 += 32) {
+                f32x16 acc;
+                zero(acc);
+                tile_mma<false, false>(dzl + m0, 1, kLdH, in + k0, in_ld, 1, 32, acc);
+                const int k = k0 + acc_col();
+#pragma unroll
+                for (int i = 0; i < 16; ++i) {
+                    const int n = m0 + acc_row(i);
+                    if (k < in_n) P[oW[layer] + n * in_n + k] = acc[i];
+                }
+            }
+        }
+        {
+            float s = 0.0f; // 64 units, one per lane
+            for (int r = 0; r < 32; ++r) s += from_bf16(dzl[r * kLdH + lane]);
+            P[ob[layer] + lane] = s;
+        }
+        if (layer > 0) {
+            // dz_{layer-1} = (dz W_layer) * silu'(z_{layer-1})
+            uint16_t *dzn = t.dz[cur ^ 1];
+#pragma unroll 1
+            for (int n0 = 0; n0 < kH; n0 += 32) {
+                f32x16 acc;
+                zero(acc);
+                tile_mma<true, false>(dzl, kLdH, 1, Wl[layer] + n0, ldw[layer], 1, kH, acc);
+                const int n = n0 + acc_col();
+#pragma unroll
+                for (int i = 0; i < 16; ++i) {
+                    const int r = acc_row(i);
+                    dzn[r * kLdH + n] = to_bf16(acc[i] * dsilu(t.z[layer - 1][r * kH + n]));
+                }
+            }
+            cur ^= 1;
+        }
+        __syncthreads();
+    }
+    for (int o = 32; o >= 1; o >>= 1) loss += __shfl_xor(loss, o, 64);
+    if (lane == 0) loss_partial[blockIdx.x] = loss;
+}
+
+__device__ __forceinline__ bool mlp_pad(int p, int K)
+{
+    if (p < ob1) return (p - oW1) % kIn >= 5;
+    if (p >= oW4 && p < ob4) return (p - oW4) / kH >= K;
+    if (p >= ob4) return (p - ob4) >= K;
+    return false;
+}
+
+// Sums the per-block gradients in block order (deterministic), applies one
+// Adam step to the float master and refreshes the bf16 copy; pads stay zero.
+__global__ void __launch_bounds__(256) k_mlp_adam(const float *__restrict__ partial, int blocks, int K,
+                                                  float *__restrict__ w, uint16_t *__restrict__ wb,
+                                                  float *__restrict__ m, float *__restrict__ v, int step, float lr,
+                                                  const float *__restrict__ loss_partial, int B,
+                                                  float *__restrict__ loss_out)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p == 0) {
+        float s = 0.0f;
+        for (int b = 0; b < blocks; ++b) s += loss_partial[b];
+        *loss_out = s / (float)B;
+    }
+    if (p >= kParams) return;
+    if (mlp_pad(p, K)) {
+        w[p] = 0.0f;
+        wb[p] = 0;
+        m[p] = 0.0f;
+        v[p] = 0.0f;
+        return;
+    }
+    float g = 0.0f;
+    for (int b = 0; b < blocks; ++b) g += partial[(int64_t)b * kParams + p];
+    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    const float mm = b1 * m[p] + (1.0f - b1) * g;
+    const float vv = b2 * v[p] + (1.0f - b2) * g * g;
+    m[p] = mm;
+    v[p] = vv;
+    const float mh = mm / (1.0f - powf(b1, (float)step));
+    const float vh = vv / (1.0f - powf(b2, (float)step));
+    const float nw = w[p] - lr * mh / (sqrtf(vh) + eps);
+    w[p] = nw;
+    wb[p] = to_bf16(nw);
+}
+
+// Full-batch gradient (block-order sum of the partials) and mean loss.
+__global__ void __launch_bounds__(256) k_mlp_sum(const float *__restrict__ partial, int blocks,
+                                                 const float *__restrict__ loss_partial, int B,
+                                                 float *__restrict__ grad, float *__restrict__ loss_out)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p == 0) {
+        float s = 0.0f;
+        for (int b = 0; b < blocks; ++b) s += loss_partial[b];
+        *loss_out = s / (float)B;
+    }
+    if (p >= kParams) return;
+    float g = 0.0f;
+    for (int b = 0; b < blocks; ++b) g += partial[(int64_t)b * kParams + p];
+    grad[p] = g;
+}
+
+// Zeroes the pad entries of the float master and writes the bf16 copy.
+__global__ void __launch_bounds__(256) k_mlp_prepare(float *__restrict__ w, uint16_t *__restrict__ wb, int K)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= kParams) return;
+    const float v = mlp_pad(p, K) ? 0.0f : w[p];
+    w[p] = v;
+    wb[p] = to_bf16(v);
+}
+
+// ---------------------------------------------------------------------------
+// inference: kInferWaves waves per block share the staged weights; wave w of
+// block b runs tiles (b * waves + w) + it * (grid * waves); every wave of a
+// block runs the same number of iterations (tiles past the end are masked),
+// so the block barriers line up.
+// ---------------------------------------------------------------------------
+struct InferInput {
+    const float *x;   // [B][5] features (src 0), or null
+    glint_gbuffer g;  // G-buffer (src 1)
+};
+
+// Features of a surface pixel: reflection direction and scaled ln alphas.
+__device__ __forceinline__ void pixel_features(const glint_gbuffer &g, int64_t i, float *f)
+{
+    const double nx = g.nx[i], ny = g.ny[i], nz = g.nz[i], vx = g.vx[i], vy = g.vy[i], vz = g.vz[i];
+    const double mu = nx * vx + ny * vy + nz * vz;
+    surrogate_features(2.0 * mu * nx - vx, 2.0 * mu * ny - vy, 2.0 * mu * nz - vz, (double)g.ax[i],
+                       (double)g.ay[i], f);
+}
+
+template <int SRC>
+__global__ void __launch_bounds__(64 * kInferWaves) k_mlp_infer(InferInput in, int64_t B, int K,
+                                                                const float *__restrict__ w,
+                                                                const uint16_t *__restrict__ wb,
+                                                                float *__restrict__ out)
+{
+    __shared__ __attribute__((aligned(16))) uint16_t s_w[kWLds];
+    __shared__ __attribute__((aligned(16))) InferTile s_t[kInferWaves];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    InferTile &t = s_t[wave];
+    stage_weights(wb, s_w);
+    const uint16_t *W1 = s_w + sW1, *W2 = s_w + sW2, *W3 = s_w + sW3, *W4 = s_w + sW4;
+    const int64_t tiles = (B + 31) / 32;
+    const int64_t stride = (int64_t)gridDim.x * kInferWaves;
+    const int64_t first = (int64_t)blockIdx.x * kInferWaves;
+    const int64_t iters = first < tiles ? (tiles - first + stride - 1) / stride : 0;
+    for (int64_t it = 0; it < iters; ++it) {
+        const int64_t row0 = (first + wave + it * stride) * 32;
+        if (lane < 32) {
+            const int64_t i = row0 + lane;
+            float f[5] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+            if (i < B) {
+                if constexpr (SRC == 0) {
+#pragma unroll
+                    for (int c = 0; c < 5; ++c) f[c] = in.x[i * 5 + c];
+                } else {
+                    if (in.g.surf_id[i] != GLINT_NO_SURFACE) pixel_features(in.g, i, f);
+                }
+            }
+            uint16_t *xr = t.x + lane * kLdX;
+#pragma unroll
+            for (int c = 0; c < 16; ++c) xr[c] = c < 5 ? to_bf16(f[c]) : (uint16_t)0;
+        }
+        __syncthreads();
+        dense_silu(t.x, kLdX, kIn, W1, kLdW1, w + ob1, t.h[0], nullptr);
+        __syncthreads();
+        dense_silu(t.h[0], kLdH, kH, W2, kLdH, w + ob2, t.h[1], nullptr);
+        __syncthreads();
+        dense_silu(t.h[1], kLdH, kH, W3, kLdH, w + ob3, t.h[0], nullptr);
+        __syncthreads();
+        float *logit = reinterpret_cast<float *>(t.h[1]);
+        dense_out(t.h[0], W4, w + ob4, logit);
+        __syncthreads();
+        if (lane < 32) {
+            const int64_t i = row0 + lane;
+            if (i < B) {
+                float mx, inv;
+                softmax_stats(logit, lane, K, mx, inv);
+                bool keep = true;
+                if constexpr (SRC == 1) keep = in.g.surf_id[i] != GLINT_NO_SURFACE;
+                for (int k = 0; k < K; ++k) out[i * K + k] = keep ? __expf(logit[lane * kOut + k] - mx) * inv : 0.0f;
+            }
+        }
+    }
+}
+
+int mlp_params() { return kParams; }
+
+static unsigned infer_blocks(int64_t B)
+{
+    const int64_t tiles = (B + 31) / 32;
+    int64_t blocks = (tiles + kInferWaves - 1) / kInferWaves;
+    if (blocks > kInferMaxBlocks) blocks = kInferMaxBlocks;
+    return (unsigned)(blocks < 1 ? 1 : blocks);
+}
+
+hipError_t launch_mlp_prepare(float *w, uint16_t *wb, int K, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_mlp_prepare, dim3((kParams + 255) / 256), dim3(256), 0, stream, w, wb, K);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_grad_step(const float *x, const float *target, int B, int K, float *w, uint16_t *wb,
+                                float *m, float *v, int step, float lr, float *partial, float *loss_partial,
+                                float *loss_out, hipStream_t stream)
+{
+    const int blocks = (B + 31) / 32;
+    hipLaunchKernelGGL(k_mlp_grad, dim3(blocks), dim3(64), 0, stream, x, target, B, K, w, wb, partial, loss_partial);
+    hipLaunchKernelGGL(k_mlp_adam, dim3((kParams + 255) / 256), dim3(256), 0, stream, partial, blocks, K, w, wb, m,
+                       v, step, lr, loss_partial, B, loss_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_gradient(const float *x, const float *target, int B, int K, const float *w,
+                               const uint16_t *wb, float *partial, float *loss_partial, float *grad, float *loss_out,
+                               hipStream_t stream)
+{
+    const int blocks = (B + 31) / 32;
+    hipLaunchKernelGGL(k_mlp_grad, dim3(blocks), dim3(64), 0, stream, x, target, B, K, w, wb, partial, loss_partial);
+    hipLaunchKernelGGL(k_mlp_sum, dim3((kParams + 255) / 256), dim3(256), 0, stream, partial, blocks, loss_partial, B,
+                       grad, loss_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_forward(const float *x, int64_t B, int K, const float *w, const uint16_t *wb, float *probs,
+                              hipStream_t stream)
+{
+    InferInput in{};
+    in.x = x;
+    hipLaunchKernelGGL(k_mlp_infer<0>, dim3(infer_blocks(B)), dim3(64 * kInferWaves), 0, stream, in, B, K, w, wb,
+                       probs);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_lookup(const glint_gbuffer &g, int64_t P, int K, const float *w, const uint16_t *wb, float *F,
+                             hipStream_t stream)
+{
+    InferInput in{};
+    in.g = g;
+    hipLaunchKernelGGL(k_mlp_infer<1>, dim3(infer_blocks(P)), dim3(64 * kInferWaves), 0, stream, in, P, K, w, wb,
+                       F);
+    return hipGetLastError();
+}
+
+} // namespace glint

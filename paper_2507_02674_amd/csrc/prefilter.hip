@@ -337,10 +337,8 @@ struct FilterLaunch {
     int xcd_chunk;          // logical blocks per XCD (grid = 8 * xcd_chunk)
 };
 
-__device__ __forceinline__ void make_tap(int j, int m, int M, int T, int R, Tap &tp)
+__device__ __forceinline__ void make_tap_alpha(int j, double alpha, int M, int T, int R, Tap &tp)
 {
-    const double a = (double)m / (double)(M - 1);
-    const double alpha = a * a;
     const double a2 = alpha * alpha;
     const double uphi = (double)j / (double)T;
     const double uth = radical_inverse((uint32_t)j);
@@ -360,6 +358,77 @@ __device__ __forceinline__ void make_tap(int j, int m, int M, int T, int R, Tap 
     double lod = 0.5 * log2(omega_s / omega_p) + 1.0;
     lod = lod < 0.0 ? 0.0 : (lod > (double)(M - 1) ? (double)(M - 1) : lod);
     tp.lod = lod;
+}
+
+// Tap j of mip m (roughness (m/(M-1))^2).
+__device__ __forceinline__ void make_tap(int j, int m, int M, int T, int R, Tap &tp)
+{
+    const double a = (double)m / (double)(M - 1);
+    make_tap_alpha(j, a * a, M, T, R, tp);
+}
+
+// Orthonormal basis around the unit direction r (Duff et al. 2017).
+__device__ __forceinline__ void onb(const d3 &r, d3 &t1, d3 &t2)
+{
+    const double sgn = copysign(1.0, r.z);
+    const double ea = -1.0 / (sgn + r.z);
+    const double eb = r.x * r.y * ea;
+    t1 = {1.0 + sgn * r.x * r.x * ea, sgn * eb, -sgn * r.x};
+    t2 = {eb, sgn + r.y * r.y * ea, -r.y};
+}
+
+// acc += W_j * (trilinear chain lookup at the tap's mirror direction, lod_j).
+template <int K>
+__device__ __forceinline__ void accumulate_tap(const Tap &tp, const d3 &r, const d3 &t1, const d3 &t2, int R,
+                                               const Level0<K> &l0, const float *__restrict__ chain,
+                                               const int64_t *lvl_off, double (&acc)[K + 3])
+{
+    constexpr int C = K + 3, CP = chain_stride(K);
+    const d3 h = {tp.hx * t1.x + tp.hy * t2.x + tp.hz * r.x, tp.hx * t1.y + tp.hy * t2.y + tp.hz * r.y,
+                  tp.hx * t1.z + tp.hy * t2.z + tp.hz * r.z};
+    const d3 l = {2.0 * tp.hz * h.x - r.x, 2.0 * tp.hz * h.y - r.y, 2.0 * tp.hz * h.z - r.z};
+    const face_st fs = locate(l);
+    const double l0f = floor(tp.lod);
+    const int s0 = (int)l0f;
+    const double fr = tp.lod - l0f;
+    const int nlev = fr > 0.0 ? 2 : 1; // fr > 0 implies s0 + 1 <= M - 1
+#pragma unroll 1
+    for (int li = 0; li < nlev; ++li) {
+        const int s = s0 + li;
+        const int ns = R >> s;
+        const bilin bl = bilinear_at(fs, ns);
+        const double lw = tp.w * (li ? fr : 1.0 - fr);
+        const double w4[4] = {lw * ((1.0 - bl.fy) * (1.0 - bl.fx)), lw * ((1.0 - bl.fy) * bl.fx),
+                              lw * (bl.fy * (1.0 - bl.fx)), lw * (bl.fy * bl.fx)};
+        const float *lvl = chain + lvl_off[s]; // global pointer arithmetic: global loads
+        if (bl.x0 >= 0 && bl.x0 + 1 < ns && bl.y0 >= 0 && bl.y0 + 1 < ns) {
+            // footprint inside the face: four loads in flight
+            const int64_t t0 = ((int64_t)fs.face * ns + bl.y0) * ns + bl.x0;
+            const int64_t tt[4] = {t0, t0 + 1, t0 + ns, t0 + ns + 1};
+            if (s == 0) {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) l0.add(tt[c], w4[c], acc);
+            } else {
+                float4 raw[4][CP / 4];
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+#pragma unroll
+                    for (int q4 = 0; q4 < CP / 4; ++q4) raw[c][q4] = reinterpret_cast<const float4 *>(lvl + tt[c] * CP)[q4];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const float *f = reinterpret_cast<const float *>(raw[c]);
+#pragma unroll
+                    for (int k = 0; k < C; ++k) acc[k] += w4[c] * (double)f[k];
+                }
+            }
+        } else {
+            // across a seam: one copy of the seam rule
+#pragma unroll 1
+            for (int c = 0; c < 4; ++c)
+                accumulate_texel<K>(l0, lvl, s, fs.face, bl.x0 + (c & 1), bl.y0 + (c >> 1), ns,
+                                    c == 0 ? w4[0] : (c == 1 ? w4[1] : (c == 2 ? w4[2] : w4[3])), acc);
+        }
+    }
 }
 
 template <int K, int DT>
@@ -409,63 +478,13 @@ __global__ void __launch_bounds__(kFilterThreads) k_prefilter(FilterLaunch fl, L
         d3 r = face_dir(f, 2.0 * ((double)x + 0.5) * inv - 1.0, 2.0 * ((double)y + 0.5) * inv - 1.0);
         const double len = sqrt(r.x * r.x + r.y * r.y + r.z * r.z);
         r.x /= len; r.y /= len; r.z /= len;
-        // orthonormal basis around r (Duff et al. 2017)
-        const double sgn = copysign(1.0, r.z);
-        const double ea = -1.0 / (sgn + r.z);
-        const double eb = r.x * r.y * ea;
-        const d3 t1 = {1.0 + sgn * r.x * r.x * ea, sgn * eb, -sgn * r.x};
-        const d3 t2 = {eb, sgn + r.y * r.y * ea, -r.y};
-
+        d3 t1, t2;
+        onb(r, t1, t2);
 #pragma unroll 1
         for (int j = sub; j < fl.T; j += kGroup) {
             const Tap tp = s_taps[j];
             if (!(tp.w > 0.0)) continue;
-            const d3 h = {tp.hx * t1.x + tp.hy * t2.x + tp.hz * r.x, tp.hx * t1.y + tp.hy * t2.y + tp.hz * r.y,
-                          tp.hx * t1.z + tp.hy * t2.z + tp.hz * r.z};
-            const d3 l = {2.0 * tp.hz * h.x - r.x, 2.0 * tp.hz * h.y - r.y, 2.0 * tp.hz * h.z - r.z};
-            const face_st fs = locate(l);
-            const double l0f = floor(tp.lod);
-            const int s0 = (int)l0f;
-            const double fr = tp.lod - l0f;
-            const int nlev = fr > 0.0 ? 2 : 1; // fr > 0 implies s0 + 1 <= M - 1
-#pragma unroll 1
-            for (int li = 0; li < nlev; ++li) {
-                const int s = s0 + li;
-                const int ns = fl.R >> s;
-                const bilin bl = bilinear_at(fs, ns);
-                const double lw = tp.w * (li ? fr : 1.0 - fr);
-                const double w4[4] = {lw * ((1.0 - bl.fy) * (1.0 - bl.fx)), lw * ((1.0 - bl.fy) * bl.fx),
-                                      lw * (bl.fy * (1.0 - bl.fx)), lw * (bl.fy * bl.fx)};
-                const float *lvl = chain + s_lvl[s]; // global pointer arithmetic: global loads
-                if (bl.x0 >= 0 && bl.x0 + 1 < ns && bl.y0 >= 0 && bl.y0 + 1 < ns) {
-                    // footprint inside the face: four loads in flight
-                    const int64_t t0 = ((int64_t)fs.face * ns + bl.y0) * ns + bl.x0;
-                    const int64_t tt[4] = {t0, t0 + 1, t0 + ns, t0 + ns + 1};
-                    if (s == 0) {
-#pragma unroll
-                        for (int c = 0; c < 4; ++c) l0.add(tt[c], w4[c], acc);
-                    } else {
-                        float4 raw[4][CP / 4];
-#pragma unroll
-                        for (int c = 0; c < 4; ++c)
-#pragma unroll
-                            for (int q4 = 0; q4 < CP / 4; ++q4)
-                                raw[c][q4] = reinterpret_cast<const float4 *>(lvl + tt[c] * CP)[q4];
-#pragma unroll
-                        for (int c = 0; c < 4; ++c) {
-                            const float *f = reinterpret_cast<const float *>(raw[c]);
-#pragma unroll
-                            for (int k = 0; k < C; ++k) acc[k] += w4[c] * (double)f[k];
-                        }
-                    }
-                } else {
-                    // across a seam: one copy of the seam rule
-#pragma unroll 1
-                    for (int c = 0; c < 4; ++c)
-                        accumulate_texel<K>(l0, lvl, s, fs.face, bl.x0 + (c & 1), bl.y0 + (c >> 1), ns,
-                                            c == 0 ? w4[0] : (c == 1 ? w4[1] : (c == 2 ? w4[2] : w4[3])), acc);
-                }
-            }
+            accumulate_tap<K>(tp, r, t1, t2, fl.R, l0, chain, s_lvl, acc);
         }
     }
     // reduce over the group's lanes
@@ -482,6 +501,98 @@ __global__ void __launch_bounds__(kFilterThreads) k_prefilter(FilterLaunch fl, L
         reinterpret_cast<float4 *>(rgb_pyr)[out] =
             make_float4((float)(acc[K] / ws), (float)(acc[K + 1] / ws), (float)(acc[K + 2] / ws), 0.0f);
     }
+}
+
+// The filter at arbitrary (direction, alpha): the mip quadrature with the
+// tap table built per sample (8 lanes per sample; the weight sum is reduced
+// across the group).
+//   MODE 0: a0 = alpha [n]; out0 = filtered values [n][K+3].
+//   MODE 1: a0 = alpha_x, a1 = alpha_y [n], filtered at sqrt(alpha_x alpha_y);
+//           out0 = surrogate inputs [n][5], out1 = F_k / sum F [n][K].
+template <int K, int MODE>
+__global__ void __launch_bounds__(kFilterThreads) k_sample_filter(int R, int M, int T, Level0<K> l0,
+                                                                   const float *__restrict__ chain,
+                                                                   const float *__restrict__ dirs,
+                                                                   const float *__restrict__ a0,
+                                                                   const float *__restrict__ a1, int64_t n,
+                                                                   float *__restrict__ out0,
+                                                                   float *__restrict__ out1)
+{
+    constexpr int C = K + 3, CP = chain_stride(K);
+    __shared__ int64_t s_lvl[16];
+    if (threadIdx.x < M) s_lvl[threadIdx.x] = threadIdx.x == 0 ? 0 : (level_offset(R, threadIdx.x) - 6LL * R * R) * CP;
+    __syncthreads();
+    const int64_t q = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kGroup;
+    const int sub = threadIdx.x % kGroup;
+    const bool active = q < n;
+    double acc[C];
+#pragma unroll
+    for (int k = 0; k < C; ++k) acc[k] = 0.0;
+    double wsum = 0.0;
+    d3 r = {0.0, 0.0, 1.0};
+    if (active) {
+        r = {(double)dirs[3 * q], (double)dirs[3 * q + 1], (double)dirs[3 * q + 2]};
+        const double len = sqrt(r.x * r.x + r.y * r.y + r.z * r.z);
+        const d3 u = {r.x / len, r.y / len, r.z / len};
+        d3 t1, t2;
+        onb(u, t1, t2);
+        const double alpha = MODE == 0 ? (double)a0[q] : sqrt((double)a0[q] * (double)a1[q]);
+#pragma unroll 1
+        for (int j = sub; j < T; j += kGroup) {
+            Tap tp;
+            make_tap_alpha(j, alpha, M, T, R, tp);
+            if (!(tp.w > 0.0)) continue;
+            wsum += tp.w;
+            accumulate_tap<K>(tp, u, t1, t2, R, l0, chain, s_lvl, acc);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+#pragma unroll
+        for (int o = kGroup / 2; o >= 1; o >>= 1) acc[k] += __shfl_xor(acc[k], o, kGroup);
+    }
+    for (int o = kGroup / 2; o >= 1; o >>= 1) wsum += __shfl_xor(wsum, o, kGroup);
+    if (!active || sub != 0) return;
+    if constexpr (MODE == 0) {
+#pragma unroll
+        for (int k = 0; k < C; ++k) out0[q * C + k] = (float)(acc[k] / wsum);
+    } else {
+        const double len = sqrt(r.x * r.x + r.y * r.y + r.z * r.z);
+        float f[5];
+        surrogate_features(r.x / len, r.y / len, r.z / len, (double)a0[q], (double)a1[q], f);
+#pragma unroll
+        for (int c = 0; c < 5; ++c) out0[q * 5 + c] = f[c];
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) s += acc[k];
+#pragma unroll
+        for (int k = 0; k < K; ++k) out1[q * K + k] = s > 0.0 ? (float)(acc[k] / s) : 1.0f / (float)K;
+    }
+}
+
+hipError_t launch_sample_filter(const float *env, const uint8_t *ind_j, const float *ind_t, const void *workspace,
+                                int R, int K, int M, int T, int mode, const float *dirs, const float *a0,
+                                const float *a1, int64_t n, float *out0, float *out1, hipStream_t stream)
+{
+    const float *chain = static_cast<const float *>(workspace);
+    const unsigned blocks = (unsigned)((n * kGroup + kFilterThreads - 1) / kFilterThreads);
+#define GLINT_SF(KK)                                                                                          \
+    if (K == KK) {                                                                                            \
+        Level0<KK> l0{env, ind_j, ind_t};                                                                     \
+        if (mode == 0)                                                                                        \
+            hipLaunchKernelGGL((k_sample_filter<KK, 0>), dim3(blocks), dim3(kFilterThreads), 0, stream, R, M, \
+                               T, l0, chain, dirs, a0, a1, n, out0, out1);                                    \
+        else                                                                                                  \
+            hipLaunchKernelGGL((k_sample_filter<KK, 1>), dim3(blocks), dim3(kFilterThreads), 0, stream, R, M, \
+                               T, l0, chain, dirs, a0, a1, n, out0, out1);                                    \
+        return hipGetLastError();                                                                             \
+    }
+    GLINT_SF(2)
+    GLINT_SF(4)
+    GLINT_SF(8)
+    GLINT_SF(16)
+#undef GLINT_SF
+    return hipErrorInvalidValue;
 }
 
 size_t chain_bytes(int R, int K, int M)

@@ -127,6 +127,7 @@ struct ShadeArgs {
     double *counts;
     uint8_t *codes;
     double *probs;
+    const float *F; // surrogate form: filtered indicator values [P][K] (else null)
 };
 
 // One dual-gated Gaussian draw (Alg. "Dual-gated Gaussian").
@@ -214,10 +215,13 @@ __device__ __forceinline__ void multinomial(double NP, const double (&p)[K], uin
     for (int k = 0; k < K; ++k) leaf[k] = Q[k];
 }
 
-// Shades pixel i of the view described by A (all of rows b1-b5).
-template <int K, int DT, int V>
+// Shades pixel i of the view described by A (all of rows b1-b5).  SURR: the
+// K filtered indicator values come from A.F (a learned surrogate's output)
+// and only RGB is read from the pyramid.
+template <int K, int DT, int V, bool SURR = false>
 __device__ __forceinline__ void shade_pixel(const ShadeArgs &A, int64_t i)
 {
+    constexpr int KL = SURR ? 0 : K; // indicator channels read from the pyramid
     const uint32_t surf = A.g.surf_id[i];
     if (surf == GLINT_NO_SURFACE) {
         A.radiance[3 * i] = 0.0f; A.radiance[3 * i + 1] = 0.0f; A.radiance[3 * i + 2] = 0.0f;
@@ -242,9 +246,9 @@ __device__ __forceinline__ void shade_pixel(const ShadeArgs &A, int64_t i)
     const int s0 = (int)l0f;
     const int s1 = s0 + 1 < A.M ? s0 + 1 : A.M - 1;
     const double fr = lod - l0f;
-    double acc[K + 3];
+    double acc[KL + 3];
 #pragma unroll
-    for (int k = 0; k < K + 3; ++k) acc[k] = 0.0;
+    for (int k = 0; k < KL + 3; ++k) acc[k] = 0.0;
     const face_st fs = locate(wr);
     const int nlev = fr > 0.0 ? 2 : 1;
 #pragma unroll 1
@@ -260,23 +264,30 @@ __device__ __forceinline__ void shade_pixel(const ShadeArgs &A, int64_t i)
             // footprint inside the face: four loads in flight
             const int64_t t0 = base + ((int64_t)fs.face * ns + bl.y0) * ns + bl.x0;
             const int64_t tt[4] = {t0, t0 + 1, t0 + ns, t0 + ns + 1};
-            double v[4][K + 3];
+            double v[4][KL + 3];
 #pragma unroll
-            for (int c = 0; c < 4; ++c) load_texel<K, DT>(A.ind_pyr, A.rgb_pyr, tt[c], v[c]);
+            for (int c = 0; c < 4; ++c) load_texel<KL, DT>(A.ind_pyr, A.rgb_pyr, tt[c], v[c]);
 #pragma unroll
             for (int c = 0; c < 4; ++c)
 #pragma unroll
-                for (int k = 0; k < K + 3; ++k) acc[k] += w4[c] * v[c][k];
+                for (int k = 0; k < KL + 3; ++k) acc[k] += w4[c] * v[c][k];
         } else {
             // across a seam: one copy of the seam rule
 #pragma unroll 1
             for (int c = 0; c < 4; ++c)
-                accumulate_pyr<K, DT>(A.ind_pyr, A.rgb_pyr, base, fs.face, bl.x0 + (c & 1), bl.y0 + (c >> 1), ns,
-                                      c == 0 ? w4[0] : (c == 1 ? w4[1] : (c == 2 ? w4[2] : w4[3])), acc);
+                accumulate_pyr<KL, DT>(A.ind_pyr, A.rgb_pyr, base, fs.face, bl.x0 + (c & 1), bl.y0 + (c >> 1), ns,
+                                       c == 0 ? w4[0] : (c == 1 ? w4[1] : (c == 2 ? w4[2] : w4[3])), acc);
         }
     }
-    const double *F = acc;
-    const double rgb[3] = {acc[K], acc[K + 1], acc[K + 2]};
+    double F[K];
+    if constexpr (SURR) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) F[k] = (double)A.F[i * K + k];
+    } else {
+#pragma unroll
+        for (int k = 0; k < K; ++k) F[k] = acc[k];
+    }
+    const double rgb[3] = {acc[KL], acc[KL + 1], acc[KL + 2]};
 
     // Sec. 4 Eq. (probhk) with Sec. 5 Eq. (rtiblndf)
     double sumF = 0.0;
@@ -366,12 +377,12 @@ __device__ __forceinline__ void shade_pixel(const ShadeArgs &A, int64_t i)
     for (int c = 0; c < 3; ++c) A.radiance[3 * i + c] = (float)((f0[c] * EA + EB) * rgb[c] * gmod);
 }
 
-template <int K, int DT, int V>
+template <int K, int DT, int V, bool SURR = false>
 __global__ void __launch_bounds__(kShadeThreads) k_shade(ShadeArgs A)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= A.P) return;
-    shade_pixel<K, DT, V>(A, i);
+    shade_pixel<K, DT, V, SURR>(A, i);
 }
 
 // All views of one (K, V) group in one launch: block b shades tile b of the
@@ -425,6 +436,7 @@ void make_shade_args(void *out, const glint_gbuffer &g, int64_t P, const glint_e
     a.counts = nullptr;
     a.codes = nullptr;
     a.probs = nullptr;
+    a.F = nullptr;
     *static_cast<ShadeArgs *>(out) = a;
 }
 
@@ -450,7 +462,7 @@ hipError_t launch_shade_views(int K, int dtype, int V, const void *views, const 
 }
 
 hipError_t launch_shade(const glint_gbuffer &g, int64_t P, const glint_env &env, const glint_shade_params &sp,
-                        float *radiance, const glint_shade_debug *dbg, hipStream_t stream)
+                        const float *F, float *radiance, const glint_shade_debug *dbg, hipStream_t stream)
 {
     ShadeArgs a;
     a.g = g;
@@ -467,7 +479,24 @@ hipError_t launch_shade(const glint_gbuffer &g, int64_t P, const glint_env &env,
     a.counts = dbg ? dbg->counts : nullptr;
     a.codes = dbg ? dbg->codes : nullptr;
     a.probs = dbg ? dbg->probs : nullptr;
+    a.F = F;
     const int K = env.K, DT = (int)env.dtype, V = sp.vertices;
+    if (F) {
+        // surrogate form: the indicator pyramid is not read, so its storage type does not matter
+        const unsigned blocks = (unsigned)((P + kShadeThreads - 1) / kShadeThreads);
+#define GLINT_SF(KK)                                                                                              \
+    if (K == KK) {                                                                                                \
+        if (V == 1) hipLaunchKernelGGL((k_shade<KK, 0, 1, true>), dim3(blocks), dim3(kShadeThreads), 0, stream, a); \
+        else hipLaunchKernelGGL((k_shade<KK, 0, 6, true>), dim3(blocks), dim3(kShadeThreads), 0, stream, a);        \
+        return hipGetLastError();                                                                                 \
+    }
+        GLINT_SF(2)
+        GLINT_SF(4)
+        GLINT_SF(8)
+        GLINT_SF(16)
+#undef GLINT_SF
+        return hipErrorInvalidValue;
+    }
 #define GLINT_SH(KK, DD)                                                                                     \
     if (K == KK && DT == DD) return launch_shade_kd<KK, DD>(a, V, stream);
 #define GLINT_SH_K(KK) GLINT_SH(KK, 0) GLINT_SH(KK, 1) GLINT_SH(KK, 2) GLINT_SH(KK, 3)

@@ -83,6 +83,26 @@ EXPORTS = {
     "glint_build_luts": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     "glint_shade": ([C.c_void_p, C.POINTER(GBuffer), C.c_int64, C.POINTER(Env), C.POINTER(ShadeParams),
                      C.c_void_p, C.POINTER(ShadeDebug), C.c_void_p], C.c_int),
+    "glint_sample_filter": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_int,
+                             C.POINTER(PrefilterParams), C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,
+                             C.c_void_p], C.c_int),
+    "glint_surrogate_samples": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_int,
+                                 C.POINTER(PrefilterParams), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                 C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
+    "glint_surrogate_params": ([], C.c_int),
+    "glint_surrogate_workspace_bytes": ([C.c_int], C.c_size_t),
+    "glint_surrogate_prepare": ([C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
+    "glint_surrogate_forward": ([C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,
+                                 C.c_void_p], C.c_int),
+    "glint_surrogate_gradient": ([C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int,
+                                  C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
+    "glint_surrogate_train_step": ([C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int,
+                                    C.c_float, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p,
+                                    C.c_void_p], C.c_int),
+    "glint_shade_surrogate_workspace_bytes": ([C.c_int64, C.c_int], C.c_size_t),
+    "glint_shade_surrogate": ([C.c_void_p, C.POINTER(GBuffer), C.c_int64, C.POINTER(Env), C.c_void_p, C.c_void_p,
+                               C.POINTER(ShadeParams), C.c_void_p, C.c_void_p, C.POINTER(ShadeDebug), C.c_void_p],
+                              C.c_int),
     "glint_batched_workspace_bytes": ([C.c_int], C.c_size_t),
     "glint_frame_batched": ([C.c_void_p, C.POINTER(EnvTask), C.c_int, C.POINTER(View), C.c_int, C.c_void_p,
                              C.c_void_p], C.c_int),
@@ -208,6 +228,77 @@ def glint_shade(ctx, gbuf: GBuffer, num_pixels: int, env: Env, params: ShadePara
                            for k in ("counts", "codes", "probs")])
     _check(lib().glint_shade(ctx, C.byref(gbuf), num_pixels, C.byref(env), C.byref(params), _ptr(radiance),
                              C.byref(dbg) if dbg is not None else None, _stream(stream)))
+
+
+def _debug(debug):
+    if debug is None:
+        return None
+    _require_cuda(*[t for t in debug.values() if t is not None])
+    return ShadeDebug(*[debug.get(k).data_ptr() if debug.get(k) is not None else None
+                        for k in ("counts", "codes", "probs")])
+
+
+def glint_sample_filter(ctx, env, ind_j, ind_t, R, K, params: PrefilterParams, workspace, dirs, alphas, out,
+                        stream=None):
+    _require_cuda(env, ind_j, ind_t, workspace, dirs, alphas, out)
+    n = int(alphas.numel())
+    _check(lib().glint_sample_filter(ctx, _ptr(env), _ptr(ind_j), _ptr(ind_t), R, K, C.byref(params),
+                                     _ptr(workspace), _ptr(dirs), _ptr(alphas), n, _ptr(out), _stream(stream)))
+
+
+def glint_surrogate_samples(ctx, env, ind_j, ind_t, R, K, params: PrefilterParams, workspace, dirs, ax, ay, x,
+                            target, stream=None):
+    _require_cuda(env, ind_j, ind_t, workspace, dirs, ax, ay, x, target)
+    n = int(ax.numel())
+    _check(lib().glint_surrogate_samples(ctx, _ptr(env), _ptr(ind_j), _ptr(ind_t), R, K, C.byref(params),
+                                         _ptr(workspace), _ptr(dirs), _ptr(ax), _ptr(ay), n, _ptr(x), _ptr(target),
+                                         _stream(stream)))
+
+
+def glint_surrogate_params() -> int:
+    return lib().glint_surrogate_params()
+
+
+def glint_surrogate_workspace_bytes(batch: int) -> int:
+    return lib().glint_surrogate_workspace_bytes(batch)
+
+
+def glint_surrogate_prepare(ctx, K, w, w_bf16, stream=None):
+    _require_cuda(w, w_bf16)
+    _check(lib().glint_surrogate_prepare(ctx, K, _ptr(w), _ptr(w_bf16), _stream(stream)))
+
+
+def glint_surrogate_forward(ctx, K, w, w_bf16, x, probs, stream=None):
+    _require_cuda(w, w_bf16, x, probs)
+    B = int(x.shape[0])
+    _check(lib().glint_surrogate_forward(ctx, K, _ptr(w), _ptr(w_bf16), _ptr(x), B, _ptr(probs), _stream(stream)))
+
+
+def glint_surrogate_gradient(ctx, K, w, w_bf16, x, target, workspace, grad, loss, stream=None):
+    _require_cuda(w, w_bf16, x, target, workspace, grad, loss)
+    B = int(x.shape[0])
+    _check(lib().glint_surrogate_gradient(ctx, K, _ptr(w), _ptr(w_bf16), _ptr(x), _ptr(target), B, _ptr(workspace),
+                                          _ptr(grad), _ptr(loss), _stream(stream)))
+
+
+def glint_surrogate_train_step(ctx, K, w, w_bf16, m, v, step, lr, x, target, workspace, loss, stream=None):
+    _require_cuda(w, w_bf16, m, v, x, target, workspace, loss)
+    B = int(x.shape[0])
+    _check(lib().glint_surrogate_train_step(ctx, K, _ptr(w), _ptr(w_bf16), _ptr(m), _ptr(v), step, lr, _ptr(x),
+                                            _ptr(target), B, _ptr(workspace), _ptr(loss), _stream(stream)))
+
+
+def glint_shade_surrogate_workspace_bytes(num_pixels: int, K: int) -> int:
+    return lib().glint_shade_surrogate_workspace_bytes(num_pixels, K)
+
+
+def glint_shade_surrogate(ctx, gbuf: GBuffer, num_pixels: int, env: Env, w, w_bf16, params: ShadeParams, workspace,
+                          radiance, debug=None, stream=None):
+    _require_cuda(w, w_bf16, workspace, radiance)
+    dbg = _debug(debug)
+    _check(lib().glint_shade_surrogate(ctx, C.byref(gbuf), num_pixels, C.byref(env), _ptr(w), _ptr(w_bf16),
+                                       C.byref(params), _ptr(workspace), _ptr(radiance),
+                                       C.byref(dbg) if dbg is not None else None, _stream(stream)))
 
 
 def glint_batched_workspace_bytes(n_views: int) -> int:

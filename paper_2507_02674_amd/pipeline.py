@@ -6,6 +6,8 @@ construction so a frame enqueues kernels only.
 """
 from __future__ import annotations
 
+import math
+
 import torch
 
 from . import glint as G
@@ -113,3 +115,156 @@ class BatchedFrame:
 
     def run(self, stream=None):
         G.glint_frame_batched(self.ctx, self.tasks, self.view_structs, self.ws, stream)
+
+
+class Surrogate:
+    """Parameters of the learned surrogate for one environment (float32 master,
+    bfloat16 copy, Adam moments) and its training loop.
+
+    The network's layout is the C ABI's padded one (glint_surrogate_params()
+    entries).  Training data come from the plain filter through
+    glint_surrogate_samples; every step runs in the library's kernels."""
+
+    HIDDEN, IN_PAD, OUT_PAD = 64, 16, 32
+    LN_LO, LN_HI = math.log(0.02), math.log(0.5)
+
+    def __init__(self, ctx, K, device="cuda"):
+        self.ctx, self.K, self.device = ctx, K, device
+        self.n = G.glint_surrogate_params()
+        self.w = torch.zeros(self.n, dtype=torch.float32, device=device)
+        self.wb = torch.zeros(self.n, dtype=torch.int16, device=device)
+        self.m = torch.zeros_like(self.w)
+        self.v = torch.zeros_like(self.w)
+        self.step = 0
+        self.loss = torch.zeros(1, dtype=torch.float32, device=device)
+        self.ws = None
+        self.ws_batch = 0
+
+    # layout: W1 [64][16], b1, W2 [64][64], b2, W3 [64][64], b3, W4 [32][64], b4 [32]
+    def offsets(self):
+        H, I, O = self.HIDDEN, self.IN_PAD, self.OUT_PAD
+        off, o = {}, 0
+        for name, n in (("W1", H * I), ("b1", H), ("W2", H * H), ("b2", H), ("W3", H * H), ("b3", H),
+                        ("W4", O * H), ("b4", O)):
+            off[name] = (o, n)
+            o += n
+        return off
+
+    def init(self, seed=7):
+        """He-uniform weights (seeded, drawn on the host), zero biases."""
+        gen = torch.Generator().manual_seed(seed)
+        H, I, O, K = self.HIDDEN, self.IN_PAD, self.OUT_PAD, self.K
+        host = torch.zeros(self.n, dtype=torch.float32)
+        off = self.offsets()
+        for name, (rows, fan_in, ld) in (("W1", (H, 5, I)), ("W2", (H, H, H)), ("W3", (H, H, H)),
+                                         ("W4", (K, H, H))):
+            lim = math.sqrt(6.0 / fan_in)
+            wmat = (torch.rand((rows, fan_in), generator=gen, dtype=torch.float64) * 2.0 - 1.0) * lim
+            o = off[name][0]
+            view = host[o:o + off[name][1]].view(-1, ld)
+            view[:rows, :fan_in] = wmat.float()
+        self.load(host)
+
+    def load(self, host_w):
+        self.w.copy_(torch.as_tensor(host_w, dtype=torch.float32).reshape(-1))
+        self.m.zero_()
+        self.v.zero_()
+        self.step = 0
+        G.glint_surrogate_prepare(self.ctx, self.K, self.w, self.wb)
+
+    def _workspace(self, batch):
+        if self.ws is None or self.ws_batch < batch:
+            nbytes = G.glint_surrogate_workspace_bytes(batch)
+            self.ws = torch.empty(nbytes // 4 + 64, dtype=torch.float32, device=self.device)
+            self.ws_batch = batch
+        return self.ws
+
+    def forward(self, x, probs=None):
+        if probs is None:
+            probs = torch.empty((x.shape[0], self.K), dtype=torch.float32, device=self.device)
+        G.glint_surrogate_forward(self.ctx, self.K, self.w, self.wb, x, probs)
+        return probs
+
+    def gradient(self, x, target):
+        grad = torch.empty(self.n, dtype=torch.float32, device=self.device)
+        G.glint_surrogate_gradient(self.ctx, self.K, self.w, self.wb, x, target, self._workspace(x.shape[0]), grad,
+                                   self.loss)
+        return grad, self.loss
+
+    def train_step(self, x, target, lr):
+        self.step += 1
+        G.glint_surrogate_train_step(self.ctx, self.K, self.w, self.wb, self.m, self.v, self.step, lr, x, target,
+                                     self._workspace(x.shape[0]), self.loss)
+        return self.loss
+
+    @staticmethod
+    def draw_lookups(n, seed, device="cuda"):
+        """Random lookups: directions uniform on the sphere, ln alpha_x and
+        ln alpha_y independently uniform on [ln 0.02, ln 0.5] (host-seeded)."""
+        gen = torch.Generator().manual_seed(seed)
+        d = torch.randn((n, 3), generator=gen, dtype=torch.float64)
+        d = d / d.norm(dim=1, keepdim=True)
+        la = torch.rand((n, 2), generator=gen, dtype=torch.float64) * (Surrogate.LN_HI - Surrogate.LN_LO) + \
+            Surrogate.LN_LO
+        a = la.exp()
+        return (d.float().contiguous().to(device), a[:, 0].float().contiguous().to(device),
+                a[:, 1].float().contiguous().to(device))
+
+    def samples(self, pipe, env, n, seed):
+        """Training pairs (x [n][5], target [n][K]) from the plain filter of pipe."""
+        dirs, ax, ay = self.draw_lookups(n, seed, self.device)
+        x = torch.empty((n, 5), dtype=torch.float32, device=self.device)
+        t = torch.empty((n, self.K), dtype=torch.float32, device=self.device)
+        G.glint_surrogate_samples(self.ctx, env, pipe.ind_j, pipe.ind_t, pipe.R, pipe.K, pipe.fp, pipe.filt_ws, dirs,
+                                  ax, ay, x, t)
+        return x, t
+
+    def fit(self, x, t, epochs=1, batch=4096, lr=1e-3, lr_min=1e-5, seed=7, log_every=0, steps=None):
+        """Adam over shuffled mini-batches with a cosine learning-rate
+        schedule; returns the list of (step, loss) read back every
+        log_every steps (the device loss is read only then)."""
+        n = x.shape[0]
+        per_epoch = max(1, n // batch)
+        total = steps if steps is not None else epochs * per_epoch
+        gen = torch.Generator().manual_seed(seed)
+        curve = []
+        s = 0
+        while s < total:
+            perm = torch.randperm(n, generator=gen).to(self.device)
+            xs, ts = x.index_select(0, perm), t.index_select(0, perm)
+            for b in range(per_epoch):
+                if s >= total:
+                    break
+                lr_s = lr_min + 0.5 * (lr - lr_min) * (1.0 + math.cos(math.pi * s / max(1, total)))
+                self.train_step(xs[b * batch:(b + 1) * batch], ts[b * batch:(b + 1) * batch], lr_s)
+                s += 1
+                if log_every and (s % log_every == 0 or s == total):
+                    curve.append((s, float(self.loss.item())))
+        return curve
+
+    def state(self):
+        """Host copy of (w, m, v, step) for checkpoints."""
+        return dict(w=self.w.cpu(), m=self.m.cpu(), v=self.v.cpu(), step=self.step, K=self.K)
+
+    def restore(self, st):
+        if int(st["K"]) != self.K:
+            raise ValueError("checkpoint K does not match")
+        self.w.copy_(st["w"])
+        self.m.copy_(st["m"])
+        self.v.copy_(st["v"])
+        self.step = int(st["step"])
+        G.glint_surrogate_prepare(self.ctx, self.K, self.w, self.wb)
+
+
+class SurrogateShader(Shader):
+    """Shading with the surrogate in place of the indicator pyramid lookup."""
+
+    def __init__(self, ctx, gbuf: dict, surrogate: Surrogate, seed=1, vertices=1, device="cuda"):
+        super().__init__(ctx, gbuf, seed=seed, vertices=vertices, device=device)
+        self.sur = surrogate
+        nbytes = G.glint_shade_surrogate_workspace_bytes(self.P, surrogate.K)
+        self.F = torch.empty(nbytes // 4, dtype=torch.float32, device=device)
+
+    def run(self, env: G.Env, stream=None, debug=None):
+        G.glint_shade_surrogate(self.ctx, self.gb, self.P, env, self.sur.w, self.sur.wb, self.sp, self.F,
+                                self.radiance, debug, stream)

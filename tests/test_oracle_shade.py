@@ -182,3 +182,31 @@ def test_explicit_microfacets_agree_with_method():
     out = oracle.shade(g, ind, rgb, levels, S_lut, E_lut, R, K, M, seed=1)
     p = out["probs"][0]
     assert np.abs(emp - p).max() < 0.06, (emp, p)
+
+
+def test_given_F_path_equals_pyramid_path_and_is_scale_free():
+    """Shading with the filtered indicator values given per pixel (the form a
+    surrogate feeds) equals shading that reads them from the pyramid when the
+    given values are the pyramid's trilinear lookup; and only F_k / sum F
+    enters p_k (Sec. 5 Eq. (rtiblndf)), so scaling F changes nothing."""
+    w = synth.WORKLOADS["tiny"]
+    env, g = w.env(), w.gbuf()
+    R = env.shape[1]
+    out = oracle.frame(env, g, w.K, w.M, w.T, lut=luts())
+    hit = np.nonzero(g["surf_id"] != synth.NO_SURFACE)[0][::7]
+    f64 = {k: g[k][hit].astype(np.float64) for k in ("nx", "ny", "nz", "vx", "vy", "vz", "ax", "ay")}
+    mu = f64["nx"] * f64["vx"] + f64["ny"] * f64["vy"] + f64["nz"] * f64["vz"]
+    wr = np.stack([2.0 * mu * f64["nx"] - f64["vx"], 2.0 * mu * f64["ny"] - f64["vy"],
+                   2.0 * mu * f64["nz"] - f64["vz"]], 1)
+    lod = np.sqrt(np.sqrt(f64["ax"] * f64["ay"])) * (w.M - 1)
+    F = oracle.pyramid_lookup(out["ind_pyr"], R, w.M, wr, lod)
+    args = (g, None, out["rgb_pyr"], out["levels"], *luts(), R, w.K, w.M, 1)
+    given = oracle.shade(*args, pixels=hit, F=F)
+    plain = oracle.shade(g, out["ind_pyr"], out["rgb_pyr"], out["levels"], *luts(), R, w.K, w.M, 1, pixels=hit)
+    for k in ("radiance", "counts", "probs"):
+        np.testing.assert_allclose(given[k], plain[k], rtol=1e-12, atol=1e-300)
+    assert np.array_equal(given["codes"], plain["codes"])
+    scaled = oracle.shade(*args, pixels=hit, F=3.75 * F)
+    ok = (scaled["flags"] == 0) & (given["flags"] == 0)
+    np.testing.assert_allclose(scaled["probs"], given["probs"], rtol=1e-13, atol=1e-15)
+    np.testing.assert_allclose(scaled["radiance"][ok], given["radiance"][ok], rtol=1e-9)
