@@ -8,14 +8,23 @@ RGB into the roughness pyramid, then glint shading of the 1920x1080 G-buffer
 lookup tables are built once per BRDF model before timing (not per frame).
 Inputs are synthetic and resident in HBM before the timed region.
 
+Forms: ``plain`` (the paper's method), ``surrogate`` (the indicator lookup
+replaced by the learned network; trained before the timed region, its
+training step timed separately).  ``--dtype`` selects the indicator
+pyramid's storage type.  ``--workload batched`` times the 64-view graph.
+
 Prints one JSON line: value = glint-shaded Mpix/s (pixels that ran the glint
-shader, per second of whole-frame time), plus prefilter ms/frame, the
-roofline record of the dominant kernel and the CPU-oracle baseline.
+shader, per second of whole-frame time), prefilter ms/frame, per-kernel
+average durations (HIP events bracketing each launch inside the timed
+region), the roofline record of the dominant kernel and the CPU-oracle
+baseline.  The cost model (algorithmic operations and bytes per unit of
+work) is in the functions below.
 """
 from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -25,20 +34,88 @@ import numpy as np
 METRIC = "glint-shaded Mpix/s + env prefilter ms/frame; surrogate/FP16 vs plain, 1 GPU"
 HBM_PEAK_GBS = 8000.0
 # Peak VALU lane-operations per second: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
-# (one wave64 VALU instruction per SIMD every 4 cycles); double FMA issues at
-# the same rate as non-packed float on this part.
+# (one wave64 VALU instruction per SIMD every 4 cycles).  Double FMA issues at
+# this rate on this part, as does non-packed float.
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+BF16_MFMA_PEAK_TFLOPS = 2500.0
+STORAGE_BYTES = {"f32": 4, "f16": 2, "bf16": 2, "unorm16": 2}
 
 
-def shade_ops_per_pixel(K: int) -> float:
-    """VALU lane-ops per pixel the algorithm needs:
-    lookup (8 texels x (K+3) channels, double FMA + convert) + per tree node
-    (hash, float gating with two powf, double Gaussian with AS 241) + combine."""
-    lookup = 8 * (K + 3) * 2 + 120
-    node = 22 + 2 * 40 + 30 + 140
-    combine = 6 * K + 40
-    return float(lookup + (K - 1) * node + combine)
+# --- cost model ---------------------------------------------------------------------
 
+def filter_taps(R, M, T, alpha):
+    """(weight > 0, lod) of the T taps of the filter at roughness alpha (the
+    quadrature's tap table: GGX half vectors from a Hammersley set, weight
+    <r, l>+, filtered-importance-sampling lod)."""
+    j = np.arange(T)
+    rev = np.array([int(format(int(i), "032b")[::-1], 2) for i in j], dtype=np.float64) / 2.0 ** 32
+    a2 = alpha * alpha
+    c2 = (1.0 - rev) / (1.0 + (a2 - 1.0) * rev)
+    w = np.maximum(0.0, 2.0 * c2 - 1.0)
+    den = 1.0 + (a2 - 1.0) * c2
+    D = a2 / (math.pi * den * den)
+    with np.errstate(divide="ignore"):
+        lod = 0.5 * np.log2((4.0 / (T * D)) / (4.0 * math.pi / (6.0 * R * R))) + 1.0
+    return w > 0, np.clip(lod, 0.0, M - 1)
+
+
+# Per tap: rotate the half vector into the texel's frame (9 FMA), mirror
+# (6), face select and projection (~12), bilinear coordinates and weights
+# (~12 per level).
+TAP_FIXED_OPS = 27
+TAP_LEVEL_OPS = 12
+
+
+def prefilter_cost(R, M, T, K, dtype_bytes=4):
+    """Algorithmic VALU lane-ops and HBM bytes of one k_prefilter launch
+    (mips 1..M-1): per output texel and effective tap (weight > 0), a
+    weighted sum of the C = K+3 channels of 4 texels on each of the one or
+    two chain levels the tap's lod touches (one FMA per channel and texel),
+    plus the tap's direction work; then C normalisations.  Bytes: the
+    pyramid written (K indicator values of the stored type + 4 RGB floats
+    per texel) and the source chain read once."""
+    C = K + 3
+    ops = 0.0
+    texels = 0
+    for m in range(1, M):
+        n = R >> m
+        eff, lod = filter_taps(R, M, T, (m / (M - 1)) ** 2)
+        levels = np.where(lod > np.floor(lod), 2, 1)[eff]
+        per_texel = float(np.sum(levels * (4 * C + TAP_LEVEL_OPS) + TAP_FIXED_OPS)) + C
+        ops += 6 * n * n * per_texel
+        texels += 6 * n * n
+    chain_texels = sum(6 * (R >> s) ** 2 for s in range(1, M))
+    bytes_ = texels * (K * dtype_bytes + 16) + 6 * R * R * (12 + 5) + chain_texels * 4 * ((C + 3) // 4 * 4)
+    return ops, bytes_, texels
+
+
+def shade_ops_per_pixel(K, V=1):
+    """Algorithmic VALU lane-ops per glint pixel (transcendentals weighted 4,
+    their issue cost at quarter rate):
+      set-up: N_P, reflection, lod, lattice level ~ 25;
+      lookup: 2 levels x 4 texels x (K+3) channel FMAs + addressing ~ 40;
+      p_k and three LUT bilinears: 2K + 30;
+      per lattice vertex and tree node: hash 16 + xi 4, gating thresholds
+        15 + 2 pow (2 transcendentals each), AS 241 quantile ~ 30 (one
+        division), Gaussian and masks 15 -> 80 + 5 transcendentals;
+      combine: 2K + 15 per vertex, radiance 10."""
+    node = 80 + 4 * 5
+    return float(25 + 8 * (K + 3) + 40 + 2 * K + 30 + V * ((K - 1) * node + 2 * K + 15) + 10)
+
+
+SHADE_BYTES_PER_PIXEL = 16 * 4 + 12  # G-buffer fields + radiance
+
+
+def mlp_flops_per_row(K, padded=False):
+    """Matrix-core flops of one network evaluation: 2 x (5x64 + 64x64 + 64x64
+    + 64xK) multiply-adds (unpadded), or the padded tiles the kernel issues
+    (16-wide input, 32-wide output)."""
+    if padded:
+        return 2.0 * (16 * 64 + 2 * 64 * 64 + 64 * 32)
+    return 2.0 * (5 * 64 + 2 * 64 * 64 + 64 * K)
+
+
+# --- helpers -------------------------------------------------------------------------
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -46,8 +123,10 @@ def parse():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="frame")
+    ap.add_argument("--form", default="plain", choices=["plain", "surrogate"])
     ap.add_argument("--dtype", default="f32", choices=["f32", "f16", "bf16", "unorm16"])
     ap.add_argument("--vertices", type=int, default=1)
+    ap.add_argument("--train-steps", type=int, default=400, help="surrogate training steps before timing")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=float, default=1.0 / 48.0,
                     help="fraction of pyramid texels and glint pixels the oracle times")
@@ -99,6 +178,21 @@ def cpu_baseline(w, env, gbuf, glint_pixels, frac, shade_inputs):
             "prefilter_s_per_frame": t_part + t_pre, "shade_s_per_frame": t_sh}
 
 
+def kernel_table(G, ctx, steps):
+    prof = G.glint_profile_collect(ctx)
+    return {k: {"avg_ms": round(ms / n, 5), "launches_per_step": n / steps} for k, (ms, n) in prof.items()}
+
+
+def alu_record(kernel, ops, avg_ms, extra=None):
+    achieved = ops / (avg_ms * 1e-3) / 1e12
+    r = {"bound": "alu", "kernel": kernel, "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 4),
+         "unit": "TOP/s (VALU lane-ops)", "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": None,
+         "ops_per_launch": ops}
+    if extra:
+        r.update(extra)
+    return r
+
+
 def batched(a):
     """64 views of uneven size over 4 maps (K = 4, 8, 16, 8), one graph
     launch per frame (glint_frame_batched)."""
@@ -138,6 +232,35 @@ def batched(a):
     print(json.dumps(out), flush=True)
 
 
+def train_surrogate(G, ctx, pipe, env, K, steps, batch=4096):
+    """Trains the surrogate on the plain filter of the current map (not
+    timed as part of a frame); then times training steps on their own."""
+    import torch
+    from paper_2507_02674_amd.pipeline import Surrogate
+    sur = Surrogate(ctx, K)
+    sur.init(seed=7)
+    x, t = sur.samples(pipe, env, 1 << 20, seed=1)
+    sur.fit(x, t, batch=batch, lr=3e-3, lr_min=1e-4, steps=steps)
+    xv, tv = sur.samples(pipe, env, 1 << 14, seed=2)
+    loss = float(sur.gradient(xv, tv)[1].item())
+    err = float((sur.forward(xv) - tv).abs().mean().item())
+    # training-step throughput (b7): 50 steps at the training batch
+    xs, ts = x[:batch].contiguous(), t[:batch].contiguous()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(50):
+        sur.train_step(xs, ts, 1e-5)
+    e1.record()
+    torch.cuda.synchronize()
+    step_ms = e0.elapsed_time(e1) / 50
+    flops = 3.0 * mlp_flops_per_row(K) * batch
+    info = {"train_steps": steps, "batch": batch, "heldout_loss": round(loss, 5), "heldout_mean_abs_F_err": err,
+            "train_step_ms": round(step_ms, 4), "train_samples_per_s": round(batch / (step_ms * 1e-3), 1),
+            "train_tflops_algorithmic": round(flops / (step_ms * 1e-3) / 1e12, 3)}
+    return sur, info
+
+
 def main():
     a = parse()
     if a.copy_probe:
@@ -151,7 +274,7 @@ def main():
 
     import synth
     from paper_2507_02674_amd import glint as G
-    from paper_2507_02674_amd.pipeline import EnvPipeline, Shader
+    from paper_2507_02674_amd.pipeline import EnvPipeline, Shader, SurrogateShader
 
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU visible"}))
@@ -166,8 +289,14 @@ def main():
     ctx = G.glint_create(0)
     env = torch.from_numpy(env_np).cuda()
     pipe = EnvPipeline(ctx, w.R, w.K, w.M, w.T, dtypes[a.dtype], w.ell)
-    shader = Shader(ctx, gbuf_np, seed=w.hash_seed, vertices=a.vertices)
     pipe.build_luts()
+    pipe.run(env)
+    extra = {}
+    if a.form == "surrogate":
+        sur, extra["surrogate"] = train_surrogate(G, ctx, pipe, env, w.K, a.train_steps)
+        shader = SurrogateShader(ctx, gbuf_np, sur, seed=w.hash_seed, vertices=a.vertices)
+    else:
+        shader = Shader(ctx, gbuf_np, seed=w.hash_seed, vertices=a.vertices)
     torch.cuda.synchronize()
     envs = pipe.env_struct()
     for _ in range(a.warmup):
@@ -175,6 +304,8 @@ def main():
         shader.run(envs)
     torch.cuda.synchronize()
 
+    # timed region: every library launch bracketed by HIP events on its stream
+    G.glint_profile_enable(ctx, True)
     ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(a.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -186,27 +317,69 @@ def main():
         ev[s][2].record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    kernels = kernel_table(G, ctx, a.steps)
+    G.glint_profile_enable(ctx, False)
     pre_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in ev]))
     sh_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in ev]))
     frame_ms = float(ev[0][0].elapsed_time(ev[-1][2])) / a.steps
     ms_per_step = max(frame_ms, 1e3 * wall / a.steps)
     value = glint_pixels / (ms_per_step * 1e-3) / 1e6
 
-    ops = shade_ops_per_pixel(w.K) * glint_pixels * a.vertices
-    achieved = ops / (sh_ms * 1e-3) / 1e12
-    roofline = {"bound": "alu", "kernel": "k_shade", "achieved": round(achieved, 3), "peak": VALU_PEAK_TOPS,
-                "unit": "TOP/s (VALU lane-ops)", "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": None,
-                "ops_per_pixel": shade_ops_per_pixel(w.K), "hbm_gbs": round(76.0 * glint_pixels / (sh_ms * 1e-3) / 1e9, 1),
-                "hbm_frac": round(76.0 * glint_pixels / (sh_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    # roofline records: prefilter, shading, and the network lookup
+    pf_ops, pf_bytes, pf_texels = prefilter_cost(w.R, w.M, w.T, w.K, STORAGE_BYTES[a.dtype])
+    records = {}
+    if "k_prefilter" in kernels:
+        ms = kernels["k_prefilter"]["avg_ms"]
+        records["k_prefilter"] = alu_record("k_prefilter", pf_ops, ms, {
+            "ops_per_texel": round(pf_ops / pf_texels, 1), "output_texels": pf_texels,
+            "hbm_gbs": round(pf_bytes / (ms * 1e-3) / 1e9, 1),
+            "hbm_frac": round(pf_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)})
+    shade_kernel = "k_shade_surrogate" if a.form == "surrogate" else "k_shade"
+    if shade_kernel in kernels:
+        ms = kernels[shade_kernel]["avg_ms"]
+        opp = shade_ops_per_pixel(w.K, a.vertices)
+        records[shade_kernel] = alu_record(shade_kernel, opp * glint_pixels, ms, {
+            "ops_per_pixel": opp, "hbm_gbs": round(SHADE_BYTES_PER_PIXEL * shader.P / (ms * 1e-3) / 1e9, 1),
+            "hbm_frac": round(SHADE_BYTES_PER_PIXEL * shader.P / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)})
+    if "k_mlp_lookup" in kernels:
+        ms = kernels["k_mlp_lookup"]["avg_ms"]
+        fl = mlp_flops_per_row(w.K) * shader.P
+        ach = fl / (ms * 1e-3) / 1e12
+        records["k_mlp_lookup"] = {"bound": "mfma", "kernel": "k_mlp_lookup", "achieved": round(ach, 3),
+                                   "peak": BF16_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s", "traffic": None,
+                                   "frac": round(ach / BF16_MFMA_PEAK_TFLOPS, 4), "flops_per_launch": fl,
+                                   "padded_flops_per_launch": mlp_flops_per_row(w.K, True) * shader.P}
+    dominant = max((k for k in records), key=lambda k: kernels[k]["avg_ms"] * kernels[k]["launches_per_step"])
+    roofline = dict(records[dominant])
+    others = {k: v for k, v in records.items() if k != dominant}
+
     out = {"metric": METRIC, "value": round(value, 3), "unit": "Mpix/s", "n_gpus": 1, "steps": a.steps,
            "warmup": a.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
            "config": {"workload": f"{w.name}: {w.W}x{w.H} sphere+plane G-buffer, cube map 6x{w.R}x{w.R}, "
                                   f"{w.M} mips, K={w.K}, T={w.T} taps, per-frame partition+prefilter+shade",
-                      "pyramid_dtype": a.dtype, "vertices": a.vertices, "glint_pixels": glint_pixels},
+                      "form": a.form, "pyramid_dtype": a.dtype, "vertices": a.vertices,
+                      "glint_pixels": glint_pixels},
            "prefilter_ms_per_frame": round(pre_ms, 4), "shade_ms_per_frame": round(sh_ms, 4),
-           "roofline": roofline}
-    if not a.no_cpu_baseline:
+           "kernels": kernels, "roofline": roofline, "other_rooflines": others}
+    out.update(extra)
+    if a.dtype != "f32" or a.form != "plain":
+        # radiance against the plain f32 path on the same frame (itself checked against the oracle)
+        ref_pipe = EnvPipeline(ctx, w.R, w.K, w.M, w.T, G.GLINT_F32, w.ell)
+        ref_pipe.build_luts()
+        ref_pipe.run(env)
+        ref_sh = Shader(ctx, gbuf_np, seed=w.hash_seed, vertices=a.vertices)
+        ref_sh.run(ref_pipe.env_struct())
+        torch.cuda.synchronize()
+        hit = torch.from_numpy(gbuf_np["surf_id"] != 0xFFFFFFFF).cuda()
+        r0 = ref_sh.radiance[hit].double().sum(1)
+        r1 = shader.radiance[hit].double().sum(1)
+        rel = ((r1 - r0).abs() / r0.abs().clamp_min(1e-12))
+        lit = r0 > 1e-6 * r0.max()
+        out["radiance_vs_plain_f32"] = {"mean_rel_err": float(rel[lit].mean().item()),
+                                        "mean_abs_err_over_mean": float(((r1 - r0).abs().mean() /
+                                                                         r0.abs().mean()).item())}
+    if not a.no_cpu_baseline and a.form == "plain":
         if a.dtype == "f32":
             ind_h = pipe.ind_pyr.cpu().numpy()
         else:

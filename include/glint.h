@@ -384,6 +384,25 @@ int glint_frame_batched(glint_ctx ctx, const glint_env_task *envs, int n_env, co
  * (K, vertices) group of the most recent set-up call; 0 before any. */
 int glint_batched_tile_px(glint_ctx ctx);
 
+/* ------------------------------------------------------------------------
+ * Per-kernel timing, for benchmarks and profiling.  While enabled, every
+ * kernel that an entry point of this context launches (outside a stream
+ * capture) is bracketed by two HIP events recorded on its launch stream;
+ * the events add a few microseconds of gap between launches.
+ * ------------------------------------------------------------------------ */
+
+/* Enables (1) or disables (0) timing; either way drops every record. */
+int glint_profile_enable(glint_ctx ctx, int enable);
+
+/* Waits for the recorded events (synchronising with the streams they were
+ * recorded on), adds their durations to per-kernel totals and stores the
+ * number of distinct kernels in *n_kernels. */
+int glint_profile_collect(glint_ctx ctx, int *n_kernels);
+
+/* Entry i < *n_kernels of the totals: kernel name (a static string owned
+ * by the library), total milliseconds and number of launches. */
+int glint_profile_entry(glint_ctx ctx, int i, const char **name, double *total_ms, int64_t *launches);
+
 #ifdef __cplusplus
 }
 #endif

@@ -5,7 +5,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["api.hip", "partition.hip", "prefilter.hip", "lut.hip", "shade.hip", "batched.hip", "mlp.hip"]
+SOURCES = ["api.hip", "partition.hip", "prefilter.hip", "lut.hip", "shade.hip", "batched.hip", "mlp.hip", "profile.hip"]
 ARCH = os.environ.get("GLINT_OFFLOAD_ARCH", "gfx950")
 
 

@@ -14,6 +14,7 @@ struct glint_ctx_s {
     int device;
     int num_cu;
     glint::BatchedCache batched;
+    glint::Profiler prof;
 };
 
 namespace {
@@ -181,6 +182,7 @@ void glint_destroy(glint_ctx ctx) { delete ctx; }
 int glint_sync(glint_ctx ctx)
 {
     if (int rc = check_ctx(ctx)) return rc;
+    glint::ProfScope prof_scope(&ctx->prof);
     return device_status(hipDeviceSynchronize(), "hipDeviceSynchronize");
 }
 
@@ -194,6 +196,7 @@ int glint_partition_env(glint_ctx ctx, const float *env, int R, const glint_part
                         double *levels, uint8_t *ind_j, float *ind_t, void *stream)
 {
     if (int rc = check_ctx(ctx)) return rc;
+    glint::ProfScope prof_scope(&ctx->prof);
     if (int rc = check_partition(env, R, pp, workspace, levels, ind_j, ind_t)) return rc;
     return device_status(glint::launch_partition(env, R, pp->K, pp->ell, pp->level_mode, pp->weight_space,
                                                  workspace, levels, ind_j, ind_t, (hipStream_t)stream),
@@ -218,6 +221,7 @@ int glint_prefilter(glint_ctx ctx, const float *env, const uint8_t *ind_j, const
                     const glint_prefilter_params *fp, void *workspace, void *ind_pyr, float *rgb_pyr, void *stream)
 {
     if (int rc = check_ctx(ctx)) return rc;
+    glint::ProfScope prof_scope(&ctx->prof);
     if (int rc = check_prefilter(env, ind_j, ind_t, R, K, fp, workspace, ind_pyr, rgb_pyr)) return rc;
     return device_status(glint::launch_prefilter(env, ind_j, ind_t, R, K, fp->num_mips, fp->taps, (int)fp->dtype,
                                                  workspace, ind_pyr, rgb_pyr, (hipStream_t)stream),
@@ -227,6 +231,7 @@ int glint_prefilter(glint_ctx ctx, const float *env, const uint8_t *ind_j, const
 int glint_build_luts(glint_ctx ctx, float *lut_S, float *lut_E, void *stream)
 {
     if (int rc = check_ctx(ctx)) return rc;
+    glint::ProfScope prof_scope(&ctx->prof);
     if (!lut_S || !lut_E) return fail(GLINT_EINVAL, "null pointer argument");
     return device_status(glint::launch_luts(lut_S, lut_E, (hipStream_t)stream), "glint_build_luts launch");
 }
@@ -235,6 +240,7 @@ int glint_shade(glint_ctx ctx, const glint_gbuffer *g, int64_t P, const glint_en
                 const glint_shade_params *sp, float *radiance, const glint_shade_debug *dbg, void *stream)
 {
     if (int rc = check_ctx(ctx)) return rc;
+    glint::ProfScope prof_scope(&ctx->prof);
     if (!g || !env || !sp) return fail(GLINT_EINVAL, "null pointer argument");
     if (P < 0) return fail(GLINT_EINVAL, "num_pixels must be >= 0");
     if (int rc = check_R(env->R)) return rc;
@@ -257,6 +263,7 @@ int glint_sample_filter(glint_ctx ctx, const float *env, const uint8_t *ind_j, c
                         const float *alphas, int64_t n, float *out, void *stream)
 {
     if (int rc = check_ctx(ctx)) return rc;
+    glint::ProfScope prof_scope(&ctx->prof);
     if (!fp || !env || !ind_j || !ind_t || !workspace) return fail(GLINT_EINVAL, "null pointer argument");
     if (int rc = check_R(R)) return rc;
     if (int rc = check_tree_K(K)) return rc;
@@ -276,6 +283,7 @@ int glint_surrogate_samples(glint_ctx ctx, const float *env, const uint8_t *ind_
                             const float *ax, const float *ay, int64_t n, float *x, float *target, void *stream)
 {
     if (int rc = check_ctx(ctx)) return rc;
+    glint::ProfScope prof_scope(&ctx->prof);
     if (!fp || !env || !ind_j || !ind_t || !workspace) return fail(GLINT_EINVAL, "null pointer argument");
     if (int rc = check_R(R)) return rc;
     if (int rc = check_tree_K(K)) return rc;
@@ -302,6 +310,7 @@ size_t glint_surrogate_workspace_bytes(int batch)
 int glint_surrogate_prepare(glint_ctx ctx, int K, float *w, uint16_t *w_bf16, void *stream)
 {
     if (int rc = check_ctx(ctx)) return rc;
+    glint::ProfScope prof_scope(&ctx->prof);
     if (int rc = check_surrogate(K, w, w_bf16)) return rc;
     return device_status(glint::launch_mlp_prepare(w, w_bf16, K, (hipStream_t)stream),
                          "glint_surrogate_prepare launch");
@@ -311,6 +320,7 @@ int glint_surrogate_forward(glint_ctx ctx, int K, const float *w, const uint16_t
                             int64_t B, float *probs, void *stream)
 {
     if (int rc = check_ctx(ctx)) return rc;
+    glint::ProfScope prof_scope(&ctx->prof);
     if (int rc = check_surrogate(K, w, w_bf16)) return rc;
     if (B < 0 || B > ((int64_t)1 << 36)) return fail(GLINT_EINVAL, "bad batch size %lld", (long long)B);
     if (B == 0) return ok();
@@ -323,6 +333,7 @@ int glint_surrogate_gradient(glint_ctx ctx, int K, const float *w, const uint16_
                              const float *target, int B, void *workspace, float *grad, float *loss, void *stream)
 {
     if (int rc = check_ctx(ctx)) return rc;
+    glint::ProfScope prof_scope(&ctx->prof);
     if (int rc = check_surrogate(K, w, w_bf16)) return rc;
     if (int rc = check_batch(B, x, target, workspace)) return rc;
     if (!grad || !loss) return fail(GLINT_EINVAL, "null pointer argument");
@@ -339,6 +350,7 @@ int glint_surrogate_train_step(glint_ctx ctx, int K, float *w, uint16_t *w_bf16,
                                void *stream)
 {
     if (int rc = check_ctx(ctx)) return rc;
+    glint::ProfScope prof_scope(&ctx->prof);
     if (int rc = check_surrogate(K, w, w_bf16)) return rc;
     if (int rc = check_batch(B, x, target, workspace)) return rc;
     if (!m || !v || !loss) return fail(GLINT_EINVAL, "null pointer argument");
@@ -364,6 +376,7 @@ int glint_shade_surrogate(glint_ctx ctx, const glint_gbuffer *g, int64_t P, cons
                           const glint_shade_debug *dbg, void *stream)
 {
     if (int rc = check_ctx(ctx)) return rc;
+    glint::ProfScope prof_scope(&ctx->prof);
     if (!g || !env || !sp) return fail(GLINT_EINVAL, "null pointer argument");
     if (P < 0) return fail(GLINT_EINVAL, "num_pixels must be >= 0");
     if (int rc = check_R(env->R)) return rc;
@@ -395,6 +408,7 @@ int glint_frame_batched(glint_ctx ctx, const glint_env_task *envs, int n_env, co
                         void *workspace, void *stream)
 {
     if (int rc = check_ctx(ctx)) return rc;
+    glint::ProfScope prof_scope(&ctx->prof);
     if (!envs || !views || !workspace) return fail(GLINT_EINVAL, "null pointer argument");
     if (n_env < 1 || n_env > 64) return fail(GLINT_EINVAL, "n_env=%d must be in [1, 64]", n_env);
     if (n_views < 1 || n_views > 4096) return fail(GLINT_EINVAL, "n_views=%d must be in [1, 4096]", n_views);
@@ -425,5 +439,33 @@ int glint_frame_batched(glint_ctx ctx, const glint_env_task *envs, int n_env, co
 }
 
 int glint_batched_tile_px(glint_ctx ctx) { return ctx ? ctx->batched.last_tile_px : 0; }
+
+int glint_profile_enable(glint_ctx ctx, int enable)
+{
+    if (int rc = check_ctx(ctx)) return rc;
+    ctx->prof.reset();
+    ctx->prof.enabled = enable != 0;
+    return ok();
+}
+
+int glint_profile_collect(glint_ctx ctx, int *n_kernels)
+{
+    if (int rc = check_ctx(ctx)) return rc;
+    if (!n_kernels) return fail(GLINT_EINVAL, "null pointer argument");
+    const hipError_t e = ctx->prof.collect();
+    *n_kernels = (int)ctx->prof.summary.size();
+    return device_status(e, "glint_profile_collect");
+}
+
+int glint_profile_entry(glint_ctx ctx, int i, const char **name, double *total_ms, int64_t *launches)
+{
+    if (!ctx) return fail(GLINT_EINVAL, "null context");
+    if (i < 0 || i >= (int)ctx->prof.summary.size()) return fail(GLINT_EINVAL, "profile entry %d out of range", i);
+    if (!name || !total_ms || !launches) return fail(GLINT_EINVAL, "null pointer argument");
+    *name = ctx->prof.summary[i].name;
+    *total_ms = ctx->prof.summary[i].total_ms;
+    *launches = ctx->prof.summary[i].launches;
+    return ok();
+}
 
 } // extern "C"

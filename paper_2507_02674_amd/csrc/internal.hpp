@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include "glint.h"
+#include "profile.hpp"
 
 namespace glint {
 

@@ -107,7 +107,7 @@ __global__ void __launch_bounds__(kLutThreads) k_lut(float *__restrict__ lut_S, 
 
 hipError_t launch_luts(float *lut_S, float *lut_E, hipStream_t stream)
 {
-    hipLaunchKernelGGL(k_lut, dim3(kLutN * kLutN), dim3(kLutThreads), 0, stream, lut_S, lut_E);
+    GLINT_LAUNCH("k_lut", k_lut, dim3(kLutN * kLutN), dim3(kLutThreads), 0, stream, lut_S, lut_E);
     return hipGetLastError();
 }
 

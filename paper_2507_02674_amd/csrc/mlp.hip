@@ -474,7 +474,7 @@ static unsigned infer_blocks(int64_t B)
 
 hipError_t launch_mlp_prepare(float *w, uint16_t *wb, int K, hipStream_t stream)
 {
-    hipLaunchKernelGGL(k_mlp_prepare, dim3((kParams + 255) / 256), dim3(256), 0, stream, w, wb, K);
+    GLINT_LAUNCH("k_mlp_prepare", k_mlp_prepare, dim3((kParams + 255) / 256), dim3(256), 0, stream, w, wb, K);
     return hipGetLastError();
 }
 
@@ -483,8 +483,11 @@ hipError_t launch_mlp_grad_step(const float *x, const float *target, int B, int 
                                 float *loss_out, hipStream_t stream)
 {
     const int blocks = (B + 31) / 32;
-    hipLaunchKernelGGL(k_mlp_grad, dim3(blocks), dim3(64), 0, stream, x, target, B, K, w, wb, partial, loss_partial);
-    hipLaunchKernelGGL(k_mlp_adam, dim3((kParams + 255) / 256), dim3(256), 0, stream, partial, blocks, K, w, wb, m,
+    {
+        GLINT_LAUNCH("k_mlp_grad", k_mlp_grad, dim3(blocks), dim3(64), 0, stream, x, target, B, K, w, wb, partial,
+                           loss_partial);
+    }
+    GLINT_LAUNCH("k_mlp_adam", k_mlp_adam, dim3((kParams + 255) / 256), dim3(256), 0, stream, partial, blocks, K, w, wb, m,
                        v, step, lr, loss_partial, B, loss_out);
     return hipGetLastError();
 }
@@ -494,8 +497,11 @@ hipError_t launch_mlp_gradient(const float *x, const float *target, int B, int K
                                hipStream_t stream)
 {
     const int blocks = (B + 31) / 32;
-    hipLaunchKernelGGL(k_mlp_grad, dim3(blocks), dim3(64), 0, stream, x, target, B, K, w, wb, partial, loss_partial);
-    hipLaunchKernelGGL(k_mlp_sum, dim3((kParams + 255) / 256), dim3(256), 0, stream, partial, blocks, loss_partial, B,
+    {
+        GLINT_LAUNCH("k_mlp_grad", k_mlp_grad, dim3(blocks), dim3(64), 0, stream, x, target, B, K, w, wb, partial,
+                           loss_partial);
+    }
+    GLINT_LAUNCH("k_mlp_sum", k_mlp_sum, dim3((kParams + 255) / 256), dim3(256), 0, stream, partial, blocks, loss_partial, B,
                        grad, loss_out);
     return hipGetLastError();
 }
@@ -505,7 +511,7 @@ hipError_t launch_mlp_forward(const float *x, int64_t B, int K, const float *w, 
 {
     InferInput in{};
     in.x = x;
-    hipLaunchKernelGGL(k_mlp_infer<0>, dim3(infer_blocks(B)), dim3(64 * kInferWaves), 0, stream, in, B, K, w, wb,
+    GLINT_LAUNCH("k_mlp_infer", k_mlp_infer<0>, dim3(infer_blocks(B)), dim3(64 * kInferWaves), 0, stream, in, B, K, w, wb,
                        probs);
     return hipGetLastError();
 }
@@ -515,7 +521,7 @@ hipError_t launch_mlp_lookup(const glint_gbuffer &g, int64_t P, int K, const flo
 {
     InferInput in{};
     in.g = g;
-    hipLaunchKernelGGL(k_mlp_infer<1>, dim3(infer_blocks(P)), dim3(64 * kInferWaves), 0, stream, in, P, K, w, wb,
+    GLINT_LAUNCH("k_mlp_lookup", k_mlp_infer<1>, dim3(infer_blocks(P)), dim3(64 * kInferWaves), 0, stream, in, P, K, w, wb,
                        F);
     return hipGetLastError();
 }

@@ -136,9 +136,13 @@ hipError_t launch_partition(const float *env, int R, int K, double ell, int leve
     const int64_t n = 6LL * R * R;
     const int blocks = partition_blocks(R);
     double *pairs = static_cast<double *>(workspace);
-    hipLaunchKernelGGL(k_minmax, dim3(blocks), dim3(kPartThreads), 0, stream, env, n, pairs);
-    hipLaunchKernelGGL(k_indicators, dim3(blocks), dim3(kPartThreads), 0, stream, env, n, pairs, blocks, K, ell,
-                       level_mode, weight_space, levels, ind_j, ind_t);
+    {
+        GLINT_LAUNCH("k_minmax", k_minmax, dim3(blocks), dim3(kPartThreads), 0, stream, env, n, pairs);
+    }
+    {
+        GLINT_LAUNCH("k_indicators", k_indicators, dim3(blocks), dim3(kPartThreads), 0, stream, env, n, pairs, blocks, K, ell,
+                           level_mode, weight_space, levels, ind_j, ind_t);
+    }
     return hipGetLastError();
 }
 

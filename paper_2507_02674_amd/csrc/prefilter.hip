@@ -4,7 +4,11 @@
 //
 // Source mip chain: level 0 is virtual (dense weights 1-t, t expanded from
 // the packed indicator plus RGB from the map); levels >= 1 are stored float,
-// [texel][CP] with CP = K+3 rounded up to 4 (16-byte texel records).
+// [texel][CP] with CP = K+3 rounded up to 4 (16-byte texel records), each
+// face with a one-texel border that holds the seam rule's value (the
+// adjacent face's texel beyond an edge, the mean of the three texels that
+// meet at a corner), so bilinear footprints on levels >= 1 never leave the
+// stored face:
 //
 //   k_chain_tiles   per 32x32 tile of level 0: mip 0 of the output pyramid
 //                   (alpha = 0, the dense level) and chain levels 1..5 via
@@ -13,6 +17,7 @@
 //   k_chain_faces   the coarser levels of each face through LDS;
 //   k_chain_level   one level per launch (only for faces larger than 32
 //                   texels that the tiles did not reach, R >= 2048);
+//   k_chain_border  the border rings of every stored level;
 //   k_prefilter     mips >= 1: a group of G = 8 lanes per output texel splits
 //                   the T taps, accumulates in double, reduces across the
 //                   group with cross-lane shuffles; the tap table of the
@@ -28,6 +33,27 @@ constexpr int kFilterThreads = 256;
 constexpr int kGroup = 8; // lanes per output texel
 
 __host__ __device__ constexpr int chain_stride(int K) { return (K + 3 + 3) & ~3; }
+
+// Records of stored chain level s >= 1 (face size n = R >> s plus border).
+__host__ __device__ inline int64_t chain_level_records(int R, int s)
+{
+    const int64_t n = R >> s;
+    return 6 * (n + 2) * (n + 2);
+}
+
+// Records before stored level s >= 1 (level 1 starts the chain).
+__host__ __device__ inline int64_t chain_level_base(int R, int s)
+{
+    int64_t o = 0;
+    for (int q = 1; q < s; ++q) o += chain_level_records(R, q);
+    return o;
+}
+
+// Record of texel (x, y), x, y in [-1, n], of `face` within its level.
+__host__ __device__ inline int64_t chain_rec(int face, int x, int y, int n)
+{
+    return ((int64_t)face * (n + 2) + (y + 1)) * (n + 2) + (x + 1);
+}
 
 // ---------------------------------------------------------------------------
 // storage types of the indicator pyramid
@@ -169,14 +195,14 @@ __global__ void __launch_bounds__(kChainThreads) k_chain_level(Level0<K> l0, con
     if (o >= total) return;
     const int x = (int)(o % n), y = (int)((o / n) % n), f = (int)(o / ((int64_t)n * n));
     const int m = 2 * n;
-    const int64_t c00 = ((int64_t)f * m + 2 * y) * m + 2 * x;
-    const int64_t idx[4] = {c00, c00 + 1, c00 + m, c00 + m + 1};
     double a[C], b[C], c[C], d[C];
     if (src == nullptr) {
-        l0.load(idx[0], a); l0.load(idx[1], b); l0.load(idx[2], c); l0.load(idx[3], d);
+        const int64_t c00 = ((int64_t)f * m + 2 * y) * m + 2 * x;
+        l0.load(c00, a); l0.load(c00 + 1, b); l0.load(c00 + m, c); l0.load(c00 + m + 1, d);
     } else {
-        load_chain<K>(src, idx[0], a); load_chain<K>(src, idx[1], b);
-        load_chain<K>(src, idx[2], c); load_chain<K>(src, idx[3], d);
+        const int64_t c00 = chain_rec(f, 2 * x, 2 * y, m);
+        load_chain<K>(src, c00, a); load_chain<K>(src, c00 + 1, b);
+        load_chain<K>(src, c00 + m + 2, c); load_chain<K>(src, c00 + m + 3, d);
     }
     float out[CP];
     {
@@ -186,7 +212,7 @@ __global__ void __launch_bounds__(kChainThreads) k_chain_level(Level0<K> l0, con
     }
 #pragma unroll
     for (int k = C; k < CP; ++k) out[k] = 0.0f;
-    float4 *q = reinterpret_cast<float4 *>(dst + o * CP);
+    float4 *q = reinterpret_cast<float4 *>(dst + chain_rec(f, x, y, n) * CP);
 #pragma unroll
     for (int i = 0; i < CP / 4; ++i) q[i] = make_float4(out[4 * i], out[4 * i + 1], out[4 * i + 2], out[4 * i + 3]);
 }
@@ -244,8 +270,7 @@ __device__ __forceinline__ void reduce_lds_level(const float *src, float *dst, i
         lds_texel<K>(src + ((2 * y) * side + 2 * x + 1) * CP, b);
         lds_texel<K>(src + ((2 * y + 1) * side + 2 * x) * CP, c);
         lds_texel<K>(src + ((2 * y + 1) * side + 2 * x + 1) * CP, d);
-        const int64_t gi = ((int64_t)face * n + oy + y) * n + ox + x;
-        mean4_store<K>(a, b, c, d, dst + o * CP, level_base + gi * CP);
+        mean4_store<K>(a, b, c, d, dst + o * CP, level_base + chain_rec(face, ox + x, oy + y, n) * CP);
     }
 }
 
@@ -281,8 +306,7 @@ __global__ void __launch_bounds__(256) k_chain_tiles(Level0<K> l0, int R, int M,
             const int64_t c00 = ((int64_t)face * R + gy) * R + gx;
             double a[K + 3], b[K + 3], c[K + 3], d[K + 3];
             l0.load(c00, a); l0.load(c00 + 1, b); l0.load(c00 + R, c); l0.load(c00 + R + 1, d);
-            const int64_t gi = ((int64_t)face * n1 + ty * half + y) * n1 + tx * half + x;
-            mean4_store<K>(a, b, c, d, s_a + o * CP, base1 + gi * CP);
+            mean4_store<K>(a, b, c, d, s_a + o * CP, base1 + chain_rec(face, tx * half + x, ty * half + y, n1) * CP);
         }
     }
     __syncthreads();
@@ -291,7 +315,7 @@ __global__ void __launch_bounds__(256) k_chain_tiles(Level0<K> l0, int R, int M,
     float *src = s_a, *dst = s_b;
     for (int s = 2; s < M && side >= 2; ++s) {
         const int n = R >> s, half = side / 2;
-        float *lvl = chain + (level_offset(R, s) - 6LL * R * R) * CP;
+        float *lvl = chain + chain_level_base(R, s) * CP;
         reduce_lds_level<K>(src, dst, side, face, tx * half, ty * half, n, lvl);
         __syncthreads();
         float *t = src; src = dst; dst = t;
@@ -308,18 +332,83 @@ __global__ void __launch_bounds__(256) k_chain_faces(int R, int M, int first, fl
     const int face = blockIdx.x;
     const int n0 = R >> (first - 1); // face size of the level the tiles finished
     float *src = s_dyn, *dst = s_dyn + n0 * n0 * CP;
-    const float *lvl0 = chain + (level_offset(R, first - 1) - 6LL * R * R) * CP;
-    for (int o = threadIdx.x; o < n0 * n0 * CP; o += blockDim.x) src[o] = lvl0[(int64_t)face * n0 * n0 * CP + o];
+    const float *lvl0 = chain + chain_level_base(R, first - 1) * CP;
+    for (int o = threadIdx.x; o < n0 * n0 * CP; o += blockDim.x) {
+        const int tex = o / CP, k = o % CP;
+        src[o] = lvl0[chain_rec(face, tex % n0, tex / n0, n0) * CP + k];
+    }
     __syncthreads();
     int side = n0;
     for (int s = first; s < M; ++s) {
         const int half = side / 2;
-        float *lvl = chain + (level_offset(R, s) - 6LL * R * R) * CP;
+        float *lvl = chain + chain_level_base(R, s) * CP;
         reduce_lds_level<K>(src, dst, side, face, 0, 0, half, lvl);
         __syncthreads();
         float *t = src; src = dst; dst = t;
         side = half;
     }
+}
+
+// Border rings of stored levels 1..M-1: texel (x, y) with x or y in {-1, n}
+// gets the seam rule's value (one texel of the owning face, or at a corner
+// the float-rounded mean ((a + b) + c) / 3 of the three corner texels, sums
+// in double).  Thread i covers ring texel i of the concatenated rings.
+template <int K>
+__global__ void __launch_bounds__(256) k_chain_border(int R, int M, float *__restrict__ chain)
+{
+    constexpr int C = K + 3, CP = chain_stride(K);
+    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int s = 1, n = R >> 1;
+    while (s < M && r >= 6LL * (4 * n + 4)) {
+        r -= 6LL * (4 * n + 4);
+        ++s;
+        n = R >> s;
+    }
+    if (s >= M) return;
+    const int face = (int)(r / (4 * n + 4));
+    const int pos = (int)(r % (4 * n + 4));
+    int x, y;
+    if (pos < n + 2) {
+        x = pos - 1;
+        y = -1;
+    } else if (pos < 2 * (n + 2)) {
+        x = pos - (n + 2) - 1;
+        y = n;
+    } else if (pos < 2 * (n + 2) + n) {
+        x = -1;
+        y = pos - 2 * (n + 2);
+    } else {
+        x = n;
+        y = pos - 2 * (n + 2) - n;
+    }
+    float *lvl = chain + chain_level_base(R, s) * CP;
+    int64_t idx[3];
+    const int cnt = resolve_texel(face, x, y, n, idx);
+    int64_t rec[3];
+    const int64_t nn = (int64_t)n * n;
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+        const int64_t i = e < cnt ? idx[e] : idx[0];
+        const int f = (int)(i / nn), rem = (int)(i % nn);
+        rec[e] = chain_rec(f, rem % n, rem / n, n);
+    }
+    float out[CP];
+    if (cnt == 1) {
+#pragma unroll
+        for (int k = 0; k < CP; ++k) out[k] = lvl[rec[0] * CP + k];
+    } else {
+#pragma clang fp contract(off)
+#pragma unroll
+        for (int k = 0; k < C; ++k)
+            out[k] = (float)((((double)lvl[rec[0] * CP + k] + (double)lvl[rec[1] * CP + k]) +
+                              (double)lvl[rec[2] * CP + k]) /
+                             3.0);
+#pragma unroll
+        for (int k = C; k < CP; ++k) out[k] = 0.0f;
+    }
+    float4 *q = reinterpret_cast<float4 *>(lvl + chain_rec(face, x, y, n) * CP);
+#pragma unroll
+    for (int i = 0; i < CP / 4; ++i) q[i] = make_float4(out[4 * i], out[4 * i + 1], out[4 * i + 2], out[4 * i + 3]);
 }
 
 // ---------------------------------------------------------------------------
@@ -401,31 +490,32 @@ __device__ __forceinline__ void accumulate_tap(const Tap &tp, const d3 &r, const
         const double w4[4] = {lw * ((1.0 - bl.fy) * (1.0 - bl.fx)), lw * ((1.0 - bl.fy) * bl.fx),
                               lw * (bl.fy * (1.0 - bl.fx)), lw * (bl.fy * bl.fx)};
         const float *lvl = chain + lvl_off[s]; // global pointer arithmetic: global loads
-        if (bl.x0 >= 0 && bl.x0 + 1 < ns && bl.y0 >= 0 && bl.y0 + 1 < ns) {
-            // footprint inside the face: four loads in flight
+        if (s > 0) {
+            // stored level: the bordered face holds the whole footprint
+            const int64_t t0 = chain_rec(fs.face, bl.x0, bl.y0, ns);
+            const int64_t tt[4] = {t0, t0 + 1, t0 + ns + 2, t0 + ns + 3};
+            float4 raw[4][CP / 4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+#pragma unroll
+                for (int q4 = 0; q4 < CP / 4; ++q4) raw[c][q4] = reinterpret_cast<const float4 *>(lvl + tt[c] * CP)[q4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const float *f = reinterpret_cast<const float *>(raw[c]);
+#pragma unroll
+                for (int k = 0; k < C; ++k) acc[k] += w4[c] * (double)f[k];
+            }
+        } else if (bl.x0 >= 0 && bl.x0 + 1 < ns && bl.y0 >= 0 && bl.y0 + 1 < ns) {
+            // level 0 (virtual), footprint inside the face
             const int64_t t0 = ((int64_t)fs.face * ns + bl.y0) * ns + bl.x0;
             const int64_t tt[4] = {t0, t0 + 1, t0 + ns, t0 + ns + 1};
-            if (s == 0) {
 #pragma unroll
-                for (int c = 0; c < 4; ++c) l0.add(tt[c], w4[c], acc);
-            } else {
-                float4 raw[4][CP / 4];
-#pragma unroll
-                for (int c = 0; c < 4; ++c)
-#pragma unroll
-                    for (int q4 = 0; q4 < CP / 4; ++q4) raw[c][q4] = reinterpret_cast<const float4 *>(lvl + tt[c] * CP)[q4];
-#pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    const float *f = reinterpret_cast<const float *>(raw[c]);
-#pragma unroll
-                    for (int k = 0; k < C; ++k) acc[k] += w4[c] * (double)f[k];
-                }
-            }
+            for (int c = 0; c < 4; ++c) l0.add(tt[c], w4[c], acc);
         } else {
-            // across a seam: one copy of the seam rule
+            // level 0 across a seam: one copy of the seam rule
 #pragma unroll 1
             for (int c = 0; c < 4; ++c)
-                accumulate_texel<K>(l0, lvl, s, fs.face, bl.x0 + (c & 1), bl.y0 + (c >> 1), ns,
+                accumulate_texel<K>(l0, lvl, 0, fs.face, bl.x0 + (c & 1), bl.y0 + (c >> 1), ns,
                                     c == 0 ? w4[0] : (c == 1 ? w4[1] : (c == 2 ? w4[2] : w4[3])), acc);
         }
     }
@@ -454,7 +544,7 @@ __global__ void __launch_bounds__(kFilterThreads) k_prefilter(FilterLaunch fl, L
     const int m = q + 1;
     for (int j = threadIdx.x; j < fl.T; j += blockDim.x) make_tap(j, m, fl.M, fl.T, fl.R, s_taps[j]);
     if (threadIdx.x < fl.M)
-        s_lvl[threadIdx.x] = threadIdx.x == 0 ? 0 : (level_offset(fl.R, threadIdx.x) - 6LL * fl.R * fl.R) * CP;
+        s_lvl[threadIdx.x] = threadIdx.x == 0 ? 0 : chain_level_base(fl.R, threadIdx.x) * CP;
     __syncthreads();
     if (threadIdx.x == 0) {
         double ws = 0.0;
@@ -520,7 +610,7 @@ __global__ void __launch_bounds__(kFilterThreads) k_sample_filter(int R, int M, 
 {
     constexpr int C = K + 3, CP = chain_stride(K);
     __shared__ int64_t s_lvl[16];
-    if (threadIdx.x < M) s_lvl[threadIdx.x] = threadIdx.x == 0 ? 0 : (level_offset(R, threadIdx.x) - 6LL * R * R) * CP;
+    if (threadIdx.x < M) s_lvl[threadIdx.x] = threadIdx.x == 0 ? 0 : chain_level_base(R, threadIdx.x) * CP;
     __syncthreads();
     const int64_t q = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kGroup;
     const int sub = threadIdx.x % kGroup;
@@ -580,11 +670,11 @@ hipError_t launch_sample_filter(const float *env, const uint8_t *ind_j, const fl
     if (K == KK) {                                                                                            \
         Level0<KK> l0{env, ind_j, ind_t};                                                                     \
         if (mode == 0)                                                                                        \
-            hipLaunchKernelGGL((k_sample_filter<KK, 0>), dim3(blocks), dim3(kFilterThreads), 0, stream, R, M, \
-                               T, l0, chain, dirs, a0, a1, n, out0, out1);                                    \
+            GLINT_LAUNCH("k_sample_filter", (k_sample_filter<KK, 0>), dim3(blocks), dim3(kFilterThreads), 0,  \
+                         stream, R, M, T, l0, chain, dirs, a0, a1, n, out0, out1);                            \
         else                                                                                                  \
-            hipLaunchKernelGGL((k_sample_filter<KK, 1>), dim3(blocks), dim3(kFilterThreads), 0, stream, R, M, \
-                               T, l0, chain, dirs, a0, a1, n, out0, out1);                                    \
+            GLINT_LAUNCH("k_sample_filter", (k_sample_filter<KK, 1>), dim3(blocks), dim3(kFilterThreads), 0,  \
+                         stream, R, M, T, l0, chain, dirs, a0, a1, n, out0, out1);                            \
         return hipGetLastError();                                                                             \
     }
     GLINT_SF(2)
@@ -597,7 +687,7 @@ hipError_t launch_sample_filter(const float *env, const uint8_t *ind_j, const fl
 
 size_t chain_bytes(int R, int K, int M)
 {
-    return (size_t)(level_offset(R, M) - 6LL * R * R) * chain_stride(K) * sizeof(float);
+    return (size_t)chain_level_base(R, M) * chain_stride(K) * sizeof(float);
 }
 
 template <int K, int DT>
@@ -609,8 +699,10 @@ static hipError_t launch_prefilter_t(const float *env, const uint8_t *ind_j, con
     // coarser chain levels per face
     const int tile = R < kTile ? R : kTile;
     const int tiles = R / tile;
-    hipLaunchKernelGGL((k_chain_tiles<K, DT>), dim3(6 * tiles * tiles), dim3(256), 0, stream, l0, R, M, chain,
-                       ind_pyr, rgb_pyr);
+    {
+        GLINT_LAUNCH("k_chain_tiles", (k_chain_tiles<K, DT>), dim3(6 * tiles * tiles), dim3(256), 0, stream, l0, R, M, chain,
+                           ind_pyr, rgb_pyr);
+    }
     int tile_levels = 0;
     while ((1 << (tile_levels + 1)) <= tile) ++tile_levels; // log2(tile)
     // levels the tiles did not build: per-level launches while the parent
@@ -620,15 +712,21 @@ static hipError_t launch_prefilter_t(const float *env, const uint8_t *ind_j, con
         if (parent <= 16) { // (16^2 + 8^2) records of <= 20 floats: < 64 KB of LDS
             const size_t shm =
                 sizeof(float) * (size_t)chain_stride(K) * (size_t)(parent * parent + (parent / 2) * (parent / 2));
-            hipLaunchKernelGGL(k_chain_faces<K>, dim3(6), dim3(256), shm, stream, R, M, s, chain);
+            GLINT_LAUNCH("k_chain_faces", k_chain_faces<K>, dim3(6), dim3(256), shm, stream, R, M, s, chain);
             break;
         }
         const int n = R >> s;
         const int64_t total = 6LL * n * n;
-        const float *src = chain + (level_offset(R, s - 1) - 6LL * R * R) * chain_stride(K);
-        float *dst = chain + (level_offset(R, s) - 6LL * R * R) * chain_stride(K);
-        hipLaunchKernelGGL(k_chain_level<K>, dim3((unsigned)((total + kChainThreads - 1) / kChainThreads)),
+        const float *src = chain + chain_level_base(R, s - 1) * chain_stride(K);
+        float *dst = chain + chain_level_base(R, s) * chain_stride(K);
+        GLINT_LAUNCH("k_chain_level", k_chain_level<K>, dim3((unsigned)((total + kChainThreads - 1) / kChainThreads)),
                            dim3(kChainThreads), 0, stream, l0, src, dst, n);
+    }
+    if (M > 1) {
+        int64_t ring = 0;
+        for (int s = 1; s < M; ++s) ring += 6LL * (4 * (R >> s) + 4);
+        GLINT_LAUNCH("k_chain_border", k_chain_border<K>, dim3((unsigned)((ring + 255) / 256)), dim3(256), 0, stream,
+                     R, M, chain);
     }
     if (M > 1) {
         FilterLaunch fl{};
@@ -644,7 +742,7 @@ static hipError_t launch_prefilter_t(const float *env, const uint8_t *ind_j, con
         fl.block_start[M - 1] = total;
         fl.xcd_chunk = (total + 7) / 8;
         const size_t shm = sizeof(Tap) * (size_t)T;
-        hipLaunchKernelGGL((k_prefilter<K, DT>), dim3(8 * fl.xcd_chunk), dim3(kFilterThreads), shm, stream, fl, l0,
+        GLINT_LAUNCH("k_prefilter", (k_prefilter<K, DT>), dim3(8 * fl.xcd_chunk), dim3(kFilterThreads), shm, stream, fl, l0,
                            chain, ind_pyr, rgb_pyr);
     }
     return hipGetLastError();

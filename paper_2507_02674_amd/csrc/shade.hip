@@ -410,8 +410,8 @@ template <int K, int DT>
 static hipError_t launch_shade_kd(const ShadeArgs &a, int V, hipStream_t stream)
 {
     const unsigned blocks = (unsigned)((a.P + kShadeThreads - 1) / kShadeThreads);
-    if (V == 1) hipLaunchKernelGGL((k_shade<K, DT, 1>), dim3(blocks), dim3(kShadeThreads), 0, stream, a);
-    else hipLaunchKernelGGL((k_shade<K, DT, 6>), dim3(blocks), dim3(kShadeThreads), 0, stream, a);
+    if (V == 1) GLINT_LAUNCH("k_shade", (k_shade<K, DT, 1>), dim3(blocks), dim3(kShadeThreads), 0, stream, a);
+    else GLINT_LAUNCH("k_shade", (k_shade<K, DT, 6>), dim3(blocks), dim3(kShadeThreads), 0, stream, a);
     return hipGetLastError();
 }
 
@@ -446,8 +446,8 @@ hipError_t launch_shade_views(int K, int dtype, int V, const void *views, const 
     const ShadeArgs *va = static_cast<const ShadeArgs *>(views);
 #define GLINT_SV(KK, DD, VV)                                                                                 \
     if (K == KK && dtype == DD && V == VV) {                                                                 \
-        hipLaunchKernelGGL((k_shade_views<KK, DD, VV>), dim3((unsigned)tiles), dim3(tile_px), 0, stream, va, \
-                           tile0, n_views);                                                                  \
+        GLINT_LAUNCH("k_shade_views", (k_shade_views<KK, DD, VV>), dim3((unsigned)tiles), dim3(tile_px), 0,  \
+                     stream, va, tile0, n_views);                                                            \
         return hipGetLastError();                                                                            \
     }
 #define GLINT_SV_K(KK) GLINT_SV(KK, 0, 1) GLINT_SV(KK, 1, 1) GLINT_SV(KK, 2, 1) GLINT_SV(KK, 3, 1) \
@@ -484,11 +484,15 @@ hipError_t launch_shade(const glint_gbuffer &g, int64_t P, const glint_env &env,
     if (F) {
         // surrogate form: the indicator pyramid is not read, so its storage type does not matter
         const unsigned blocks = (unsigned)((P + kShadeThreads - 1) / kShadeThreads);
-#define GLINT_SF(KK)                                                                                              \
-    if (K == KK) {                                                                                                \
-        if (V == 1) hipLaunchKernelGGL((k_shade<KK, 0, 1, true>), dim3(blocks), dim3(kShadeThreads), 0, stream, a); \
-        else hipLaunchKernelGGL((k_shade<KK, 0, 6, true>), dim3(blocks), dim3(kShadeThreads), 0, stream, a);        \
-        return hipGetLastError();                                                                                 \
+#define GLINT_SF(KK)                                                                                        \
+    if (K == KK) {                                                                                          \
+        if (V == 1)                                                                                         \
+            GLINT_LAUNCH("k_shade_surrogate", (k_shade<KK, 0, 1, true>), dim3(blocks), dim3(kShadeThreads), \
+                         0, stream, a);                                                                     \
+        else                                                                                                \
+            GLINT_LAUNCH("k_shade_surrogate", (k_shade<KK, 0, 6, true>), dim3(blocks), dim3(kShadeThreads), \
+                         0, stream, a);                                                                     \
+        return hipGetLastError();                                                                           \
     }
         GLINT_SF(2)
         GLINT_SF(4)

@@ -107,6 +107,10 @@ EXPORTS = {
     "glint_frame_batched": ([C.c_void_p, C.POINTER(EnvTask), C.c_int, C.POINTER(View), C.c_int, C.c_void_p,
                              C.c_void_p], C.c_int),
     "glint_batched_tile_px": ([C.c_void_p], C.c_int),
+    "glint_profile_enable": ([C.c_void_p, C.c_int], C.c_int),
+    "glint_profile_collect": ([C.c_void_p, C.POINTER(C.c_int)], C.c_int),
+    "glint_profile_entry": ([C.c_void_p, C.c_int, C.POINTER(C.c_char_p), C.POINTER(C.c_double),
+                             C.POINTER(C.c_int64)], C.c_int),
 }
 
 
@@ -315,3 +319,19 @@ def glint_frame_batched(ctx, envs, views, workspace, stream=None):
 
 def glint_batched_tile_px(ctx) -> int:
     return lib().glint_batched_tile_px(ctx)
+
+
+def glint_profile_enable(ctx, enable: bool = True) -> None:
+    _check(lib().glint_profile_enable(ctx, 1 if enable else 0))
+
+
+def glint_profile_collect(ctx) -> dict:
+    """Per-kernel totals so far: {name: (total_ms, launches)} (cumulative)."""
+    n = C.c_int()
+    _check(lib().glint_profile_collect(ctx, C.byref(n)))
+    out = {}
+    for i in range(n.value):
+        name, ms, cnt = C.c_char_p(), C.c_double(), C.c_int64()
+        _check(lib().glint_profile_entry(ctx, i, C.byref(name), C.byref(ms), C.byref(cnt)))
+        out[name.value.decode()] = (ms.value, cnt.value)
+    return out

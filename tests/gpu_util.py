@@ -43,9 +43,25 @@ def prefilter(ctx, env, ind_j, ind_t, K, M, T=64, dtype=G.GLINT_F32):
     rgb_pyr = torch.empty((n, 4), dtype=torch.float32, device="cuda")
     G.glint_prefilter(ctx, dev(env), dev(ind_j), dev(ind_t), R, K, fp, ws, ind_pyr, rgb_pyr)
     raw = host(ind_pyr).view(ndt) if ndt == np.uint16 else host(ind_pyr)
+    return raw, host(rgb_pyr), chain_levels(host(ws), R, K, M)
+
+
+def chain_levels(ws, R, K, M, borders=False):
+    """Chain levels 1..M-1 from the prefilter workspace: each level is stored
+    as 6 faces of (n+2)^2 records of CP floats (a one-texel border around
+    each face).  Returns the interiors concatenated [texels, K+3] (the
+    oracle's layout), or with borders=True the list of [6, n+2, n+2, K+3]."""
     CP = (K + 3 + 3) & ~3
-    chain = host(ws)[: (n - 6 * R * R) * CP].reshape(-1, CP)[:, : K + 3]
-    return raw, host(rgb_pyr), chain
+    out, o = [], 0
+    for s in range(1, M):
+        n = R >> s
+        cnt = 6 * (n + 2) * (n + 2) * CP
+        lvl = ws[o:o + cnt].reshape(6, n + 2, n + 2, CP)[..., : K + 3]
+        out.append(lvl if borders else lvl[:, 1:-1, 1:-1].reshape(-1, K + 3))
+        o += cnt
+    if borders:
+        return out
+    return np.concatenate(out) if out else np.zeros((0, K + 3), np.float32)
 
 
 def decode(raw, dtype):

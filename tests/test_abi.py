@@ -38,8 +38,8 @@ def test_host_side_queries():
     assert G.glint_pyramid_texels(3, 1) == 0  # not a power of two
     assert G.glint_pyramid_texels(32, 7) == 0  # too many mips
     fp = G.PrefilterParams(8, 64, G.GLINT_F32)
-    # chain levels 1..7, K+3 = 11 channels padded to 12 floats
-    assert G.glint_prefilter_workspace_bytes(256, 8, fp) == (524280 - 6 * 256 * 256) * 12 * 4
+    # chain levels 1..7 with a one-texel border per face, K+3 = 11 channels padded to 12 floats
+    assert G.glint_prefilter_workspace_bytes(256, 8, fp) == sum(6 * ((256 >> s) + 2) ** 2 for s in range(1, 8)) * 12 * 4
     assert G.glint_partition_workspace_bytes(256) > 0
     assert G.glint_partition_workspace_bytes(100) == 0
 

@@ -129,6 +129,47 @@ def test_prefilter_full_pyramid(ctx, R, K, M):
     assert d.max() <= 1 and np.all(rgb[:, 3] == 0)
 
 
+def seam_texel(level, face, x, y, n):
+    """The seam rule for texel (x, y) of `face` beyond the face (x or y in
+    {-1, n}), from the interior texels of one level [6, n, n, C] (float64):
+    beyond an edge the texel of the owning face nearest the extended
+    centre's direction; beyond a corner the mean of the three corner texels."""
+    def owner(xx, yy):
+        d = oracle.face_dir(int(face), 2.0 * (xx + 0.5) / n - 1.0, 2.0 * (yy + 0.5) / n - 1.0)
+        f2, s, t = oracle.dir_face(d)
+        a = min(max(int(np.floor((s + 1.0) * 0.5 * n)), 0), n - 1)
+        b = min(max(int(np.floor((t + 1.0) * 0.5 * n)), 0), n - 1)
+        return level[f2, b, a]
+    xin, yin = 0 <= x < n, 0 <= y < n
+    if xin or yin:
+        return owner(x, y)
+    xc, yc = (0 if x < 0 else n - 1), (0 if y < 0 else n - 1)
+    return ((level[face, yc, xc] + owner(x, yc)) + owner(xc, y)) / 3.0
+
+
+@pytest.mark.parametrize("R,K,M", [(32, 4, 6), (16, 8, 5)])
+def test_chain_borders_follow_seam_rule(ctx, R, K, M):
+    """Every border texel of every stored chain level holds the seam rule's
+    value (edges bit-exact copies; corners the mean rounded once to float)."""
+    import torch
+    from paper_2507_02674_amd.pipeline import EnvPipeline
+    env = synth.make_env(R, 2)
+    pipe = EnvPipeline(ctx, R, K, M, 64)
+    pipe.run(torch.from_numpy(env).cuda())
+    levels = U.chain_levels(U.host(pipe.filt_ws), R, K, M, borders=True)
+    for s, lvl in enumerate(levels, start=1):
+        n = R >> s
+        inner = lvl[:, 1:-1, 1:-1].astype(np.float64)
+        for face in range(6):
+            for y in range(-1, n + 1):
+                for x in range(-1, n + 1):
+                    if 0 <= x < n and 0 <= y < n:
+                        continue
+                    want = seam_texel(inner, face, x, y, n).astype(np.float32)
+                    got = lvl[face, y + 1, x + 1]
+                    assert np.array_equal(got, want), (s, face, x, y, got, want)
+
+
 @pytest.mark.parametrize("dtype", [G.GLINT_F16, G.GLINT_BF16, G.GLINT_UNORM16])
 def test_prefilter_storage_types(ctx, dtype):
     U.log(f"prefilter dtype={dtype}")
