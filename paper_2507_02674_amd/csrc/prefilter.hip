@@ -18,7 +18,7 @@
 //   k_chain_level   one level per launch (only for faces larger than 32
 //                   texels that the tiles did not reach, R >= 2048);
 //   k_chain_border  the border rings of every stored level;
-//   k_prefilter     mips >= 1: a group of G = 8 lanes per output texel splits
+//   k_prefilter     mips >= 1: a group of G lanes per output texel splits
 //                   the T taps, accumulates in double, reduces across the
 //                   group with cross-lane shuffles; the tap table of the
 //                   block's mip lives in LDS.  Blocks are mip-homogeneous and
@@ -29,8 +29,22 @@
 namespace glint {
 
 constexpr int kChainThreads = 256;
+// Tuning knobs of the filter kernels (build-time; results do not depend on
+// them beyond the order of the group's double sums).  Measured on the
+// 6x256^2, K=8, T=64 frame: 2 lanes per texel with both trilinear levels
+// loaded together is the fastest of 1, 2, 4, 8 lanes with and without it
+// (the kernel is bound by vector-cache tag throughput, not by the ALUs).
+#ifndef GLINT_FILTER_LANES
+#define GLINT_FILTER_LANES 2
+#endif
+#ifndef GLINT_FILTER_MIN_WAVES
+#define GLINT_FILTER_MIN_WAVES 1
+#endif
+#ifndef GLINT_FILTER_LEVEL_UNROLL
+#define GLINT_FILTER_LEVEL_UNROLL 1
+#endif
 constexpr int kFilterThreads = 256;
-constexpr int kGroup = 8; // lanes per output texel
+constexpr int kGroup = GLINT_FILTER_LANES; // lanes per output texel
 
 __host__ __device__ constexpr int chain_stride(int K) { return (K + 3 + 3) & ~3; }
 
@@ -481,6 +495,35 @@ __device__ __forceinline__ void accumulate_tap(const Tap &tp, const d3 &r, const
     const int s0 = (int)l0f;
     const double fr = tp.lod - l0f;
     const int nlev = fr > 0.0 ? 2 : 1; // fr > 0 implies s0 + 1 <= M - 1
+#if GLINT_FILTER_LEVEL_UNROLL
+    if (s0 >= 1) {
+        // both stored levels at once (the second repeats the first with weight 0 when lod is whole)
+        const int s1 = nlev == 2 ? s0 + 1 : s0;
+        const int n0 = R >> s0, n1 = R >> s1;
+        const bilin b0 = bilinear_at(fs, n0), b1 = bilinear_at(fs, n1);
+        const double lw0 = tp.w * (1.0 - fr), lw1 = tp.w * fr;
+        const double w8[8] = {lw0 * ((1.0 - b0.fy) * (1.0 - b0.fx)), lw0 * ((1.0 - b0.fy) * b0.fx),
+                              lw0 * (b0.fy * (1.0 - b0.fx)),         lw0 * (b0.fy * b0.fx),
+                              lw1 * ((1.0 - b1.fy) * (1.0 - b1.fx)), lw1 * ((1.0 - b1.fy) * b1.fx),
+                              lw1 * (b1.fy * (1.0 - b1.fx)),         lw1 * (b1.fy * b1.fx)};
+        const float *lv0 = chain + lvl_off[s0], *lv1 = chain + lvl_off[s1];
+        const int64_t a0 = chain_rec(fs.face, b0.x0, b0.y0, n0), a1 = chain_rec(fs.face, b1.x0, b1.y0, n1);
+        const float *src[8] = {lv0 + a0 * CP, lv0 + (a0 + 1) * CP, lv0 + (a0 + n0 + 2) * CP, lv0 + (a0 + n0 + 3) * CP,
+                               lv1 + a1 * CP, lv1 + (a1 + 1) * CP, lv1 + (a1 + n1 + 2) * CP, lv1 + (a1 + n1 + 3) * CP};
+        float4 raw[8][CP / 4];
+#pragma unroll
+        for (int c = 0; c < 8; ++c)
+#pragma unroll
+            for (int q4 = 0; q4 < CP / 4; ++q4) raw[c][q4] = reinterpret_cast<const float4 *>(src[c])[q4];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const float *f = reinterpret_cast<const float *>(raw[c]);
+#pragma unroll
+            for (int k = 0; k < C; ++k) acc[k] += w8[c] * (double)f[k];
+        }
+        return;
+    }
+#endif
 #pragma unroll 1
     for (int li = 0; li < nlev; ++li) {
         const int s = s0 + li;
@@ -522,7 +565,7 @@ __device__ __forceinline__ void accumulate_tap(const Tap &tp, const d3 &r, const
 }
 
 template <int K, int DT>
-__global__ void __launch_bounds__(kFilterThreads) k_prefilter(FilterLaunch fl, Level0<K> l0,
+__global__ void __launch_bounds__(kFilterThreads, GLINT_FILTER_MIN_WAVES) k_prefilter(FilterLaunch fl, Level0<K> l0,
                                                                const float *__restrict__ chain,
                                                                void *__restrict__ ind_pyr,
                                                                float *__restrict__ rgb_pyr)
@@ -562,8 +605,11 @@ __global__ void __launch_bounds__(kFilterThreads) k_prefilter(FilterLaunch fl, L
 #pragma unroll
     for (int k = 0; k < C; ++k) acc[k] = 0.0;
 
+    int x = 0, y = 0, f = 0;
     if (active) {
-        const int x = (int)(texel % n), y = (int)((texel / n) % n), f = (int)(texel / ((int64_t)n * n));
+        x = (int)(texel % n);
+        y = (int)((texel / n) % n);
+        f = (int)(texel / ((int64_t)n * n));
         const double inv = 1.0 / (double)n;
         d3 r = face_dir(f, 2.0 * ((double)x + 0.5) * inv - 1.0, 2.0 * ((double)y + 0.5) * inv - 1.0);
         const double len = sqrt(r.x * r.x + r.y * r.y + r.z * r.z);
@@ -585,7 +631,7 @@ __global__ void __launch_bounds__(kFilterThreads) k_prefilter(FilterLaunch fl, L
     }
     if (active && sub == 0) {
         const double ws = s_wsum;
-        const int64_t out = level_offset(fl.R, m) + texel;
+        const int64_t out = level_offset(fl.R, m) + ((int64_t)f * n + y) * n + x;
 #pragma unroll
         for (int k = 0; k < K; ++k) store_value<DT>(ind_pyr, out * K + k, acc[k] / ws);
         reinterpret_cast<float4 *>(rgb_pyr)[out] =
