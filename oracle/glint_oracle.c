@@ -691,11 +691,14 @@ static void dual_gated(double N, double p, float xi1, float xi2, int N_exact, no
 }
 
 /* A sampled count is "near an integer" if it lies within 1e-5 of one
- * without being one. */
+ * without being one, or, for counts so large that a double's spacing
+ * approaches that band (beyond ~1e10), within 8 units in the last place:
+ * there the evaluation order alone moves a count by a few ulps. */
 static int near_int_flag(double v)
 {
     double d = fabs(v - floor(v + 0.5));
-    return d > 0.0 && d < 1e-5;
+    double band = 8.0 * (nextafter(fabs(v), INFINITY) - fabs(v));
+    return d > 0.0 && d < (band > 1e-5 ? band : 1e-5);
 }
 
 /* Sec. 6 (hierarchical multinomial from recursive binomials): balanced binary

@@ -134,6 +134,10 @@ struct ShadeArgs {
 __device__ __forceinline__ void dual_gated(double N, double p, float xi1, float xi2, double &n, double &nb,
                                            uint32_t &code)
 {
+    // Rounded as written (no fused multiply-add): at N ~ 1e12 one ulp of mu
+    // is ~1e-4, so every operation must round as in the definition for the
+    // counts' integer parts to agree.
+#pragma clang fp contract(off)
     const gate_f g = gate_thresholds((float)N, (float)p);
     const bool BnN = xi1 < g.th_nN;
     const bool Bn1N = xi1 < g.th_n1N;

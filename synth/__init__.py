@@ -212,6 +212,34 @@ def scene_frame(W: int, H: int, seed: int = 7, density_decades=(6.0, 9.0), eye=(
     return _finish(g)
 
 
+def n_sweep(W: int = 512, rows: int = 64, max_decades: float = 12.0, seed: int = 5) -> dict:
+    """Counts sweep: row r has N_P = 10^(max_decades r / (rows-1)) (1 .. 1e12,
+    the range where float counts lose integers); along a row the normal tilts
+    and the roughness runs log-uniformly over [0.02, 0.5], so each row sees a
+    fixed pattern of reflection probabilities.  Footprint area 1e-4."""
+    j, i = np.meshgrid(np.arange(rows), np.arange(W), indexing="ij")
+    j, i = j.ravel(), i.ravel()
+    P = W * rows
+    g = _empty_gbuf(P)
+    rng = np.random.default_rng(seed)
+    phi = 2.0 * np.pi * i / W
+    tilt = 0.25 + 0.5 * ((i * 7) % W) / W
+    n = np.stack([np.sin(tilt) * np.cos(phi), np.cos(tilt), np.sin(tilt) * np.sin(phi)], -1)
+    g["nx"][:], g["ny"][:], g["nz"][:] = n[:, 0], n[:, 1], n[:, 2]
+    v = np.stack([np.zeros(P), np.ones(P), np.zeros(P)], -1)
+    g["vx"][:], g["vy"][:], g["vz"][:] = v[:, 0], v[:, 1], v[:, 2]
+    g["u"][:] = rng.uniform(-40.0, 40.0, P)
+    g["v"][:] = rng.uniform(-40.0, 40.0, P)
+    g["area"][:] = 1e-4
+    a = 0.02 * 25.0 ** (((i * 13) % W) / (W - 1.0))
+    g["ax"][:] = a
+    g["ay"][:] = a * (0.5 + ((i * 5) % W) / W)
+    g["density"][:] = 10.0 ** (max_decades * j / (rows - 1.0)) / 1e-4
+    g["f0r"][:] = g["f0g"][:] = g["f0b"][:] = 0.9
+    g["surf_id"][:] = 1 + j
+    return _finish(g)
+
+
 def subsample_gbuf(g: dict, pixels: np.ndarray) -> dict:
     return {k: np.ascontiguousarray(v[pixels]) for k, v in g.items()}
 
