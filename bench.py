@@ -73,7 +73,8 @@ def prefilter_cost(R, M, T, K, dtype_bytes=4):
     two chain levels the tap's lod touches (one FMA per channel and texel),
     plus the tap's direction work; then C normalisations.  Bytes: the
     pyramid written (K indicator values of the stored type + 4 RGB floats
-    per texel) and the source chain read once."""
+    per texel) and the stored source chain (levels >= 1 with their border
+    rings, 16-byte-padded records) read once."""
     C = K + 3
     ops = 0.0
     texels = 0
@@ -84,8 +85,8 @@ def prefilter_cost(R, M, T, K, dtype_bytes=4):
         per_texel = float(np.sum(levels * (4 * C + TAP_LEVEL_OPS) + TAP_FIXED_OPS)) + C
         ops += 6 * n * n * per_texel
         texels += 6 * n * n
-    chain_texels = sum(6 * (R >> s) ** 2 for s in range(1, M))
-    bytes_ = texels * (K * dtype_bytes + 16) + 6 * R * R * (12 + 5) + chain_texels * 4 * ((C + 3) // 4 * 4)
+    chain_records = sum(6 * ((R >> s) + 2) ** 2 for s in range(1, M))
+    bytes_ = texels * (K * dtype_bytes + 16) + chain_records * 4 * ((C + 3) // 4 * 4)
     return ops, bytes_, texels
 
 
@@ -113,6 +114,40 @@ def mlp_flops_per_row(K, padded=False):
     if padded:
         return 2.0 * (16 * 64 + 2 * 64 * 64 + 64 * 32)
     return 2.0 * (5 * 64 + 2 * 64 * 64 + 64 * K)
+
+
+# --- measured HBM traffic ---------------------------------------------------------
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SOURCES = {"k_prefilter": ("prefilter.hip", "device.hpp"), "k_shade": ("shade.hip", "device.hpp"),
+                  "k_shade_surrogate": ("shade.hip", "device.hpp"), "k_mlp_lookup": ("mlp.hip", "device.hpp")}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "frame_hbm_counters.md")
+
+
+def kernel_source_hash(kernel):
+    """Short hash of the sources a kernel is built from (to tell whether
+    recorded counters still describe the built kernel)."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[kernel]:
+        with open(os.path.join(ROOT, "paper_2507_02674_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(kernel, config_tag):
+    """HBM bytes per launch of `kernel` on configuration `config_tag` from the
+    counter summary (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy of
+    known size), or None if absent or recorded for other kernel sources."""
+    import re
+    try:
+        text = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    for m in re.finditer(r"^traffic (\S+) (\S+) bytes=(\d+) sources=([0-9a-f]+)$", text, re.M):
+        if m.group(1) == kernel and m.group(2) == config_tag and m.group(4) == kernel_source_hash(kernel):
+            return int(m.group(3))
+    return None
 
 
 # --- helpers -------------------------------------------------------------------------
@@ -183,11 +218,11 @@ def kernel_table(G, ctx, steps):
     return {k: {"avg_ms": round(ms / n, 5), "launches_per_step": n / steps} for k, (ms, n) in prof.items()}
 
 
-def alu_record(kernel, ops, avg_ms, extra=None):
+def alu_record(kernel, ops, avg_ms, extra=None, config_tag=None):
     achieved = ops / (avg_ms * 1e-3) / 1e12
     r = {"bound": "alu", "kernel": kernel, "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 4),
-         "unit": "TOP/s (VALU lane-ops)", "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": None,
-         "ops_per_launch": ops}
+         "unit": "TOP/s (VALU lane-ops)", "frac": round(achieved / VALU_PEAK_TOPS, 4),
+         "traffic": recorded_traffic(kernel, config_tag) if config_tag else None, "ops_per_launch": ops}
     if extra:
         r.update(extra)
     return r
@@ -326,27 +361,30 @@ def main():
     value = glint_pixels / (ms_per_step * 1e-3) / 1e6
 
     # roofline records: prefilter, shading, and the network lookup
+    config_tag = f"{w.name}-{a.form}-{a.dtype}-v{a.vertices}"
     pf_ops, pf_bytes, pf_texels = prefilter_cost(w.R, w.M, w.T, w.K, STORAGE_BYTES[a.dtype])
     records = {}
     if "k_prefilter" in kernels:
         ms = kernels["k_prefilter"]["avg_ms"]
         records["k_prefilter"] = alu_record("k_prefilter", pf_ops, ms, {
             "ops_per_texel": round(pf_ops / pf_texels, 1), "output_texels": pf_texels,
-            "hbm_gbs": round(pf_bytes / (ms * 1e-3) / 1e9, 1),
-            "hbm_frac": round(pf_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)})
+            "algorithmic_bytes": pf_bytes, "hbm_gbs": round(pf_bytes / (ms * 1e-3) / 1e9, 1),
+            "hbm_frac": round(pf_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}, config_tag)
     shade_kernel = "k_shade_surrogate" if a.form == "surrogate" else "k_shade"
     if shade_kernel in kernels:
         ms = kernels[shade_kernel]["avg_ms"]
         opp = shade_ops_per_pixel(w.K, a.vertices)
         records[shade_kernel] = alu_record(shade_kernel, opp * glint_pixels, ms, {
-            "ops_per_pixel": opp, "hbm_gbs": round(SHADE_BYTES_PER_PIXEL * shader.P / (ms * 1e-3) / 1e9, 1),
-            "hbm_frac": round(SHADE_BYTES_PER_PIXEL * shader.P / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)})
+            "ops_per_pixel": opp, "algorithmic_bytes": SHADE_BYTES_PER_PIXEL * shader.P,
+            "hbm_gbs": round(SHADE_BYTES_PER_PIXEL * shader.P / (ms * 1e-3) / 1e9, 1),
+            "hbm_frac": round(SHADE_BYTES_PER_PIXEL * shader.P / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}, config_tag)
     if "k_mlp_lookup" in kernels:
         ms = kernels["k_mlp_lookup"]["avg_ms"]
         fl = mlp_flops_per_row(w.K) * shader.P
         ach = fl / (ms * 1e-3) / 1e12
         records["k_mlp_lookup"] = {"bound": "mfma", "kernel": "k_mlp_lookup", "achieved": round(ach, 3),
-                                   "peak": BF16_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s", "traffic": None,
+                                   "peak": BF16_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                   "traffic": recorded_traffic("k_mlp_lookup", config_tag),
                                    "frac": round(ach / BF16_MFMA_PEAK_TFLOPS, 4), "flops_per_launch": fl,
                                    "padded_flops_per_launch": mlp_flops_per_row(w.K, True) * shader.P}
     dominant = max((k for k in records), key=lambda k: kernels[k]["avg_ms"] * kernels[k]["launches_per_step"])
@@ -364,21 +402,27 @@ def main():
            "kernels": kernels, "roofline": roofline, "other_rooflines": others}
     out.update(extra)
     if a.dtype != "f32" or a.form != "plain":
-        # radiance against the plain f32 path on the same frame (itself checked against the oracle)
+        # against the plain f32 path on the same frame (itself checked against the oracle): reflection
+        # probabilities p_k, per-pixel radiance, and the frame's mean radiance
         ref_pipe = EnvPipeline(ctx, w.R, w.K, w.M, w.T, G.GLINT_F32, w.ell)
         ref_pipe.build_luts()
         ref_pipe.run(env)
         ref_sh = Shader(ctx, gbuf_np, seed=w.hash_seed, vertices=a.vertices)
-        ref_sh.run(ref_pipe.env_struct())
+        P = shader.P
+        dbg0 = {"probs": torch.empty((P, w.K), dtype=torch.float64, device="cuda")}
+        dbg1 = {"probs": torch.empty((P, w.K), dtype=torch.float64, device="cuda")}
+        ref_sh.run(ref_pipe.env_struct(), debug=dbg0)
+        shader.run(envs, debug=dbg1)
         torch.cuda.synchronize()
         hit = torch.from_numpy(gbuf_np["surf_id"] != 0xFFFFFFFF).cuda()
         r0 = ref_sh.radiance[hit].double().sum(1)
         r1 = shader.radiance[hit].double().sum(1)
         rel = ((r1 - r0).abs() / r0.abs().clamp_min(1e-12))
         lit = r0 > 1e-6 * r0.max()
-        out["radiance_vs_plain_f32"] = {"mean_rel_err": float(rel[lit].mean().item()),
-                                        "mean_abs_err_over_mean": float(((r1 - r0).abs().mean() /
-                                                                         r0.abs().mean()).item())}
+        out["vs_plain_f32"] = {
+            "probs_mean_abs_err": float((dbg1["probs"][hit] - dbg0["probs"][hit]).abs().mean().item()),
+            "radiance_mean_rel_err": float(rel[lit].mean().item()),
+            "frame_mean_radiance_ratio": float((r1.mean() / r0.mean()).item())}
     if not a.no_cpu_baseline and a.form == "plain":
         if a.dtype == "f32":
             ind_h = pipe.ind_pyr.cpu().numpy()
