@@ -37,19 +37,28 @@ constexpr int kInferMaxBlocks = 1024;
 
 __device__ __forceinline__ uint16_t to_bf16(float f)
 {
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7F800000u) == 0x7F800000u && (u & 0x7FFFFFu)) return (uint16_t)((u >> 16) | 0x40u);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
+    return __builtin_bit_cast(uint16_t, (__bf16)f); // round to nearest even (v_cvt_pk_bf16_f32)
+}
+
+// Four floats to four packed bfloat16 (two conversions of two).
+__device__ __forceinline__ uint2 pack_bf16x4(float a, float b, float c, float d)
+{
+    const uint32_t lo = (uint32_t)to_bf16(a) | ((uint32_t)to_bf16(b) << 16);
+    const uint32_t hi = (uint32_t)to_bf16(c) | ((uint32_t)to_bf16(d) << 16);
+    return make_uint2(lo, hi);
 }
 
 __device__ __forceinline__ float from_bf16(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
-__device__ __forceinline__ float silu(float z) { return z / (1.0f + __expf(-z)); }
+// Logistic function with the hardware exp and reciprocal (a few ulp; the
+// result is rounded to bfloat16 or scales a bfloat16 error signal).
+__device__ __forceinline__ float sigmoid(float z) { return __builtin_amdgcn_rcpf(1.0f + __expf(-z)); }
+
+__device__ __forceinline__ float silu(float z) { return z * sigmoid(z); }
 
 __device__ __forceinline__ float dsilu(float z)
 {
-    const float s = 1.0f / (1.0f + __expf(-z));
+    const float s = sigmoid(z);
     return s * (1.0f + z * (1.0f - s));
 }
 
@@ -118,65 +127,99 @@ __device__ __forceinline__ void stage_weights(const uint16_t *__restrict__ wb, u
     }
 }
 
-// out[r][n] = bf16(silu(in[r][:Kd] . W[n][:Kd] + bias[n])) for the 32 rows
+// Transposed product tile: acc[t] = sum_k W[n0 + u][k] in[r][k] with
+// u = 8(t/4) + 4(lane/32) + t%4 and r = lane%32: the weights are the
+// first operand and the activations the second, so both are read as
+// 16-byte rows, and each lane ends with four runs of four consecutive units
+// of one sample (stored as 8-byte bfloat16 quads).
+__device__ __forceinline__ void unit_tile(const uint16_t *W, int ldw, const uint16_t *in, int ldi, int Kd, int n0,
+                                          f32x16 &acc)
+{
+    const int l = threadIdx.x & 63, r = l & 31, kg = (l >> 5) * 8;
+    zero(acc);
+    for (int k0 = 0; k0 < Kd; k0 += 16) {
+        const bf16x8 a = *reinterpret_cast<const bf16x8 *>(W + (n0 + r) * ldw + k0 + kg);
+        const bf16x8 b = *reinterpret_cast<const bf16x8 *>(in + r * ldi + k0 + kg);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+    }
+}
+
+// out[r][n] = bf16(silu(in[r][:Kd] . W[n][:Kd] + bias[n])) for the 32 samples
 // and 64 units; z[r][n] keeps the float pre-activation when z is non-null.
 __device__ __forceinline__ void dense_silu(const uint16_t *in, int ldi, int Kd, const uint16_t *W, int ldw,
                                            const float *__restrict__ bias, uint16_t *out, float *z)
 {
-#pragma unroll 1
+    const int r = threadIdx.x & 31, h = (threadIdx.x & 63) >> 5;
+#pragma unroll
     for (int n0 = 0; n0 < kH; n0 += 32) {
         f32x16 acc;
-        zero(acc);
-        tile_mma<true, true>(in, ldi, 1, W + n0 * ldw, 1, ldw, Kd, acc);
-        const int n = n0 + acc_col();
-        const float bn = bias[n];
+        unit_tile(W, ldw, in, ldi, Kd, n0, acc);
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            const int r = acc_row(i);
-            const float zz = acc[i] + bn;
-            if (z) z[r * kH + n] = zz;
-            out[r * kLdH + n] = to_bf16(silu(zz));
+        for (int q = 0; q < 4; ++q) {
+            const int n = n0 + 8 * q + 4 * h;
+            const float4 b4 = *reinterpret_cast<const float4 *>(bias + n);
+            const float z0 = acc[4 * q] + b4.x, z1 = acc[4 * q + 1] + b4.y, z2 = acc[4 * q + 2] + b4.z,
+                        z3 = acc[4 * q + 3] + b4.w;
+            if (z) *reinterpret_cast<float4 *>(z + r * kH + n) = make_float4(z0, z1, z2, z3);
+            *reinterpret_cast<uint2 *>(out + r * kLdH + n) = pack_bf16x4(silu(z0), silu(z1), silu(z2), silu(z3));
         }
     }
 }
 
-// logit[r][n] = h[r][:] . W4[n][:] + b4[n] for n < 32 (float, [32][32]).
-__device__ __forceinline__ void dense_out(const uint16_t *h, const uint16_t *W4, const float *__restrict__ b4,
-                                          float *logit)
+// Output layer in registers: logit[4q + i] = h[r][:] . W4[u][:] + b4[u] for
+// u = 8q + 4(lane/32) + i (16 of the 32 padded outputs; the lane with the
+// other half is lane ^ 32).
+__device__ __forceinline__ void dense_out(const uint16_t *hin, const uint16_t *W4, const float *__restrict__ b4,
+                                          float (&logit)[16])
 {
+    const int h = (threadIdx.x & 63) >> 5;
     f32x16 acc;
-    zero(acc);
-    tile_mma<true, true>(h, kLdH, 1, W4, 1, kLdH, kH, acc);
-    const int n = acc_col();
-    const float bn = b4[n];
+    unit_tile(W4, kLdH, hin, kLdH, kH, 0, acc);
 #pragma unroll
-    for (int i = 0; i < 16; ++i) logit[acc_row(i) * kOut + n] = acc[i] + bn;
+    for (int q = 0; q < 4; ++q) {
+        const float4 b = *reinterpret_cast<const float4 *>(b4 + 8 * q + 4 * h);
+        logit[4 * q] = acc[4 * q] + b.x;
+        logit[4 * q + 1] = acc[4 * q + 1] + b.y;
+        logit[4 * q + 2] = acc[4 * q + 2] + b.z;
+        logit[4 * q + 3] = acc[4 * q + 3] + b.w;
+    }
 }
 
-// Softmax of row r's first K logits: y_k = exp(logit_k - mx) * inv.
-__device__ __forceinline__ void softmax_stats(const float *logit, int r, int K, float &mx, float &inv)
+__device__ __forceinline__ int out_unit(int j) { return 8 * (j >> 2) + 4 * ((threadIdx.x & 63) >> 5) + (j & 3); }
+
+// Softmax over the first K outputs of each sample, across the lane pair
+// (lane, lane ^ 32): y[j] for this lane's units (0 for units >= K).
+__device__ __forceinline__ void softmax_pair(const float (&logit)[16], int K, float (&y)[16])
 {
-    mx = -3.4e38f;
-    for (int k = 0; k < K; ++k) mx = fmaxf(mx, logit[r * kOut + k]);
+    float mx = -3.4e38f;
+#pragma unroll
+    for (int j = 0; j < 16; ++j)
+        if (out_unit(j) < K) mx = fmaxf(mx, logit[j]);
+    mx = fmaxf(mx, __shfl_xor(mx, 32, 64));
     float se = 0.0f;
-    for (int k = 0; k < K; ++k) se += __expf(logit[r * kOut + k] - mx);
-    inv = 1.0f / se;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        y[j] = out_unit(j) < K ? __expf(logit[j] - mx) : 0.0f;
+        se += y[j];
+    }
+    se += __shfl_xor(se, 32, 64);
+    const float inv = 1.0f / se;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) y[j] *= inv;
 }
 
 // Per-wave LDS of the inference kernels: inputs and two ping-pong hidden
-// buffers; the float logits reuse the second hidden buffer.
+// buffers (the output layer and softmax stay in registers).
 struct InferTile {
     uint16_t x[32 * kLdX];
     uint16_t h[2][32 * kLdH];
 };
-static_assert(32 * kOut * sizeof(float) <= sizeof(uint16_t) * 32 * kLdH, "logits fit a hidden buffer");
 
 // Per-wave LDS of the training kernel (one wave per block).
 struct TrainTile {
     uint16_t x[32 * kLdX];    // inputs, bf16 (cols 5.. zero)
     uint16_t h[3][32 * kLdH]; // h1..h3, bf16
     float z[3][32 * kH];      // z1..z3, float
-    float logit[32 * kOut];   // output logits, float
     uint16_t dz[2][32 * kLdH]; // hidden error signals (ping-pong), bf16
     uint16_t dz4[32 * kLdO];  // output error signal, bf16 (cols K.. zero)
 };
@@ -208,26 +251,30 @@ __global__ void __launch_bounds__(64) k_mlp_grad(const float *__restrict__ x, co
     __syncthreads();
     dense_silu(t.h[1], kLdH, kH, W3, kLdH, w + ob3, t.h[2], t.z[2]);
     __syncthreads();
-    dense_out(t.h[2], W4, w + ob4, t.logit);
-    __syncthreads();
-
-    // softmax, loss and the output error signal (y - t) / B; one row per lane
+    // output layer, softmax, loss and the output error signal (y - t) / B,
+    // in registers (sample r = lane % 32, 16 of its outputs per lane)
+    float logit[16], y[16];
+    dense_out(t.h[2], W4, w + ob4, logit);
+    softmax_pair(logit, K, y);
     float loss = 0.0f;
-    if (lane < 32) {
-        const int r = lane;
+    {
+        const int r = lane & 31;
         const bool valid = row0 + r < B;
-        float mx, inv;
-        softmax_stats(t.logit, r, K, mx, inv);
-        for (int k = 0; k < kOut; ++k) {
-            float d = 0.0f;
-            if (k < K && valid) {
-                const float y = __expf(t.logit[r * kOut + k] - mx) * inv;
-                const float tk = target[(int64_t)(row0 + r) * K + k];
-                d = (y - tk) / (float)B;
-                loss -= tk * logf(fmaxf(y, 1e-30f));
+        float d[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const int o = out_unit(j);
+            d[j] = 0.0f;
+            if (o < K && valid) {
+                const float tk = target[(int64_t)(row0 + r) * K + o];
+                d[j] = (y[j] - tk) / (float)B;
+                loss -= tk * logf(fmaxf(y[j], 1e-30f));
             }
-            t.dz4[r * kLdO + k] = to_bf16(d);
         }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            *reinterpret_cast<uint2 *>(t.dz4 + r * kLdO + out_unit(4 * q)) =
+                pack_bf16x4(d[4 * q], d[4 * q + 1], d[4 * q + 2], d[4 * q + 3]);
     }
     __syncthreads();
     float *P = partial + (int64_t)blockIdx.x * kParams;
@@ -398,12 +445,17 @@ struct InferInput {
 };
 
 // Features of a surface pixel: reflection direction and scaled ln alphas.
+// (float arithmetic: the inputs are rounded to bfloat16 before use).
 __device__ __forceinline__ void pixel_features(const glint_gbuffer &g, int64_t i, float *f)
 {
-    const double nx = g.nx[i], ny = g.ny[i], nz = g.nz[i], vx = g.vx[i], vy = g.vy[i], vz = g.vz[i];
-    const double mu = nx * vx + ny * vy + nz * vz;
-    surrogate_features(2.0 * mu * nx - vx, 2.0 * mu * ny - vy, 2.0 * mu * nz - vz, (double)g.ax[i],
-                       (double)g.ay[i], f);
+    const float nx = g.nx[i], ny = g.ny[i], nz = g.nz[i], vx = g.vx[i], vy = g.vy[i], vz = g.vz[i];
+    const float mu = nx * vx + ny * vy + nz * vz;
+    const float c = -2.3025850929940457f, h = 1.6094379124341003f; // centre, half width of [ln 0.02, ln 0.5]
+    f[0] = 2.0f * mu * nx - vx;
+    f[1] = 2.0f * mu * ny - vy;
+    f[2] = 2.0f * mu * nz - vz;
+    f[3] = (__logf(g.ax[i]) - c) / h;
+    f[4] = (__logf(g.ay[i]) - c) / h;
 }
 
 template <int SRC>
@@ -435,9 +487,10 @@ __global__ void __launch_bounds__(64 * kInferWaves) k_mlp_infer(InferInput in, i
                     if (in.g.surf_id[i] != GLINT_NO_SURFACE) pixel_features(in.g, i, f);
                 }
             }
-            uint16_t *xr = t.x + lane * kLdX;
-#pragma unroll
-            for (int c = 0; c < 16; ++c) xr[c] = c < 5 ? to_bf16(f[c]) : (uint16_t)0;
+            uint4 *xr = reinterpret_cast<uint4 *>(t.x + lane * kLdX);
+            const uint2 lo = pack_bf16x4(f[0], f[1], f[2], f[3]);
+            xr[0] = make_uint4(lo.x, lo.y, (uint32_t)to_bf16(f[4]), 0u);
+            xr[1] = make_uint4(0u, 0u, 0u, 0u);
         }
         __syncthreads();
         dense_silu(t.x, kLdX, kIn, W1, kLdW1, w + ob1, t.h[0], nullptr);
@@ -446,18 +499,16 @@ __global__ void __launch_bounds__(64 * kInferWaves) k_mlp_infer(InferInput in, i
         __syncthreads();
         dense_silu(t.h[1], kLdH, kH, W3, kLdH, w + ob3, t.h[0], nullptr);
         __syncthreads();
-        float *logit = reinterpret_cast<float *>(t.h[1]);
+        float logit[16], y[16];
         dense_out(t.h[0], W4, w + ob4, logit);
-        __syncthreads();
-        if (lane < 32) {
-            const int64_t i = row0 + lane;
-            if (i < B) {
-                float mx, inv;
-                softmax_stats(logit, lane, K, mx, inv);
-                bool keep = true;
-                if constexpr (SRC == 1) keep = in.g.surf_id[i] != GLINT_NO_SURFACE;
-                for (int k = 0; k < K; ++k) out[i * K + k] = keep ? __expf(logit[lane * kOut + k] - mx) * inv : 0.0f;
-            }
+        softmax_pair(logit, K, y);
+        const int64_t i = row0 + (lane & 31);
+        if (i < B) {
+            bool keep = true;
+            if constexpr (SRC == 1) keep = in.g.surf_id[i] != GLINT_NO_SURFACE;
+#pragma unroll
+            for (int j = 0; j < 16; ++j)
+                if (out_unit(j) < K) out[i * K + out_unit(j)] = keep ? y[j] : 0.0f;
         }
     }
 }
