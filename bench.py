@@ -13,10 +13,15 @@ replaced by the learned network; trained before the timed region, its
 training step timed separately).  ``--dtype`` selects the indicator
 pyramid's storage type.  ``--workload batched`` times the 64-view graph.
 
+Frames run back to back with the environment work of frame f+1 overlapping
+the shading of frame f (two buffer sets, two streams; `--no-overlap` runs
+them serially); every frame does the whole path.
+
 Prints one JSON line: value = glint-shaded Mpix/s (pixels that ran the glint
-shader, per second of whole-frame time), prefilter ms/frame, per-kernel
-average durations (HIP events bracketing each launch inside the timed
-region), the roofline record of the dominant kernel and the CPU-oracle
+shader, per second of wall time over the timed frames), prefilter ms/frame
+and per-kernel durations from a serial pass, per-kernel average durations of
+the roofline kernels inside the timed region (HIP events carried by their
+dispatches), the roofline record of the dominant kernel and the CPU-oracle
 baseline.  The cost model (algorithmic operations and bytes per unit of
 work) is in the functions below.
 """
@@ -163,6 +168,8 @@ def parse():
     ap.add_argument("--vertices", type=int, default=1)
     ap.add_argument("--train-steps", type=int, default=400, help="surrogate training steps before timing")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-overlap", action="store_true",
+                    help="run frames back to back on one stream (no environment/shading overlap)")
     ap.add_argument("--cpu-sample", type=float, default=1.0 / 48.0,
                     help="fraction of pyramid texels and glint pixels the oracle times")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -296,72 +303,9 @@ def train_surrogate(G, ctx, pipe, env, K, steps, batch=4096):
     return sur, info
 
 
-def main():
-    a = parse()
-    if a.copy_probe:
-        copy_probe(a.copy_probe)
-        return
-    if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it",
-                          "n_gpus": a.gpus}))
-        sys.exit(2)
-    import torch
-
-    import synth
-    from paper_2507_02674_amd import glint as G
-    from paper_2507_02674_amd.pipeline import EnvPipeline, Shader, SurrogateShader
-
-    if not torch.cuda.is_available():
-        print(json.dumps({"error": "no GPU visible"}))
-        sys.exit(1)
-    if a.workload == "batched":
-        batched(a)
-        return
-    dtypes = {"f32": G.GLINT_F32, "f16": G.GLINT_F16, "bf16": G.GLINT_BF16, "unorm16": G.GLINT_UNORM16}
-    w = synth.WORKLOADS[a.workload]
-    env_np, gbuf_np = w.env(), w.gbuf()
-    glint_pixels = int((gbuf_np["surf_id"] != 0xFFFFFFFF).sum())
-    ctx = G.glint_create(0)
-    env = torch.from_numpy(env_np).cuda()
-    pipe = EnvPipeline(ctx, w.R, w.K, w.M, w.T, dtypes[a.dtype], w.ell)
-    pipe.build_luts()
-    pipe.run(env)
-    extra = {}
-    if a.form == "surrogate":
-        sur, extra["surrogate"] = train_surrogate(G, ctx, pipe, env, w.K, a.train_steps)
-        shader = SurrogateShader(ctx, gbuf_np, sur, seed=w.hash_seed, vertices=a.vertices)
-    else:
-        shader = Shader(ctx, gbuf_np, seed=w.hash_seed, vertices=a.vertices)
-    torch.cuda.synchronize()
-    envs = pipe.env_struct()
-    for _ in range(a.warmup):
-        pipe.run(env)
-        shader.run(envs)
-    torch.cuda.synchronize()
-
-    # timed region: every library launch bracketed by HIP events on its stream
-    G.glint_profile_enable(ctx, True)
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(a.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for s in range(a.steps):
-        ev[s][0].record()
-        pipe.run(env)
-        ev[s][1].record()
-        shader.run(envs)
-        ev[s][2].record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    kernels = kernel_table(G, ctx, a.steps)
-    G.glint_profile_enable(ctx, False)
-    pre_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in ev]))
-    sh_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in ev]))
-    frame_ms = float(ev[0][0].elapsed_time(ev[-1][2])) / a.steps
-    ms_per_step = max(frame_ms, 1e3 * wall / a.steps)
-    value = glint_pixels / (ms_per_step * 1e-3) / 1e6
-
-    # roofline records: prefilter, shading, and the network lookup
-    config_tag = f"{w.name}-{a.form}-{a.dtype}-v{a.vertices}"
+def roofline_records(kernels, w, a, shader, glint_pixels, config_tag):
+    """Roofline record per timed kernel (cost model of this file over the
+    kernel's average launch duration)."""
     pf_ops, pf_bytes, pf_texels = prefilter_cost(w.R, w.M, w.T, w.K, STORAGE_BYTES[a.dtype])
     records = {}
     if "k_prefilter" in kernels:
@@ -387,9 +331,99 @@ def main():
                                    "traffic": recorded_traffic("k_mlp_lookup", config_tag),
                                    "frac": round(ach / BF16_MFMA_PEAK_TFLOPS, 4), "flops_per_launch": fl,
                                    "padded_flops_per_launch": mlp_flops_per_row(w.K, True) * shader.P}
-    dominant = max((k for k in records), key=lambda k: kernels[k]["avg_ms"] * kernels[k]["launches_per_step"])
+    return records
+
+
+def main():
+    a = parse()
+    if a.copy_probe:
+        copy_probe(a.copy_probe)
+        return
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it",
+                          "n_gpus": a.gpus}))
+        sys.exit(2)
+    import torch
+
+    import synth
+    from paper_2507_02674_amd import glint as G
+    from paper_2507_02674_amd.pipeline import EnvPipeline, FramePipeline, Shader, SurrogateShader
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(1)
+    if a.workload == "batched":
+        batched(a)
+        return
+    dtypes = {"f32": G.GLINT_F32, "f16": G.GLINT_F16, "bf16": G.GLINT_BF16, "unorm16": G.GLINT_UNORM16}
+    w = synth.WORKLOADS[a.workload]
+    env_np, gbuf_np = w.env(), w.gbuf()
+    glint_pixels = int((gbuf_np["surf_id"] != 0xFFFFFFFF).sum())
+    ctx = G.glint_create(0)
+    env = torch.from_numpy(env_np).cuda()
+
+    def new_env():
+        return EnvPipeline(ctx, w.R, w.K, w.M, w.T, dtypes[a.dtype], w.ell)
+
+    pipe = new_env()  # the serial pass's buffers (also the surrogate's training source)
+    pipe.build_luts()
+    pipe.run(env)
+    extra = {}
+    if a.form == "surrogate":
+        sur, extra["surrogate"] = train_surrogate(G, ctx, pipe, env, w.K, a.train_steps)
+        shader = SurrogateShader(ctx, gbuf_np, sur, seed=w.hash_seed, vertices=a.vertices)
+    else:
+        shader = Shader(ctx, gbuf_np, seed=w.hash_seed, vertices=a.vertices)
+    frames = FramePipeline(new_env, shader, overlap=not a.no_overlap)
+    frames.build_luts()
+    for _ in range(a.warmup):
+        frames.step(env)
+    torch.cuda.synchronize()
+
+    # timed region: K frames, each the whole per-frame path; with overlap the
+    # environment work of frame f+1 runs beside the shading of frame f.  The
+    # roofline kernels carry HIP events in their dispatches.
+    timed = ["k_prefilter", "k_mlp_lookup", "k_shade_surrogate"] if a.form == "surrogate" else ["k_prefilter", "k_shade"]
+    G.glint_profile_select(ctx, timed)
+    G.glint_profile_enable(ctx, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        frames.step(env)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kernels = kernel_table(G, ctx, a.steps)
+    G.glint_profile_enable(ctx, False)
+    ms_per_step = 1e3 * wall / a.steps
+    value = glint_pixels / (ms_per_step * 1e-3) / 1e6
+
+    # serial reference pass (not the timed region): one stream, every kernel
+    # timed, environment and shading bracketed separately
+    G.glint_profile_select(ctx, None)
+    G.glint_profile_enable(ctx, True)
+    envs = pipe.env_struct()
+    n_ser = max(5, min(a.steps, 20))
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(n_ser)]
+    torch.cuda.synchronize()
+    for s in range(n_ser):
+        ev[s][0].record()
+        pipe.run(env)
+        ev[s][1].record()
+        shader.run(envs)
+        ev[s][2].record()
+    torch.cuda.synchronize()
+    kernels_serial = kernel_table(G, ctx, n_ser)
+    G.glint_profile_enable(ctx, False)
+    pre_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in ev]))
+    sh_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in ev]))
+    serial_ms = float(ev[0][0].elapsed_time(ev[-1][2])) / n_ser
+
+    config_tag = f"{w.name}-{a.form}-{a.dtype}-v{a.vertices}"
+    records = roofline_records(kernels, w, a, shader, glint_pixels, config_tag)
+    dominant = max(records, key=lambda k: kernels[k]["avg_ms"] * kernels[k]["launches_per_step"])
     roofline = dict(records[dominant])
     others = {k: v for k, v in records.items() if k != dominant}
+    serial_records = roofline_records(kernels_serial, w, a, shader, glint_pixels, config_tag)
 
     out = {"metric": METRIC, "value": round(value, 3), "unit": "Mpix/s", "n_gpus": 1, "steps": a.steps,
            "warmup": a.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True, "scaling": "weak",
@@ -397,14 +431,19 @@ def main():
            "config": {"workload": f"{w.name}: {w.W}x{w.H} sphere+plane G-buffer, cube map 6x{w.R}x{w.R}, "
                                   f"{w.M} mips, K={w.K}, T={w.T} taps, per-frame partition+prefilter+shade",
                       "form": a.form, "pyramid_dtype": a.dtype, "vertices": a.vertices,
-                      "glint_pixels": glint_pixels},
+                      "glint_pixels": glint_pixels, "total_pixels": shader.P,
+                      "frames_overlapped": not a.no_overlap},
            "prefilter_ms_per_frame": round(pre_ms, 4), "shade_ms_per_frame": round(sh_ms, 4),
-           "kernels": kernels, "roofline": roofline, "other_rooflines": others}
+           "serial_ms_per_step": round(serial_ms, 4),
+           "kernels": kernels, "roofline": roofline, "other_rooflines": others,
+           "serial_pass": {"kernels": kernels_serial,
+                           "rooflines": {k: {"achieved": v["achieved"], "frac": v["frac"], "unit": v["unit"]}
+                                         for k, v in serial_records.items()}}}
     out.update(extra)
     if a.dtype != "f32" or a.form != "plain":
         # against the plain f32 path on the same frame (itself checked against the oracle): reflection
         # probabilities p_k, per-pixel radiance, and the frame's mean radiance
-        ref_pipe = EnvPipeline(ctx, w.R, w.K, w.M, w.T, G.GLINT_F32, w.ell)
+        ref_pipe = new_env()
         ref_pipe.build_luts()
         ref_pipe.run(env)
         ref_sh = Shader(ctx, gbuf_np, seed=w.hash_seed, vertices=a.vertices)

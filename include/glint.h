@@ -388,11 +388,16 @@ int glint_batched_tile_px(glint_ctx ctx);
  * Per-kernel timing, for benchmarks and profiling.  While enabled, every
  * kernel that an entry point of this context launches (outside a stream
  * capture) is bracketed by two HIP events recorded on its launch stream;
- * the events add a few microseconds of gap between launches.
+ * the events travel with the dispatch, but the runtime adds a few
+ * microseconds per timed launch, so time only the kernels of interest.
  * ------------------------------------------------------------------------ */
 
 /* Enables (1) or disables (0) timing; either way drops every record. */
 int glint_profile_enable(glint_ctx ctx, int enable);
+
+/* Restricts timing to the kernels named in `kernels` (comma-separated, e.g.
+ * "k_prefilter,k_shade"); NULL or "" times every kernel. */
+int glint_profile_select(glint_ctx ctx, const char *kernels);
 
 /* Waits for the recorded events (synchronising with the streams they were
  * recorded on), adds their durations to per-kernel totals and stores the

@@ -448,6 +448,13 @@ int glint_profile_enable(glint_ctx ctx, int enable)
     return ok();
 }
 
+int glint_profile_select(glint_ctx ctx, const char *kernels)
+{
+    if (!ctx) return fail(GLINT_EINVAL, "null context");
+    ctx->prof.only = kernels ? kernels : "";
+    return ok();
+}
+
 int glint_profile_collect(glint_ctx ctx, int *n_kernels)
 {
     if (int rc = check_ctx(ctx)) return rc;

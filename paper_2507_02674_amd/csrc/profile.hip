@@ -13,6 +13,20 @@ Profiler *&current_profiler()
 
 Profiler::~Profiler() { reset(); }
 
+bool Profiler::selected(const char *name) const
+{
+    if (only.empty()) return true;
+    const size_t n = strlen(name);
+    size_t pos = 0;
+    while (pos <= only.size()) {
+        size_t end = only.find(',', pos);
+        if (end == std::string::npos) end = only.size();
+        if (end - pos == n && only.compare(pos, n, name) == 0) return true;
+        pos = end + 1;
+    }
+    return false;
+}
+
 hipEvent_t Profiler::event()
 {
     if (!pool.empty()) {
@@ -68,7 +82,7 @@ void Profiler::reset()
 KernelTimer::KernelTimer(const char *name, hipStream_t s) : name_(name)
 {
     Profiler *p = current_profiler();
-    if (!p) return;
+    if (!p || !p->selected(name)) return;
     hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(s, &st) != hipSuccess || st != hipStreamCaptureStatusNone) return;
     start_ = p->event();

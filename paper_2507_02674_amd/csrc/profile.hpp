@@ -12,6 +12,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <string>
 #include <vector>
 
 namespace glint {
@@ -29,6 +30,8 @@ struct ProfSummary {
 
 struct Profiler {
     bool enabled = false;
+    std::string only;                // comma-separated kernel names to time; empty: all
+    bool selected(const char *name) const;
     std::vector<ProfRecord> records; // in launch order, not yet resolved
     std::vector<hipEvent_t> pool;    // events of resolved records, for reuse
     std::vector<ProfSummary> summary;

@@ -108,6 +108,7 @@ EXPORTS = {
                              C.c_void_p], C.c_int),
     "glint_batched_tile_px": ([C.c_void_p], C.c_int),
     "glint_profile_enable": ([C.c_void_p, C.c_int], C.c_int),
+    "glint_profile_select": ([C.c_void_p, C.c_char_p], C.c_int),
     "glint_profile_collect": ([C.c_void_p, C.POINTER(C.c_int)], C.c_int),
     "glint_profile_entry": ([C.c_void_p, C.c_int, C.POINTER(C.c_char_p), C.POINTER(C.c_double),
                              C.POINTER(C.c_int64)], C.c_int),
@@ -323,6 +324,11 @@ def glint_batched_tile_px(ctx) -> int:
 
 def glint_profile_enable(ctx, enable: bool = True) -> None:
     _check(lib().glint_profile_enable(ctx, 1 if enable else 0))
+
+
+def glint_profile_select(ctx, kernels=None) -> None:
+    """Times only the named kernels (iterable of names; None: all)."""
+    _check(lib().glint_profile_select(ctx, ",".join(kernels).encode() if kernels else None))
 
 
 def glint_profile_collect(ctx) -> dict:

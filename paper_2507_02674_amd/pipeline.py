@@ -268,3 +268,55 @@ class SurrogateShader(Shader):
     def run(self, env: G.Env, stream=None, debug=None):
         G.glint_shade_surrogate(self.ctx, self.gb, self.P, env, self.sur.w, self.sur.wb, self.sp, self.F,
                                 self.radiance, debug, stream)
+
+
+class FramePipeline:
+    """Per-frame path with the environment work of frame f+1 overlapping the
+    shading of frame f: two sets of environment buffers used alternately, the
+    environment kernels on one stream and shading on another, ordered by
+    events (a buffer set is refilled only after the shading that read it).
+
+    env_factory() -> EnvPipeline, shader: Shader or SurrogateShader."""
+
+    def __init__(self, env_factory, shader, overlap=True):
+        self.pipes = [env_factory(), env_factory()] if overlap else [env_factory()]
+        self.shader = shader
+        self.overlap = overlap
+        self.s_env = torch.cuda.Stream() if overlap else None
+        self.s_shade = torch.cuda.Stream() if overlap else None
+        self.frame = 0
+        self._shade_done = [None, None]
+
+    def build_luts(self):
+        for p in self.pipes:
+            p.build_luts()
+
+    def step(self, env):
+        """Enqueues one frame (no synchronisation)."""
+        if not self.overlap:
+            p = self.pipes[0]
+            p.run(env)
+            self.shader.run(p.env_struct())
+            self.frame += 1
+            return
+        b = self.frame % 2
+        p = self.pipes[b]
+        with torch.cuda.stream(self.s_env):
+            if self._shade_done[b] is not None:
+                self.s_env.wait_event(self._shade_done[b])
+            p.run(env, stream=self.s_env)
+            env_done = torch.cuda.Event()
+            env_done.record(self.s_env)
+        with torch.cuda.stream(self.s_shade):
+            self.s_shade.wait_event(env_done)
+            self.shader.run(p.env_struct(), stream=self.s_shade)
+            done = torch.cuda.Event()
+            done.record(self.s_shade)
+        self._shade_done[b] = done
+        self.frame += 1
+
+    def streams(self):
+        return [self.s_env, self.s_shade] if self.overlap else [torch.cuda.current_stream()]
+
+    def last_env(self):
+        return self.pipes[(self.frame - 1) % len(self.pipes)]
