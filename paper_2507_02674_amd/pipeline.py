@@ -320,3 +320,107 @@ class FramePipeline:
 
     def last_env(self):
         return self.pipes[(self.frame - 1) % len(self.pipes)]
+
+
+# --- surrogate checkpoints ---------------------------------------------------------
+
+CKPT_MAGIC = b"GLSGCKPT"
+CKPT_VERSION = 1
+
+
+def pack_checkpoint(w, m, v, step: int, K: int) -> bytes:
+    """Versioned binary of the surrogate's training state: header (magic,
+    version, K, parameter count, step, dtype code 0 = float32), then the
+    float32 master weights and the two Adam moments, then a CRC32 of
+    everything before it."""
+    import struct
+    import zlib
+
+    import numpy as np
+    arrs = [np.ascontiguousarray(np.asarray(a, dtype=np.float32)).reshape(-1) for a in (w, m, v)]
+    n = arrs[0].size
+    if any(a.size != n for a in arrs):
+        raise ValueError("weights and moments differ in size")
+    body = CKPT_MAGIC + struct.pack("<IIIqI", CKPT_VERSION, K, n, step, 0) + b"".join(a.tobytes() for a in arrs)
+    return body + struct.pack("<I", zlib.crc32(body) & 0xFFFFFFFF)
+
+
+def unpack_checkpoint(blob: bytes) -> dict:
+    """Inverse of pack_checkpoint; raises ValueError on a bad magic, version,
+    size or CRC."""
+    import struct
+    import zlib
+
+    import numpy as np
+    head = len(CKPT_MAGIC) + struct.calcsize("<IIIqI")
+    if len(blob) < head + 4 or blob[:len(CKPT_MAGIC)] != CKPT_MAGIC:
+        raise ValueError("not a surrogate checkpoint")
+    version, K, n, step, dtype = struct.unpack("<IIIqI", blob[len(CKPT_MAGIC):head])
+    if version != CKPT_VERSION or dtype != 0:
+        raise ValueError(f"unsupported checkpoint version {version} / dtype {dtype}")
+    if len(blob) != head + 3 * 4 * n + 4:
+        raise ValueError("checkpoint size does not match its header")
+    (crc,) = struct.unpack("<I", blob[-4:])
+    if zlib.crc32(blob[:-4]) & 0xFFFFFFFF != crc:
+        raise ValueError("checkpoint CRC mismatch")
+    arr = np.frombuffer(blob, dtype=np.float32, count=3 * n, offset=head).reshape(3, n)
+    return dict(w=arr[0].copy(), m=arr[1].copy(), v=arr[2].copy(), step=int(step), K=int(K))
+
+
+def save_surrogate(sur: "Surrogate", path: str) -> None:
+    st = sur.state()
+    blob = pack_checkpoint(st["w"].numpy(), st["m"].numpy(), st["v"].numpy(), st["step"], st["K"])
+    with open(path, "wb") as f:
+        f.write(blob)
+
+
+def load_surrogate(sur: "Surrogate", path: str) -> None:
+    with open(path, "rb") as f:
+        st = unpack_checkpoint(f.read())
+    sur.restore({k: (torch.from_numpy(val) if hasattr(val, "dtype") else val) for k, val in st.items()})
+
+
+# --- surrogate fallback -----------------------------------------------------------
+
+class GuardedShader:
+    """Surrogate shading with a fallback to the plain form: every `every`
+    frames the network's F_k/sum F on a fixed probe set of lookups is
+    compared with the plain filter of the current map (glint_surrogate_samples
+    and glint_surrogate_forward); while the mean absolute error exceeds
+    `threshold` the plain shader (indicator pyramid) is used."""
+
+    def __init__(self, surrogate_shader: "SurrogateShader", plain_shader: Shader, probe=4096, every=8,
+                 threshold=0.02, seed=99):
+        self.sur_sh, self.plain_sh = surrogate_shader, plain_shader
+        self.sur = surrogate_shader.sur
+        self.every, self.threshold = every, threshold
+        self.dirs, self.ax, self.ay = Surrogate.draw_lookups(probe, seed, surrogate_shader.radiance.device)
+        K = self.sur.K
+        self.x = torch.empty((probe, 5), dtype=torch.float32, device=self.dirs.device)
+        self.t = torch.empty((probe, K), dtype=torch.float32, device=self.dirs.device)
+        self.y = torch.empty((probe, K), dtype=torch.float32, device=self.dirs.device)
+        self.frame = 0
+        self.use_surrogate = True
+        self.last_error = None
+
+    def check(self, pipe: EnvPipeline, env, stream=None) -> float:
+        G.glint_surrogate_samples(self.sur.ctx, env, pipe.ind_j, pipe.ind_t, pipe.R, pipe.K, pipe.fp, pipe.filt_ws,
+                                  self.dirs, self.ax, self.ay, self.x, self.t, stream)
+        G.glint_surrogate_forward(self.sur.ctx, self.sur.K, self.sur.w, self.sur.wb, self.x, self.y, stream)
+        err = float((self.y - self.t).abs().mean().item())
+        self.last_error = err
+        self.use_surrogate = err <= self.threshold
+        return err
+
+    @property
+    def radiance(self):
+        return self.sur_sh.radiance if self.use_surrogate else self.plain_sh.radiance
+
+    def run(self, pipe: EnvPipeline, env, stream=None):
+        if self.frame % self.every == 0:
+            self.check(pipe, env, stream)
+        self.frame += 1
+        if self.use_surrogate:
+            self.sur_sh.run(pipe.env_struct(), stream)
+        else:
+            self.plain_sh.run(pipe.env_struct(), stream)

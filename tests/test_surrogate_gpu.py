@@ -308,3 +308,52 @@ def test_surrogate_rejects_bad_arguments(ctx):
         G.glint_surrogate_train_step(ctx, K, wt, wb, m, m.clone(), 0, 1e-3, x, t, ws, loss)
     # empty batch is a no-op for the forward pass
     G.glint_surrogate_forward(ctx, K, wt, wb, x[:0], probs)
+
+
+def test_checkpoint_resume_reproduces_training(ctx, tmp_path):
+    """Weights, Adam moments and the step counter saved mid-training; a fresh
+    surrogate loaded from the file continues with identical losses and
+    bit-identical weights (the kernels are deterministic)."""
+    from paper_2507_02674_amd.pipeline import Surrogate, load_surrogate, save_surrogate
+    env, et, pipe = env_setup(ctx, R=32, K=8, M=6)
+    a = Surrogate(ctx, 8)
+    a.init(seed=3)
+    x, t = a.samples(pipe, et, 1 << 13, seed=4)
+    a.fit(x, t, batch=512, lr=2e-3, steps=30, seed=5)
+    path = str(tmp_path / "sur.ckpt")
+    save_surrogate(a, path)
+    curve_a = a.fit(x, t, batch=512, lr=2e-3, steps=30, seed=6, log_every=1)
+    b = Surrogate(ctx, 8)
+    load_surrogate(b, path)
+    assert b.step == 30
+    curve_b = b.fit(x, t, batch=512, lr=2e-3, steps=30, seed=6, log_every=1)
+    assert curve_a == curve_b
+    assert np.array_equal(U.host(a.w), U.host(b.w)) and np.array_equal(U.host(a.wb), U.host(b.wb))
+
+
+def test_fallback_to_plain_filter_on_bad_weights(ctx):
+    """The guard keeps the surrogate while its probe error is small and falls
+    back to the plain form (identical radiance) when the weights are corrupted."""
+    import torch
+    from paper_2507_02674_amd.pipeline import GuardedShader, Shader, Surrogate, SurrogateShader
+    env, et, pipe = env_setup(ctx, R=32, K=8, M=6)
+    sur = Surrogate(ctx, 8)
+    sur.init(seed=7)
+    x, t = sur.samples(pipe, et, 1 << 15, seed=1)
+    sur.fit(x, t, batch=1024, lr=3e-3, lr_min=1e-4, steps=400)
+    gb = synth.scene_frame(96, 64, seed=3)
+    guard = GuardedShader(SurrogateShader(ctx, gb, sur, seed=5), Shader(ctx, gb, seed=5), every=2, threshold=0.03)
+    guard.run(pipe, et)
+    U.log(f"  probe error trained {guard.last_error:.4f}")
+    assert guard.use_surrogate
+    with torch.no_grad():
+        sur.w.copy_(torch.randn_like(sur.w) * 0.5)
+    G.glint_surrogate_prepare(ctx, 8, sur.w, sur.wb)
+    guard.run(pipe, et)  # frame 1: no check yet
+    assert guard.use_surrogate
+    guard.run(pipe, et)  # frame 2: check -> fall back
+    U.log(f"  probe error corrupted {guard.last_error:.4f}")
+    assert not guard.use_surrogate
+    plain = Shader(ctx, gb, seed=5)
+    plain.run(pipe.env_struct())
+    assert np.array_equal(U.host(guard.radiance), U.host(plain.radiance))
