@@ -247,7 +247,18 @@ def batched(a):
     views = synth.batched_views(64)
     envs = [(torch.from_numpy(synth.make_env(256, seed)).cuda(), K, 8, 64) for (seed, K) in synth.BATCHED_ENVS]
     ctx = G.glint_create(0)
-    bf = BatchedFrame(ctx, envs, views)
+    surrogates, train_info = None, None
+    if a.form == "surrogate":
+        from paper_2507_02674_amd.pipeline import EnvPipeline
+        surrogates, train_info = [], []
+        for (env, K, M, T) in envs:
+            pipe = EnvPipeline(ctx, int(env.shape[1]), K, M, T)
+            pipe.build_luts()
+            pipe.run(env)
+            sur, info = train_surrogate(G, ctx, pipe, env, K, a.train_steps)
+            surrogates.append(sur)
+            train_info.append(info)
+    bf = BatchedFrame(ctx, envs, views, surrogates=surrogates)
     glint_pixels = sum(int((gb["surf_id"] != 0xFFFFFFFF).sum()) for (gb, _, _, _) in views)
     bf.run()  # set-up call (autotune + capture)
     torch.cuda.synchronize()
@@ -268,8 +279,10 @@ def batched(a):
            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
            "config": {"workload": "batched: 64 views (256^2..1920x1080, log-uniform pixels), 4 cube maps "
                                   "6x256x256 with K=4,8,16,8, M=8, T=64; one graph launch per frame",
-                      "views": len(views), "total_pixels": bf.total_pixels, "glint_pixels": glint_pixels,
-                      "tile_px": G.glint_batched_tile_px(ctx)}}
+                      "form": a.form, "views": len(views), "total_pixels": bf.total_pixels,
+                      "glint_pixels": glint_pixels, "tile_px": G.glint_batched_tile_px(ctx)}}
+    if train_info is not None:
+        out["surrogate"] = train_info
     G.glint_destroy(ctx)
     print(json.dumps(out), flush=True)
 

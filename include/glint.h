@@ -330,8 +330,9 @@ int glint_shade_surrogate(glint_ctx ctx, const glint_gbuffer *gbuf, int64_t num_
  * Batched frame: several environment maps and many views of uneven size,
  * with mixed K, materials and vertex counts, in one graph launch.  The
  * result is defined as glint_partition_env + glint_prefilter for every
- * environment followed by glint_shade for every view (no debug outputs);
- * outputs are bit-identical to those calls.
+ * environment followed by glint_shade (or glint_shade_surrogate, for views
+ * of an environment that carries surrogate parameters) for every view (no
+ * debug outputs); outputs are bit-identical to those calls.
  *
  * The first call for a given argument set (compared byte-wise, including
  * the pointers) is a set-up call: it times the shading launch for each
@@ -360,6 +361,11 @@ typedef struct glint_env_task {
     void *ind_pyr;
     float *rgb_pyr;
     const float *lut_S, *lut_E;     /* device LUTs from glint_build_luts */
+    /* Surrogate form (NULL, NULL: plain form): the parameters of a network
+     * for this environment's K (see glint_shade_surrogate); views lit by
+     * this environment are shaded with it. */
+    const float *surrogate_w;
+    const uint16_t *surrogate_w_bf16;
 } glint_env_task;
 
 typedef struct glint_view {
@@ -368,6 +374,8 @@ typedef struct glint_view {
     int env_index;                  /* 0 .. n_env-1 */
     glint_shade_params shade;
     float *radiance;                /* device [num_pixels][3] */
+    float *surrogate_F;             /* device [num_pixels][K] f32 workspace, 16-byte aligned, when the
+                                       view's environment has a surrogate (else ignored) */
 } glint_view;
 
 /* Device workspace (bytes, 16-byte aligned) for n_views views. */

@@ -423,6 +423,10 @@ int glint_frame_batched(glint_ctx ctx, const glint_env_task *envs, int n_env, co
         if (!t.lut_S || !t.lut_E) return fail(GLINT_EINVAL, "environment %d: null LUT", e);
         if (t.prefilter.dtype != envs[0].prefilter.dtype)
             return fail(GLINT_EINVAL, "all environments of one call must share the pyramid dtype");
+        if ((t.surrogate_w == nullptr) != (t.surrogate_w_bf16 == nullptr))
+            return fail(GLINT_EINVAL, "environment %d: surrogate weights and their bf16 copy go together", e);
+        if (t.surrogate_w)
+            if (int rc = check_surrogate(t.partition.K, t.surrogate_w, t.surrogate_w_bf16)) return rc;
     }
     for (int v = 0; v < n_views; ++v) {
         const glint_view &w = views[v];
@@ -431,6 +435,10 @@ int glint_frame_batched(glint_ctx ctx, const glint_env_task *envs, int n_env, co
             return fail(GLINT_EINVAL, "view %d: bad num_pixels", v);
         if (w.shade.vertices != 1 && w.shade.vertices != 6) return fail(GLINT_EINVAL, "view %d: vertices", v);
         if (!w.radiance) return fail(GLINT_EINVAL, "view %d: null radiance", v);
+        if (envs[w.env_index].surrogate_w &&
+            (!w.surrogate_F || reinterpret_cast<uintptr_t>(w.surrogate_F) % 16))
+            return fail(GLINT_EINVAL, "view %d: its environment has a surrogate; surrogate_F must be a 16-byte "
+                                      "aligned [num_pixels][K] buffer", v);
         if (int rc = check_gbuffer(&w.gbuf)) return rc;
     }
     return device_status(glint::frame_batched(ctx->batched, envs, n_env, views, n_views, workspace,

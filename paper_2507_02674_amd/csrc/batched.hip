@@ -26,6 +26,7 @@ constexpr int kTileCandidates[] = {64, 128, 256, 512};
 
 struct Group {
     int K, V;
+    bool surrogate;           // views shaded with their environment's network
     std::vector<int> views;   // indices into the caller's view array
     int64_t tiles = 0;
     size_t desc_off = 0, tile_off = 0; // byte offsets in the workspace
@@ -52,7 +53,8 @@ hipError_t upload_group(const Group &g, const glint_env_task *envs, const glint_
         const glint_env_task &e = envs[v.env_index];
         glint_env env{e.ind_pyr, e.rgb_pyr, e.levels, e.lut_S, e.lut_E, e.R, e.partition.K, e.prefilter.num_mips,
                       e.prefilter.dtype};
-        make_shade_args(desc.data() + q * ab, v.gbuf, v.num_pixels, env, v.shade, v.radiance);
+        make_shade_args(desc.data() + q * ab, v.gbuf, v.num_pixels, env, v.shade, v.radiance,
+                        g.surrogate ? v.surrogate_F : nullptr);
         tile0[q] = t;
         t += (v.num_pixels + px - 1) / px;
     }
@@ -81,11 +83,26 @@ hipError_t launch_env(const glint_env_task &e, hipStream_t s)
                             (int)e.prefilter.dtype, e.prefilter_workspace, e.ind_pyr, e.rgb_pyr, s);
 }
 
+// Network lookups of a surrogate group's views (one launch per view).
+hipError_t launch_lookups(const Group &g, const glint_env_task *envs, const glint_view *views, hipStream_t s)
+{
+    if (!g.surrogate) return hipSuccess;
+    for (int vi : g.views) {
+        const glint_view &v = views[vi];
+        const glint_env_task &e = envs[v.env_index];
+        hipError_t err = launch_mlp_lookup(v.gbuf, v.num_pixels, e.partition.K, e.surrogate_w, e.surrogate_w_bf16,
+                                           v.surrogate_F, s);
+        if (err != hipSuccess) return err;
+    }
+    return hipSuccess;
+}
+
 hipError_t launch_group(const Group &g, int dtype, void *workspace, hipStream_t s)
 {
     char *ws = static_cast<char *>(workspace);
-    return launch_shade_views(g.K, dtype, g.V, ws + g.desc_off, reinterpret_cast<const int64_t *>(ws + g.tile_off),
-                              (int)g.views.size(), g.tiles, g.tile_px, s);
+    return launch_shade_views(g.K, dtype, g.V, g.surrogate, ws + g.desc_off,
+                              reinterpret_cast<const int64_t *>(ws + g.tile_off), (int)g.views.size(), g.tiles,
+                              g.tile_px, s);
 }
 
 } // namespace
@@ -93,8 +110,9 @@ hipError_t launch_group(const Group &g, int dtype, void *workspace, hipStream_t 
 size_t batched_workspace_bytes(int n_views)
 {
     // descriptors and tile tables of at most n_views views, each group
-    // aligned to 256 bytes (at most 8 groups: K in {2,4,8,16} x V in {1,6})
-    return (size_t)n_views * (shade_args_bytes() + sizeof(int64_t)) + 16 * 256;
+    // aligned to 256 bytes (at most 16 groups: K in {2,4,8,16} x V in {1,6}
+    // x plain/surrogate)
+    return (size_t)n_views * (shade_args_bytes() + sizeof(int64_t)) + 32 * 256;
 }
 
 BatchedCache::~BatchedCache()
@@ -146,13 +164,16 @@ hipError_t frame_batched(BatchedCache &c, const glint_env_task *envs, int n_env,
     if (err != hipSuccess) return err;
     const int dtype = (int)envs[0].prefilter.dtype;
 
-    // groups by (K, V), views in caller order
+    // groups by (K, V, form), views in caller order
     std::vector<Group> groups;
     for (int v = 0; v < n_views; ++v) {
-        const int K = envs[views[v].env_index].partition.K, V = views[v].shade.vertices;
-        auto g = std::find_if(groups.begin(), groups.end(), [&](const Group &x) { return x.K == K && x.V == V; });
+        const glint_env_task &e = envs[views[v].env_index];
+        const int K = e.partition.K, V = views[v].shade.vertices;
+        const bool S = e.surrogate_w != nullptr;
+        auto g = std::find_if(groups.begin(), groups.end(),
+                              [&](const Group &x) { return x.K == K && x.V == V && x.surrogate == S; });
         if (g == groups.end()) {
-            groups.push_back(Group{K, V, {}, 0, 0, 0, 256});
+            groups.push_back(Group{K, V, S, {}, 0, 0, 0, 256});
             g = groups.end() - 1;
         }
         g->views.push_back(v);
@@ -177,13 +198,14 @@ hipError_t frame_batched(BatchedCache &c, const glint_env_task *envs, int n_env,
     for (auto &g : groups) {
         int64_t px_total = 0;
         for (int vi : g.views) px_total += views[vi].num_pixels;
-        const long long tkey = ((long long)g.K << 40) | ((long long)dtype << 32) | ((long long)g.V << 16) |
-                               size_class(px_total);
+        const long long tkey = ((long long)g.K << 40) | ((long long)dtype << 32) | ((long long)g.surrogate << 24) |
+                               ((long long)g.V << 16) | size_class(px_total);
         auto tuned = c.tuned.find(tkey);
         if (tuned != c.tuned.end()) {
             g.tile_px = tuned->second;
         } else {
             float best = 1e30f;
+            if ((err = launch_lookups(g, envs, views, stream)) != hipSuccess) return err;
             for (int px : kTileCandidates) {
                 g.tile_px = px;
                 g.tiles = group_tiles(g, views, px);
@@ -230,6 +252,7 @@ hipError_t frame_batched(BatchedCache &c, const glint_env_task *envs, int n_env,
         if (cap == hipSuccess) cap = hipStreamWaitEvent(cs, c.joins[e], 0);
     }
     for (auto &g : groups) {
+        if (cap == hipSuccess) cap = launch_lookups(g, envs, views, cs);
         if (cap == hipSuccess) cap = launch_group(g, dtype, workspace, cs);
     }
     err = hipStreamEndCapture(cs, &graph);

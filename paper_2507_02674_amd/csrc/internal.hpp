@@ -49,8 +49,8 @@ hipError_t launch_shade(const glint_gbuffer &g, int64_t P, const glint_env &env,
 // output) and the first tile of each view
 size_t shade_args_bytes();
 void make_shade_args(void *out, const glint_gbuffer &g, int64_t P, const glint_env &env,
-                     const glint_shade_params &sp, float *radiance);
-hipError_t launch_shade_views(int K, int dtype, int V, const void *views, const int64_t *tile0, int n_views,
-                              int64_t tiles, int tile_px, hipStream_t stream);
+                     const glint_shade_params &sp, float *radiance, const float *F);
+hipError_t launch_shade_views(int K, int dtype, int V, bool surrogate, const void *views, const int64_t *tile0,
+                              int n_views, int64_t tiles, int tile_px, hipStream_t stream);
 
 } // namespace glint

@@ -392,7 +392,7 @@ __global__ void __launch_bounds__(kShadeThreads) k_shade(ShadeArgs A)
 // All views of one (K, V) group in one launch: block b shades tile b of the
 // concatenated views (tile = blockDim.x pixels); tile0[v] is the first tile
 // of view v (ascending), so the view is found by a scan of <= n_views entries.
-template <int K, int DT, int V>
+template <int K, int DT, int V, bool SURR = false>
 __global__ void __launch_bounds__(512) k_shade_views(const ShadeArgs *__restrict__ views,
                                                      const int64_t *__restrict__ tile0, int n_views)
 {
@@ -407,7 +407,7 @@ __global__ void __launch_bounds__(512) k_shade_views(const ShadeArgs *__restrict
     const ShadeArgs A = views[s_view];
     const int64_t i = (b - tile0[s_view]) * blockDim.x + threadIdx.x;
     if (i >= A.P) return;
-    shade_pixel<K, DT, V>(A, i);
+    shade_pixel<K, DT, V, SURR>(A, i);
 }
 
 template <int K, int DT>
@@ -423,7 +423,7 @@ size_t shade_args_bytes() { return sizeof(ShadeArgs); }
 
 // Fills the device-side descriptor of one view (host memory, copied later).
 void make_shade_args(void *out, const glint_gbuffer &g, int64_t P, const glint_env &env,
-                     const glint_shade_params &sp, float *radiance)
+                     const glint_shade_params &sp, float *radiance, const float *F)
 {
     ShadeArgs a;
     a.g = g;
@@ -440,14 +440,27 @@ void make_shade_args(void *out, const glint_gbuffer &g, int64_t P, const glint_e
     a.counts = nullptr;
     a.codes = nullptr;
     a.probs = nullptr;
-    a.F = nullptr;
+    a.F = F;
     *static_cast<ShadeArgs *>(out) = a;
 }
 
-hipError_t launch_shade_views(int K, int dtype, int V, const void *views, const int64_t *tile0, int n_views,
-                              int64_t tiles, int tile_px, hipStream_t stream)
+hipError_t launch_shade_views(int K, int dtype, int V, bool surrogate, const void *views, const int64_t *tile0,
+                              int n_views, int64_t tiles, int tile_px, hipStream_t stream)
 {
     const ShadeArgs *va = static_cast<const ShadeArgs *>(views);
+    if (surrogate) {
+        // the indicator pyramid is not read, so its storage type does not matter
+#define GLINT_SVS(KK, VV)                                                                                    \
+    if (K == KK && V == VV) {                                                                                \
+        GLINT_LAUNCH("k_shade_views", (k_shade_views<KK, 0, VV, true>), dim3((unsigned)tiles), dim3(tile_px), \
+                     0, stream, va, tile0, n_views);                                                         \
+        return hipGetLastError();                                                                            \
+    }
+        GLINT_SVS(2, 1) GLINT_SVS(4, 1) GLINT_SVS(8, 1) GLINT_SVS(16, 1)
+        GLINT_SVS(2, 6) GLINT_SVS(4, 6) GLINT_SVS(8, 6) GLINT_SVS(16, 6)
+#undef GLINT_SVS
+        return hipErrorInvalidValue;
+    }
 #define GLINT_SV(KK, DD, VV)                                                                                 \
     if (K == KK && dtype == DD && V == VV) {                                                                 \
         GLINT_LAUNCH("k_shade_views", (k_shade_views<KK, DD, VV>), dim3((unsigned)tiles), dim3(tile_px), 0,  \

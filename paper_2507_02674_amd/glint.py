@@ -57,12 +57,13 @@ class EnvTask(C.Structure):
     _fields_ = [("env", C.c_void_p), ("R", C.c_int), ("partition", PartitionParams), ("prefilter", PrefilterParams),
                 ("partition_workspace", C.c_void_p), ("prefilter_workspace", C.c_void_p), ("levels", C.c_void_p),
                 ("ind_j", C.c_void_p), ("ind_t", C.c_void_p), ("ind_pyr", C.c_void_p), ("rgb_pyr", C.c_void_p),
-                ("lut_S", C.c_void_p), ("lut_E", C.c_void_p)]
+                ("lut_S", C.c_void_p), ("lut_E", C.c_void_p), ("surrogate_w", C.c_void_p),
+                ("surrogate_w_bf16", C.c_void_p)]
 
 
 class View(C.Structure):
     _fields_ = [("gbuf", GBuffer), ("num_pixels", C.c_int64), ("env_index", C.c_int), ("shade", ShadeParams),
-                ("radiance", C.c_void_p)]
+                ("radiance", C.c_void_p), ("surrogate_F", C.c_void_p)]
 
 
 _LIB = None

@@ -82,9 +82,11 @@ class BatchedFrame:
     """Many environments and views in one graph launch (glint_frame_batched).
 
     envs: list of (env tensor [6,R,R,3], K, M, T); views: list of
-    (gbuf dict, env_index, seed, vertices).  Allocates every buffer once."""
+    (gbuf dict, env_index, seed, vertices); surrogates: optional list (one
+    per environment) of Surrogate or None: views of an environment with a
+    surrogate are shaded with it.  Allocates every buffer once."""
 
-    def __init__(self, ctx, envs, views, dtype=G.GLINT_F32, ell=1e-3, device="cuda"):
+    def __init__(self, ctx, envs, views, dtype=G.GLINT_F32, ell=1e-3, device="cuda", surrogates=None):
         self.ctx = ctx
         self.pipes, self.env_tensors = [], []
         for (env, K, M, T) in envs:
@@ -95,14 +97,23 @@ class BatchedFrame:
             self.env_tensors.append(env)
         self.shaders = [Shader(ctx, gb, seed=seed, vertices=V, device=device) for (gb, _, seed, V) in views]
         self.env_index = [e for (_, e, _, _) in views]
+        self.surrogates = list(surrogates) if surrogates is not None else [None] * len(envs)
         self.tasks = []
-        for pipe, env in zip(self.pipes, self.env_tensors):
+        for pipe, env, sur in zip(self.pipes, self.env_tensors, self.surrogates):
             self.tasks.append(G.EnvTask(env.data_ptr(), pipe.R, pipe.pp, pipe.fp, pipe.part_ws.data_ptr(),
                                         pipe.filt_ws.data_ptr(), pipe.levels.data_ptr(), pipe.ind_j.data_ptr(),
                                         pipe.ind_t.data_ptr(), pipe.ind_pyr.data_ptr(), pipe.rgb_pyr.data_ptr(),
-                                        pipe.lut_S.data_ptr(), pipe.lut_E.data_ptr()))
-        self.view_structs = [G.View(sh.gb, sh.P, e, sh.sp, sh.radiance.data_ptr())
-                             for sh, e in zip(self.shaders, self.env_index)]
+                                        pipe.lut_S.data_ptr(), pipe.lut_E.data_ptr(),
+                                        sur.w.data_ptr() if sur is not None else None,
+                                        sur.wb.data_ptr() if sur is not None else None))
+        self.F = []
+        for sh, e in zip(self.shaders, self.env_index):
+            sur = self.surrogates[e]
+            self.F.append(torch.empty(max(1, sh.P * sur.K), dtype=torch.float32, device=device)
+                          if sur is not None else None)
+        self.view_structs = [G.View(sh.gb, sh.P, e, sh.sp, sh.radiance.data_ptr(),
+                                    F.data_ptr() if F is not None else None)
+                             for sh, e, F in zip(self.shaders, self.env_index, self.F)]
         nbytes = G.glint_batched_workspace_bytes(len(views))
         self.workspace = torch.empty(nbytes // 8 + 64, dtype=torch.float64, device=device)
         # 256-byte aligned view into the workspace

@@ -82,15 +82,59 @@ def test_batched_rejects_bad_arguments(ctx):
     envs, views = small_setup()
     bf = BatchedFrame(ctx, envs, views[:2])
     bad = G.View(bf.view_structs[0].gbuf, bf.view_structs[0].num_pixels, 7, bf.view_structs[0].shade,
-                 bf.view_structs[0].radiance)
+                 bf.view_structs[0].radiance, None)
     with pytest.raises(G.GlintError) as e:
         G.glint_frame_batched(ctx, bf.tasks, [bad], bf.ws)
     assert e.value.code == G.GLINT_EINVAL
     t = bf.tasks[1]
     odd = G.EnvTask(t.env, t.R, t.partition, G.PrefilterParams(t.prefilter.num_mips, t.prefilter.taps, G.GLINT_F16),
                     t.partition_workspace, t.prefilter_workspace, t.levels, t.ind_j, t.ind_t, t.ind_pyr, t.rgb_pyr,
-                    t.lut_S, t.lut_E)
+                    t.lut_S, t.lut_E, None, None)
     with pytest.raises(G.GlintError):
         G.glint_frame_batched(ctx, [bf.tasks[0], odd], bf.view_structs, bf.ws)
     with pytest.raises(G.GlintError):
         G.glint_frame_batched(ctx, bf.tasks, [], bf.ws)
+
+
+def test_batched_surrogate_form_equals_per_call_path(ctx):
+    """Environments with surrogate parameters: their views go through the
+    network lookup and the surrogate shading inside the graph, bit-identical
+    to glint_shade_surrogate per view; plain environments are unchanged."""
+    import torch
+    from paper_2507_02674_amd.pipeline import Surrogate, SurrogateShader
+    U.log("batched surrogate form")
+    envs, views = small_setup()
+    surs = []
+    for e, (env, K, M, T) in enumerate(envs):
+        if e == 1:
+            surs.append(None)  # stays plain
+            continue
+        s = Surrogate(ctx, K)
+        s.init(seed=10 + e)
+        surs.append(s)
+    bf = BatchedFrame(ctx, envs, views, surrogates=surs)
+    bf.run()
+    torch.cuda.synchronize()
+    pipes, ref_plain = reference(ctx, envs, views)
+    for v, (gb, e, seed, V) in enumerate(views):
+        got = U.host(bf.shaders[v].radiance)
+        if surs[e] is None:
+            assert np.array_equal(got, ref_plain[v]), v
+        else:
+            sh = SurrogateShader(ctx, gb, surs[e], seed=seed, vertices=V)
+            sh.run(pipes[e].env_struct())
+            assert np.array_equal(got, U.host(sh.radiance)), v
+    first = [U.host(sh.radiance) for sh in bf.shaders]
+    for rep in range(2):
+        for sh in bf.shaders:
+            sh.radiance.fill_(-1.0)
+        _ = torch.ones(1000, device="cuda").sum().item()
+        bf.run()
+        torch.cuda.synchronize()
+        for v in range(len(views)):
+            assert np.array_equal(U.host(bf.shaders[v].radiance), first[v]), (rep, v)
+    # a surrogate environment's view without an F buffer is rejected
+    bad = G.View(bf.view_structs[0].gbuf, bf.view_structs[0].num_pixels, 0, bf.view_structs[0].shade,
+                 bf.view_structs[0].radiance, None)
+    with pytest.raises(G.GlintError):
+        G.glint_frame_batched(ctx, bf.tasks, [bad], bf.ws)
