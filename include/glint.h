@@ -243,6 +243,21 @@ int glint_surrogate_train_step(glint_ctx ctx, int K, float *w, uint16_t *w_bf16,
 int glint_build_luts(glint_ctx ctx, float *lut_S, float *lut_E, void *stream);
 
 /* ------------------------------------------------------------------------
+ * Tail table of the Gaussian quantile (an implementation aid, same results).
+ * Shading draws xi2 = (h9 + 1/2) 2^-23 from the 23-bit hash value h9; the
+ * quantile (AS 241) takes its tail branch (|xi2 - 1/2| > 0.425) exactly for
+ * h9 < 629146 or h9 > 7759461.  The table holds the quantile of those
+ * 1,258,292 values (double, low tail then high tail, ascending h9),
+ * computed by the same device code as the per-draw evaluation, so shading
+ * with or without it gives bit-identical results; with it, a draw in a tail
+ * is one load instead of a divergent log, square root and rational function.
+ * Build once per context; `table` is device memory of
+ * glint_quantile_table_bytes() bytes, 8-byte aligned.
+ * ------------------------------------------------------------------------ */
+size_t glint_quantile_table_bytes(void);
+int glint_build_quantile_table(glint_ctx ctx, double *table, void *stream);
+
+/* ------------------------------------------------------------------------
  * Per-pixel glint shading (Sec. 3.2, Sec. 3.3 Eq. (anisogrid), Sec. 4
  * Eq. (probhk) and Eq. (iblglints:fin), Sec. 6 Alg. "Dual-gated Gaussian").
  *
@@ -289,6 +304,8 @@ typedef struct glint_env {
     const float *lut_E;    /* device [64][64][2] */
     int R, K, num_mips;
     glint_dtype dtype;
+    const double *quantile_tail; /* device table from glint_build_quantile_table, or NULL
+                                    (then the quantile's tails are evaluated per draw) */
 } glint_env;
 
 typedef struct glint_shade_params {
@@ -361,6 +378,7 @@ typedef struct glint_env_task {
     void *ind_pyr;
     float *rgb_pyr;
     const float *lut_S, *lut_E;     /* device LUTs from glint_build_luts */
+    const double *quantile_tail;    /* device table from glint_build_quantile_table, or NULL */
     /* Surrogate form (NULL, NULL: plain form): the parameters of a network
      * for this environment's K (see glint_shade_surrogate); views lit by
      * this environment are shaded with it. */

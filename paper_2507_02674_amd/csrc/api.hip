@@ -236,6 +236,17 @@ int glint_build_luts(glint_ctx ctx, float *lut_S, float *lut_E, void *stream)
     return device_status(glint::launch_luts(lut_S, lut_E, (hipStream_t)stream), "glint_build_luts launch");
 }
 
+size_t glint_quantile_table_bytes(void) { return (size_t)glint::kTailEntries * sizeof(double); }
+
+int glint_build_quantile_table(glint_ctx ctx, double *table, void *stream)
+{
+    if (int rc = check_ctx(ctx)) return rc;
+    glint::ProfScope prof_scope(&ctx->prof);
+    if (!table) return fail(GLINT_EINVAL, "null pointer argument");
+    if (reinterpret_cast<uintptr_t>(table) % 8) return fail(GLINT_EINVAL, "table must be 8-byte aligned");
+    return device_status(glint::launch_quantile_table(table, (hipStream_t)stream), "glint_build_quantile_table");
+}
+
 int glint_shade(glint_ctx ctx, const glint_gbuffer *g, int64_t P, const glint_env *env,
                 const glint_shade_params *sp, float *radiance, const glint_shade_debug *dbg, void *stream)
 {

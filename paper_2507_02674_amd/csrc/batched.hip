@@ -52,7 +52,7 @@ hipError_t upload_group(const Group &g, const glint_env_task *envs, const glint_
         const glint_view &v = views[g.views[q]];
         const glint_env_task &e = envs[v.env_index];
         glint_env env{e.ind_pyr, e.rgb_pyr, e.levels, e.lut_S, e.lut_E, e.R, e.partition.K, e.prefilter.num_mips,
-                      e.prefilter.dtype};
+                      e.prefilter.dtype, e.quantile_tail};
         make_shade_args(desc.data() + q * ab, v.gbuf, v.num_pixels, env, v.shade, v.radiance,
                         g.surrogate ? v.surrogate_F : nullptr);
         tile0[q] = t;

@@ -198,19 +198,22 @@ __device__ __forceinline__ float hash_unit(uint32_t h)
 // ---------------------------------------------------------------------------
 // Inverse standard normal CDF, AS 241 PPND16 (Wichura 1988), double.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double ppnd16(double p)
+// Central region of AS 241 (|p - 1/2| <= 0.425), q = p - 1/2.
+__device__ __forceinline__ double ppnd16_central(double q)
 {
-    const double q = p - 0.5;
-    if (fabs(q) <= 0.425) {
-        const double r = 0.180625 - q * q;
-        const double num = (((((((r * 2509.0809287301226727 + 33430.575583588128105) * r + 67265.770927008700853) * r
-                                + 45921.953931549871457) * r + 13731.693765509461125) * r + 1971.5909503065514427) * r
-                             + 133.14166789178437745) * r + 3.387132872796366608);
-        const double den = (((((((r * 5226.495278852545925 + 28729.085735721942674) * r + 39307.89580009271061) * r
-                                + 21213.794301586595867) * r + 5394.1960214247511077) * r + 687.1870074920579083) * r
-                             + 42.313330701600911252) * r + 1.0);
-        return q * num / den;
-    }
+    const double r = 0.180625 - q * q;
+    const double num = (((((((r * 2509.0809287301226727 + 33430.575583588128105) * r + 67265.770927008700853) * r
+                            + 45921.953931549871457) * r + 13731.693765509461125) * r + 1971.5909503065514427) * r
+                         + 133.14166789178437745) * r + 3.387132872796366608);
+    const double den = (((((((r * 5226.495278852545925 + 28729.085735721942674) * r + 39307.89580009271061) * r
+                            + 21213.794301586595867) * r + 5394.1960214247511077) * r + 687.1870074920579083) * r
+                         + 42.313330701600911252) * r + 1.0);
+    return q * num / den;
+}
+
+// Tails of AS 241 (|p - 1/2| > 0.425).
+__device__ __forceinline__ double ppnd16_tail(double p, double q)
+{
     double r = q < 0.0 ? p : 1.0 - p;
     r = sqrt(-log(r));
     double num, den;
@@ -233,6 +236,34 @@ __device__ __forceinline__ double ppnd16(double p)
     }
     const double val = num / den;
     return q < 0.0 ? -val : val;
+}
+
+// Standard normal quantile, AS 241 PPND16 (Wichura 1988), double.
+__device__ __forceinline__ double ppnd16(double p)
+{
+    const double q = p - 0.5;
+    if (fabs(q) <= 0.425) return ppnd16_central(q);
+    return ppnd16_tail(p, q);
+}
+
+// The quantile's tails for the hash-derived uniforms: xi = (h9 + 1/2) 2^-23
+// with h9 = h >> 9 is in a tail exactly when h9 < kTailLo or h9 > kTailHi;
+// a table of those 2 kTailLo values (built with ppnd16_tail) replaces the
+// divergent tail evaluation in shading.
+constexpr uint32_t kTailLo = 629146u, kTailHi = 7759461u;
+constexpr int64_t kTailEntries = 2 * (int64_t)kTailLo;
+
+__device__ __forceinline__ bool tail_index(uint32_t h9, uint32_t &idx)
+{
+    if (h9 < kTailLo) {
+        idx = h9;
+        return true;
+    }
+    if (h9 > kTailHi) {
+        idx = h9 - (kTailHi + 1u) + kTailLo;
+        return true;
+    }
+    return false;
 }
 
 // ---------------------------------------------------------------------------

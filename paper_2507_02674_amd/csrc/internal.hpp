@@ -26,6 +26,7 @@ hipError_t launch_sample_filter(const float *env, const uint8_t *ind_j, const fl
                                 const float *a1, int64_t n, float *out0, float *out1, hipStream_t stream);
 
 hipError_t launch_luts(float *lut_S, float *lut_E, hipStream_t stream);
+hipError_t launch_quantile_table(double *table, hipStream_t stream);
 
 // learned surrogate
 int mlp_params();

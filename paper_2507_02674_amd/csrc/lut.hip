@@ -105,6 +105,24 @@ __global__ void __launch_bounds__(kLutThreads) k_lut(float *__restrict__ lut_S, 
     }
 }
 
+// Quantile of every tail uniform the hash can produce (see tail_index).
+__global__ void __launch_bounds__(256) k_quantile_tail(double *__restrict__ table)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= kTailEntries) return;
+    const uint32_t h9 = i < (int64_t)kTailLo ? (uint32_t)i : (uint32_t)(i - kTailLo) + kTailHi + 1u;
+    const float xi = ((float)h9 + 0.5f) * 1.1920928955078125e-07f;
+    const double xd = (double)xi;
+    table[i] = ppnd16_tail(xd, xd - 0.5);
+}
+
+hipError_t launch_quantile_table(double *table, hipStream_t stream)
+{
+    GLINT_LAUNCH("k_quantile_tail", k_quantile_tail, dim3((unsigned)((kTailEntries + 255) / 256)), dim3(256), 0,
+                 stream, table);
+    return hipGetLastError();
+}
+
 hipError_t launch_luts(float *lut_S, float *lut_E, hipStream_t stream)
 {
     GLINT_LAUNCH("k_lut", k_lut, dim3(kLutN * kLutN), dim3(kLutThreads), 0, stream, lut_S, lut_E);

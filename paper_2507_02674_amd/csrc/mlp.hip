@@ -476,15 +476,18 @@ __global__ void __launch_bounds__(64 * kInferWaves) k_mlp_infer(InferInput in, i
     const int64_t iters = first < tiles ? (tiles - first + stride - 1) / stride : 0;
     for (int64_t it = 0; it < iters; ++it) {
         const int64_t row0 = (first + wave + it * stride) * 32;
+        bool needed = false; // this lane's row is a sample or a surface pixel
         if (lane < 32) {
             const int64_t i = row0 + lane;
             float f[5] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
             if (i < B) {
                 if constexpr (SRC == 0) {
+                    needed = true;
 #pragma unroll
                     for (int c = 0; c < 5; ++c) f[c] = in.x[i * 5 + c];
                 } else {
-                    if (in.g.surf_id[i] != GLINT_NO_SURFACE) pixel_features(in.g, i, f);
+                    needed = in.g.surf_id[i] != GLINT_NO_SURFACE;
+                    if (needed) pixel_features(in.g, i, f);
                 }
             }
             uint4 *xr = reinterpret_cast<uint4 *>(t.x + lane * kLdX);
@@ -492,16 +495,23 @@ __global__ void __launch_bounds__(64 * kInferWaves) k_mlp_infer(InferInput in, i
             xr[0] = make_uint4(lo.x, lo.y, (uint32_t)to_bf16(f[4]), 0u);
             xr[1] = make_uint4(0u, 0u, 0u, 0u);
         }
+        // a tile with no sample and no surface pixel (background) skips the
+        // network; the block's barriers are still reached by every wave
+        const bool active = __ballot(needed) != 0;
         __syncthreads();
-        dense_silu(t.x, kLdX, kIn, W1, kLdW1, w + ob1, t.h[0], nullptr);
+        if (active) dense_silu(t.x, kLdX, kIn, W1, kLdW1, w + ob1, t.h[0], nullptr);
         __syncthreads();
-        dense_silu(t.h[0], kLdH, kH, W2, kLdH, w + ob2, t.h[1], nullptr);
+        if (active) dense_silu(t.h[0], kLdH, kH, W2, kLdH, w + ob2, t.h[1], nullptr);
         __syncthreads();
-        dense_silu(t.h[1], kLdH, kH, W3, kLdH, w + ob3, t.h[0], nullptr);
+        if (active) dense_silu(t.h[1], kLdH, kH, W3, kLdH, w + ob3, t.h[0], nullptr);
         __syncthreads();
         float logit[16], y[16];
-        dense_out(t.h[0], W4, w + ob4, logit);
-        softmax_pair(logit, K, y);
+#pragma unroll
+        for (int j = 0; j < 16; ++j) y[j] = 0.0f;
+        if (active) {
+            dense_out(t.h[0], W4, w + ob4, logit);
+            softmax_pair(logit, K, y);
+        }
         const int64_t i = row0 + (lane & 31);
         if (i < B) {
             bool keep = true;

@@ -127,17 +127,25 @@ struct ShadeArgs {
     double *counts;
     uint8_t *codes;
     double *probs;
-    const float *F; // surrogate form: filtered indicator values [P][K] (else null)
+    const float *F;      // surrogate form: filtered indicator values [P][K] (else null)
+    const double *qtail; // quantile tail table (else null: tails evaluated inline)
 };
 
 // One dual-gated Gaussian draw (Alg. "Dual-gated Gaussian").
-__device__ __forceinline__ void dual_gated(double N, double p, float xi1, float xi2, double &n, double &nb,
-                                           uint32_t &code)
+// xi2 = (h9 + 1/2) 2^-23; qtail: the quantile's tail table (or null: the
+// tails are evaluated here).
+__device__ __forceinline__ void dual_gated(double N, double p, float xi1, float xi2, uint32_t h9,
+                                           const double *__restrict__ qtail, double &n, double &nb, uint32_t &code)
 {
     // Rounded as written (no fused multiply-add): at N ~ 1e12 one ulp of mu
     // is ~1e-4, so every operation must round as in the definition for the
     // counts' integer parts to agree.
 #pragma clang fp contract(off)
+    // the tail value is fetched first so its latency overlaps the gating
+    uint32_t tidx = 0;
+    const bool tail = tail_index(h9, tidx);
+    double ztab = 0.0;
+    if (qtail && tail) ztab = qtail[tidx];
     const gate_f g = gate_thresholds((float)N, (float)p);
     const bool BnN = xi1 < g.th_nN;
     const bool Bn1N = xi1 < g.th_n1N;
@@ -149,7 +157,9 @@ __device__ __forceinline__ void dual_gated(double N, double p, float xi1, float 
     if (BG) {
         const double mu = 1.0 + (N2 - 2.0) * p;
         const double sig = sqrt((N2 - 2.0) * p * (1.0 - p));
-        const double x = mu + sig * ppnd16((double)xi2);
+        const double xd = (double)xi2, q = xd - 0.5;
+        const double z = !tail ? ppnd16_central(q) : (qtail ? ztab : ppnd16_tail(xd, q));
+        const double x = mu + sig * z;
         G = x < 1.0 ? 1.0 : (x > N2 - 1.0 ? N2 - 1.0 : x);
         Gb = N2 - G;
     }
@@ -171,7 +181,8 @@ __device__ __forceinline__ void dual_gated(double N, double p, float xi1, float 
 // array is indexed dynamically.
 template <int K>
 __device__ __forceinline__ void multinomial(double NP, const double (&p)[K], uint32_t seed_mix, int lev, int64_t a,
-                                            int64_t b, double (&leaf)[K], uint8_t *codes)
+                                            int64_t b, const double *__restrict__ qtail, double (&leaf)[K],
+                                            uint8_t *codes)
 {
     double Q[K]; // counts of the current depth, in node order
     Q[0] = NP;
@@ -205,7 +216,7 @@ __device__ __forceinline__ void multinomial(double NP, const double (&p)[K], uin
             const u4 h = pcg4d({(uint32_t)a, (uint32_t)b, (((uint32_t)lev & 0xFFFFu) << 16) | (uint32_t)node, seed_mix});
             double n, nb;
             uint32_t code;
-            dual_gated(N, pj, hash_unit(h.x), hash_unit(h.y), n, nb, code);
+            dual_gated(N, pj, hash_unit(h.x), hash_unit(h.y), h.y >> 9, qtail, n, nb, code);
             if (codes) codes[node] = (uint8_t)code;
 #pragma unroll
             for (int k = 0; k + 2 < 2 * nd; ++k) Rq[k] = Rq[k + 2];
@@ -357,7 +368,7 @@ __device__ __forceinline__ void shade_pixel(const ShadeArgs &A, int64_t i)
         }
         double Mv[K];
         uint8_t *cod = A.codes ? A.codes + (i * V + vi) * (K - 1) : nullptr;
-        multinomial<K>(NP, p, seed_mix, lev, a, b, Mv, cod);
+        multinomial<K>(NP, p, seed_mix, lev, a, b, A.qtail, Mv, cod);
 #pragma unroll
         for (int k = 0; k < K; ++k) Msum[k] += w * Mv[k];
         if (A.counts) {
@@ -441,6 +452,7 @@ void make_shade_args(void *out, const glint_gbuffer &g, int64_t P, const glint_e
     a.codes = nullptr;
     a.probs = nullptr;
     a.F = F;
+    a.qtail = env.quantile_tail;
     *static_cast<ShadeArgs *>(out) = a;
 }
 
@@ -497,6 +509,7 @@ hipError_t launch_shade(const glint_gbuffer &g, int64_t P, const glint_env &env,
     a.codes = dbg ? dbg->codes : nullptr;
     a.probs = dbg ? dbg->probs : nullptr;
     a.F = F;
+    a.qtail = env.quantile_tail;
     const int K = env.K, DT = (int)env.dtype, V = sp.vertices;
     if (F) {
         // surrogate form: the indicator pyramid is not read, so its storage type does not matter

@@ -42,7 +42,7 @@ class GBuffer(C.Structure):
 class Env(C.Structure):
     _fields_ = [("ind_pyr", C.c_void_p), ("rgb_pyr", C.c_void_p), ("levels", C.c_void_p),
                 ("lut_S", C.c_void_p), ("lut_E", C.c_void_p), ("R", C.c_int), ("K", C.c_int),
-                ("num_mips", C.c_int), ("dtype", C.c_int)]
+                ("num_mips", C.c_int), ("dtype", C.c_int), ("quantile_tail", C.c_void_p)]
 
 
 class ShadeParams(C.Structure):
@@ -57,8 +57,8 @@ class EnvTask(C.Structure):
     _fields_ = [("env", C.c_void_p), ("R", C.c_int), ("partition", PartitionParams), ("prefilter", PrefilterParams),
                 ("partition_workspace", C.c_void_p), ("prefilter_workspace", C.c_void_p), ("levels", C.c_void_p),
                 ("ind_j", C.c_void_p), ("ind_t", C.c_void_p), ("ind_pyr", C.c_void_p), ("rgb_pyr", C.c_void_p),
-                ("lut_S", C.c_void_p), ("lut_E", C.c_void_p), ("surrogate_w", C.c_void_p),
-                ("surrogate_w_bf16", C.c_void_p)]
+                ("lut_S", C.c_void_p), ("lut_E", C.c_void_p), ("quantile_tail", C.c_void_p),
+                ("surrogate_w", C.c_void_p), ("surrogate_w_bf16", C.c_void_p)]
 
 
 class View(C.Structure):
@@ -82,6 +82,8 @@ EXPORTS = {
     "glint_prefilter": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_int,
                          C.POINTER(PrefilterParams), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     "glint_build_luts": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
+    "glint_quantile_table_bytes": ([], C.c_size_t),
+    "glint_build_quantile_table": ([C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     "glint_shade": ([C.c_void_p, C.POINTER(GBuffer), C.c_int64, C.POINTER(Env), C.POINTER(ShadeParams),
                      C.c_void_p, C.POINTER(ShadeDebug), C.c_void_p], C.c_int),
     "glint_sample_filter": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_int,
@@ -212,16 +214,26 @@ def glint_build_luts(ctx, lut_S, lut_E, stream=None):
     _check(lib().glint_build_luts(ctx, _ptr(lut_S), _ptr(lut_E), _stream(stream)))
 
 
+def glint_quantile_table_bytes() -> int:
+    return lib().glint_quantile_table_bytes()
+
+
+def glint_build_quantile_table(ctx, table, stream=None):
+    _require_cuda(table)
+    _check(lib().glint_build_quantile_table(ctx, _ptr(table), _stream(stream)))
+
+
 def make_gbuffer(fields: dict) -> GBuffer:
     """Maps a dict of device tensors (one per G-buffer field) to the C struct."""
     _require_cuda(*fields.values())
     return GBuffer(*[fields[k].data_ptr() for k in GBUF_FIELDS])
 
 
-def make_env(ind_pyr, rgb_pyr, levels, lut_S, lut_E, R, K, num_mips, dtype) -> Env:
-    _require_cuda(ind_pyr, rgb_pyr, levels, lut_S, lut_E)
-    return Env(ind_pyr.data_ptr(), rgb_pyr.data_ptr(), levels.data_ptr(), lut_S.data_ptr(), lut_E.data_ptr(),
-               R, K, num_mips, dtype)
+def make_env(ind_pyr, rgb_pyr, levels, lut_S, lut_E, R, K, num_mips, dtype, quantile_tail=None) -> Env:
+    _require_cuda(ind_pyr, rgb_pyr, levels, lut_S, lut_E, quantile_tail)
+    return Env(ind_pyr.data_ptr() if ind_pyr is not None else None, rgb_pyr.data_ptr(), levels.data_ptr(),
+               lut_S.data_ptr(), lut_E.data_ptr(), R, K, num_mips, dtype,
+               quantile_tail.data_ptr() if quantile_tail is not None else None)
 
 
 def glint_shade(ctx, gbuf: GBuffer, num_pixels: int, env: Env, params: ShadeParams, radiance, debug=None,

@@ -37,9 +37,12 @@ class EnvPipeline:
         self.rgb_pyr = torch.empty((self.texels, 4), dtype=torch.float32, device=device)
         self.lut_S = torch.empty((G.LUT_N, G.LUT_N), dtype=torch.float32, device=device)
         self.lut_E = torch.empty((G.LUT_N, G.LUT_N, 2), dtype=torch.float32, device=device)
+        self.qtail = torch.empty(G.glint_quantile_table_bytes() // 8, dtype=torch.float64, device=device)
 
     def build_luts(self, stream=None):
+        """Lookup tables once per BRDF model, and the quantile's tail table."""
         G.glint_build_luts(self.ctx, self.lut_S, self.lut_E, stream)
+        G.glint_build_quantile_table(self.ctx, self.qtail, stream)
 
     def partition(self, env, stream=None):
         G.glint_partition_env(self.ctx, env, self.R, self.pp, self.part_ws, self.levels, self.ind_j, self.ind_t,
@@ -53,9 +56,9 @@ class EnvPipeline:
         self.partition(env, stream)
         self.prefilter(env, stream)
 
-    def env_struct(self):
+    def env_struct(self, quantile_table=True):
         return G.make_env(self.ind_pyr, self.rgb_pyr, self.levels, self.lut_S, self.lut_E, self.R, self.K,
-                          self.M, self.dtype)
+                          self.M, self.dtype, self.qtail if quantile_table else None)
 
 
 class Shader:
@@ -103,7 +106,7 @@ class BatchedFrame:
             self.tasks.append(G.EnvTask(env.data_ptr(), pipe.R, pipe.pp, pipe.fp, pipe.part_ws.data_ptr(),
                                         pipe.filt_ws.data_ptr(), pipe.levels.data_ptr(), pipe.ind_j.data_ptr(),
                                         pipe.ind_t.data_ptr(), pipe.ind_pyr.data_ptr(), pipe.rgb_pyr.data_ptr(),
-                                        pipe.lut_S.data_ptr(), pipe.lut_E.data_ptr(),
+                                        pipe.lut_S.data_ptr(), pipe.lut_E.data_ptr(), pipe.qtail.data_ptr(),
                                         sur.w.data_ptr() if sur is not None else None,
                                         sur.wb.data_ptr() if sur is not None else None))
         self.F = []

@@ -105,14 +105,14 @@ def gbuf_to_device(gbuf):
 
 
 def shade(ctx, gbuf, ind_raw, rgb, levels, lut_S, lut_E, R, K, M, dtype=G.GLINT_F32, seed=1, vertices=1,
-          debug=True, num_pixels=None):
+          debug=True, num_pixels=None, qtail=None):
     fields = gbuf_to_device(gbuf)
     P = len(gbuf["nx"]) if num_pixels is None else num_pixels
     tdt, ndt = STORAGE[dtype]
     ind = torch.from_numpy(np.ascontiguousarray(ind_raw).view(np.int16) if ndt == np.uint16 else
                            np.ascontiguousarray(ind_raw)).cuda()
     rgb_t, lev_t, S_t, E_t = dev(rgb), dev(levels), dev(lut_S), dev(lut_E)
-    env = G.make_env(ind, rgb_t, lev_t, S_t, E_t, R, K, M, dtype)
+    env = G.make_env(ind, rgb_t, lev_t, S_t, E_t, R, K, M, dtype, qtail)
     rad = torch.full((max(P, 1), 3), -1.0, dtype=torch.float32, device="cuda")
     dbg = None
     if debug:
@@ -132,3 +132,9 @@ def ulp_diff(a, b):
     a = np.ascontiguousarray(a, dtype=np.float32).view(np.int32).astype(np.int64)
     b = np.ascontiguousarray(b, dtype=np.float32).view(np.int32).astype(np.int64)
     return np.abs(a - b)
+
+
+def quantile_table(ctx):
+    t = torch.empty(G.glint_quantile_table_bytes() // 8, dtype=torch.float64, device="cuda")
+    G.glint_build_quantile_table(ctx, t)
+    return t

@@ -89,7 +89,7 @@ def test_batched_rejects_bad_arguments(ctx):
     t = bf.tasks[1]
     odd = G.EnvTask(t.env, t.R, t.partition, G.PrefilterParams(t.prefilter.num_mips, t.prefilter.taps, G.GLINT_F16),
                     t.partition_workspace, t.prefilter_workspace, t.levels, t.ind_j, t.ind_t, t.ind_pyr, t.rgb_pyr,
-                    t.lut_S, t.lut_E, None, None)
+                    t.lut_S, t.lut_E, t.quantile_tail, None, None)
     with pytest.raises(G.GlintError):
         G.glint_frame_batched(ctx, [bf.tasks[0], odd], bf.view_structs, bf.ws)
     with pytest.raises(G.GlintError):

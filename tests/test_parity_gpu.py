@@ -373,6 +373,33 @@ def test_precision_workload_sampled(ctx):
     check_shade({k: v[pix] for k, v in gpu.items()}, orc, w.K, "precision workload sampled")
 
 
+def test_quantile_tail_table(ctx):
+    """The tail table holds AS 241 of every tail uniform the hash can give
+    (against the oracle's quantile), and shading with it is bit-identical to
+    shading that evaluates the tails per draw."""
+    qt = U.quantile_table(ctx)
+    tab = U.host(qt)
+    assert len(tab) == 1258292
+    rng = np.random.default_rng(4)
+    idx = np.concatenate([[0, 629145, 629146, len(tab) - 1], rng.choice(len(tab), 2000, replace=False)])
+    h9 = np.where(idx < 629146, idx, idx - 629146 + 7759462)
+    xi = ((h9.astype(np.float32) + np.float32(0.5)) * np.float32(2.0 ** -23)).astype(np.float64)
+    ref = np.array([oracle.ppnd16(float(x)) for x in xi])
+    np.testing.assert_allclose(tab[idx], ref, rtol=1e-14, atol=0)
+    assert np.all(np.abs(xi - 0.5) > 0.425)
+    w = synth.WORKLOADS["frame"]
+    env = synth.make_env(64, 9)
+    lv, ij, it = U.partition(ctx, env, w.K)
+    raw, rgb, _ = U.prefilter(ctx, env, ij, it, w.K, 7)
+    S, E = U.luts(ctx)
+    g = synth.subsample_gbuf(w.gbuf(), np.arange(0, 1920 * 1080, 37))
+    for V in (1, 6):
+        a = U.shade(ctx, g, raw, rgb, lv, S, E, 64, w.K, 7, seed=5, vertices=V)
+        b = U.shade(ctx, g, raw, rgb, lv, S, E, 64, w.K, 7, seed=5, vertices=V, qtail=qt)
+        for k in a:
+            assert np.array_equal(a[k], b[k]), (V, k)
+
+
 def test_end_to_end_tiny(ctx):
     """GPU partition -> prefilter -> LUTs -> shade against the oracle run on its
     own from the same map and G-buffer."""
