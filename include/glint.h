@@ -309,8 +309,11 @@ typedef struct glint_env {
 } glint_env;
 
 typedef struct glint_shade_params {
-    uint32_t seed; /* material seed mixed into the hash */
-    int vertices;  /* 1 or 6 */
+    uint32_t seed;    /* material seed mixed into the hash */
+    int vertices;     /* 1 or 6 */
+    int exact_gating; /* 0: gating decisions from hardware log2/exp2 powers, re-evaluated with powf
+                         only within a safety margin of a threshold (same decisions); 1: always
+                         powf (for verification) */
 } glint_shade_params;
 
 /* Optional per-pixel outputs for verification (each pointer may be NULL). */

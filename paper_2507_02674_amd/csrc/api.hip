@@ -259,6 +259,7 @@ int glint_shade(glint_ctx ctx, const glint_gbuffer *g, int64_t P, const glint_en
     if (int rc = check_mips(env->R, env->num_mips)) return rc;
     if (int rc = check_dtype(env->dtype)) return rc;
     if (sp->vertices != 1 && sp->vertices != 6) return fail(GLINT_EINVAL, "vertices must be 1 or 6");
+    if (sp->exact_gating != 0 && sp->exact_gating != 1) return fail(GLINT_EINVAL, "exact_gating must be 0 or 1");
     if (P == 0) return ok();
     if (!radiance || !env->ind_pyr || !env->rgb_pyr || !env->levels || !env->lut_S || !env->lut_E)
         return fail(GLINT_EINVAL, "null pointer argument");
@@ -395,6 +396,7 @@ int glint_shade_surrogate(glint_ctx ctx, const glint_gbuffer *g, int64_t P, cons
     if (int rc = check_mips(env->R, env->num_mips)) return rc;
     if (int rc = check_surrogate(env->K, w, w_bf16)) return rc;
     if (sp->vertices != 1 && sp->vertices != 6) return fail(GLINT_EINVAL, "vertices must be 1 or 6");
+    if (sp->exact_gating != 0 && sp->exact_gating != 1) return fail(GLINT_EINVAL, "exact_gating must be 0 or 1");
     if (P == 0) return ok();
     if (!radiance || !workspace || !env->rgb_pyr || !env->levels || !env->lut_S || !env->lut_E)
         return fail(GLINT_EINVAL, "null pointer argument");
@@ -445,6 +447,8 @@ int glint_frame_batched(glint_ctx ctx, const glint_env_task *envs, int n_env, co
         if (w.num_pixels < 0 || w.num_pixels > ((int64_t)1 << 40))
             return fail(GLINT_EINVAL, "view %d: bad num_pixels", v);
         if (w.shade.vertices != 1 && w.shade.vertices != 6) return fail(GLINT_EINVAL, "view %d: vertices", v);
+        if (w.shade.exact_gating != 0 && w.shade.exact_gating != 1)
+            return fail(GLINT_EINVAL, "view %d: exact_gating must be 0 or 1", v);
         if (!w.radiance) return fail(GLINT_EINVAL, "view %d: null radiance", v);
         if (envs[w.env_index].surrogate_w &&
             (!w.surrogate_F || reinterpret_cast<uintptr_t>(w.surrogate_F) % 16))

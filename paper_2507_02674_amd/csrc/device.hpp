@@ -300,6 +300,54 @@ __device__ __forceinline__ gate_f gate_thresholds(float Nf, float pf)
     return g;
 }
 
+// The four gating decisions of a node (xi1 against the thresholds of
+// gate_thresholds), computed first from powers evaluated with the hardware
+// log2/exp2: their relative error is below 2^-17 whenever the power is
+// above 2^-64 (both instructions are within one ulp of the result and the
+// exponent's magnitude is then at most 64), so a decision whose xi1 lies
+// farther than 2^-14 P + 2^-22 from its approximate threshold equals the
+// decision from the exactly rounded thresholds.  Only when some xi1 is that
+// close (or a value is not finite) are the thresholds evaluated with powf.
+struct gate_d {
+    bool nN, n1N, nbN, nb1N;
+};
+
+__device__ __forceinline__ gate_d gate_decide(float Nf, float pf, float xi1, bool exact_only = false)
+{
+#pragma clang fp contract(off)
+    const float eps = 2.8840315031266055e-04f; // 10^-3.54
+    const float N2 = fmaxf(2.0f, Nf);
+    const float cN = fminf(fmaxf(Nf - 1.0f, 0.0f), 1.0f);
+    const float cp = fmaxf(pf, eps);
+    const float ex = N2 * fminf(1.0f, pf / eps);
+    const float d1 = fmaxf(0.0f, 1.0f - fabsf(1.0f - Nf));
+    const float bN = 1.0f - cp;
+    const float P_nN = cN * __builtin_amdgcn_exp2f(N2 * __builtin_amdgcn_logf(pf));
+    const float P_nbN = cN * __builtin_amdgcn_exp2f(ex * __builtin_amdgcn_logf(bN));
+    const float P_n1 = d1 * pf;
+    const float P_nb1 = d1 * (1.0f - pf);
+    const float t_nN = P_nN, t_n1N = P_nN + P_n1;
+    const float t_nbN = 1.0f - P_nbN, t_nb1N = (1.0f - P_nbN) - P_nb1;
+    const float mN = 6.103515625e-05f * P_nN + 2.384185791015625e-07f;   // 2^-14 P + 2^-22
+    const float mB = 6.103515625e-05f * P_nbN + 2.384185791015625e-07f;
+    const bool robust = !exact_only && fabsf(xi1 - t_nN) > mN && fabsf(xi1 - t_n1N) > mN &&
+                        fabsf(xi1 - t_nbN) > mB && fabsf(xi1 - t_nb1N) > mB;
+    gate_d d;
+    if (robust) {
+        d.nN = xi1 < t_nN;
+        d.n1N = xi1 < t_n1N;
+        d.nbN = t_nbN <= xi1;
+        d.nb1N = t_nb1N <= xi1;
+    } else {
+        const gate_f g = gate_thresholds(Nf, pf);
+        d.nN = xi1 < g.th_nN;
+        d.n1N = xi1 < g.th_n1N;
+        d.nbN = g.th_nbN <= xi1;
+        d.nb1N = g.th_nb1N <= xi1;
+    }
+    return d;
+}
+
 // Learned-surrogate inputs of a lookup (the project's extension, not the
 // paper's): the reflection direction, then (ln alpha - c) / h for alpha_x
 // and alpha_y, where c and h map [ln 0.02, ln 0.5] onto [-1, 1].

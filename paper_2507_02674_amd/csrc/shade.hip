@@ -129,13 +129,15 @@ struct ShadeArgs {
     double *probs;
     const float *F;      // surrogate form: filtered indicator values [P][K] (else null)
     const double *qtail; // quantile tail table (else null: tails evaluated inline)
+    int exact_gating;    // 1: gating thresholds always through powf (verification)
 };
 
 // One dual-gated Gaussian draw (Alg. "Dual-gated Gaussian").
 // xi2 = (h9 + 1/2) 2^-23; qtail: the quantile's tail table (or null: the
 // tails are evaluated here).
 __device__ __forceinline__ void dual_gated(double N, double p, float xi1, float xi2, uint32_t h9,
-                                           const double *__restrict__ qtail, double &n, double &nb, uint32_t &code)
+                                           const double *__restrict__ qtail, bool exact_gating, double &n,
+                                           double &nb, uint32_t &code)
 {
     // Rounded as written (no fused multiply-add): at N ~ 1e12 one ulp of mu
     // is ~1e-4, so every operation must round as in the definition for the
@@ -146,11 +148,11 @@ __device__ __forceinline__ void dual_gated(double N, double p, float xi1, float 
     const bool tail = tail_index(h9, tidx);
     double ztab = 0.0;
     if (qtail && tail) ztab = qtail[tidx];
-    const gate_f g = gate_thresholds((float)N, (float)p);
-    const bool BnN = xi1 < g.th_nN;
-    const bool Bn1N = xi1 < g.th_n1N;
-    const bool BnbN = g.th_nbN <= xi1;
-    const bool Bnb1N = g.th_nb1N <= xi1;
+    const gate_d gd = gate_decide((float)N, (float)p, xi1, exact_gating);
+    const bool BnN = gd.nN;
+    const bool Bn1N = gd.n1N;
+    const bool BnbN = gd.nbN;
+    const bool Bnb1N = gd.nb1N;
     const bool BG = ((float)N > 1.0f) && !Bn1N && !Bnb1N;
     const double N2 = N > 2.0 ? N : 2.0;
     double G = 0.0, Gb = 0.0;
@@ -181,8 +183,8 @@ __device__ __forceinline__ void dual_gated(double N, double p, float xi1, float 
 // array is indexed dynamically.
 template <int K>
 __device__ __forceinline__ void multinomial(double NP, const double (&p)[K], uint32_t seed_mix, int lev, int64_t a,
-                                            int64_t b, const double *__restrict__ qtail, double (&leaf)[K],
-                                            uint8_t *codes)
+                                            int64_t b, const double *__restrict__ qtail, bool exact_gating,
+                                            double (&leaf)[K], uint8_t *codes)
 {
     double Q[K]; // counts of the current depth, in node order
     Q[0] = NP;
@@ -216,7 +218,7 @@ __device__ __forceinline__ void multinomial(double NP, const double (&p)[K], uin
             const u4 h = pcg4d({(uint32_t)a, (uint32_t)b, (((uint32_t)lev & 0xFFFFu) << 16) | (uint32_t)node, seed_mix});
             double n, nb;
             uint32_t code;
-            dual_gated(N, pj, hash_unit(h.x), hash_unit(h.y), h.y >> 9, qtail, n, nb, code);
+            dual_gated(N, pj, hash_unit(h.x), hash_unit(h.y), h.y >> 9, qtail, exact_gating, n, nb, code);
             if (codes) codes[node] = (uint8_t)code;
 #pragma unroll
             for (int k = 0; k + 2 < 2 * nd; ++k) Rq[k] = Rq[k + 2];
@@ -368,7 +370,7 @@ __device__ __forceinline__ void shade_pixel(const ShadeArgs &A, int64_t i)
         }
         double Mv[K];
         uint8_t *cod = A.codes ? A.codes + (i * V + vi) * (K - 1) : nullptr;
-        multinomial<K>(NP, p, seed_mix, lev, a, b, A.qtail, Mv, cod);
+        multinomial<K>(NP, p, seed_mix, lev, a, b, A.qtail, A.exact_gating != 0, Mv, cod);
 #pragma unroll
         for (int k = 0; k < K; ++k) Msum[k] += w * Mv[k];
         if (A.counts) {
@@ -453,6 +455,7 @@ void make_shade_args(void *out, const glint_gbuffer &g, int64_t P, const glint_e
     a.probs = nullptr;
     a.F = F;
     a.qtail = env.quantile_tail;
+    a.exact_gating = sp.exact_gating;
     *static_cast<ShadeArgs *>(out) = a;
 }
 
@@ -510,6 +513,7 @@ hipError_t launch_shade(const glint_gbuffer &g, int64_t P, const glint_env &env,
     a.probs = dbg ? dbg->probs : nullptr;
     a.F = F;
     a.qtail = env.quantile_tail;
+    a.exact_gating = sp.exact_gating;
     const int K = env.K, DT = (int)env.dtype, V = sp.vertices;
     if (F) {
         // surrogate form: the indicator pyramid is not read, so its storage type does not matter

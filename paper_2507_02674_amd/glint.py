@@ -46,7 +46,7 @@ class Env(C.Structure):
 
 
 class ShadeParams(C.Structure):
-    _fields_ = [("seed", C.c_uint32), ("vertices", C.c_int)]
+    _fields_ = [("seed", C.c_uint32), ("vertices", C.c_int), ("exact_gating", C.c_int)]
 
 
 class ShadeDebug(C.Structure):

@@ -400,6 +400,28 @@ def test_quantile_tail_table(ctx):
             assert np.array_equal(a[k], b[k]), (V, k)
 
 
+@pytest.mark.parametrize("vertices", [1, 6])
+def test_fast_gating_equals_exact_gating(ctx, vertices):
+    """Gating decisions from hardware log2/exp2 powers with the powf
+    re-evaluation near a threshold are identical, on every pixel (flagged or
+    not), to decisions from powf throughout: frame-size sample and the count
+    sweep to 1e12."""
+    w = synth.WORKLOADS["frame"]
+    env = w.env()
+    lv, ij, it = U.partition(ctx, env, w.K)
+    raw, rgb, _ = U.prefilter(ctx, env, ij, it, w.K, w.M, w.T)
+    S, E = U.luts(ctx)
+    qt = U.quantile_table(ctx)
+    for g in (synth.subsample_gbuf(w.gbuf(), np.arange(0, 1920 * 1080, 7)), synth.n_sweep()):
+        a = U.shade(ctx, g, raw, rgb, lv, S, E, w.R, w.K, w.M, seed=11, vertices=vertices, qtail=qt)
+        b = U.shade(ctx, g, raw, rgb, lv, S, E, w.R, w.K, w.M, seed=11, vertices=vertices, qtail=qt,
+                    exact_gating=1)
+        for k in a:
+            assert np.array_equal(a[k], b[k]), (vertices, k)
+    with pytest.raises(G.GlintError):
+        U.shade(ctx, g, raw, rgb, lv, S, E, w.R, w.K, w.M, exact_gating=2)
+
+
 def test_end_to_end_tiny(ctx):
     """GPU partition -> prefilter -> LUTs -> shade against the oracle run on its
     own from the same map and G-buffer."""
