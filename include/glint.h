@@ -273,7 +273,8 @@ int glint_build_quantile_table(glint_ctx ctx, double *table, void *stream);
  * evaluated in float with the bias c = max(1, eps/p), eps = 10^-3.54
  * (Sec. 6 "Numeric Gating Issues"); the Gaussian quantile (AS 241) and all
  * other arithmetic in double.  Random numbers per (surface, lattice vertex,
- * node) from the pcg4d hash (Jarzynski & Olano 2020).
+ * node) from the pcg4d hash (Jarzynski & Olano 2020), one hash per pair of
+ * nodes: node 2i takes outputs (x, y), node 2i+1 outputs (z, w).
  * Lattice (the footprint grid of Sec. 3.3, used as a black box by the
  * paper): level l0 = floor(log2(area)/2) on the uv plane, spacing 2^l0.
  * vertices = 1: the nearest vertex; vertices = 6: the 3 vertices of the uv

@@ -586,17 +586,19 @@ static void pcg4d(uint32_t v[4])
 
 static float to_unit(uint32_t h) { return ((float)(h >> 9) + 0.5f) * 1.1920928955078125e-07f; }
 
+/* One hash serves two tree nodes: nodes 2i and 2i+1 of a lattice vertex
+ * take (x, y) and (z, w) of pcg4d(a, b, level << 16 | i, seed ^ surf * phi). */
 void orc_hash_xi(uint32_t seed, uint32_t surf, int32_t level, int64_t a, int64_t b, int node, float *xi1,
                  float *xi2)
 {
     uint32_t v[4];
     v[0] = (uint32_t)a;
     v[1] = (uint32_t)b;
-    v[2] = (((uint32_t)level & 0xFFFFu) << 16) | ((uint32_t)node & 0xFFFFu);
+    v[2] = (((uint32_t)level & 0xFFFFu) << 16) | (((uint32_t)node >> 1) & 0xFFFFu);
     v[3] = seed ^ (surf * 0x9E3779B9u);
     pcg4d(v);
-    *xi1 = to_unit(v[0]);
-    *xi2 = to_unit(v[1]);
+    *xi1 = to_unit(v[(node & 1) ? 2 : 0]);
+    *xi2 = to_unit(v[(node & 1) ? 3 : 1]);
 }
 
 /* ------------------------------------------------------------------------ */

@@ -188,6 +188,9 @@ __device__ __forceinline__ void multinomial(double NP, const double (&p)[K], uin
 {
     double Q[K]; // counts of the current depth, in node order
     Q[0] = NP;
+    // one hash per node pair: node 2i takes (x, y), node 2i+1 the (z, w)
+    // carried over (nodes run in increasing order across the depths)
+    uint32_t carry_z = 0, carry_w = 0;
 #pragma unroll
     for (int k = 1; k < K; ++k) Q[k] = 0.0;
 #pragma unroll
@@ -215,10 +218,21 @@ __device__ __forceinline__ void multinomial(double NP, const double (&p)[K], uin
 #pragma unroll
             for (int k = 0; k + 1 < nd; ++k) { Q[k] = Q[k + 1]; P[k] = P[k + 1]; }
             const int node = nd - 1 + j;
-            const u4 h = pcg4d({(uint32_t)a, (uint32_t)b, (((uint32_t)lev & 0xFFFFu) << 16) | (uint32_t)node, seed_mix});
+            uint32_t hx, hy;
+            if ((node & 1) == 0) {
+                const u4 h = pcg4d({(uint32_t)a, (uint32_t)b, (((uint32_t)lev & 0xFFFFu) << 16) | ((uint32_t)node >> 1),
+                                    seed_mix});
+                hx = h.x;
+                hy = h.y;
+                carry_z = h.z;
+                carry_w = h.w;
+            } else {
+                hx = carry_z;
+                hy = carry_w;
+            }
             double n, nb;
             uint32_t code;
-            dual_gated(N, pj, hash_unit(h.x), hash_unit(h.y), h.y >> 9, qtail, exact_gating, n, nb, code);
+            dual_gated(N, pj, hash_unit(hx), hash_unit(hy), hy >> 9, qtail, exact_gating, n, nb, code);
             if (codes) codes[node] = (uint8_t)code;
 #pragma unroll
             for (int k = 0; k + 2 < 2 * nd; ++k) Rq[k] = Rq[k + 2];
