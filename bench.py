@@ -157,6 +157,9 @@ def recorded_traffic(kernel, config_tag):
 
 # --- helpers -------------------------------------------------------------------------
 
+SAMPLERS = {"dual": 0, "single": 1, "single-floor": 2}
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -166,6 +169,8 @@ def parse():
     ap.add_argument("--form", default="plain", choices=["plain", "surrogate"])
     ap.add_argument("--dtype", default="f32", choices=["f32", "f16", "bf16", "unorm16"])
     ap.add_argument("--vertices", type=int, default=1)
+    ap.add_argument("--sampler", default="dual", choices=list(SAMPLERS),
+                    help="binomial approximation at every tree node (dual-gated is the paper's method)")
     ap.add_argument("--train-steps", type=int, default=400, help="surrogate training steps before timing")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-overlap", action="store_true",
@@ -375,8 +380,8 @@ def main():
     ctx = G.glint_create(0)
     env = torch.from_numpy(env_np).cuda()
 
-    def new_env():
-        return EnvPipeline(ctx, w.R, w.K, w.M, w.T, dtypes[a.dtype], w.ell)
+    def new_env(dtype=a.dtype):
+        return EnvPipeline(ctx, w.R, w.K, w.M, w.T, dtypes[dtype], w.ell)
 
     pipe = new_env()  # the serial pass's buffers (also the surrogate's training source)
     pipe.build_luts()
@@ -384,9 +389,10 @@ def main():
     extra = {}
     if a.form == "surrogate":
         sur, extra["surrogate"] = train_surrogate(G, ctx, pipe, env, w.K, a.train_steps)
-        shader = SurrogateShader(ctx, gbuf_np, sur, seed=w.hash_seed, vertices=a.vertices)
+        shader = SurrogateShader(ctx, gbuf_np, sur, seed=w.hash_seed, vertices=a.vertices,
+                                 sampler=SAMPLERS[a.sampler])
     else:
-        shader = Shader(ctx, gbuf_np, seed=w.hash_seed, vertices=a.vertices)
+        shader = Shader(ctx, gbuf_np, seed=w.hash_seed, vertices=a.vertices, sampler=SAMPLERS[a.sampler])
     frames = FramePipeline(new_env, shader, overlap=not a.no_overlap)
     frames.build_luts()
     for _ in range(a.warmup):
@@ -431,7 +437,7 @@ def main():
     sh_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in ev]))
     serial_ms = float(ev[0][0].elapsed_time(ev[-1][2])) / n_ser
 
-    config_tag = f"{w.name}-{a.form}-{a.dtype}-v{a.vertices}"
+    config_tag = f"{w.name}-{a.form}-{a.dtype}-v{a.vertices}" + ("" if a.sampler == "dual" else f"-{a.sampler}")
     records = roofline_records(kernels, w, a, shader, glint_pixels, config_tag)
     dominant = max(records, key=lambda k: kernels[k]["avg_ms"] * kernels[k]["launches_per_step"])
     roofline = dict(records[dominant])
@@ -443,7 +449,7 @@ def main():
            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
            "config": {"workload": f"{w.name}: {w.W}x{w.H} sphere+plane G-buffer, cube map 6x{w.R}x{w.R}, "
                                   f"{w.M} mips, K={w.K}, T={w.T} taps, per-frame partition+prefilter+shade",
-                      "form": a.form, "pyramid_dtype": a.dtype, "vertices": a.vertices,
+                      "form": a.form, "pyramid_dtype": a.dtype, "vertices": a.vertices, "sampler": a.sampler,
                       "glint_pixels": glint_pixels, "total_pixels": shader.P,
                       "frames_overlapped": not a.no_overlap},
            "prefilter_ms_per_frame": round(pre_ms, 4), "shade_ms_per_frame": round(sh_ms, 4),
@@ -453,10 +459,10 @@ def main():
                            "rooflines": {k: {"achieved": v["achieved"], "frac": v["frac"], "unit": v["unit"]}
                                          for k, v in serial_records.items()}}}
     out.update(extra)
-    if a.dtype != "f32" or a.form != "plain":
+    if a.dtype != "f32" or a.form != "plain" or a.sampler != "dual":
         # against the plain f32 path on the same frame (itself checked against the oracle): reflection
         # probabilities p_k, per-pixel radiance, and the frame's mean radiance
-        ref_pipe = new_env()
+        ref_pipe = new_env("f32")
         ref_pipe.build_luts()
         ref_pipe.run(env)
         ref_sh = Shader(ctx, gbuf_np, seed=w.hash_seed, vertices=a.vertices)
@@ -475,7 +481,7 @@ def main():
             "probs_mean_abs_err": float((dbg1["probs"][hit] - dbg0["probs"][hit]).abs().mean().item()),
             "radiance_mean_rel_err": float(rel[lit].mean().item()),
             "frame_mean_radiance_ratio": float((r1.mean() / r0.mean()).item())}
-    if not a.no_cpu_baseline and a.form == "plain":
+    if not a.no_cpu_baseline and a.form == "plain" and a.sampler == "dual":
         if a.dtype == "f32":
             ind_h = pipe.ind_pyr.cpu().numpy()
         else:

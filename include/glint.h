@@ -258,6 +258,35 @@ size_t glint_quantile_table_bytes(void);
 int glint_build_quantile_table(glint_ctx ctx, double *table, void *stream);
 
 /* ------------------------------------------------------------------------
+ * Binomial approximations b(N, p) of Sec. 6, one draw per element, with the
+ * random numbers given: xi1 = ((h1 >> 9) + 1/2) 2^-23 decides the gates and
+ * xi2 = ((h2 >> 9) + 1/2) 2^-23 the Gaussian, as the shading kernel maps its
+ * hash outputs.  N >= 0 and p in [0, 1] are real.
+ *  GLINT_SAMPLER_DUAL: Alg. "Dual-gated Gaussian" with the bias of
+ *    paragraph "Numeric Gating Issues" (the node sampler of glint_shade).
+ *  GLINT_SAMPLER_SINGLE: Eq. (gated), the single-gated Gaussian generalised
+ *    to real N: gate passed with probability min(N p, 1 - (1-p)^N), the
+ *    power with the same bias; past it, the Gaussian of mean 1 + (N1-1) p
+ *    and variance (N1-1) p (1-p), N1 = max(N, 1), clamped to [1, N1].
+ *  GLINT_SAMPLER_SINGLE_FLOOR: Eq. (oldgated), the prior form: gate
+ *    probability 1 - (1-p)^N without bias, floor of the same clamped
+ *    Gaussian.
+ * Single-gated forms return nbar = max(N - n, 0).  Gates are evaluated in
+ * float (powf), the Gaussian (AS 241) in double.
+ * All arrays are device memory of `count` elements; quantile_tail may be
+ * NULL (see glint_build_quantile_table).  code: bits as in
+ * glint_shade_debug for the dual form; 1 = gate passed, 16 = Gaussian for
+ * the single forms.  GLINT_EINVAL: unknown sampler, count < 0 or a null
+ * array (count = 0 is a no-op).
+ * ------------------------------------------------------------------------ */
+#define GLINT_SAMPLER_DUAL 0
+#define GLINT_SAMPLER_SINGLE 1
+#define GLINT_SAMPLER_SINGLE_FLOOR 2
+int glint_sample_binomial(glint_ctx ctx, int sampler, int exact_gating, const double *N, const double *p,
+                          const uint32_t *h1, const uint32_t *h2, int64_t count, const double *quantile_tail,
+                          double *n, double *nbar, uint8_t *code, void *stream);
+
+/* ------------------------------------------------------------------------
  * Per-pixel glint shading (Sec. 3.2, Sec. 3.3 Eq. (anisogrid), Sec. 4
  * Eq. (probhk) and Eq. (iblglints:fin), Sec. 6 Alg. "Dual-gated Gaussian").
  *
@@ -269,7 +298,8 @@ int glint_build_quantile_table(glint_ctx ctx, double *table, void *stream);
  * Counts: a balanced binary tree over the K bins (K a power of two, nodes
  * in breadth-first order), node probability S_left / S_node, the left child
  * receiving the positive count n and the right child the negative count
- * nbar of the dual-gated Gaussian.  Gating probabilities and masks are
+ * nbar of the dual-gated Gaussian (or of the single-gated forms, selected
+ * by params->sampler, see glint_sample_binomial).  Gating probabilities and masks are
  * evaluated in float with the bias c = max(1, eps/p), eps = 10^-3.54
  * (Sec. 6 "Numeric Gating Issues"); the Gaussian quantile (AS 241) and all
  * other arithmetic in double.  Random numbers per (surface, lattice vertex,
@@ -315,6 +345,11 @@ typedef struct glint_shade_params {
     int exact_gating; /* 0: gating decisions from hardware log2/exp2 powers, re-evaluated with powf
                          only within a safety margin of a threshold (same decisions); 1: always
                          powf (for verification) */
+    int sampler;      /* binomial approximation at every tree node (see glint_sample_binomial):
+                         GLINT_SAMPLER_DUAL (the paper's method), GLINT_SAMPLER_SINGLE,
+                         GLINT_SAMPLER_SINGLE_FLOOR; the single-gated forms need a float32
+                         pyramid and are not available in glint_frame_batched
+                         (GLINT_EUNSUPPORTED) */
 } glint_shade_params;
 
 /* Optional per-pixel outputs for verification (each pointer may be NULL). */

@@ -63,10 +63,13 @@ def _declare(L):
     L.orc_hash_xi.argtypes = [C.c_uint32, C.c_uint32, C.c_int32, C.c_int64, C.c_int64, C.c_int,
                               f32p, f32p]
     L.orc_shade_pixels.argtypes = [C.POINTER(f32p), f32p, f32p, f64p, f32p, f32p, C.c_int, C.c_int, C.c_int,
-                                   C.c_uint32, C.c_int, i64p, C.c_int64, f64p, f64p, u8p, f64p, u8p, C.c_int]
+                                   C.c_uint32, C.c_int, C.c_int, i64p, C.c_int64, f64p, f64p, u8p, f64p, u8p,
+                                   C.c_int]
     L.orc_shade_pixels_given_F.argtypes = [C.POINTER(f32p), f64p, f32p, f64p, f32p, f32p, C.c_int, C.c_int,
-                                           C.c_int, C.c_uint32, C.c_int, i64p, C.c_int64, f64p, f64p, u8p, f64p,
-                                           u8p, C.c_int]
+                                           C.c_int, C.c_uint32, C.c_int, C.c_int, i64p, C.c_int64, f64p, f64p,
+                                           u8p, f64p, u8p, C.c_int]
+    u32p = C.POINTER(C.c_uint32)
+    L.orc_sample_binomial.argtypes = [C.c_int, f64p, f64p, u32p, u32p, C.c_int64, f64p, f64p, u8p, u8p, C.c_int]
     L.orc_gate_probs.argtypes = [C.c_float, C.c_float, f32p]
     L.orc_dual_gated.argtypes = [C.c_double, C.c_double, C.c_float, C.c_float, f64p, f64p, u8p]
     L.orc_face_dir.argtypes = [C.c_int, C.c_double, C.c_double, f64p]
@@ -174,9 +177,16 @@ GBUF_FIELDS = ("nx", "ny", "nz", "vx", "vy", "vz", "u", "v", "area", "ax", "ay",
                "f0r", "f0g", "f0b", "surf_id")
 
 
+SAMPLERS = {"dual": 0, "single": 1, "single-floor": 2}
+
+
 def shade(gbuf: dict, ind_pyr, rgb_pyr, levels, lut_S, lut_E, R: int, K: int, M: int, seed: int,
-          vertices: int = 1, pixels=None, threads=None, F=None):
+          vertices: int = 1, pixels=None, threads=None, F=None, sampler: int = 0):
     """Glint radiance of the requested pixels (all when None).
+
+    sampler: binomial approximation of every tree node, 0 dual-gated (Sec. 6
+    Alg. "Dual-gated Gaussian"), 1 single-gated Eq. (gated), 2 the prior
+    single-gated form Eq. (oldgated).
 
     gbuf: dict of flat float32 arrays (surf_id uint32).  ind_pyr [texels,K]
     float32 and rgb_pyr [texels,4] float32 are the stored pyramids.  With F
@@ -205,7 +215,7 @@ def shade(gbuf: dict, ind_pyr, rgb_pyr, levels, lut_S, lut_E, R: int, K: int, M:
         F = np.ascontiguousarray(F, dtype=np.float64).reshape(n, K)
         rc = lib().orc_shade_pixels_given_F(arr, _p(F, C.c_double), _p(rgb_pyr, C.c_float), _p(levels, C.c_double),
                                             _p(lut_S, C.c_float), _p(lut_E, C.c_float), R, K, M, seed, vertices,
-                                            _p(pixels, C.c_int64), n, _p(out["radiance"], C.c_double),
+                                            sampler, _p(pixels, C.c_int64), n, _p(out["radiance"], C.c_double),
                                             _p(out["counts"], C.c_double), _p(out["codes"], C.c_uint8),
                                             _p(out["probs"], C.c_double), _p(out["flags"], C.c_uint8),
                                             threads or threads_default())
@@ -214,7 +224,7 @@ def shade(gbuf: dict, ind_pyr, rgb_pyr, levels, lut_S, lut_E, R: int, K: int, M:
         return out
     rc = lib().orc_shade_pixels(arr, _p(ind_pyr, C.c_float), _p(rgb_pyr, C.c_float), _p(levels, C.c_double),
                                 _p(lut_S, C.c_float), _p(lut_E, C.c_float), R, K, M, seed, vertices,
-                                _p(pixels, C.c_int64), n, _p(out["radiance"], C.c_double),
+                                sampler, _p(pixels, C.c_int64), n, _p(out["radiance"], C.c_double),
                                 _p(out["counts"], C.c_double), _p(out["codes"], C.c_uint8),
                                 _p(out["probs"], C.c_double), _p(out["flags"], C.c_uint8),
                                 threads or threads_default())
@@ -260,6 +270,27 @@ def dual_gated(N: float, p: float, xi1: float, xi2: float):
     n, nb, code = C.c_double(), C.c_double(), C.c_uint8()
     lib().orc_dual_gated(N, p, xi1, xi2, C.byref(n), C.byref(nb), C.byref(code))
     return n.value, nb.value, code.value
+
+
+def sample_binomial(sampler: int, N, p, h1, h2, threads=None):
+    """Binomial approximation of Sec. 6 for each element (sampler as in
+    shade), with the random words h1 (gate) and h2 (Gaussian) mapped to
+    (0,1) as the hash outputs are.  Returns dict(n, nb, code, flags)."""
+    N = np.ascontiguousarray(N, dtype=np.float64)
+    p = np.ascontiguousarray(p, dtype=np.float64)
+    h1 = np.ascontiguousarray(h1, dtype=np.uint32)
+    h2 = np.ascontiguousarray(h2, dtype=np.uint32)
+    m = len(N)
+    if not (len(p) == len(h1) == len(h2) == m):
+        raise ValueError("length mismatch")
+    out = dict(n=np.zeros(m), nb=np.zeros(m), code=np.zeros(m, np.uint8), flags=np.zeros(m, np.uint8))
+    rc = lib().orc_sample_binomial(sampler, _p(N, C.c_double), _p(p, C.c_double), _p(h1, C.c_uint32),
+                                   _p(h2, C.c_uint32), m, _p(out["n"], C.c_double), _p(out["nb"], C.c_double),
+                                   _p(out["code"], C.c_uint8), _p(out["flags"], C.c_uint8),
+                                   threads or threads_default())
+    if rc:
+        raise ValueError("orc_sample_binomial rejected its arguments")
+    return out
 
 
 def face_dir(face, s, t):

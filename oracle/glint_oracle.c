@@ -692,6 +692,68 @@ static void dual_gated(double N, double p, float xi1, float xi2, int N_exact, no
     o->flag = gate_band_flag(&g, xi1) | (round_flag(p) << 1) | ((!N_exact && round_flag(N)) << 2);
 }
 
+/* Sec. 6 paragraphs "Single-Gated Gaussians" and "Gating Generalization".
+ * form 1, Eq. (gated): one gate, passed with probability min(N p, P_any),
+ * P_any = 1 - (1-p)^N, the power taken with the bias of paragraph "Numeric
+ * Gating Issues" (the paper names the single gate among those it fixes):
+ * (1 - max(p, eps))^(N min(1, p/eps)).  Past the gate the count is the
+ * Gaussian of mean 1 + (N1-1) p and variance (N1-1) p (1-p), N1 = max(N, 1),
+ * clamped to [1, N1] (so exactly 1 for N <= 1).
+ * form 2, Eq. (oldgated), the prior form: gate probability P_any without
+ * the bias and without the N < 1 generalisation, and the floor of the same
+ * clamped Gaussian.
+ * Both forms: the negative count is what remains, max(N - n, 0).  The gate
+ * is evaluated in float, as the dual gate; the Gaussian in double. */
+static void single_gated(int form, double N, double p, float xi1, float xi2, int N_exact, node_out *o)
+{
+    const float eps = (float)EPS_GATE;
+    float Nf = (float)N, pf = (float)p;
+    float th;
+    if (form == 1) {
+        float cp = fmaxf(pf, eps);
+        float ex = Nf * fminf(1.0f, pf / eps);
+        float pany = 1.0f - powf(1.0f - cp, ex);
+        float np = Nf * pf;
+        th = np < pany ? np : pany;
+    } else {
+        th = 1.0f - powf(1.0f - pf, Nf);
+    }
+    int hit = xi1 < th;
+    int gauss = hit && N > 1.0;
+    double N1 = N > 1.0 ? N : 1.0;
+    double n = hit ? 1.0 : 0.0;
+    int fl = 0;
+    if (gauss) {
+        double mu = 1.0 + (N1 - 1.0) * p;
+        double sig = sqrt((N1 - 1.0) * p * (1.0 - p));
+        double x = mu + sig * orc_ppnd16((double)xi2);
+        n = x < 1.0 ? 1.0 : (x > N1 ? N1 : x);
+        if (form == 2) {
+            /* the floor decides an integer: flag a Gaussian value (not a
+             * clamp bound, which is exact) next to one */
+            double d = fabs(x - floor(x + 0.5));
+            double band = 8.0 * (nextafter(fabs(x), INFINITY) - fabs(x));
+            fl |= (x > 1.0 && x < N1 && d < (band > 1e-5 ? band : 1e-5)) << 3;
+            n = floor(n);
+        }
+    }
+    double r = N - n;
+    o->n = n;
+    o->nb = r > 0.0 ? r : 0.0;
+    o->code = (uint8_t)(hit | (gauss << 4));
+    double bandg = 9.5367431640625e-07 * (double)th + 5.9604644775390625e-08;
+    fl |= fabs((double)xi1 - (double)th) <= bandg;
+    o->flag = fl | (round_flag(p) << 1) | ((!N_exact && round_flag(N)) << 2);
+}
+
+/* The binomial approximation selected by `sampler`: 0 dual-gated (Alg.
+ * "Dual-gated Gaussian"), 1 single-gated Eq. (gated), 2 Eq. (oldgated). */
+static void sample_node(int sampler, double N, double p, float xi1, float xi2, int N_exact, node_out *o)
+{
+    if (sampler == 0) dual_gated(N, p, xi1, xi2, N_exact, o);
+    else single_gated(sampler, N, p, xi1, xi2, N_exact, o);
+}
+
 /* A sampled count is "near an integer" if it lies within 1e-5 of one
  * without being one, or, for counts so large that a double's spacing
  * approaches that band (beyond ~1e10), within 8 units in the last place:
@@ -707,8 +769,8 @@ static int near_int_flag(double v)
  * tree over the K bins, nodes numbered breadth first (heap order); node i
  * splits [lo,hi) at the midpoint; the left child receives the positive count
  * n, the right child the negative count nb.  p_node = S_left / S_node. */
-static int multinomial(double NP, const double *p, int K, uint32_t seed, uint32_t surf, int32_t level, int64_t a,
-                       int64_t b, double *M, uint8_t *codes)
+static int multinomial(int sampler, double NP, const double *p, int K, uint32_t seed, uint32_t surf, int32_t level,
+                       int64_t a, int64_t b, double *M, uint8_t *codes)
 {
     int nodes = K - 1;
     double Nn[32];
@@ -728,7 +790,7 @@ static int multinomial(double NP, const double *p, int K, uint32_t seed, uint32_
         float xi1, xi2;
         orc_hash_xi(seed, surf, level, a, b, i, &xi1, &xi2);
         node_out o;
-        dual_gated(Nn[i], pn, xi1, xi2, exact[i], &o);
+        sample_node(sampler, Nn[i], pn, xi1, xi2, exact[i], &o);
         codes[i] = o.code;
         flag |= o.flag;
         int c1 = 2 * i + 1, c2 = 2 * i + 2;
@@ -825,10 +887,11 @@ typedef struct {
  * count within 1e-5 of an integer (without being one). */
 static int shade_impl(const float *const *gb, const float *ind_pyr, const float *rgb_pyr, const double *levels,
                       const float *lut_S, const float *lut_E, int R, int K, int M, uint32_t seed, int V,
-                      const int64_t *pix, int64_t count, const double *Fext, double *radiance, double *counts,
-                      uint8_t *codes, double *probs, uint8_t *flags, int threads)
+                      int sampler, const int64_t *pix, int64_t count, const double *Fext, double *radiance,
+                      double *counts, uint8_t *codes, double *probs, uint8_t *flags, int threads)
 {
-    if (R < 1 || K < 2 || K > 16 || (K & (K - 1)) || M < 1 || (R >> (M - 1)) < 1 || (V != 1 && V != 6))
+    if (R < 1 || K < 2 || K > 16 || (K & (K - 1)) || M < 1 || (R >> (M - 1)) < 1 || (V != 1 && V != 6) ||
+        sampler < 0 || sampler > 2)
         return ORC_EINVAL;
     gbuf_t g = {gb[0], gb[1], gb[2], gb[3], gb[4], gb[5], gb[6], gb[7], gb[8], gb[9], gb[10], gb[11],
                 gb[12], gb[13], gb[14], (const uint32_t *)gb[15]};
@@ -917,7 +980,7 @@ static int shade_impl(const float *const *gb, const float *ind_pyr, const float 
             }
             double Mv[16];
             uint8_t cv[16];
-            flag |= multinomial(NP, p, K, seed, surf, lev, a, b, Mv, cv);
+            flag |= multinomial(sampler, NP, p, K, seed, surf, lev, a, b, Mv, cv);
             for (int k = 0; k < K; ++k) Msum[k] += w * Mv[k];
             if (cnt) for (int k = 0; k < K; ++k) cnt[vi * K + k] = Mv[k];
             if (cod) for (int k = 0; k < K - 1; ++k) cod[vi * (K - 1) + k] = cv[k];
@@ -942,12 +1005,12 @@ static int shade_impl(const float *const *gb, const float *ind_pyr, const float 
 }
 
 int orc_shade_pixels(const float *const *gb, const float *ind_pyr, const float *rgb_pyr, const double *levels,
-                     const float *lut_S, const float *lut_E, int R, int K, int M, uint32_t seed, int V,
+                     const float *lut_S, const float *lut_E, int R, int K, int M, uint32_t seed, int V, int sampler,
                      const int64_t *pix, int64_t count, double *radiance, double *counts, uint8_t *codes,
                      double *probs, uint8_t *flags, int threads)
 {
-    return shade_impl(gb, ind_pyr, rgb_pyr, levels, lut_S, lut_E, R, K, M, seed, V, pix, count, NULL, radiance,
-                      counts, codes, probs, flags, threads);
+    return shade_impl(gb, ind_pyr, rgb_pyr, levels, lut_S, lut_E, R, K, M, seed, V, sampler, pix, count, NULL,
+                      radiance, counts, codes, probs, flags, threads);
 }
 
 /* As orc_shade_pixels, with the K filtered indicator values of each requested
@@ -956,12 +1019,12 @@ int orc_shade_pixels(const float *const *gb, const float *ind_pyr, const float *
  * ind_pyr is not read. */
 int orc_shade_pixels_given_F(const float *const *gb, const double *F, const float *rgb_pyr, const double *levels,
                              const float *lut_S, const float *lut_E, int R, int K, int M, uint32_t seed, int V,
-                             const int64_t *pix, int64_t count, double *radiance, double *counts, uint8_t *codes,
-                             double *probs, uint8_t *flags, int threads)
+                             int sampler, const int64_t *pix, int64_t count, double *radiance, double *counts,
+                             uint8_t *codes, double *probs, uint8_t *flags, int threads)
 {
     if (!F) return ORC_EINVAL;
-    return shade_impl(gb, NULL, rgb_pyr, levels, lut_S, lut_E, R, K, M, seed, V, pix, count, F, radiance, counts,
-                      codes, probs, flags, threads);
+    return shade_impl(gb, NULL, rgb_pyr, levels, lut_S, lut_E, R, K, M, seed, V, sampler, pix, count, F, radiance,
+                      counts, codes, probs, flags, threads);
 }
 
 /* Exposed pieces for the definition tests. */
@@ -977,6 +1040,29 @@ void orc_dual_gated(double N, double p, float xi1, float xi2, double *n, double 
     node_out o;
     dual_gated(N, p, xi1, xi2, 0, &o);
     *n = o.n; *nb = o.nb; *code = o.code;
+}
+
+/* One binomial draw per element with the given random words: xi1 from h1,
+ * xi2 from h2 (as the hash outputs are mapped).  N and p are inputs, so
+ * their float roundings are shared; flags keep bits 1 (gate band) and 8
+ * (floor next to an integer). */
+int orc_sample_binomial(int sampler, const double *N, const double *p, const uint32_t *h1, const uint32_t *h2,
+                        int64_t count, double *n, double *nb, uint8_t *code, uint8_t *flags, int threads)
+{
+    if (sampler < 0 || sampler > 2 || count < 0) return ORC_EINVAL;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static) num_threads(threads > 0 ? threads : 1)
+#endif
+    for (int64_t i = 0; i < count; ++i) {
+        node_out o;
+        sample_node(sampler, N[i], p[i], to_unit(h1[i]), to_unit(h2[i]), 1, &o);
+        n[i] = o.n;
+        nb[i] = o.nb;
+        code[i] = o.code;
+        flags[i] = (uint8_t)(o.flag & 9);
+    }
+    (void)threads;
+    return ORC_OK;
 }
 
 void orc_face_dir(int face, double s, double t, double *d) { face_to_dir(face, s, t, d); }

@@ -228,6 +228,18 @@ int glint_prefilter(glint_ctx ctx, const float *env, const uint8_t *ind_j, const
                          "glint_prefilter launch");
 }
 
+// view >= 0 names the batched view in the message
+static int check_shade_params(const glint_shade_params &sp, int view)
+{
+    const char *what = nullptr;
+    if (sp.vertices != 1 && sp.vertices != 6) what = "vertices must be 1 or 6";
+    else if (sp.exact_gating != 0 && sp.exact_gating != 1) what = "exact_gating must be 0 or 1";
+    else if (sp.sampler < GLINT_SAMPLER_DUAL || sp.sampler > GLINT_SAMPLER_SINGLE_FLOOR) what = "unknown sampler";
+    if (!what) return GLINT_OK;
+    if (view >= 0) return fail(GLINT_EINVAL, "view %d: %s", view, what);
+    return fail(GLINT_EINVAL, "%s", what);
+}
+
 int glint_build_luts(glint_ctx ctx, float *lut_S, float *lut_E, void *stream)
 {
     if (int rc = check_ctx(ctx)) return rc;
@@ -247,6 +259,23 @@ int glint_build_quantile_table(glint_ctx ctx, double *table, void *stream)
     return device_status(glint::launch_quantile_table(table, (hipStream_t)stream), "glint_build_quantile_table");
 }
 
+int glint_sample_binomial(glint_ctx ctx, int sampler, int exact_gating, const double *N, const double *p,
+                          const uint32_t *h1, const uint32_t *h2, int64_t count, const double *quantile_tail,
+                          double *n, double *nbar, uint8_t *code, void *stream)
+{
+    if (int rc = check_ctx(ctx)) return rc;
+    glint::ProfScope prof_scope(&ctx->prof);
+    if (sampler < GLINT_SAMPLER_DUAL || sampler > GLINT_SAMPLER_SINGLE_FLOOR)
+        return fail(GLINT_EINVAL, "unknown sampler %d", sampler);
+    if (exact_gating != 0 && exact_gating != 1) return fail(GLINT_EINVAL, "exact_gating must be 0 or 1");
+    if (count < 0 || count > ((int64_t)1 << 40)) return fail(GLINT_EINVAL, "bad count %lld", (long long)count);
+    if (count == 0) return ok();
+    if (!N || !p || !h1 || !h2 || !n || !nbar || !code) return fail(GLINT_EINVAL, "null pointer argument");
+    return device_status(glint::launch_sample_binomial(sampler, exact_gating, N, p, h1, h2, count, quantile_tail, n,
+                                                       nbar, code, (hipStream_t)stream),
+                         "glint_sample_binomial launch");
+}
+
 int glint_shade(glint_ctx ctx, const glint_gbuffer *g, int64_t P, const glint_env *env,
                 const glint_shade_params *sp, float *radiance, const glint_shade_debug *dbg, void *stream)
 {
@@ -258,8 +287,9 @@ int glint_shade(glint_ctx ctx, const glint_gbuffer *g, int64_t P, const glint_en
     if (int rc = check_tree_K(env->K)) return rc;
     if (int rc = check_mips(env->R, env->num_mips)) return rc;
     if (int rc = check_dtype(env->dtype)) return rc;
-    if (sp->vertices != 1 && sp->vertices != 6) return fail(GLINT_EINVAL, "vertices must be 1 or 6");
-    if (sp->exact_gating != 0 && sp->exact_gating != 1) return fail(GLINT_EINVAL, "exact_gating must be 0 or 1");
+    if (int rc = check_shade_params(*sp, -1)) return rc;
+    if (sp->sampler != GLINT_SAMPLER_DUAL && env->dtype != GLINT_F32)
+        return fail(GLINT_EUNSUPPORTED, "single-gated samplers need a float32 pyramid");
     if (P == 0) return ok();
     if (!radiance || !env->ind_pyr || !env->rgb_pyr || !env->levels || !env->lut_S || !env->lut_E)
         return fail(GLINT_EINVAL, "null pointer argument");
@@ -395,8 +425,7 @@ int glint_shade_surrogate(glint_ctx ctx, const glint_gbuffer *g, int64_t P, cons
     if (int rc = check_tree_K(env->K)) return rc;
     if (int rc = check_mips(env->R, env->num_mips)) return rc;
     if (int rc = check_surrogate(env->K, w, w_bf16)) return rc;
-    if (sp->vertices != 1 && sp->vertices != 6) return fail(GLINT_EINVAL, "vertices must be 1 or 6");
-    if (sp->exact_gating != 0 && sp->exact_gating != 1) return fail(GLINT_EINVAL, "exact_gating must be 0 or 1");
+    if (int rc = check_shade_params(*sp, -1)) return rc;
     if (P == 0) return ok();
     if (!radiance || !workspace || !env->rgb_pyr || !env->levels || !env->lut_S || !env->lut_E)
         return fail(GLINT_EINVAL, "null pointer argument");
@@ -446,9 +475,9 @@ int glint_frame_batched(glint_ctx ctx, const glint_env_task *envs, int n_env, co
         if (w.env_index < 0 || w.env_index >= n_env) return fail(GLINT_EINVAL, "view %d: env_index out of range", v);
         if (w.num_pixels < 0 || w.num_pixels > ((int64_t)1 << 40))
             return fail(GLINT_EINVAL, "view %d: bad num_pixels", v);
-        if (w.shade.vertices != 1 && w.shade.vertices != 6) return fail(GLINT_EINVAL, "view %d: vertices", v);
-        if (w.shade.exact_gating != 0 && w.shade.exact_gating != 1)
-            return fail(GLINT_EINVAL, "view %d: exact_gating must be 0 or 1", v);
+        if (int rc = check_shade_params(w.shade, v)) return rc;
+        if (w.shade.sampler != GLINT_SAMPLER_DUAL)
+            return fail(GLINT_EUNSUPPORTED, "view %d: batched frames use the dual-gated sampler", v);
         if (!w.radiance) return fail(GLINT_EINVAL, "view %d: null radiance", v);
         if (envs[w.env_index].surrogate_w &&
             (!w.surrogate_F || reinterpret_cast<uintptr_t>(w.surrogate_F) % 16))

@@ -348,6 +348,23 @@ __device__ __forceinline__ gate_d gate_decide(float Nf, float pf, float xi1, boo
     return d;
 }
 
+// Gate threshold of the single-gated Gaussian (Sec. 6): form 1, Eq. (gated),
+// min(N p, 1 - (1-p)^N) with the power biased as in the dual gate; form 2,
+// Eq. (oldgated), the prior 1 - (1-p)^N without bias.  float, powf.
+__device__ __forceinline__ float single_gate_threshold(int form, float Nf, float pf)
+{
+#pragma clang fp contract(off)
+    if (form == 1) {
+        const float eps = 2.8840315031266055e-04f; // 10^-3.54
+        const float cp = fmaxf(pf, eps);
+        const float ex = Nf * fminf(1.0f, pf / eps);
+        const float pany = 1.0f - powf(1.0f - cp, ex);
+        const float np = Nf * pf;
+        return np < pany ? np : pany;
+    }
+    return 1.0f - powf(1.0f - pf, Nf);
+}
+
 // Learned-surrogate inputs of a lookup (the project's extension, not the
 // paper's): the reflection direction, then (ln alpha - c) / h for alpha_x
 // and alpha_y, where c and h map [ln 0.02, ln 0.5] onto [-1, 1].

@@ -46,6 +46,10 @@ hipError_t launch_mlp_lookup(const glint_gbuffer &g, int64_t P, int K, const flo
 hipError_t launch_shade(const glint_gbuffer &g, int64_t P, const glint_env &env, const glint_shade_params &sp,
                         const float *F, float *radiance, const glint_shade_debug *dbg, hipStream_t stream);
 
+hipError_t launch_sample_binomial(int sampler, int exact_gating, const double *N, const double *p, const uint32_t *h1,
+                                  const uint32_t *h2, int64_t count, const double *qtail, double *n, double *nb,
+                                  uint8_t *code, hipStream_t stream);
+
 // batched shading: per-view descriptors (device copies of make_shade_args
 // output) and the first tile of each view
 size_t shade_args_bytes();

@@ -34,7 +34,7 @@ __device__ __forceinline__ double load_value<2>(const void *base, int64_t i)
 template <>
 __device__ __forceinline__ double load_value<3>(const void *base, int64_t i)
 {
-    return (double)static_cast<const uint16_t *>(base)[i] / 65535.0;
+    return (double)static_cast<const uint16_t *>(base)[i] * (1.0 / 65535.0);
 }
 
 // One pyramid texel: K indicator channels (stored type DT) and RGB, as double.
@@ -61,7 +61,7 @@ __device__ __forceinline__ void load_texel(const void *__restrict__ ind, const f
                 double val;
                 if constexpr (DT == 1) val = (double)__builtin_bit_cast(_Float16, h);
                 else if constexpr (DT == 2) val = (double)__uint_as_float((uint32_t)h << 16);
-                else val = (double)h / 65535.0;
+                else val = (double)h * (1.0 / 65535.0);
                 v[8 * q + e] = val;
             }
         }
@@ -130,6 +130,7 @@ struct ShadeArgs {
     const float *F;      // surrogate form: filtered indicator values [P][K] (else null)
     const double *qtail; // quantile tail table (else null: tails evaluated inline)
     int exact_gating;    // 1: gating thresholds always through powf (verification)
+    int sampler;         // GLINT_SAMPLER_*: node sampler of the multinomial tree
 };
 
 // One dual-gated Gaussian draw (Alg. "Dual-gated Gaussian").
@@ -171,6 +172,49 @@ __device__ __forceinline__ void dual_gated(double N, double p, float xi1, float 
            ((uint32_t)BG << 4);
 }
 
+// Single-gated Gaussian (Sec. 6 "Single-Gated Gaussians", "Gating
+// Generalization"): form 1 Eq. (gated), form 2 the prior Eq. (oldgated)
+// (floor, no bias, no N < 1 generalisation).  The negative count is what
+// remains, max(N - n, 0).
+__device__ __forceinline__ void single_gated(int form, double N, double p, float xi1, float xi2, uint32_t h9,
+                                             const double *__restrict__ qtail, double &n, double &nb,
+                                             uint32_t &code)
+{
+#pragma clang fp contract(off)
+    uint32_t tidx = 0;
+    const bool tail = tail_index(h9, tidx);
+    double ztab = 0.0;
+    if (qtail && tail) ztab = qtail[tidx];
+    const bool hit = xi1 < single_gate_threshold(form, (float)N, (float)p);
+    const bool BG = hit && N > 1.0;
+    double c = hit ? 1.0 : 0.0;
+    if (BG) {
+        const double mu = 1.0 + (N - 1.0) * p;
+        const double sig = sqrt((N - 1.0) * p * (1.0 - p));
+        const double xd = (double)xi2, q = xd - 0.5;
+        const double z = !tail ? ppnd16_central(q) : (qtail ? ztab : ppnd16_tail(xd, q));
+        const double x = mu + sig * z;
+        c = x < 1.0 ? 1.0 : (x > N ? N : x);
+        if (form == 2) c = floor(c);
+    }
+    n = c;
+    const double r = N - c;
+    nb = r > 0.0 ? r : 0.0;
+    code = (uint32_t)hit | ((uint32_t)BG << 4);
+}
+
+// SG: a single-gated form (`sampler` says which); else the dual gate.  A
+// compile-time switch, so the dual-gated kernels carry no trace of the
+// other forms (registers, code size).
+template <bool SG>
+__device__ __forceinline__ void node_sample(int sampler, double N, double p, float xi1, float xi2, uint32_t h9,
+                                            const double *__restrict__ qtail, bool exact_gating, double &n,
+                                            double &nb, uint32_t &code)
+{
+    if constexpr (SG) single_gated(sampler, N, p, xi1, xi2, h9, qtail, n, nb, code);
+    else dual_gated(N, p, xi1, xi2, h9, qtail, exact_gating, n, nb, code);
+}
+
 // Hierarchical multinomial over K bins: balanced binary tree, nodes in
 // breadth-first (heap) order; node i covers a contiguous run of bins, its
 // probability is S_left / S_node, its left child 2i+1 receives the positive
@@ -181,10 +225,10 @@ __device__ __forceinline__ void dual_gated(double N, double p, float xi1, float 
 // its inputs from the front of small register queues and appends the two
 // child counts at the back, shifting with static indices, so no register
 // array is indexed dynamically.
-template <int K>
+template <int K, bool SG>
 __device__ __forceinline__ void multinomial(double NP, const double (&p)[K], uint32_t seed_mix, int lev, int64_t a,
                                             int64_t b, const double *__restrict__ qtail, bool exact_gating,
-                                            double (&leaf)[K], uint8_t *codes)
+                                            int sampler, double (&leaf)[K], uint8_t *codes)
 {
     double Q[K]; // counts of the current depth, in node order
     Q[0] = NP;
@@ -232,7 +276,7 @@ __device__ __forceinline__ void multinomial(double NP, const double (&p)[K], uin
             }
             double n, nb;
             uint32_t code;
-            dual_gated(N, pj, hash_unit(hx), hash_unit(hy), hy >> 9, qtail, exact_gating, n, nb, code);
+            node_sample<SG>(sampler, N, pj, hash_unit(hx), hash_unit(hy), hy >> 9, qtail, exact_gating, n, nb, code);
             if (codes) codes[node] = (uint8_t)code;
 #pragma unroll
             for (int k = 0; k + 2 < 2 * nd; ++k) Rq[k] = Rq[k + 2];
@@ -249,7 +293,7 @@ __device__ __forceinline__ void multinomial(double NP, const double (&p)[K], uin
 // Shades pixel i of the view described by A (all of rows b1-b5).  SURR: the
 // K filtered indicator values come from A.F (a learned surrogate's output)
 // and only RGB is read from the pyramid.
-template <int K, int DT, int V, bool SURR = false>
+template <int K, int DT, int V, bool SURR = false, bool SG = false>
 __device__ __forceinline__ void shade_pixel(const ShadeArgs &A, int64_t i)
 {
     constexpr int KL = SURR ? 0 : K; // indicator channels read from the pyramid
@@ -384,7 +428,7 @@ __device__ __forceinline__ void shade_pixel(const ShadeArgs &A, int64_t i)
         }
         double Mv[K];
         uint8_t *cod = A.codes ? A.codes + (i * V + vi) * (K - 1) : nullptr;
-        multinomial<K>(NP, p, seed_mix, lev, a, b, A.qtail, A.exact_gating != 0, Mv, cod);
+        multinomial<K, SG>(NP, p, seed_mix, lev, a, b, A.qtail, A.exact_gating != 0, A.sampler, Mv, cod);
 #pragma unroll
         for (int k = 0; k < K; ++k) Msum[k] += w * Mv[k];
         if (A.counts) {
@@ -408,12 +452,12 @@ __device__ __forceinline__ void shade_pixel(const ShadeArgs &A, int64_t i)
     for (int c = 0; c < 3; ++c) A.radiance[3 * i + c] = (float)((f0[c] * EA + EB) * rgb[c] * gmod);
 }
 
-template <int K, int DT, int V, bool SURR = false>
+template <int K, int DT, int V, bool SURR = false, bool SG = false>
 __global__ void __launch_bounds__(kShadeThreads) k_shade(ShadeArgs A)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= A.P) return;
-    shade_pixel<K, DT, V, SURR>(A, i);
+    shade_pixel<K, DT, V, SURR, SG>(A, i);
 }
 
 // All views of one (K, V) group in one launch: block b shades tile b of the
@@ -441,6 +485,17 @@ template <int K, int DT>
 static hipError_t launch_shade_kd(const ShadeArgs &a, int V, hipStream_t stream)
 {
     const unsigned blocks = (unsigned)((a.P + kShadeThreads - 1) / kShadeThreads);
+    if (a.sampler != GLINT_SAMPLER_DUAL) {
+        // single-gated forms: float32 pyramids only (the API checks)
+        if constexpr (DT == 0) {
+            if (V == 1)
+                GLINT_LAUNCH("k_shade", (k_shade<K, 0, 1, false, true>), dim3(blocks), dim3(kShadeThreads), 0, stream, a);
+            else
+                GLINT_LAUNCH("k_shade", (k_shade<K, 0, 6, false, true>), dim3(blocks), dim3(kShadeThreads), 0, stream, a);
+            return hipGetLastError();
+        }
+        return hipErrorInvalidValue;
+    }
     if (V == 1) GLINT_LAUNCH("k_shade", (k_shade<K, DT, 1>), dim3(blocks), dim3(kShadeThreads), 0, stream, a);
     else GLINT_LAUNCH("k_shade", (k_shade<K, DT, 6>), dim3(blocks), dim3(kShadeThreads), 0, stream, a);
     return hipGetLastError();
@@ -470,6 +525,7 @@ void make_shade_args(void *out, const glint_gbuffer &g, int64_t P, const glint_e
     a.F = F;
     a.qtail = env.quantile_tail;
     a.exact_gating = sp.exact_gating;
+    a.sampler = sp.sampler;
     *static_cast<ShadeArgs *>(out) = a;
 }
 
@@ -528,13 +584,21 @@ hipError_t launch_shade(const glint_gbuffer &g, int64_t P, const glint_env &env,
     a.F = F;
     a.qtail = env.quantile_tail;
     a.exact_gating = sp.exact_gating;
+    a.sampler = sp.sampler;
     const int K = env.K, DT = (int)env.dtype, V = sp.vertices;
     if (F) {
         // surrogate form: the indicator pyramid is not read, so its storage type does not matter
         const unsigned blocks = (unsigned)((P + kShadeThreads - 1) / kShadeThreads);
 #define GLINT_SF(KK)                                                                                        \
     if (K == KK) {                                                                                          \
-        if (V == 1)                                                                                         \
+        if (sp.sampler != GLINT_SAMPLER_DUAL) {                                                             \
+            if (V == 1)                                                                                     \
+                GLINT_LAUNCH("k_shade_surrogate", (k_shade<KK, 0, 1, true, true>), dim3(blocks),            \
+                             dim3(kShadeThreads), 0, stream, a);                                            \
+            else                                                                                            \
+                GLINT_LAUNCH("k_shade_surrogate", (k_shade<KK, 0, 6, true, true>), dim3(blocks),            \
+                             dim3(kShadeThreads), 0, stream, a);                                            \
+        } else if (V == 1)                                                                                  \
             GLINT_LAUNCH("k_shade_surrogate", (k_shade<KK, 0, 1, true>), dim3(blocks), dim3(kShadeThreads), \
                          0, stream, a);                                                                     \
         else                                                                                                \
@@ -559,6 +623,41 @@ hipError_t launch_shade(const glint_gbuffer &g, int64_t P, const glint_env &env,
 #undef GLINT_SH_K
 #undef GLINT_SH
     return hipErrorInvalidValue;
+}
+
+// One binomial draw per element with given random words (the sampler of
+// every tree node, exposed for distribution checks and timing).
+__global__ void __launch_bounds__(256) k_sample_binomial(int sampler, int exact_gating, const double *__restrict__ N,
+                                                         const double *__restrict__ p, const uint32_t *__restrict__ h1,
+                                                         const uint32_t *__restrict__ h2, int64_t count,
+                                                         const double *__restrict__ qtail, double *__restrict__ n,
+                                                         double *__restrict__ nb, uint8_t *__restrict__ code)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const uint32_t b = h2[i];
+    double a, c;
+    uint32_t cd;
+    if (sampler == GLINT_SAMPLER_DUAL)
+        node_sample<false>(sampler, N[i], p[i], hash_unit(h1[i]), hash_unit(b), b >> 9, qtail, exact_gating != 0, a, c,
+                           cd);
+    else
+        node_sample<true>(sampler, N[i], p[i], hash_unit(h1[i]), hash_unit(b), b >> 9, qtail, exact_gating != 0, a, c,
+                          cd);
+    n[i] = a;
+    nb[i] = c;
+    code[i] = (uint8_t)cd;
+}
+
+hipError_t launch_sample_binomial(int sampler, int exact_gating, const double *N, const double *p, const uint32_t *h1,
+                                  const uint32_t *h2, int64_t count, const double *qtail, double *n, double *nb,
+                                  uint8_t *code, hipStream_t stream)
+{
+    const int64_t blocks = (count + 255) / 256;
+    if (blocks > 0x7FFFFFFF) return hipErrorInvalidValue;
+    GLINT_LAUNCH("k_sample_binomial", k_sample_binomial, dim3((unsigned)blocks), dim3(256), 0, stream, sampler,
+                 exact_gating, N, p, h1, h2, count, qtail, n, nb, code);
+    return hipGetLastError();
 }
 
 } // namespace glint

@@ -14,6 +14,7 @@ from . import build as _build
 
 GLINT_OK, GLINT_EINVAL, GLINT_EUNSUPPORTED, GLINT_EDEVICE, GLINT_ENOMEM = 0, 1, 2, 3, 4
 GLINT_F32, GLINT_F16, GLINT_BF16, GLINT_UNORM16 = 0, 1, 2, 3
+GLINT_SAMPLER_DUAL, GLINT_SAMPLER_SINGLE, GLINT_SAMPLER_SINGLE_FLOOR = 0, 1, 2
 GLINT_NO_SURFACE = 0xFFFFFFFF
 LUT_N = 64
 
@@ -46,7 +47,7 @@ class Env(C.Structure):
 
 
 class ShadeParams(C.Structure):
-    _fields_ = [("seed", C.c_uint32), ("vertices", C.c_int), ("exact_gating", C.c_int)]
+    _fields_ = [("seed", C.c_uint32), ("vertices", C.c_int), ("exact_gating", C.c_int), ("sampler", C.c_int)]
 
 
 class ShadeDebug(C.Structure):
@@ -84,6 +85,8 @@ EXPORTS = {
     "glint_build_luts": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     "glint_quantile_table_bytes": ([], C.c_size_t),
     "glint_build_quantile_table": ([C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
+    "glint_sample_binomial": ([C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                               C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     "glint_shade": ([C.c_void_p, C.POINTER(GBuffer), C.c_int64, C.POINTER(Env), C.POINTER(ShadeParams),
                      C.c_void_p, C.POINTER(ShadeDebug), C.c_void_p], C.c_int),
     "glint_sample_filter": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_int,
@@ -221,6 +224,18 @@ def glint_quantile_table_bytes() -> int:
 def glint_build_quantile_table(ctx, table, stream=None):
     _require_cuda(table)
     _check(lib().glint_build_quantile_table(ctx, _ptr(table), _stream(stream)))
+
+
+def glint_sample_binomial(ctx, sampler, N, p, h1, h2, n, nbar, code, quantile_tail=None, exact_gating=0,
+                          stream=None):
+    """N, p: float64; h1, h2: 32-bit words (int32 or uint32 storage); n, nbar:
+    float64 outputs; code: uint8 output; all device tensors of one length."""
+    _require_cuda(N, p, h1, h2, n, nbar, code, quantile_tail)
+    count = N.numel()
+    if any(t.numel() != count for t in (p, h1, h2, n, nbar, code)):
+        raise ValueError("all arrays must have the same length")
+    _check(lib().glint_sample_binomial(ctx, sampler, exact_gating, _ptr(N), _ptr(p), _ptr(h1), _ptr(h2), count,
+                                       _ptr(quantile_tail), _ptr(n), _ptr(nbar), _ptr(code), _stream(stream)))
 
 
 def make_gbuffer(fields: dict) -> GBuffer:

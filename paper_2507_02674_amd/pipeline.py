@@ -64,7 +64,7 @@ class EnvPipeline:
 class Shader:
     """Per-pixel glint shading of a fixed G-buffer."""
 
-    def __init__(self, ctx, gbuf: dict, seed=1, vertices=1, device="cuda"):
+    def __init__(self, ctx, gbuf: dict, seed=1, vertices=1, device="cuda", sampler=G.GLINT_SAMPLER_DUAL):
         self.ctx = ctx
         self.fields = {k: (v if isinstance(v, torch.Tensor) else torch.from_numpy(v)).to(device)
                        for k, v in gbuf.items()}
@@ -73,7 +73,7 @@ class Shader:
                 if self.fields["surf_id"].dtype == torch.uint32 else self.fields["surf_id"].to(torch.int32)
         self.P = int(self.fields["nx"].numel())
         self.gb = G.make_gbuffer(self.fields)
-        self.sp = G.ShadeParams(seed, vertices)
+        self.sp = G.ShadeParams(seed, vertices, 0, sampler)
         self.vertices = vertices
         self.radiance = torch.empty((self.P, 3), dtype=torch.float32, device=device)
 
@@ -273,8 +273,9 @@ class Surrogate:
 class SurrogateShader(Shader):
     """Shading with the surrogate in place of the indicator pyramid lookup."""
 
-    def __init__(self, ctx, gbuf: dict, surrogate: Surrogate, seed=1, vertices=1, device="cuda"):
-        super().__init__(ctx, gbuf, seed=seed, vertices=vertices, device=device)
+    def __init__(self, ctx, gbuf: dict, surrogate: Surrogate, seed=1, vertices=1, device="cuda",
+                 sampler=G.GLINT_SAMPLER_DUAL):
+        super().__init__(ctx, gbuf, seed=seed, vertices=vertices, device=device, sampler=sampler)
         self.sur = surrogate
         nbytes = G.glint_shade_surrogate_workspace_bytes(self.P, surrogate.K)
         self.F = torch.empty(nbytes // 4, dtype=torch.float32, device=device)

@@ -105,7 +105,7 @@ def gbuf_to_device(gbuf):
 
 
 def shade(ctx, gbuf, ind_raw, rgb, levels, lut_S, lut_E, R, K, M, dtype=G.GLINT_F32, seed=1, vertices=1,
-          debug=True, num_pixels=None, qtail=None, exact_gating=0):
+          debug=True, num_pixels=None, qtail=None, exact_gating=0, sampler=0):
     fields = gbuf_to_device(gbuf)
     P = len(gbuf["nx"]) if num_pixels is None else num_pixels
     tdt, ndt = STORAGE[dtype]
@@ -119,7 +119,7 @@ def shade(ctx, gbuf, ind_raw, rgb, levels, lut_S, lut_E, R, K, M, dtype=G.GLINT_
         dbg = dict(counts=torch.empty((max(P, 1), vertices, K), dtype=torch.float64, device="cuda"),
                    codes=torch.empty((max(P, 1), vertices, K - 1), dtype=torch.uint8, device="cuda"),
                    probs=torch.empty((max(P, 1), K), dtype=torch.float64, device="cuda"))
-    G.glint_shade(ctx, G.make_gbuffer(fields), P, env, G.ShadeParams(seed, vertices, exact_gating), rad, dbg)
+    G.glint_shade(ctx, G.make_gbuffer(fields), P, env, G.ShadeParams(seed, vertices, exact_gating, sampler), rad, dbg)
     out = dict(radiance=host(rad)[:P])
     if debug:
         for k, v in dbg.items():

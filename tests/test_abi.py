@@ -50,8 +50,37 @@ def test_struct_layouts_match_header():
     assert G.PartitionParams.ell.offset == 8
     assert C.sizeof(G.GBuffer) == 16 * 8
     assert C.sizeof(G.Env) == 5 * 8 + 4 * 4 + 8
-    assert C.sizeof(G.ShadeParams) == 12
+    assert C.sizeof(G.ShadeParams) == 16
     assert C.sizeof(G.ShadeDebug) == 24
+
+
+def test_struct_layouts_match_a_c_compiler(tmp_path):
+    """sizeof/offsetof of every struct the binding mirrors, as a C compiler
+    lays it out from include/glint.h, against the ctypes structures."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = {"glint_partition_params": G.PartitionParams, "glint_prefilter_params": G.PrefilterParams,
+               "glint_gbuffer": G.GBuffer, "glint_env": G.Env, "glint_shade_params": G.ShadeParams,
+               "glint_shade_debug": G.ShadeDebug, "glint_env_task": G.EnvTask, "glint_view": G.View}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "glint.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l}
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == C.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
 
 
 def test_calls_validate_before_touching_the_device():
@@ -61,4 +90,6 @@ def test_calls_validate_before_touching_the_device():
     assert rc == G.GLINT_EINVAL
     assert "context" in lib.glint_last_error().decode()
     rc = lib.glint_shade(None, None, 10, None, None, None, None, None)
+    assert rc == G.GLINT_EINVAL
+    rc = lib.glint_sample_binomial(None, 0, 0, None, None, None, None, 10, None, None, None, None, None)
     assert rc == G.GLINT_EINVAL
