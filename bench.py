@@ -171,6 +171,11 @@ def parse():
     ap.add_argument("--vertices", type=int, default=1)
     ap.add_argument("--sampler", default="dual", choices=list(SAMPLERS),
                     help="binomial approximation at every tree node (dual-gated is the paper's method)")
+    ap.add_argument("--probs", default="env", choices=["env", "constant"],
+                    help="reflection probabilities from the map (the paper) or one constant for every facet")
+    ap.add_argument("--gamma", type=float, default=0.05, help="the constant probability of --probs constant")
+    ap.add_argument("--visibility", default="none", choices=["none", "contact"],
+                    help="occlusion that attenuates the probabilities (contact: the scene's AO-like field)")
     ap.add_argument("--train-steps", type=int, default=400, help="surrogate training steps before timing")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-overlap", action="store_true",
@@ -376,6 +381,10 @@ def main():
     dtypes = {"f32": G.GLINT_F32, "f16": G.GLINT_F16, "bf16": G.GLINT_BF16, "unorm16": G.GLINT_UNORM16}
     w = synth.WORKLOADS[a.workload]
     env_np, gbuf_np = w.env(), w.gbuf()
+    if a.visibility == "contact":
+        gbuf_np["visibility"] = synth.contact_visibility(gbuf_np)
+    prob_mode = G.GLINT_PROBS_CONSTANT if a.probs == "constant" else G.GLINT_PROBS_ENV
+    default_path = a.sampler == "dual" and a.probs == "env" and a.visibility == "none"
     glint_pixels = int((gbuf_np["surf_id"] != 0xFFFFFFFF).sum())
     ctx = G.glint_create(0)
     env = torch.from_numpy(env_np).cuda()
@@ -392,7 +401,8 @@ def main():
         shader = SurrogateShader(ctx, gbuf_np, sur, seed=w.hash_seed, vertices=a.vertices,
                                  sampler=SAMPLERS[a.sampler])
     else:
-        shader = Shader(ctx, gbuf_np, seed=w.hash_seed, vertices=a.vertices, sampler=SAMPLERS[a.sampler])
+        shader = Shader(ctx, gbuf_np, seed=w.hash_seed, vertices=a.vertices, sampler=SAMPLERS[a.sampler],
+                        prob_mode=prob_mode, gamma=a.gamma)
     frames = FramePipeline(new_env, shader, overlap=not a.no_overlap)
     frames.build_luts()
     for _ in range(a.warmup):
@@ -437,7 +447,8 @@ def main():
     sh_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in ev]))
     serial_ms = float(ev[0][0].elapsed_time(ev[-1][2])) / n_ser
 
-    config_tag = f"{w.name}-{a.form}-{a.dtype}-v{a.vertices}" + ("" if a.sampler == "dual" else f"-{a.sampler}")
+    config_tag = f"{w.name}-{a.form}-{a.dtype}-v{a.vertices}" + (
+        "" if default_path else f"-{a.sampler}-{a.probs}-{a.visibility}")
     records = roofline_records(kernels, w, a, shader, glint_pixels, config_tag)
     dominant = max(records, key=lambda k: kernels[k]["avg_ms"] * kernels[k]["launches_per_step"])
     roofline = dict(records[dominant])
@@ -450,6 +461,8 @@ def main():
            "config": {"workload": f"{w.name}: {w.W}x{w.H} sphere+plane G-buffer, cube map 6x{w.R}x{w.R}, "
                                   f"{w.M} mips, K={w.K}, T={w.T} taps, per-frame partition+prefilter+shade",
                       "form": a.form, "pyramid_dtype": a.dtype, "vertices": a.vertices, "sampler": a.sampler,
+                      "probs": a.probs if a.probs == "env" else f"constant gamma={a.gamma}",
+                      "visibility": a.visibility,
                       "glint_pixels": glint_pixels, "total_pixels": shader.P,
                       "frames_overlapped": not a.no_overlap},
            "prefilter_ms_per_frame": round(pre_ms, 4), "shade_ms_per_frame": round(sh_ms, 4),
@@ -459,16 +472,18 @@ def main():
                            "rooflines": {k: {"achieved": v["achieved"], "frac": v["frac"], "unit": v["unit"]}
                                          for k, v in serial_records.items()}}}
     out.update(extra)
-    if a.dtype != "f32" or a.form != "plain" or a.sampler != "dual":
+    if a.dtype != "f32" or a.form != "plain" or not default_path:
         # against the plain f32 path on the same frame (itself checked against the oracle): reflection
         # probabilities p_k, per-pixel radiance, and the frame's mean radiance
         ref_pipe = new_env("f32")
         ref_pipe.build_luts()
         ref_pipe.run(env)
-        ref_sh = Shader(ctx, gbuf_np, seed=w.hash_seed, vertices=a.vertices)
+        ref_sh = Shader(ctx, {k: v for k, v in gbuf_np.items() if k != "visibility"}, seed=w.hash_seed,
+                        vertices=a.vertices)
         P = shader.P
         dbg0 = {"probs": torch.empty((P, w.K), dtype=torch.float64, device="cuda")}
-        dbg1 = {"probs": torch.empty((P, w.K), dtype=torch.float64, device="cuda")}
+        Kd = 2 if prob_mode == G.GLINT_PROBS_CONSTANT else w.K  # constant probabilities: two bins
+        dbg1 = {"probs": torch.empty((P, Kd), dtype=torch.float64, device="cuda")}
         ref_sh.run(ref_pipe.env_struct(), debug=dbg0)
         shader.run(envs, debug=dbg1)
         torch.cuda.synchronize()
@@ -478,10 +493,11 @@ def main():
         rel = ((r1 - r0).abs() / r0.abs().clamp_min(1e-12))
         lit = r0 > 1e-6 * r0.max()
         out["vs_plain_f32"] = {
-            "probs_mean_abs_err": float((dbg1["probs"][hit] - dbg0["probs"][hit]).abs().mean().item()),
+            "probs_mean_abs_err": float((dbg1["probs"][hit] - dbg0["probs"][hit]).abs().mean().item())
+            if Kd == w.K else None,
             "radiance_mean_rel_err": float(rel[lit].mean().item()),
             "frame_mean_radiance_ratio": float((r1.mean() / r0.mean()).item())}
-    if not a.no_cpu_baseline and a.form == "plain" and a.sampler == "dual":
+    if not a.no_cpu_baseline and a.form == "plain" and default_path:
         if a.dtype == "f32":
             ind_h = pipe.ind_pyr.cpu().numpy()
         else:

@@ -312,6 +312,16 @@ int glint_sample_binomial(glint_ctx ctx, int sampler, int exact_gating, const do
  * times (1-f, f), f = log2(area)/2 - l0.  Each vertex draws with N_i = N_P;
  * the counts are blended with the weights.
  * Radiance = L_o * sum_k L_k M_k / (N_P sum_k L_k p_k) (0 if either sum is 0).
+ * Occlusion (Sec. 8 "Limitations & Future Work": attenuate the
+ * probabilities, not the output): with gbuf->visibility, the tree samples
+ * with p'_k = v p_k (k >= 1), p'_0 = 1 - sum_{k>=1} p'_k, while the
+ * normalisation keeps the unattenuated p_k, so the expected radiance is
+ * v L_o and each glint keeps its brightness.
+ * prob_mode = GLINT_PROBS_CONSTANT (Sec. 7 "Comparison with Previous Work",
+ * after Wang et al. 2020): p = (1 - gamma, gamma) and levels (0, 1) for
+ * every pixel, i.e. the two-bin case of the same path; the indicator
+ * pyramid, env->levels and lut_S are not read, env->K and env->dtype are
+ * ignored and the debug outputs are laid out for K = 2.
  * ------------------------------------------------------------------------ */
 #define GLINT_NO_SURFACE 0xFFFFFFFFu
 
@@ -325,6 +335,9 @@ typedef struct glint_gbuffer {
     const float *density;      /* microfacets per unit area N */
     const float *f0r, *f0g, *f0b; /* Fresnel reflectance at normal incidence */
     const uint32_t *surf_id;   /* surface id (hash input); GLINT_NO_SURFACE = background */
+    const float *visibility;   /* optional (NULL: unoccluded): unoccluded fraction v in [0, 1] of the
+                                  pixel's reflection lobe; scales the reflection probabilities, see
+                                  glint_shade */
 } glint_gbuffer;
 
 typedef struct glint_env {
@@ -350,7 +363,14 @@ typedef struct glint_shade_params {
                          GLINT_SAMPLER_SINGLE_FLOOR; the single-gated forms need a float32
                          pyramid and are not available in glint_frame_batched
                          (GLINT_EUNSUPPORTED) */
+    int prob_mode;    /* GLINT_PROBS_ENV: p_k from the map (the paper's method);
+                         GLINT_PROBS_CONSTANT: every facet reflects with probability gamma,
+                         independent of the map (the comparison of Sec. 7) */
+    float gamma;      /* in (0, 1], GLINT_PROBS_CONSTANT only */
 } glint_shade_params;
+
+#define GLINT_PROBS_ENV 0
+#define GLINT_PROBS_CONSTANT 1
 
 /* Optional per-pixel outputs for verification (each pointer may be NULL). */
 typedef struct glint_shade_debug {

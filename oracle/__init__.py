@@ -63,8 +63,8 @@ def _declare(L):
     L.orc_hash_xi.argtypes = [C.c_uint32, C.c_uint32, C.c_int32, C.c_int64, C.c_int64, C.c_int,
                               f32p, f32p]
     L.orc_shade_pixels.argtypes = [C.POINTER(f32p), f32p, f32p, f64p, f32p, f32p, C.c_int, C.c_int, C.c_int,
-                                   C.c_uint32, C.c_int, C.c_int, i64p, C.c_int64, f64p, f64p, u8p, f64p, u8p,
-                                   C.c_int]
+                                   C.c_uint32, C.c_int, C.c_int, C.c_int, C.c_double, i64p, C.c_int64, f64p, f64p,
+                                   u8p, f64p, u8p, C.c_int]
     L.orc_shade_pixels_given_F.argtypes = [C.POINTER(f32p), f64p, f32p, f64p, f32p, f32p, C.c_int, C.c_int,
                                            C.c_int, C.c_uint32, C.c_int, C.c_int, i64p, C.c_int64, f64p, f64p,
                                            u8p, f64p, u8p, C.c_int]
@@ -181,12 +181,17 @@ SAMPLERS = {"dual": 0, "single": 1, "single-floor": 2}
 
 
 def shade(gbuf: dict, ind_pyr, rgb_pyr, levels, lut_S, lut_E, R: int, K: int, M: int, seed: int,
-          vertices: int = 1, pixels=None, threads=None, F=None, sampler: int = 0):
+          vertices: int = 1, pixels=None, threads=None, F=None, sampler: int = 0, prob_mode: int = 0,
+          gamma: float = 1.0):
     """Glint radiance of the requested pixels (all when None).
 
     sampler: binomial approximation of every tree node, 0 dual-gated (Sec. 6
     Alg. "Dual-gated Gaussian"), 1 single-gated Eq. (gated), 2 the prior
     single-gated form Eq. (oldgated).
+    prob_mode 1: one reflection probability gamma for every facet (the
+    comparison method of Sec. 7), outputs laid out for K = 2.
+    gbuf may carry "visibility" (float32 in [0, 1]) to attenuate the
+    reflection probabilities.
 
     gbuf: dict of flat float32 arrays (surf_id uint32).  ind_pyr [texels,K]
     float32 and rgb_pyr [texels,4] float32 are the stored pyramids.  With F
@@ -202,7 +207,14 @@ def shade(gbuf: dict, ind_pyr, rgb_pyr, levels, lut_S, lut_E, R: int, K: int, M:
         pixels = np.arange(P, dtype=np.int64)
     pixels = np.ascontiguousarray(pixels, dtype=np.int64)
     n = len(pixels)
-    arr = (C.POINTER(C.c_float) * 16)(*[f.ctypes.data_as(C.POINTER(C.c_float)) for f in fields])
+    vis = gbuf.get("visibility")
+    if vis is not None:
+        vis = np.ascontiguousarray(vis, dtype=np.float32)
+        fields.append(vis)
+    arr = (C.POINTER(C.c_float) * 17)(*[f.ctypes.data_as(C.POINTER(C.c_float)) for f in fields])
+    if prob_mode == 1:
+        K = 2
+    gamma = float(np.float32(gamma))  # a float parameter, as in the C interface
     ind_pyr = np.ascontiguousarray(ind_pyr if F is None else np.zeros(1), dtype=np.float32)
     rgb_pyr = np.ascontiguousarray(rgb_pyr, dtype=np.float32)
     levels = np.ascontiguousarray(levels, dtype=np.float64)
@@ -224,7 +236,7 @@ def shade(gbuf: dict, ind_pyr, rgb_pyr, levels, lut_S, lut_E, R: int, K: int, M:
         return out
     rc = lib().orc_shade_pixels(arr, _p(ind_pyr, C.c_float), _p(rgb_pyr, C.c_float), _p(levels, C.c_double),
                                 _p(lut_S, C.c_float), _p(lut_E, C.c_float), R, K, M, seed, vertices,
-                                sampler, _p(pixels, C.c_int64), n, _p(out["radiance"], C.c_double),
+                                sampler, prob_mode, gamma, _p(pixels, C.c_int64), n, _p(out["radiance"], C.c_double),
                                 _p(out["counts"], C.c_double), _p(out["codes"], C.c_uint8),
                                 _p(out["probs"], C.c_double), _p(out["flags"], C.c_uint8),
                                 threads or threads_default())

@@ -876,6 +876,7 @@ static int lattice_level(double area, double *frac)
 typedef struct {
     const float *nx, *ny, *nz, *vx, *vy, *vz, *u, *v, *area, *ax, *ay, *density, *f0r, *f0g, *f0b;
     const uint32_t *surf;
+    const float *vis; /* optional visibility in [0, 1] (NULL: unoccluded) */
 } gbuf_t;
 
 /* Shades the requested pixels.  Outputs (double): radiance [n][3], counts
@@ -887,14 +888,23 @@ typedef struct {
  * count within 1e-5 of an integer (without being one). */
 static int shade_impl(const float *const *gb, const float *ind_pyr, const float *rgb_pyr, const double *levels,
                       const float *lut_S, const float *lut_E, int R, int K, int M, uint32_t seed, int V,
-                      int sampler, const int64_t *pix, int64_t count, const double *Fext, double *radiance,
-                      double *counts, uint8_t *codes, double *probs, uint8_t *flags, int threads)
+                      int sampler, int prob_mode, double gamma, const int64_t *pix, int64_t count,
+                      const double *Fext, double *radiance, double *counts, uint8_t *codes, double *probs,
+                      uint8_t *flags, int threads)
 {
     if (R < 1 || K < 2 || K > 16 || (K & (K - 1)) || M < 1 || (R >> (M - 1)) < 1 || (V != 1 && V != 6) ||
-        sampler < 0 || sampler > 2)
+        sampler < 0 || sampler > 2 || prob_mode < 0 || prob_mode > 1 ||
+        (prob_mode == 1 && !(gamma > 0.0 && gamma <= 1.0)))
         return ORC_EINVAL;
     gbuf_t g = {gb[0], gb[1], gb[2], gb[3], gb[4], gb[5], gb[6], gb[7], gb[8], gb[9], gb[10], gb[11],
-                gb[12], gb[13], gb[14], (const uint32_t *)gb[15]};
+                gb[12], gb[13], gb[14], (const uint32_t *)gb[15], gb[16]};
+    /* prob_mode 1 (the comparison of Sec. 7 "Comparison with Previous Work",
+     * after Wang et al. 2020): every facet reflects with one probability
+     * gamma, independent of the map; this is the two-bin case of the same
+     * machinery with p = (1 - gamma, gamma) and levels (0, 1). */
+    if (prob_mode == 1) K = 2;
+    static const double unit_levels[2] = {0.0, 1.0};
+    if (prob_mode == 1) levels = unit_levels;
     pyr_src ps_ind = {ind_pyr, R, K};
     pyr_src ps_rgb = {rgb_pyr, R, 4};
 #ifdef _OPENMP
@@ -925,24 +935,37 @@ static int shade_impl(const float *const *gb, const float *ind_pyr, const float 
         /* Sec. 4 Eq. (probhk) with Sec. 5 Eq. (rtiblndf): p_k = S F_k / sum F for
          * k >= 2 (one-based); the zero-radiance bin absorbs the rest. */
         double F[20], rgb[4];
-        if (Fext)
-            for (int k = 0; k < K; ++k) F[k] = Fext[q * K + k];
-        else
-            trilinear(pyr_texel, &ps_ind, R, M, K, wr, lod, F);
+        if (prob_mode == 0) {
+            if (Fext)
+                for (int k = 0; k < K; ++k) F[k] = Fext[q * K + k];
+            else
+                trilinear(pyr_texel, &ps_ind, R, M, K, wr, lod, F);
+        }
         trilinear(pyr_texel, &ps_rgb, R, M, 4, wr, lod, rgb);
-        double sumF = 0.0;
-        for (int k = 0; k < K; ++k) sumF += F[k];
-        double S = lut_bilinear(lut_S, 1, 0, mu, sa);
         double A = lut_bilinear(lut_E, 2, 0, mu, sa);
         double B = lut_bilinear(lut_E, 2, 1, mu, sa);
-        double p[16];
+        /* Sec. 8 "Limitations & Future Work": occlusion attenuates the
+         * reflection probabilities rather than the output.  A visibility v
+         * scales p_k (k >= 1); occluded facets join bin 0.  The normalisation
+         * below keeps the unattenuated p, so the expected output is v times
+         * the smooth radiance while each glint keeps its brightness. */
+        double vis = g.vis ? (double)g.vis[i] : 1.0;
+        double p[16], pa[16];
         double rest = 0.0;
-        for (int k = 1; k < K; ++k) {
-            p[k] = sumF > 0.0 ? S * F[k] / sumF : 0.0;
-            rest += p[k];
+        if (prob_mode == 1) {
+            p[1] = gamma;
+        } else {
+            double sumF = 0.0;
+            for (int k = 0; k < K; ++k) sumF += F[k];
+            double S = lut_bilinear(lut_S, 1, 0, mu, sa);
+            for (int k = 1; k < K; ++k) p[k] = sumF > 0.0 ? S * F[k] / sumF : 0.0;
         }
-        p[0] = 1.0 - rest;
-        if (pr) for (int k = 0; k < K; ++k) pr[k] = p[k];
+        for (int k = 1; k < K; ++k) {
+            pa[k] = p[k] * vis;
+            rest += pa[k];
+        }
+        pa[0] = 1.0 - rest;
+        if (pr) for (int k = 0; k < K; ++k) pr[k] = pa[k];
         /* Sec. 3.3 Eq. (anisogrid): weighted sum of independent multinomial
          * draws at lattice vertices, each with N_i = N_P. */
         double lt;
@@ -980,17 +1003,15 @@ static int shade_impl(const float *const *gb, const float *ind_pyr, const float 
             }
             double Mv[16];
             uint8_t cv[16];
-            flag |= multinomial(sampler, NP, p, K, seed, surf, lev, a, b, Mv, cv);
+            flag |= multinomial(sampler, NP, pa, K, seed, surf, lev, a, b, Mv, cv);
             for (int k = 0; k < K; ++k) Msum[k] += w * Mv[k];
             if (cnt) for (int k = 0; k < K; ++k) cnt[vi * K + k] = Mv[k];
             if (cod) for (int k = 0; k < K - 1; ++k) cod[vi * (K - 1) + k] = cv[k];
         }
         /* Sec. 4 Eq. (iblglints:fin). */
         double num = 0.0, den = 0.0;
-        for (int k = 0; k < K; ++k) {
-            num += levels[k] * Msum[k];
-            den += levels[k] * p[k];
-        }
+        for (int k = 0; k < K; ++k) num += levels[k] * Msum[k];
+        for (int k = 1; k < K; ++k) den += levels[k] * p[k];
         den *= NP;
         double gmod = (num > 0.0 && den > 0.0) ? num / den : 0.0;
         const float *f0[3] = {g.f0r, g.f0g, g.f0b};
@@ -1006,11 +1027,11 @@ static int shade_impl(const float *const *gb, const float *ind_pyr, const float 
 
 int orc_shade_pixels(const float *const *gb, const float *ind_pyr, const float *rgb_pyr, const double *levels,
                      const float *lut_S, const float *lut_E, int R, int K, int M, uint32_t seed, int V, int sampler,
-                     const int64_t *pix, int64_t count, double *radiance, double *counts, uint8_t *codes,
-                     double *probs, uint8_t *flags, int threads)
+                     int prob_mode, double gamma, const int64_t *pix, int64_t count, double *radiance,
+                     double *counts, uint8_t *codes, double *probs, uint8_t *flags, int threads)
 {
-    return shade_impl(gb, ind_pyr, rgb_pyr, levels, lut_S, lut_E, R, K, M, seed, V, sampler, pix, count, NULL,
-                      radiance, counts, codes, probs, flags, threads);
+    return shade_impl(gb, ind_pyr, rgb_pyr, levels, lut_S, lut_E, R, K, M, seed, V, sampler, prob_mode, gamma, pix,
+                      count, NULL, radiance, counts, codes, probs, flags, threads);
 }
 
 /* As orc_shade_pixels, with the K filtered indicator values of each requested
@@ -1023,8 +1044,8 @@ int orc_shade_pixels_given_F(const float *const *gb, const double *F, const floa
                              uint8_t *codes, double *probs, uint8_t *flags, int threads)
 {
     if (!F) return ORC_EINVAL;
-    return shade_impl(gb, NULL, rgb_pyr, levels, lut_S, lut_E, R, K, M, seed, V, sampler, pix, count, F, radiance,
-                      counts, codes, probs, flags, threads);
+    return shade_impl(gb, NULL, rgb_pyr, levels, lut_S, lut_E, R, K, M, seed, V, sampler, 0, 1.0, pix, count, F,
+                      radiance, counts, codes, probs, flags, threads);
 }
 
 /* Exposed pieces for the definition tests. */

@@ -131,6 +131,7 @@ struct ShadeArgs {
     const double *qtail; // quantile tail table (else null: tails evaluated inline)
     int exact_gating;    // 1: gating thresholds always through powf (verification)
     int sampler;         // GLINT_SAMPLER_*: node sampler of the multinomial tree
+    double gamma;        // constant reflection probability (prob_mode GLINT_PROBS_CONSTANT)
 };
 
 // One dual-gated Gaussian draw (Alg. "Dual-gated Gaussian").
@@ -292,11 +293,13 @@ __device__ __forceinline__ void multinomial(double NP, const double (&p)[K], uin
 
 // Shades pixel i of the view described by A (all of rows b1-b5).  SURR: the
 // K filtered indicator values come from A.F (a learned surrogate's output)
-// and only RGB is read from the pyramid.
-template <int K, int DT, int V, bool SURR = false, bool SG = false>
+// and only RGB is read from the pyramid.  PC: constant reflection
+// probability A.gamma (K = 2, levels (0, 1)), no indicator lookup.
+template <int K, int DT, int V, bool SURR = false, bool SG = false, bool PC = false>
 __device__ __forceinline__ void shade_pixel(const ShadeArgs &A, int64_t i)
 {
-    constexpr int KL = SURR ? 0 : K; // indicator channels read from the pyramid
+    static_assert(!PC || (K == 2 && !SURR), "constant probabilities use two bins");
+    constexpr int KL = (SURR || PC) ? 0 : K; // indicator channels read from the pyramid
     const uint32_t surf = A.g.surf_id[i];
     if (surf == GLINT_NO_SURFACE) {
         A.radiance[3 * i] = 0.0f; A.radiance[3 * i + 1] = 0.0f; A.radiance[3 * i + 2] = 0.0f;
@@ -354,29 +357,44 @@ __device__ __forceinline__ void shade_pixel(const ShadeArgs &A, int64_t i)
                                        c == 0 ? w4[0] : (c == 1 ? w4[1] : (c == 2 ? w4[2] : w4[3])), acc);
         }
     }
-    double F[K];
-    if constexpr (SURR) {
-#pragma unroll
-        for (int k = 0; k < K; ++k) F[k] = (double)A.F[i * K + k];
-    } else {
-#pragma unroll
-        for (int k = 0; k < K; ++k) F[k] = acc[k];
-    }
     const double rgb[3] = {acc[KL], acc[KL + 1], acc[KL + 2]};
-
-    // Sec. 4 Eq. (probhk) with Sec. 5 Eq. (rtiblndf)
-    double sumF = 0.0;
-#pragma unroll
-    for (int k = 0; k < K; ++k) sumF += F[k];
-    const double S = lut_bilinear(A.lut_S, 1, 0, mu, sa);
     const double EA = lut_bilinear(A.lut_E, 2, 0, mu, sa);
     const double EB = lut_bilinear(A.lut_E, 2, 1, mu, sa);
+
+    // Sec. 4 Eq. (probhk) with Sec. 5 Eq. (rtiblndf); the normalisation of
+    // Eq. (iblglints:fin) uses these (unattenuated) probabilities
     double p[K];
+    double den = 0.0;
+    if constexpr (PC) {
+        p[1] = A.gamma;
+        den = A.gamma;
+    } else {
+        double F[K];
+        if constexpr (SURR) {
+#pragma unroll
+            for (int k = 0; k < K; ++k) F[k] = (double)A.F[i * K + k];
+        } else {
+#pragma unroll
+            for (int k = 0; k < K; ++k) F[k] = acc[k];
+        }
+        double sumF = 0.0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) sumF += F[k];
+        const double S = lut_bilinear(A.lut_S, 1, 0, mu, sa);
+        const double scale = sumF > 0.0 ? S / sumF : 0.0;
+#pragma unroll
+        for (int k = 1; k < K; ++k) {
+            p[k] = scale * F[k];
+            den += A.levels[k] * p[k];
+        }
+    }
+    // occlusion attenuates the probabilities (occluded facets join bin 0),
+    // not the output
+    const double vis = A.g.visibility ? (double)A.g.visibility[i] : 1.0;
     double rest = 0.0;
-    const double scale = sumF > 0.0 ? S / sumF : 0.0;
 #pragma unroll
     for (int k = 1; k < K; ++k) {
-        p[k] = scale * F[k];
+        p[k] = p[k] * vis;
         rest += p[k];
     }
     p[0] = 1.0 - rest;
@@ -438,12 +456,12 @@ __device__ __forceinline__ void shade_pixel(const ShadeArgs &A, int64_t i)
     }
 
     // Sec. 4 Eq. (iblglints:fin)
-    double num = 0.0, den = 0.0;
+    double num = 0.0;
+    if constexpr (PC) {
+        num = Msum[1];
+    } else {
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-        const double L = A.levels[k];
-        num += L * Msum[k];
-        den += L * p[k];
+        for (int k = 1; k < K; ++k) num += A.levels[k] * Msum[k];
     }
     den *= NP;
     const double gmod = (num > 0.0 && den > 0.0) ? num / den : 0.0;
@@ -452,12 +470,12 @@ __device__ __forceinline__ void shade_pixel(const ShadeArgs &A, int64_t i)
     for (int c = 0; c < 3; ++c) A.radiance[3 * i + c] = (float)((f0[c] * EA + EB) * rgb[c] * gmod);
 }
 
-template <int K, int DT, int V, bool SURR = false, bool SG = false>
+template <int K, int DT, int V, bool SURR = false, bool SG = false, bool PC = false>
 __global__ void __launch_bounds__(kShadeThreads) k_shade(ShadeArgs A)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= A.P) return;
-    shade_pixel<K, DT, V, SURR, SG>(A, i);
+    shade_pixel<K, DT, V, SURR, SG, PC>(A, i);
 }
 
 // All views of one (K, V) group in one launch: block b shades tile b of the
@@ -526,6 +544,7 @@ void make_shade_args(void *out, const glint_gbuffer &g, int64_t P, const glint_e
     a.qtail = env.quantile_tail;
     a.exact_gating = sp.exact_gating;
     a.sampler = sp.sampler;
+    a.gamma = (double)sp.gamma;
     *static_cast<ShadeArgs *>(out) = a;
 }
 
@@ -585,7 +604,26 @@ hipError_t launch_shade(const glint_gbuffer &g, int64_t P, const glint_env &env,
     a.qtail = env.quantile_tail;
     a.exact_gating = sp.exact_gating;
     a.sampler = sp.sampler;
+    a.gamma = (double)sp.gamma;
     const int K = env.K, DT = (int)env.dtype, V = sp.vertices;
+    if (sp.prob_mode == GLINT_PROBS_CONSTANT) {
+        // two bins, indicator pyramid not read
+        const unsigned blocks = (unsigned)((P + kShadeThreads - 1) / kShadeThreads);
+        const bool sg = sp.sampler != GLINT_SAMPLER_DUAL;
+        if (V == 1 && !sg)
+            GLINT_LAUNCH("k_shade", (k_shade<2, 0, 1, false, false, true>), dim3(blocks), dim3(kShadeThreads), 0,
+                         stream, a);
+        else if (V == 1)
+            GLINT_LAUNCH("k_shade", (k_shade<2, 0, 1, false, true, true>), dim3(blocks), dim3(kShadeThreads), 0,
+                         stream, a);
+        else if (!sg)
+            GLINT_LAUNCH("k_shade", (k_shade<2, 0, 6, false, false, true>), dim3(blocks), dim3(kShadeThreads), 0,
+                         stream, a);
+        else
+            GLINT_LAUNCH("k_shade", (k_shade<2, 0, 6, false, true, true>), dim3(blocks), dim3(kShadeThreads), 0,
+                         stream, a);
+        return hipGetLastError();
+    }
     if (F) {
         // surrogate form: the indicator pyramid is not read, so its storage type does not matter
         const unsigned blocks = (unsigned)((P + kShadeThreads - 1) / kShadeThreads);

@@ -15,6 +15,7 @@ from . import build as _build
 GLINT_OK, GLINT_EINVAL, GLINT_EUNSUPPORTED, GLINT_EDEVICE, GLINT_ENOMEM = 0, 1, 2, 3, 4
 GLINT_F32, GLINT_F16, GLINT_BF16, GLINT_UNORM16 = 0, 1, 2, 3
 GLINT_SAMPLER_DUAL, GLINT_SAMPLER_SINGLE, GLINT_SAMPLER_SINGLE_FLOOR = 0, 1, 2
+GLINT_PROBS_ENV, GLINT_PROBS_CONSTANT = 0, 1
 GLINT_NO_SURFACE = 0xFFFFFFFF
 LUT_N = 64
 
@@ -37,7 +38,7 @@ class PrefilterParams(C.Structure):
 
 
 class GBuffer(C.Structure):
-    _fields_ = [(k, C.c_void_p) for k in GBUF_FIELDS]
+    _fields_ = [(k, C.c_void_p) for k in GBUF_FIELDS] + [("visibility", C.c_void_p)]
 
 
 class Env(C.Structure):
@@ -47,7 +48,8 @@ class Env(C.Structure):
 
 
 class ShadeParams(C.Structure):
-    _fields_ = [("seed", C.c_uint32), ("vertices", C.c_int), ("exact_gating", C.c_int), ("sampler", C.c_int)]
+    _fields_ = [("seed", C.c_uint32), ("vertices", C.c_int), ("exact_gating", C.c_int), ("sampler", C.c_int),
+                ("prob_mode", C.c_int), ("gamma", C.c_float)]
 
 
 class ShadeDebug(C.Structure):
@@ -239,16 +241,19 @@ def glint_sample_binomial(ctx, sampler, N, p, h1, h2, n, nbar, code, quantile_ta
 
 
 def make_gbuffer(fields: dict) -> GBuffer:
-    """Maps a dict of device tensors (one per G-buffer field) to the C struct."""
+    """Maps a dict of device tensors (one per G-buffer field, plus an optional
+    float32 "visibility") to the C struct."""
     _require_cuda(*fields.values())
-    return GBuffer(*[fields[k].data_ptr() for k in GBUF_FIELDS])
+    vis = fields.get("visibility")
+    return GBuffer(*[fields[k].data_ptr() for k in GBUF_FIELDS], vis.data_ptr() if vis is not None else None)
 
 
 def make_env(ind_pyr, rgb_pyr, levels, lut_S, lut_E, R, K, num_mips, dtype, quantile_tail=None) -> Env:
     _require_cuda(ind_pyr, rgb_pyr, levels, lut_S, lut_E, quantile_tail)
-    return Env(ind_pyr.data_ptr() if ind_pyr is not None else None, rgb_pyr.data_ptr(), levels.data_ptr(),
-               lut_S.data_ptr(), lut_E.data_ptr(), R, K, num_mips, dtype,
-               quantile_tail.data_ptr() if quantile_tail is not None else None)
+    def ptr(t):
+        return t.data_ptr() if t is not None else None
+    return Env(ptr(ind_pyr), ptr(rgb_pyr), ptr(levels), ptr(lut_S), ptr(lut_E), R, K, num_mips, dtype,
+               ptr(quantile_tail))
 
 
 def glint_shade(ctx, gbuf: GBuffer, num_pixels: int, env: Env, params: ShadeParams, radiance, debug=None,

@@ -212,6 +212,20 @@ def scene_frame(W: int, H: int, seed: int = 7, density_decades=(6.0, 9.0), eye=(
     return _finish(g)
 
 
+def contact_visibility(g: dict) -> np.ndarray:
+    """Occlusion stand-in for the sphere-and-plane scene (an ambient-occlusion
+    like field, float32 in [0, 1]): on the plane (surface 2) it falls to 0.2
+    towards the sphere's contact point at the uv origin, on the sphere
+    (surface 1) from 1 at the top to 0.6 at the bottom; 1 elsewhere."""
+    vis = np.ones(len(g["nx"]), np.float32)
+    sphere = g["surf_id"] == 1
+    plane = g["surf_id"] == 2
+    vis[sphere] = 0.6 + 0.4 * np.clip(0.5 * g["ny"][sphere] + 0.5, 0.0, 1.0)
+    r = np.hypot(g["u"][plane].astype(np.float64), g["v"][plane].astype(np.float64))
+    vis[plane] = np.clip(0.2 + 0.8 * (r - 0.2) / 1.3, 0.2, 1.0)
+    return vis
+
+
 def n_sweep(W: int = 512, rows: int = 64, max_decades: float = 12.0, seed: int = 5) -> dict:
     """Counts sweep: row r has N_P = 10^(max_decades r / (rows-1)) (1 .. 1e12,
     the range where float counts lose integers); along a row the normal tilts

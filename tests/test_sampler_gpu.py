@@ -1,5 +1,7 @@
 """GPU parity of the binomial approximations of Sec. 6 (glint_sample_binomial)
-and of shading with each of them, against the FP64 oracle.
+and of shading with each of them, and of the two reflection-probability
+modes (occlusion-attenuated probabilities, the map-independent constant
+probability of the comparison method), against the FP64 oracle.
 
 Bar: gating codes bit-exact and counts within 1e-9 relative (integer parts
 equal) except where the oracle flags the draw (xi1 within the tolerance band
@@ -137,6 +139,20 @@ def oracle_env(env, K, M):
     return levels, ind, rgb
 
 
+def check_pixels(gpu, orc, tag, max_flagged=5e-3):
+    flags = orc["flags"].astype(bool)
+    ok = ~flags
+    assert flags.mean() < max_flagged, (tag, flags.mean())
+    np.testing.assert_allclose(gpu["probs"], orc["probs"], rtol=1e-12, atol=1e-15, err_msg=tag)
+    assert np.array_equal(gpu["codes"][ok], orc["codes"][ok]), tag
+    gc, oc = gpu["counts"][ok], orc["counts"][ok]
+    assert np.array_equal(np.floor(gc), np.floor(oc)), tag
+    np.testing.assert_allclose(gc, oc, rtol=1e-9, atol=1e-9, err_msg=tag)
+    gr, orad = gpu["radiance"][ok].astype(np.float64), orc["radiance"][ok]
+    assert np.all(np.abs(gr - orad) <= 1e-5 * np.abs(orad) + 1e-30), tag
+    U.log(f"  {tag}: {len(flags)} px, flagged {int(flags.sum())}")
+
+
 @pytest.mark.parametrize("sampler", [G.GLINT_SAMPLER_SINGLE, G.GLINT_SAMPLER_SINGLE_FLOOR])
 @pytest.mark.parametrize("vertices", [1, 6])
 def test_shade_with_single_gated_sampler(ctx, qtail, sampler, vertices):
@@ -151,17 +167,7 @@ def test_shade_with_single_gated_sampler(ctx, qtail, sampler, vertices):
     gpu = U.shade(ctx, g, ind, rgb, levels, S, E, R, K, M, seed=7, vertices=vertices, qtail=qtail,
                   sampler=sampler)
     orc = oracle.shade(g, ind, rgb, levels, S, E, R, K, M, 7, vertices, sampler=sampler)
-    flags = orc["flags"].astype(bool)
-    ok = ~flags
-    assert flags.mean() < 5e-3
-    np.testing.assert_allclose(gpu["probs"], orc["probs"], rtol=1e-12, atol=1e-15)
-    assert np.array_equal(gpu["codes"][ok], orc["codes"][ok])
-    gc, oc = gpu["counts"][ok], orc["counts"][ok]
-    assert np.array_equal(np.floor(gc), np.floor(oc))
-    np.testing.assert_allclose(gc, oc, rtol=1e-9, atol=1e-9)
-    gr, orad = gpu["radiance"][ok].astype(np.float64), orc["radiance"][ok]
-    assert np.all(np.abs(gr - orad) <= 1e-5 * np.abs(orad) + 1e-30)
-    U.log(f"  {len(flags)} px, flagged {int(flags.sum())}")
+    check_pixels(gpu, orc, f"sampler={sampler} V={vertices}")
 
 
 def test_single_gated_sampler_needs_f32_pyramid(ctx):
@@ -182,3 +188,70 @@ def test_single_gated_sampler_needs_f32_pyramid(ctx):
     with pytest.raises(G.GlintError) as e:
         G.glint_shade(ctx, G.make_gbuffer(fields), len(g["nx"]), envs, G.ShadeParams(1, 1, 0, 7), rad)
     assert e.value.code == G.GLINT_EINVAL
+
+
+# --- reflection-probability modes: occlusion and constant probability ---------------
+
+@pytest.mark.parametrize("vertices", [1, 6])
+def test_shade_with_visibility_matches_oracle(ctx, qtail, vertices):
+    """Occlusion attenuates the probabilities (a visibility per pixel, with
+    exact 0 and 1 among the values), every pixel against the oracle."""
+    R, K, M = 16, 8, 5
+    U.log(f"shade visibility V={vertices}")
+    env = synth.make_env(R, 6)
+    levels, ind, rgb = oracle_env(env, K, M)
+    S, E = oracle.lut_tables()
+    g = synth.scene_frame(96, 54, seed=3, density_decades=(0.0, 7.0))
+    vis = synth.contact_visibility(g)
+    rng = np.random.default_rng(2)
+    vis[rng.random(len(vis)) < 0.05] = 0.0
+    vis[rng.random(len(vis)) < 0.05] = 1.0
+    g["visibility"] = vis
+    gpu = U.shade(ctx, g, ind, rgb, levels, S, E, R, K, M, seed=7, vertices=vertices, qtail=qtail)
+    orc = oracle.shade(g, ind, rgb, levels, S, E, R, K, M, 7, vertices)
+    check_pixels(gpu, orc, f"visibility V={vertices}")
+
+
+@pytest.mark.parametrize("sampler", [G.GLINT_SAMPLER_DUAL, G.GLINT_SAMPLER_SINGLE])
+@pytest.mark.parametrize("vertices", [1, 6])
+def test_shade_constant_probability_matches_oracle(ctx, qtail, sampler, vertices):
+    """The map-independent comparison mode (one probability gamma for every
+    facet, two bins), with a visibility field and without the indicator
+    pyramid (not read in this mode)."""
+    import torch
+    R, K, M = 16, 8, 5
+    U.log(f"shade constant probability sampler={sampler} V={vertices}")
+    env = synth.make_env(R, 6)
+    levels, ind, rgb = oracle_env(env, K, M)
+    S, E = oracle.lut_tables()
+    g = synth.scene_frame(96, 54, seed=4, density_decades=(0.0, 8.0))
+    g["visibility"] = synth.contact_visibility(g)
+    gamma = 0.05
+    orc = oracle.shade(g, ind, rgb, levels, S, E, R, K, M, 7, vertices, sampler=sampler, prob_mode=1,
+                       gamma=gamma)
+    gpu = U.shade(ctx, g, ind, rgb, levels, S, E, R, K, M, seed=7, vertices=vertices, qtail=qtail,
+                  sampler=sampler, prob_mode=G.GLINT_PROBS_CONSTANT, gamma=gamma)
+    check_pixels(gpu, orc, f"constant sampler={sampler} V={vertices}")
+    # no indicator pyramid, no levels, no S table: same radiance
+    fields = U.gbuf_to_device(g)
+    envs = G.make_env(None, U.dev(rgb), None, None, U.dev(E), R, K, M, G.GLINT_F32, qtail)
+    rad = torch.empty((len(g["nx"]), 3), dtype=torch.float32, device="cuda")
+    G.glint_shade(ctx, G.make_gbuffer(fields), len(g["nx"]), envs,
+                  G.ShadeParams(7, vertices, 0, sampler, G.GLINT_PROBS_CONSTANT, gamma), rad)
+    assert np.array_equal(U.host(rad), gpu["radiance"])
+
+
+def test_prob_mode_arguments_rejected(ctx):
+    import torch
+    R, K, M = 16, 4, 5
+    env = synth.make_env(R, 2)
+    levels, ind, rgb = oracle_env(env, K, M)
+    S, E = oracle.lut_tables()
+    g = synth.scene_frame(32, 18, seed=1)
+    fields = U.gbuf_to_device(g)
+    envs = G.make_env(U.dev(ind), U.dev(rgb), U.dev(levels), U.dev(S), U.dev(E), R, K, M, G.GLINT_F32)
+    rad = torch.empty((len(g["nx"]), 3), dtype=torch.float32, device="cuda")
+    for pm, gamma in ((G.GLINT_PROBS_CONSTANT, 0.0), (G.GLINT_PROBS_CONSTANT, 1.5), (2, 0.5)):
+        with pytest.raises(G.GlintError) as e:
+            G.glint_shade(ctx, G.make_gbuffer(fields), len(g["nx"]), envs, G.ShadeParams(1, 1, 0, 0, pm, gamma), rad)
+        assert e.value.code == G.GLINT_EINVAL
