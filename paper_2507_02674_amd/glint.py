@@ -245,15 +245,19 @@ def make_gbuffer(fields: dict) -> GBuffer:
     float32 "visibility") to the C struct."""
     _require_cuda(*fields.values())
     vis = fields.get("visibility")
-    return GBuffer(*[fields[k].data_ptr() for k in GBUF_FIELDS], vis.data_ptr() if vis is not None else None)
+    g = GBuffer(*[fields[k].data_ptr() for k in GBUF_FIELDS], vis.data_ptr() if vis is not None else None)
+    g._keep = dict(fields)  # the struct holds raw pointers: keep the tensors alive with it
+    return g
 
 
 def make_env(ind_pyr, rgb_pyr, levels, lut_S, lut_E, R, K, num_mips, dtype, quantile_tail=None) -> Env:
     _require_cuda(ind_pyr, rgb_pyr, levels, lut_S, lut_E, quantile_tail)
     def ptr(t):
         return t.data_ptr() if t is not None else None
-    return Env(ptr(ind_pyr), ptr(rgb_pyr), ptr(levels), ptr(lut_S), ptr(lut_E), R, K, num_mips, dtype,
-               ptr(quantile_tail))
+    e = Env(ptr(ind_pyr), ptr(rgb_pyr), ptr(levels), ptr(lut_S), ptr(lut_E), R, K, num_mips, dtype,
+            ptr(quantile_tail))
+    e._keep = (ind_pyr, rgb_pyr, levels, lut_S, lut_E, quantile_tail)  # keeps the tensors alive with the struct
+    return e
 
 
 def glint_shade(ctx, gbuf: GBuffer, num_pixels: int, env: Env, params: ShadeParams, radiance, debug=None,
