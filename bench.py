@@ -174,6 +174,8 @@ def parse():
     ap.add_argument("--probs", default="env", choices=["env", "constant"],
                     help="reflection probabilities from the map (the paper) or one constant for every facet")
     ap.add_argument("--gamma", type=float, default=0.05, help="the constant probability of --probs constant")
+    ap.add_argument("--lobe-taps", type=int, default=0, choices=[0, 2, 4, 8],
+                    help="anisotropic lookup with this many taps along the lobe (0: one lookup)")
     ap.add_argument("--visibility", default="none", choices=["none", "contact"],
                     help="occlusion that attenuates the probabilities (contact: the scene's AO-like field)")
     ap.add_argument("--train-steps", type=int, default=400, help="surrogate training steps before timing")
@@ -383,8 +385,10 @@ def main():
     env_np, gbuf_np = w.env(), w.gbuf()
     if a.visibility == "contact":
         gbuf_np["visibility"] = synth.contact_visibility(gbuf_np)
+    if a.lobe_taps:
+        gbuf_np["tx"], gbuf_np["ty"], gbuf_np["tz"] = synth.surface_tangents(gbuf_np)
     prob_mode = G.GLINT_PROBS_CONSTANT if a.probs == "constant" else G.GLINT_PROBS_ENV
-    default_path = a.sampler == "dual" and a.probs == "env" and a.visibility == "none"
+    default_path = a.sampler == "dual" and a.probs == "env" and a.visibility == "none" and a.lobe_taps == 0
     glint_pixels = int((gbuf_np["surf_id"] != 0xFFFFFFFF).sum())
     ctx = G.glint_create(0)
     env = torch.from_numpy(env_np).cuda()
@@ -402,7 +406,7 @@ def main():
                                  sampler=SAMPLERS[a.sampler])
     else:
         shader = Shader(ctx, gbuf_np, seed=w.hash_seed, vertices=a.vertices, sampler=SAMPLERS[a.sampler],
-                        prob_mode=prob_mode, gamma=a.gamma)
+                        prob_mode=prob_mode, gamma=a.gamma, lobe_taps=a.lobe_taps)
     frames = FramePipeline(new_env, shader, overlap=not a.no_overlap)
     frames.build_luts()
     for _ in range(a.warmup):
@@ -448,7 +452,7 @@ def main():
     serial_ms = float(ev[0][0].elapsed_time(ev[-1][2])) / n_ser
 
     config_tag = f"{w.name}-{a.form}-{a.dtype}-v{a.vertices}" + (
-        "" if default_path else f"-{a.sampler}-{a.probs}-{a.visibility}")
+        "" if default_path else f"-{a.sampler}-{a.probs}-{a.visibility}-t{a.lobe_taps}")
     records = roofline_records(kernels, w, a, shader, glint_pixels, config_tag)
     dominant = max(records, key=lambda k: kernels[k]["avg_ms"] * kernels[k]["launches_per_step"])
     roofline = dict(records[dominant])
@@ -462,7 +466,7 @@ def main():
                                   f"{w.M} mips, K={w.K}, T={w.T} taps, per-frame partition+prefilter+shade",
                       "form": a.form, "pyramid_dtype": a.dtype, "vertices": a.vertices, "sampler": a.sampler,
                       "probs": a.probs if a.probs == "env" else f"constant gamma={a.gamma}",
-                      "visibility": a.visibility,
+                      "visibility": a.visibility, "lobe_taps": a.lobe_taps,
                       "glint_pixels": glint_pixels, "total_pixels": shader.P,
                       "frames_overlapped": not a.no_overlap},
            "prefilter_ms_per_frame": round(pre_ms, 4), "shade_ms_per_frame": round(sh_ms, 4),
@@ -478,7 +482,7 @@ def main():
         ref_pipe = new_env("f32")
         ref_pipe.build_luts()
         ref_pipe.run(env)
-        ref_sh = Shader(ctx, {k: v for k, v in gbuf_np.items() if k != "visibility"}, seed=w.hash_seed,
+        ref_sh = Shader(ctx, {k: v for k, v in gbuf_np.items() if k not in G.GBUF_OPTIONAL}, seed=w.hash_seed,
                         vertices=a.vertices)
         P = shader.P
         dbg0 = {"probs": torch.empty((P, w.K), dtype=torch.float64, device="cuda")}

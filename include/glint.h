@@ -317,6 +317,15 @@ int glint_sample_binomial(glint_ctx ctx, int sampler, int exact_gating, const do
  * with p'_k = v p_k (k >= 1), p'_0 = 1 - sum_{k>=1} p'_k, while the
  * normalisation keeps the unattenuated p_k, so the expected radiance is
  * v L_o and each glint keeps its brightness.
+ * Anisotropic lookup (Sec. 8 names several samples of the prefiltered map
+ * as the way to anisotropic distributions; the tap layout is this
+ * library's): with lobe_taps = T, F and RGB are the mean, weighted by
+ * <n, w_j>+, of T trilinear lookups at lod sqrt(a_t)(M-1),
+ * a_t = max(a_min, a_max/T), in directions
+ * w_j = 2<v,h_j>h_j - v, h_j = (n - x_j d)/sqrt(1+x_j^2), x_j = s u_j/sqrt(1-u_j^2),
+ * u_j = (2j+1)/T - 1, s = sqrt(a_max^2 - a_t^2), d the tangent made
+ * orthogonal to n (n x d when alpha_y > alpha_x).  S and E_rho stay at
+ * alpha = sqrt(alpha_x alpha_y).
  * prob_mode = GLINT_PROBS_CONSTANT (Sec. 7 "Comparison with Previous Work",
  * after Wang et al. 2020): p = (1 - gamma, gamma) and levels (0, 1) for
  * every pixel, i.e. the two-bin case of the same path; the indicator
@@ -338,6 +347,8 @@ typedef struct glint_gbuffer {
     const float *visibility;   /* optional (NULL: unoccluded): unoccluded fraction v in [0, 1] of the
                                   pixel's reflection lobe; scales the reflection probabilities, see
                                   glint_shade */
+    const float *tx, *ty, *tz; /* optional surface tangent, the axis of alpha_x (needed only for
+                                  anisotropic lookups, glint_shade_params.lobe_taps > 0) */
 } glint_gbuffer;
 
 typedef struct glint_env {
@@ -367,6 +378,9 @@ typedef struct glint_shade_params {
                          GLINT_PROBS_CONSTANT: every facet reflects with probability gamma,
                          independent of the map (the comparison of Sec. 7) */
     float gamma;      /* in (0, 1], GLINT_PROBS_CONSTANT only */
+    int lobe_taps;    /* 0: one lookup at alpha = sqrt(alpha_x alpha_y); 2, 4 or 8: anisotropic
+                         lookup with that many taps along the lobe (see glint_shade; needs the
+                         G-buffer tangent; float32 pyramid, dual-gated sampler, GLINT_PROBS_ENV) */
 } glint_shade_params;
 
 #define GLINT_PROBS_ENV 0

@@ -63,8 +63,8 @@ def _declare(L):
     L.orc_hash_xi.argtypes = [C.c_uint32, C.c_uint32, C.c_int32, C.c_int64, C.c_int64, C.c_int,
                               f32p, f32p]
     L.orc_shade_pixels.argtypes = [C.POINTER(f32p), f32p, f32p, f64p, f32p, f32p, C.c_int, C.c_int, C.c_int,
-                                   C.c_uint32, C.c_int, C.c_int, C.c_int, C.c_double, i64p, C.c_int64, f64p, f64p,
-                                   u8p, f64p, u8p, C.c_int]
+                                   C.c_uint32, C.c_int, C.c_int, C.c_int, C.c_double, C.c_int, i64p, C.c_int64, f64p,
+                                   f64p, u8p, f64p, u8p, C.c_int]
     L.orc_shade_pixels_given_F.argtypes = [C.POINTER(f32p), f64p, f32p, f64p, f32p, f32p, C.c_int, C.c_int,
                                            C.c_int, C.c_uint32, C.c_int, C.c_int, i64p, C.c_int64, f64p, f64p,
                                            u8p, f64p, u8p, C.c_int]
@@ -182,7 +182,7 @@ SAMPLERS = {"dual": 0, "single": 1, "single-floor": 2}
 
 def shade(gbuf: dict, ind_pyr, rgb_pyr, levels, lut_S, lut_E, R: int, K: int, M: int, seed: int,
           vertices: int = 1, pixels=None, threads=None, F=None, sampler: int = 0, prob_mode: int = 0,
-          gamma: float = 1.0):
+          gamma: float = 1.0, lobe_taps: int = 0):
     """Glint radiance of the requested pixels (all when None).
 
     sampler: binomial approximation of every tree node, 0 dual-gated (Sec. 6
@@ -192,6 +192,8 @@ def shade(gbuf: dict, ind_pyr, rgb_pyr, levels, lut_S, lut_E, R: int, K: int, M:
     comparison method of Sec. 7), outputs laid out for K = 2.
     gbuf may carry "visibility" (float32 in [0, 1]) to attenuate the
     reflection probabilities.
+    lobe_taps in {2, 4, 8}: anisotropic lookup along the lobe's major axis
+    (gbuf must carry the tangent "tx", "ty", "tz").
 
     gbuf: dict of flat float32 arrays (surf_id uint32).  ind_pyr [texels,K]
     float32 and rgb_pyr [texels,4] float32 are the stored pyramids.  With F
@@ -207,11 +209,12 @@ def shade(gbuf: dict, ind_pyr, rgb_pyr, levels, lut_S, lut_E, R: int, K: int, M:
         pixels = np.arange(P, dtype=np.int64)
     pixels = np.ascontiguousarray(pixels, dtype=np.int64)
     n = len(pixels)
-    vis = gbuf.get("visibility")
-    if vis is not None:
-        vis = np.ascontiguousarray(vis, dtype=np.float32)
-        fields.append(vis)
-    arr = (C.POINTER(C.c_float) * 17)(*[f.ctypes.data_as(C.POINTER(C.c_float)) for f in fields])
+    extra = [gbuf.get(k) for k in ("visibility", "tx", "ty", "tz")]
+    extra = [None if a is None else np.ascontiguousarray(a, dtype=np.float32) for a in extra]
+    keep = fields + [a for a in extra if a is not None]
+    ptrs = [f.ctypes.data_as(C.POINTER(C.c_float)) for f in fields] + \
+        [a.ctypes.data_as(C.POINTER(C.c_float)) if a is not None else C.POINTER(C.c_float)() for a in extra]
+    arr = (C.POINTER(C.c_float) * 20)(*ptrs)
     if prob_mode == 1:
         K = 2
     gamma = float(np.float32(gamma))  # a float parameter, as in the C interface
@@ -236,7 +239,7 @@ def shade(gbuf: dict, ind_pyr, rgb_pyr, levels, lut_S, lut_E, R: int, K: int, M:
         return out
     rc = lib().orc_shade_pixels(arr, _p(ind_pyr, C.c_float), _p(rgb_pyr, C.c_float), _p(levels, C.c_double),
                                 _p(lut_S, C.c_float), _p(lut_E, C.c_float), R, K, M, seed, vertices,
-                                sampler, prob_mode, gamma, _p(pixels, C.c_int64), n, _p(out["radiance"], C.c_double),
+                                sampler, prob_mode, gamma, lobe_taps, _p(pixels, C.c_int64), n, _p(out["radiance"], C.c_double),
                                 _p(out["counts"], C.c_double), _p(out["codes"], C.c_uint8),
                                 _p(out["probs"], C.c_double), _p(out["flags"], C.c_uint8),
                                 threads or threads_default())

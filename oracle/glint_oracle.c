@@ -877,7 +877,70 @@ typedef struct {
     const float *nx, *ny, *nz, *vx, *vy, *vz, *u, *v, *area, *ax, *ay, *density, *f0r, *f0g, *f0b;
     const uint32_t *surf;
     const float *vis; /* optional visibility in [0, 1] (NULL: unoccluded) */
+    const float *tx, *ty, *tz; /* optional tangent (the alpha_x axis) */
 } gbuf_t;
+
+/* Anisotropic lookup: the future work of Sec. 8 (several samples of the
+ * prefiltered map for anisotropic distributions) as this library designs
+ * it.  T taps of isotropic roughness a_t = max(a_min, a_max / T) lie along
+ * the lobe's major axis at the stratified quantiles u_j = (2j+1)/T - 1 of
+ * the GGX slope marginal of scale s = sqrt(a_max^2 - a_t^2): slope
+ * x_j = s u_j / sqrt(1 - u_j^2), microfacet normal
+ * h_j = (n - x_j d) / sqrt(1 + x_j^2),
+ * direction w_j = 2 <v, h_j> h_j - v, read at lod sqrt(a_t)(M-1); the taps
+ * are averaged with weights <n, w_j>+ (the cosine of the filter kernel,
+ * whose half vectors the quantiles stand for).  d is the tangent made
+ * orthogonal to n (the alpha_x axis),
+ * or n x d when alpha_y > alpha_x; a tangent parallel to n is replaced by
+ * the first axis of the frame onb(n). */
+static void aniso_lookup(const pyr_src *ind, const pyr_src *rgbs, int R, int M, int K, int T, int read_ind,
+                         const double n[3], const double v[3], const double t[3], double ax, double ay, double *F,
+                         double *rgb)
+{
+    double tn = t[0] * n[0] + t[1] * n[1] + t[2] * n[2];
+    double tt[3] = {t[0] - tn * n[0], t[1] - tn * n[1], t[2] - tn * n[2]};
+    double tl = sqrt(tt[0] * tt[0] + tt[1] * tt[1] + tt[2] * tt[2]);
+    if (tl > 1e-12) {
+        for (int c = 0; c < 3; ++c) tt[c] /= tl;
+    } else {
+        double b2[3];
+        onb(n, tt, b2);
+    }
+    double bt[3] = {n[1] * tt[2] - n[2] * tt[1], n[2] * tt[0] - n[0] * tt[2], n[0] * tt[1] - n[1] * tt[0]};
+    double amin = ax < ay ? ax : ay, amax = ax < ay ? ay : ax;
+    const double *d = ax >= ay ? tt : bt;
+    double at = amax / (double)T;
+    if (at < amin) at = amin;
+    double s2 = amax * amax - at * at;
+    double s = s2 > 0.0 ? sqrt(s2) : 0.0;
+    double lod = sqrt(at) * (double)(M - 1);
+    for (int k = 0; k < K; ++k) F[k] = 0.0;
+    for (int c = 0; c < 4; ++c) rgb[c] = 0.0;
+    double wsum = 0.0;
+    for (int j = 0; j < T; ++j) {
+        double u = (double)(2 * j + 1) / (double)T - 1.0;
+        double x = s * u / sqrt(1.0 - u * u);
+        /* n and d are orthonormal, so |n - x d| = sqrt(1 + x^2) */
+        double hl = sqrt(1.0 + x * x);
+        double h[3] = {(n[0] - x * d[0]) / hl, (n[1] - x * d[1]) / hl, (n[2] - x * d[2]) / hl};
+        double vh = v[0] * h[0] + v[1] * h[1] + v[2] * h[2];
+        double w[3] = {2.0 * vh * h[0] - v[0], 2.0 * vh * h[1] - v[1], 2.0 * vh * h[2] - v[2]};
+        double cw = w[0] * n[0] + w[1] * n[1] + w[2] * n[2];
+        cw = cw > 0.0 ? cw : 0.0;
+        double fj[20], cj[4];
+        if (read_ind) {
+            trilinear(pyr_texel, ind, R, M, K, w, lod, fj);
+            for (int k = 0; k < K; ++k) F[k] += cw * fj[k];
+        }
+        trilinear(pyr_texel, rgbs, R, M, 4, w, lod, cj);
+        for (int c = 0; c < 4; ++c) rgb[c] += cw * cj[c];
+        wsum += cw;
+    }
+    if (wsum > 0.0) { /* else every tap is below the horizon: nothing reflected */
+        for (int k = 0; k < K; ++k) F[k] /= wsum;
+        for (int c = 0; c < 4; ++c) rgb[c] /= wsum;
+    }
+}
 
 /* Shades the requested pixels.  Outputs (double): radiance [n][3], counts
  * [n][V][K], probs [n][K]; codes [n][V][K-1]; flags [n], a bit mask of the
@@ -888,16 +951,18 @@ typedef struct {
  * count within 1e-5 of an integer (without being one). */
 static int shade_impl(const float *const *gb, const float *ind_pyr, const float *rgb_pyr, const double *levels,
                       const float *lut_S, const float *lut_E, int R, int K, int M, uint32_t seed, int V,
-                      int sampler, int prob_mode, double gamma, const int64_t *pix, int64_t count,
+                      int sampler, int prob_mode, double gamma, int lobe_taps, const int64_t *pix, int64_t count,
                       const double *Fext, double *radiance, double *counts, uint8_t *codes, double *probs,
                       uint8_t *flags, int threads)
 {
     if (R < 1 || K < 2 || K > 16 || (K & (K - 1)) || M < 1 || (R >> (M - 1)) < 1 || (V != 1 && V != 6) ||
         sampler < 0 || sampler > 2 || prob_mode < 0 || prob_mode > 1 ||
-        (prob_mode == 1 && !(gamma > 0.0 && gamma <= 1.0)))
+        (prob_mode == 1 && !(gamma > 0.0 && gamma <= 1.0)) ||
+        !(lobe_taps == 0 || lobe_taps == 2 || lobe_taps == 4 || lobe_taps == 8) ||
+        (lobe_taps && (!gb[17] || !gb[18] || !gb[19])))
         return ORC_EINVAL;
     gbuf_t g = {gb[0], gb[1], gb[2], gb[3], gb[4], gb[5], gb[6], gb[7], gb[8], gb[9], gb[10], gb[11],
-                gb[12], gb[13], gb[14], (const uint32_t *)gb[15], gb[16]};
+                gb[12], gb[13], gb[14], (const uint32_t *)gb[15], gb[16], gb[17], gb[18], gb[19]};
     /* prob_mode 1 (the comparison of Sec. 7 "Comparison with Previous Work",
      * after Wang et al. 2020): every facet reflects with one probability
      * gamma, independent of the map; this is the two-bin case of the same
@@ -935,13 +1000,21 @@ static int shade_impl(const float *const *gb, const float *ind_pyr, const float 
         /* Sec. 4 Eq. (probhk) with Sec. 5 Eq. (rtiblndf): p_k = S F_k / sum F for
          * k >= 2 (one-based); the zero-radiance bin absorbs the rest. */
         double F[20], rgb[4];
-        if (prob_mode == 0) {
-            if (Fext)
+        if (lobe_taps) {
+            double t[3] = {g.tx[i], g.ty[i], g.tz[i]};
+            aniso_lookup(&ps_ind, &ps_rgb, R, M, K, lobe_taps, prob_mode == 0 && !Fext, n, v, t, (double)g.ax[i],
+                         (double)g.ay[i], F, rgb);
+            if (prob_mode == 0 && Fext)
                 for (int k = 0; k < K; ++k) F[k] = Fext[q * K + k];
-            else
-                trilinear(pyr_texel, &ps_ind, R, M, K, wr, lod, F);
+        } else {
+            if (prob_mode == 0) {
+                if (Fext)
+                    for (int k = 0; k < K; ++k) F[k] = Fext[q * K + k];
+                else
+                    trilinear(pyr_texel, &ps_ind, R, M, K, wr, lod, F);
+            }
+            trilinear(pyr_texel, &ps_rgb, R, M, 4, wr, lod, rgb);
         }
-        trilinear(pyr_texel, &ps_rgb, R, M, 4, wr, lod, rgb);
         double A = lut_bilinear(lut_E, 2, 0, mu, sa);
         double B = lut_bilinear(lut_E, 2, 1, mu, sa);
         /* Sec. 8 "Limitations & Future Work": occlusion attenuates the
@@ -1027,11 +1100,11 @@ static int shade_impl(const float *const *gb, const float *ind_pyr, const float 
 
 int orc_shade_pixels(const float *const *gb, const float *ind_pyr, const float *rgb_pyr, const double *levels,
                      const float *lut_S, const float *lut_E, int R, int K, int M, uint32_t seed, int V, int sampler,
-                     int prob_mode, double gamma, const int64_t *pix, int64_t count, double *radiance,
-                     double *counts, uint8_t *codes, double *probs, uint8_t *flags, int threads)
+                     int prob_mode, double gamma, int lobe_taps, const int64_t *pix, int64_t count,
+                     double *radiance, double *counts, uint8_t *codes, double *probs, uint8_t *flags, int threads)
 {
-    return shade_impl(gb, ind_pyr, rgb_pyr, levels, lut_S, lut_E, R, K, M, seed, V, sampler, prob_mode, gamma, pix,
-                      count, NULL, radiance, counts, codes, probs, flags, threads);
+    return shade_impl(gb, ind_pyr, rgb_pyr, levels, lut_S, lut_E, R, K, M, seed, V, sampler, prob_mode, gamma,
+                      lobe_taps, pix, count, NULL, radiance, counts, codes, probs, flags, threads);
 }
 
 /* As orc_shade_pixels, with the K filtered indicator values of each requested
@@ -1044,7 +1117,7 @@ int orc_shade_pixels_given_F(const float *const *gb, const double *F, const floa
                              uint8_t *codes, double *probs, uint8_t *flags, int threads)
 {
     if (!F) return ORC_EINVAL;
-    return shade_impl(gb, NULL, rgb_pyr, levels, lut_S, lut_E, R, K, M, seed, V, sampler, 0, 1.0, pix, count, F,
+    return shade_impl(gb, NULL, rgb_pyr, levels, lut_S, lut_E, R, K, M, seed, V, sampler, 0, 1.0, 0, pix, count, F,
                       radiance, counts, codes, probs, flags, threads);
 }
 

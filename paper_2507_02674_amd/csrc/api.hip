@@ -238,6 +238,8 @@ static int check_shade_params(const glint_shade_params &sp, int view)
     else if (sp.prob_mode != GLINT_PROBS_ENV && sp.prob_mode != GLINT_PROBS_CONSTANT) what = "unknown prob_mode";
     else if (sp.prob_mode == GLINT_PROBS_CONSTANT && !(sp.gamma > 0.0f && sp.gamma <= 1.0f))
         what = "gamma must be in (0, 1]";
+    else if (sp.lobe_taps != 0 && sp.lobe_taps != 2 && sp.lobe_taps != 4 && sp.lobe_taps != 8)
+        what = "lobe_taps must be 0, 2, 4 or 8";
     if (!what) return GLINT_OK;
     if (view >= 0) return fail(GLINT_EINVAL, "view %d: %s", view, what);
     return fail(GLINT_EINVAL, "%s", what);
@@ -294,11 +296,16 @@ int glint_shade(glint_ctx ctx, const glint_gbuffer *g, int64_t P, const glint_en
     const bool constant = sp->prob_mode == GLINT_PROBS_CONSTANT;
     if (sp->sampler != GLINT_SAMPLER_DUAL && env->dtype != GLINT_F32 && !constant)
         return fail(GLINT_EUNSUPPORTED, "single-gated samplers need a float32 pyramid");
+    if (sp->lobe_taps > 0 && (env->dtype != GLINT_F32 || sp->sampler != GLINT_SAMPLER_DUAL || constant))
+        return fail(GLINT_EUNSUPPORTED, "anisotropic lookups need a float32 pyramid, the dual gate and the map's "
+                    "probabilities");
     if (P == 0) return ok();
     if (!radiance || !env->rgb_pyr || !env->lut_E ||
         (!constant && (!env->ind_pyr || !env->levels || !env->lut_S)))
         return fail(GLINT_EINVAL, "null pointer argument");
     if (int rc = check_gbuffer(g)) return rc;
+    if (sp->lobe_taps > 0 && (!g->tx || !g->ty || !g->tz))
+        return fail(GLINT_EINVAL, "anisotropic lookups need the G-buffer tangent");
     if (reinterpret_cast<uintptr_t>(env->rgb_pyr) % 16) return fail(GLINT_EINVAL, "rgb_pyr must be 16-byte aligned");
     if (P > ((int64_t)1 << 40)) return fail(GLINT_EINVAL, "num_pixels too large");
     return device_status(glint::launch_shade(*g, P, *env, *sp, nullptr, radiance, dbg, (hipStream_t)stream),
@@ -431,8 +438,8 @@ int glint_shade_surrogate(glint_ctx ctx, const glint_gbuffer *g, int64_t P, cons
     if (int rc = check_mips(env->R, env->num_mips)) return rc;
     if (int rc = check_surrogate(env->K, w, w_bf16)) return rc;
     if (int rc = check_shade_params(*sp, -1)) return rc;
-    if (sp->prob_mode != GLINT_PROBS_ENV)
-        return fail(GLINT_EUNSUPPORTED, "the surrogate form computes the map's probabilities");
+    if (sp->prob_mode != GLINT_PROBS_ENV || sp->lobe_taps != 0)
+        return fail(GLINT_EUNSUPPORTED, "the surrogate form computes the map's probabilities with one lookup");
     if (P == 0) return ok();
     if (!radiance || !workspace || !env->rgb_pyr || !env->levels || !env->lut_S || !env->lut_E)
         return fail(GLINT_EINVAL, "null pointer argument");
@@ -483,9 +490,9 @@ int glint_frame_batched(glint_ctx ctx, const glint_env_task *envs, int n_env, co
         if (w.num_pixels < 0 || w.num_pixels > ((int64_t)1 << 40))
             return fail(GLINT_EINVAL, "view %d: bad num_pixels", v);
         if (int rc = check_shade_params(w.shade, v)) return rc;
-        if (w.shade.sampler != GLINT_SAMPLER_DUAL || w.shade.prob_mode != GLINT_PROBS_ENV)
+        if (w.shade.sampler != GLINT_SAMPLER_DUAL || w.shade.prob_mode != GLINT_PROBS_ENV || w.shade.lobe_taps != 0)
             return fail(GLINT_EUNSUPPORTED, "view %d: batched frames use the dual-gated sampler and the map's "
-                        "probabilities", v);
+                        "probabilities with one lookup", v);
         if (!w.radiance) return fail(GLINT_EINVAL, "view %d: null radiance", v);
         if (envs[w.env_index].surrogate_w &&
             (!w.surrogate_F || reinterpret_cast<uintptr_t>(w.surrogate_F) % 16))

@@ -17,6 +17,17 @@ struct d3 {
     double x, y, z;
 };
 
+// Orthonormal frame (t1, t2) around the unit vector r (branchless form of
+// Duff et al. 2017).
+__device__ __forceinline__ void onb(const d3 &r, d3 &t1, d3 &t2)
+{
+    const double sgn = copysign(1.0, r.z);
+    const double ea = -1.0 / (sgn + r.z);
+    const double eb = r.x * r.y * ea;
+    t1 = {1.0 + sgn * r.x * r.x * ea, sgn * eb, -sgn * r.x};
+    t2 = {eb, sgn + r.y * r.y * ea, -r.y};
+}
+
 // Direction of face coordinates (s, t) in [-1,1]^2 (unnormalised).
 __device__ __forceinline__ d3 face_dir(int face, double s, double t)
 {

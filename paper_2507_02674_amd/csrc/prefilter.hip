@@ -471,14 +471,6 @@ __device__ __forceinline__ void make_tap(int j, int m, int M, int T, int R, Tap 
 }
 
 // Orthonormal basis around the unit direction r (Duff et al. 2017).
-__device__ __forceinline__ void onb(const d3 &r, d3 &t1, d3 &t2)
-{
-    const double sgn = copysign(1.0, r.z);
-    const double ea = -1.0 / (sgn + r.z);
-    const double eb = r.x * r.y * ea;
-    t1 = {1.0 + sgn * r.x * r.x * ea, sgn * eb, -sgn * r.x};
-    t2 = {eb, sgn + r.y * r.y * ea, -r.y};
-}
 
 // acc += W_j * (trilinear chain lookup at the tap's mirror direction, lod_j).
 template <int K>

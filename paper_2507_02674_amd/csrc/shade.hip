@@ -132,7 +132,51 @@ struct ShadeArgs {
     int exact_gating;    // 1: gating thresholds always through powf (verification)
     int sampler;         // GLINT_SAMPLER_*: node sampler of the multinomial tree
     double gamma;        // constant reflection probability (prob_mode GLINT_PROBS_CONSTANT)
+    int lobe_taps;       // anisotropic lookup taps (2, 4, 8; 0: isotropic lookup)
 };
+
+// acc += w * trilinear lookup of the pyramid (KL indicator channels, then
+// RGB) in direction dir at lod (clamped to [0, M-1]).
+template <int KL, int DT>
+__device__ __forceinline__ void pyramid_trilinear(const ShadeArgs &A, const d3 &dir, double lod, double w,
+                                                  double (&acc)[KL + 3])
+{
+    lod = lod < 0.0 ? 0.0 : (lod > (double)(A.M - 1) ? (double)(A.M - 1) : lod);
+    const double l0f = floor(lod);
+    const int s0 = (int)l0f;
+    const int s1 = s0 + 1 < A.M ? s0 + 1 : A.M - 1;
+    const double fr = lod - l0f;
+    const face_st fs = locate(dir);
+    const int nlev = fr > 0.0 ? 2 : 1;
+#pragma unroll 1
+    for (int li = 0; li < nlev; ++li) {
+        const int s = li == 0 ? s0 : s1;
+        const double lw = w * (li == 0 ? 1.0 - fr : fr);
+        const int ns = A.R >> s;
+        const bilin bl = bilinear_at(fs, ns);
+        const int64_t base = level_offset(A.R, s);
+        const double w4[4] = {lw * ((1.0 - bl.fy) * (1.0 - bl.fx)), lw * ((1.0 - bl.fy) * bl.fx),
+                              lw * (bl.fy * (1.0 - bl.fx)), lw * (bl.fy * bl.fx)};
+        if (bl.x0 >= 0 && bl.x0 + 1 < ns && bl.y0 >= 0 && bl.y0 + 1 < ns) {
+            // footprint inside the face: four loads in flight
+            const int64_t t0 = base + ((int64_t)fs.face * ns + bl.y0) * ns + bl.x0;
+            const int64_t tt[4] = {t0, t0 + 1, t0 + ns, t0 + ns + 1};
+            double v[4][KL + 3];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) load_texel<KL, DT>(A.ind_pyr, A.rgb_pyr, tt[c], v[c]);
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+#pragma unroll
+                for (int k = 0; k < KL + 3; ++k) acc[k] += w4[c] * v[c][k];
+        } else {
+            // across a seam: one copy of the seam rule
+#pragma unroll 1
+            for (int c = 0; c < 4; ++c)
+                accumulate_pyr<KL, DT>(A.ind_pyr, A.rgb_pyr, base, fs.face, bl.x0 + (c & 1), bl.y0 + (c >> 1), ns,
+                                       c == 0 ? w4[0] : (c == 1 ? w4[1] : (c == 2 ? w4[2] : w4[3])), acc);
+        }
+    }
+}
 
 // One dual-gated Gaussian draw (Alg. "Dual-gated Gaussian").
 // xi2 = (h9 + 1/2) 2^-23; qtail: the quantile's tail table (or null: the
@@ -295,7 +339,7 @@ __device__ __forceinline__ void multinomial(double NP, const double (&p)[K], uin
 // K filtered indicator values come from A.F (a learned surrogate's output)
 // and only RGB is read from the pyramid.  PC: constant reflection
 // probability A.gamma (K = 2, levels (0, 1)), no indicator lookup.
-template <int K, int DT, int V, bool SURR = false, bool SG = false, bool PC = false>
+template <int K, int DT, int V, bool SURR = false, bool SG = false, bool PC = false, bool AN = false>
 __device__ __forceinline__ void shade_pixel(const ShadeArgs &A, int64_t i)
 {
     static_assert(!PC || (K == 2 && !SURR), "constant probabilities use two bins");
@@ -316,46 +360,53 @@ __device__ __forceinline__ void shade_pixel(const ShadeArgs &A, int64_t i)
     const d3 wr = {2.0 * mu * n.x - v.x, 2.0 * mu * n.y - v.y, 2.0 * mu * n.z - v.z};
     const double aeff = sqrt((double)A.g.ax[i] * (double)A.g.ay[i]);
     const double sa = sqrt(aeff);
-    double lod = sa * (double)(A.M - 1);
-    lod = lod < 0.0 ? 0.0 : (lod > (double)(A.M - 1) ? (double)(A.M - 1) : lod);
-
     // trilinear pyramid lookup of the K indicator channels and RGB
-    const double l0f = floor(lod);
-    const int s0 = (int)l0f;
-    const int s1 = s0 + 1 < A.M ? s0 + 1 : A.M - 1;
-    const double fr = lod - l0f;
     double acc[KL + 3];
 #pragma unroll
     for (int k = 0; k < KL + 3; ++k) acc[k] = 0.0;
-    const face_st fs = locate(wr);
-    const int nlev = fr > 0.0 ? 2 : 1;
-#pragma unroll 1
-    for (int li = 0; li < nlev; ++li) {
-        const int s = li == 0 ? s0 : s1;
-        const double lw = li == 0 ? 1.0 - fr : fr;
-        const int ns = A.R >> s;
-        const bilin bl = bilinear_at(fs, ns);
-        const int64_t base = level_offset(A.R, s);
-        const double w4[4] = {lw * ((1.0 - bl.fy) * (1.0 - bl.fx)), lw * ((1.0 - bl.fy) * bl.fx),
-                              lw * (bl.fy * (1.0 - bl.fx)), lw * (bl.fy * bl.fx)};
-        if (bl.x0 >= 0 && bl.x0 + 1 < ns && bl.y0 >= 0 && bl.y0 + 1 < ns) {
-            // footprint inside the face: four loads in flight
-            const int64_t t0 = base + ((int64_t)fs.face * ns + bl.y0) * ns + bl.x0;
-            const int64_t tt[4] = {t0, t0 + 1, t0 + ns, t0 + ns + 1};
-            double v[4][KL + 3];
-#pragma unroll
-            for (int c = 0; c < 4; ++c) load_texel<KL, DT>(A.ind_pyr, A.rgb_pyr, tt[c], v[c]);
-#pragma unroll
-            for (int c = 0; c < 4; ++c)
-#pragma unroll
-                for (int k = 0; k < KL + 3; ++k) acc[k] += w4[c] * v[c][k];
+    if constexpr (AN) {
+        // anisotropic lookup: lobe_taps isotropic lookups along the lobe's
+        // major axis (layout in the header), averaged
+        const int T = A.lobe_taps;
+        const double ax = (double)A.g.ax[i], ay = (double)A.g.ay[i];
+        d3 t = {(double)A.g.tx[i], (double)A.g.ty[i], (double)A.g.tz[i]};
+        const double tn = t.x * n.x + t.y * n.y + t.z * n.z;
+        t = {t.x - tn * n.x, t.y - tn * n.y, t.z - tn * n.z};
+        const double tl = sqrt(t.x * t.x + t.y * t.y + t.z * t.z);
+        if (tl > 1e-12) {
+            t = {t.x / tl, t.y / tl, t.z / tl};
         } else {
-            // across a seam: one copy of the seam rule
-#pragma unroll 1
-            for (int c = 0; c < 4; ++c)
-                accumulate_pyr<KL, DT>(A.ind_pyr, A.rgb_pyr, base, fs.face, bl.x0 + (c & 1), bl.y0 + (c >> 1), ns,
-                                       c == 0 ? w4[0] : (c == 1 ? w4[1] : (c == 2 ? w4[2] : w4[3])), acc);
+            d3 b2;
+            onb(n, t, b2);
         }
+        const d3 bt = {n.y * t.z - n.z * t.y, n.z * t.x - n.x * t.z, n.x * t.y - n.y * t.x};
+        const double amin = ax < ay ? ax : ay, amax = ax < ay ? ay : ax;
+        const d3 d = ax >= ay ? t : bt;
+        double at = amax / (double)T;
+        at = at < amin ? amin : at;
+        const double s2 = amax * amax - at * at;
+        const double sp = s2 > 0.0 ? sqrt(s2) : 0.0;
+        const double lodt = sqrt(at) * (double)(A.M - 1);
+        double wsum = 0.0;
+#pragma unroll 1
+        for (int j = 0; j < T; ++j) {
+            const double u = (double)(2 * j + 1) / (double)T - 1.0;
+            const double x = sp * u / sqrt(1.0 - u * u);
+            const double hl = sqrt(1.0 + x * x); // |n - x d| for orthonormal n, d
+            const d3 h = {(n.x - x * d.x) / hl, (n.y - x * d.y) / hl, (n.z - x * d.z) / hl};
+            const double vh = v.x * h.x + v.y * h.y + v.z * h.z;
+            const d3 w = {2.0 * vh * h.x - v.x, 2.0 * vh * h.y - v.y, 2.0 * vh * h.z - v.z};
+            double cw = w.x * n.x + w.y * n.y + w.z * n.z;
+            cw = cw > 0.0 ? cw : 0.0;
+            if (cw > 0.0) pyramid_trilinear<KL, DT>(A, w, lodt, cw, acc);
+            wsum += cw;
+        }
+        if (wsum > 0.0) { // else every tap is below the horizon: nothing reflected
+#pragma unroll
+            for (int k = 0; k < KL + 3; ++k) acc[k] /= wsum;
+        }
+    } else {
+        pyramid_trilinear<KL, DT>(A, wr, sa * (double)(A.M - 1), 1.0, acc);
     }
     const double rgb[3] = {acc[KL], acc[KL + 1], acc[KL + 2]};
     const double EA = lut_bilinear(A.lut_E, 2, 0, mu, sa);
@@ -470,12 +521,12 @@ __device__ __forceinline__ void shade_pixel(const ShadeArgs &A, int64_t i)
     for (int c = 0; c < 3; ++c) A.radiance[3 * i + c] = (float)((f0[c] * EA + EB) * rgb[c] * gmod);
 }
 
-template <int K, int DT, int V, bool SURR = false, bool SG = false, bool PC = false>
+template <int K, int DT, int V, bool SURR = false, bool SG = false, bool PC = false, bool AN = false>
 __global__ void __launch_bounds__(kShadeThreads) k_shade(ShadeArgs A)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= A.P) return;
-    shade_pixel<K, DT, V, SURR, SG, PC>(A, i);
+    shade_pixel<K, DT, V, SURR, SG, PC, AN>(A, i);
 }
 
 // All views of one (K, V) group in one launch: block b shades tile b of the
@@ -503,6 +554,19 @@ template <int K, int DT>
 static hipError_t launch_shade_kd(const ShadeArgs &a, int V, hipStream_t stream)
 {
     const unsigned blocks = (unsigned)((a.P + kShadeThreads - 1) / kShadeThreads);
+    if (a.lobe_taps > 0) {
+        // anisotropic lookups: float32 pyramid, dual gate (the API checks)
+        if constexpr (DT == 0) {
+            if (V == 1)
+                GLINT_LAUNCH("k_shade", (k_shade<K, 0, 1, false, false, false, true>), dim3(blocks),
+                             dim3(kShadeThreads), 0, stream, a);
+            else
+                GLINT_LAUNCH("k_shade", (k_shade<K, 0, 6, false, false, false, true>), dim3(blocks),
+                             dim3(kShadeThreads), 0, stream, a);
+            return hipGetLastError();
+        }
+        return hipErrorInvalidValue;
+    }
     if (a.sampler != GLINT_SAMPLER_DUAL) {
         // single-gated forms: float32 pyramids only (the API checks)
         if constexpr (DT == 0) {
@@ -545,6 +609,7 @@ void make_shade_args(void *out, const glint_gbuffer &g, int64_t P, const glint_e
     a.exact_gating = sp.exact_gating;
     a.sampler = sp.sampler;
     a.gamma = (double)sp.gamma;
+    a.lobe_taps = sp.lobe_taps;
     *static_cast<ShadeArgs *>(out) = a;
 }
 
@@ -605,6 +670,7 @@ hipError_t launch_shade(const glint_gbuffer &g, int64_t P, const glint_env &env,
     a.exact_gating = sp.exact_gating;
     a.sampler = sp.sampler;
     a.gamma = (double)sp.gamma;
+    a.lobe_taps = sp.lobe_taps;
     const int K = env.K, DT = (int)env.dtype, V = sp.vertices;
     if (sp.prob_mode == GLINT_PROBS_CONSTANT) {
         // two bins, indicator pyramid not read

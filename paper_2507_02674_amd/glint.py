@@ -21,6 +21,7 @@ LUT_N = 64
 
 GBUF_FIELDS = ("nx", "ny", "nz", "vx", "vy", "vz", "u", "v", "area", "ax", "ay", "density",
                "f0r", "f0g", "f0b", "surf_id")
+GBUF_OPTIONAL = ("visibility", "tx", "ty", "tz")  # float32, may be absent
 
 
 class GlintError(RuntimeError):
@@ -38,7 +39,7 @@ class PrefilterParams(C.Structure):
 
 
 class GBuffer(C.Structure):
-    _fields_ = [(k, C.c_void_p) for k in GBUF_FIELDS] + [("visibility", C.c_void_p)]
+    _fields_ = [(k, C.c_void_p) for k in GBUF_FIELDS] + [(k, C.c_void_p) for k in GBUF_OPTIONAL]
 
 
 class Env(C.Structure):
@@ -49,7 +50,7 @@ class Env(C.Structure):
 
 class ShadeParams(C.Structure):
     _fields_ = [("seed", C.c_uint32), ("vertices", C.c_int), ("exact_gating", C.c_int), ("sampler", C.c_int),
-                ("prob_mode", C.c_int), ("gamma", C.c_float)]
+                ("prob_mode", C.c_int), ("gamma", C.c_float), ("lobe_taps", C.c_int)]
 
 
 class ShadeDebug(C.Structure):
@@ -241,11 +242,11 @@ def glint_sample_binomial(ctx, sampler, N, p, h1, h2, n, nbar, code, quantile_ta
 
 
 def make_gbuffer(fields: dict) -> GBuffer:
-    """Maps a dict of device tensors (one per G-buffer field, plus an optional
-    float32 "visibility") to the C struct."""
+    """Maps a dict of device tensors (one per G-buffer field, plus the optional
+    float32 fields of GBUF_OPTIONAL) to the C struct."""
     _require_cuda(*fields.values())
-    vis = fields.get("visibility")
-    g = GBuffer(*[fields[k].data_ptr() for k in GBUF_FIELDS], vis.data_ptr() if vis is not None else None)
+    opt = [fields.get(k) for k in GBUF_OPTIONAL]
+    g = GBuffer(*[fields[k].data_ptr() for k in GBUF_FIELDS], *[t.data_ptr() if t is not None else None for t in opt])
     g._keep = dict(fields)  # the struct holds raw pointers: keep the tensors alive with it
     return g
 

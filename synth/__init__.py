@@ -226,6 +226,26 @@ def contact_visibility(g: dict) -> np.ndarray:
     return vis
 
 
+def surface_tangents(g: dict):
+    """Tangent of the alpha_x axis for the sphere-and-plane scene (float32
+    tx, ty, tz): on the sphere the direction of increasing longitude u
+    (normalised (n_z, 0, -n_x), (1, 0, 0) at the poles), on the plane +x
+    (the u axis); (1, 0, 0) elsewhere."""
+    P = len(g["nx"])
+    t = np.zeros((P, 3))
+    t[:, 0] = 1.0
+    sphere = g["surf_id"] == 1
+    nx, nz = g["nx"][sphere].astype(np.float64), g["nz"][sphere].astype(np.float64)
+    ln = np.hypot(nx, nz)
+    ok = ln > 1e-9
+    ts = np.zeros((sphere.sum(), 3))
+    ts[:, 0] = 1.0
+    ts[ok, 0] = nz[ok] / ln[ok]
+    ts[ok, 2] = -nx[ok] / ln[ok]
+    t[sphere] = ts
+    return t[:, 0].astype(np.float32), t[:, 1].astype(np.float32), t[:, 2].astype(np.float32)
+
+
 def n_sweep(W: int = 512, rows: int = 64, max_decades: float = 12.0, seed: int = 5) -> dict:
     """Counts sweep: row r has N_P = 10^(max_decades r / (rows-1)) (1 .. 1e12,
     the range where float counts lose integers); along a row the normal tilts

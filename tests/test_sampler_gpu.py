@@ -255,3 +255,45 @@ def test_prob_mode_arguments_rejected(ctx):
         with pytest.raises(G.GlintError) as e:
             G.glint_shade(ctx, G.make_gbuffer(fields), len(g["nx"]), envs, G.ShadeParams(1, 1, 0, 0, pm, gamma), rad)
         assert e.value.code == G.GLINT_EINVAL
+
+
+# --- anisotropic lookup --------------------------------------------------------------
+
+@pytest.mark.parametrize("taps", [2, 4, 8])
+@pytest.mark.parametrize("vertices", [1, 6])
+def test_shade_anisotropic_lookup_matches_oracle(ctx, qtail, taps, vertices):
+    """Several pyramid lookups along the lobe's major axis (tangent from the
+    scene), every pixel against the oracle."""
+    R, K, M = 16, 8, 5
+    U.log(f"shade anisotropic taps={taps} V={vertices}")
+    env = synth.make_env(R, 6)
+    levels, ind, rgb = oracle_env(env, K, M)
+    S, E = oracle.lut_tables()
+    g = synth.scene_frame(96, 54, seed=5, density_decades=(1.0, 8.0))
+    g["tx"], g["ty"], g["tz"] = synth.surface_tangents(g)
+    gpu = U.shade(ctx, g, ind, rgb, levels, S, E, R, K, M, seed=7, vertices=vertices, qtail=qtail, lobe_taps=taps)
+    orc = oracle.shade(g, ind, rgb, levels, S, E, R, K, M, 7, vertices, lobe_taps=taps)
+    check_pixels(gpu, orc, f"anisotropic taps={taps} V={vertices}")
+
+
+def test_anisotropic_lookup_arguments_rejected(ctx):
+    import torch
+    R, K, M = 16, 4, 5
+    env = synth.make_env(R, 2)
+    levels, ind, rgb = oracle_env(env, K, M)
+    S, E = oracle.lut_tables()
+    g = synth.scene_frame(32, 18, seed=1)
+    fields = U.gbuf_to_device(g)  # no tangent
+    envs = G.make_env(U.dev(ind), U.dev(rgb), U.dev(levels), U.dev(S), U.dev(E), R, K, M, G.GLINT_F32)
+    rad = torch.empty((len(g["nx"]), 3), dtype=torch.float32, device="cuda")
+    for taps, code in ((3, G.GLINT_EINVAL), (16, G.GLINT_EINVAL), (4, G.GLINT_EINVAL)):
+        with pytest.raises(G.GlintError) as e:
+            G.glint_shade(ctx, G.make_gbuffer(fields), len(g["nx"]), envs, G.ShadeParams(1, 1, 0, 0, 0, 1.0, taps),
+                          rad)
+        assert e.value.code == code
+    g["tx"], g["ty"], g["tz"] = synth.surface_tangents(g)
+    fields = U.gbuf_to_device(g)
+    with pytest.raises(G.GlintError) as e:
+        G.glint_shade(ctx, G.make_gbuffer(fields), len(g["nx"]), envs,
+                      G.ShadeParams(1, 1, 0, G.GLINT_SAMPLER_SINGLE, 0, 1.0, 4), rad)
+    assert e.value.code == G.GLINT_EUNSUPPORTED
