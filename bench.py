@@ -168,7 +168,8 @@ def parse():
     ap.add_argument("--workload", default="frame")
     ap.add_argument("--form", default="plain", choices=["plain", "surrogate"])
     ap.add_argument("--dtype", default="f32", choices=["f32", "f16", "bf16", "unorm16"])
-    ap.add_argument("--vertices", type=int, default=1)
+    ap.add_argument("--vertices", type=int, default=1, choices=[1, 6, 12],
+                    help="lattice vertices per pixel: 1, 6 (uv triangle x 2 scales) or 12 (footprint grid)")
     ap.add_argument("--sampler", default="dual", choices=list(SAMPLERS),
                     help="binomial approximation at every tree node (dual-gated is the paper's method)")
     ap.add_argument("--probs", default="env", choices=["env", "constant"],
@@ -387,6 +388,8 @@ def main():
         gbuf_np["visibility"] = synth.contact_visibility(gbuf_np)
     if a.lobe_taps:
         gbuf_np["tx"], gbuf_np["ty"], gbuf_np["tz"] = synth.surface_tangents(gbuf_np)
+    if a.vertices == 12:
+        gbuf_np["dudx"], gbuf_np["dudy"], gbuf_np["dvdx"], gbuf_np["dvdy"] = synth.uv_jacobian(gbuf_np, w.W, w.H)
     prob_mode = G.GLINT_PROBS_CONSTANT if a.probs == "constant" else G.GLINT_PROBS_ENV
     default_path = a.sampler == "dual" and a.probs == "env" and a.visibility == "none" and a.lobe_taps == 0
     glint_pixels = int((gbuf_np["surf_id"] != 0xFFFFFFFF).sum())

@@ -311,6 +311,21 @@ int glint_sample_binomial(glint_ctx ctx, int sampler, int exact_gating, const do
  * triangle containing the point at levels l0 and l0+1, barycentric weights
  * times (1-f, f), f = log2(area)/2 - l0.  Each vertex draws with N_i = N_P;
  * the counts are blended with the weights.
+ * vertices = 12, the footprint grid (Sec. 3.3 describes the footprint by
+ * length, anisotropy and orientation and distributes its facets over a
+ * tetrahedral cell of that space; the layout is this library's): with
+ * J = [[du/dx, du/dy], [dv/dx, dv/dy]], s_maj = sqrt(largest eigenvalue of
+ * J J^T), s_min = max(|det J| / s_maj, s_maj / 16), theta in [0, pi) the
+ * major axis; grid coordinates (log2 s_maj, log2(s_maj/s_min), 8 theta/pi)
+ * (orientation periodic, 8 cells); the Kuhn tetrahedron (axes by
+ * decreasing fraction, ties in axis order) gives 4 vertices (l, a, o) with
+ * weights (1-f1, f1-f2, f2-f3, f3); vertex (l, a, o) draws
+ * N_i = N_P (4^l / 2^a) / (s_maj s_min) facets at the 3 vertices of the uv
+ * triangle grid of its footprint (uv rotated by -o pi/8, scaled by
+ * (2^-l, 2^(a-l)), squares split along the diagonal, barycentric weights),
+ * hash key (lattice x, lattice y, l << 24 | a << 20 | o << 16 | node/2);
+ * the radiance is normalised by sum_i w_i N_i instead of N_P.  A zero
+ * Jacobian draws nothing (radiance 0).
  * Radiance = L_o * sum_k L_k M_k / (N_P sum_k L_k p_k) (0 if either sum is 0).
  * Occlusion (Sec. 8 "Limitations & Future Work": attenuate the
  * probabilities, not the output): with gbuf->visibility, the tree samples
@@ -349,6 +364,8 @@ typedef struct glint_gbuffer {
                                   glint_shade */
     const float *tx, *ty, *tz; /* optional surface tangent, the axis of alpha_x (needed only for
                                   anisotropic lookups, glint_shade_params.lobe_taps > 0) */
+    const float *dudx, *dudy, *dvdx, *dvdy; /* optional uv Jacobian of the pixel footprint (needed
+                                  only for the footprint grid, vertices = 12) */
 } glint_gbuffer;
 
 typedef struct glint_env {
@@ -365,7 +382,8 @@ typedef struct glint_env {
 
 typedef struct glint_shade_params {
     uint32_t seed;    /* material seed mixed into the hash */
-    int vertices;     /* 1 or 6 */
+    int vertices;     /* 1, 6 or 12 (the footprint grid; float32 pyramid, dual gate, map
+                         probabilities, one lookup; needs the G-buffer uv Jacobian) */
     int exact_gating; /* 0: gating decisions from hardware log2/exp2 powers, re-evaluated with powf
                          only within a safety margin of a threshold (same decisions); 1: always
                          powf (for verification) */

@@ -69,6 +69,8 @@ def _declare(L):
                                            C.c_int, C.c_uint32, C.c_int, C.c_int, i64p, C.c_int64, f64p, f64p,
                                            u8p, f64p, u8p, C.c_int]
     u32p = C.POINTER(C.c_uint32)
+    L.orc_footprint_grid.argtypes = [C.c_double] * 6 + [f64p, f64p, u32p, i64p, i64p]
+    L.orc_footprint_grid.restype = C.c_int
     L.orc_sample_binomial.argtypes = [C.c_int, f64p, f64p, u32p, u32p, C.c_int64, f64p, f64p, u8p, u8p, C.c_int]
     L.orc_gate_probs.argtypes = [C.c_float, C.c_float, f32p]
     L.orc_dual_gated.argtypes = [C.c_double, C.c_double, C.c_float, C.c_float, f64p, f64p, u8p]
@@ -194,6 +196,8 @@ def shade(gbuf: dict, ind_pyr, rgb_pyr, levels, lut_S, lut_E, R: int, K: int, M:
     reflection probabilities.
     lobe_taps in {2, 4, 8}: anisotropic lookup along the lobe's major axis
     (gbuf must carry the tangent "tx", "ty", "tz").
+    vertices 12: the footprint grid (gbuf must carry the uv Jacobian
+    "dudx", "dudy", "dvdx", "dvdy").
 
     gbuf: dict of flat float32 arrays (surf_id uint32).  ind_pyr [texels,K]
     float32 and rgb_pyr [texels,4] float32 are the stored pyramids.  With F
@@ -209,12 +213,12 @@ def shade(gbuf: dict, ind_pyr, rgb_pyr, levels, lut_S, lut_E, R: int, K: int, M:
         pixels = np.arange(P, dtype=np.int64)
     pixels = np.ascontiguousarray(pixels, dtype=np.int64)
     n = len(pixels)
-    extra = [gbuf.get(k) for k in ("visibility", "tx", "ty", "tz")]
+    extra = [gbuf.get(k) for k in ("visibility", "tx", "ty", "tz", "dudx", "dudy", "dvdx", "dvdy")]
     extra = [None if a is None else np.ascontiguousarray(a, dtype=np.float32) for a in extra]
     keep = fields + [a for a in extra if a is not None]
     ptrs = [f.ctypes.data_as(C.POINTER(C.c_float)) for f in fields] + \
         [a.ctypes.data_as(C.POINTER(C.c_float)) if a is not None else C.POINTER(C.c_float)() for a in extra]
-    arr = (C.POINTER(C.c_float) * 20)(*ptrs)
+    arr = (C.POINTER(C.c_float) * 24)(*ptrs)
     if prob_mode == 1:
         K = 2
     gamma = float(np.float32(gamma))  # a float parameter, as in the C interface
@@ -306,6 +310,19 @@ def sample_binomial(sampler: int, N, p, h1, h2, threads=None):
     if rc:
         raise ValueError("orc_sample_binomial rejected its arguments")
     return out
+
+
+def footprint_grid(u, v, dudx, dudy, dvdx, dvdy):
+    """The footprint grid's 12 draws of one pixel: dict(w, r, key, a, b,
+    flag), or None for a degenerate Jacobian."""
+    w, r = np.zeros(12), np.zeros(12)
+    key = np.zeros(12, np.uint32)
+    a, b = np.zeros(12, np.int64), np.zeros(12, np.int64)
+    rc = lib().orc_footprint_grid(u, v, dudx, dudy, dvdx, dvdy, _p(w, C.c_double), _p(r, C.c_double),
+                                  _p(key, C.c_uint32), _p(a, C.c_int64), _p(b, C.c_int64))
+    if rc < 0:
+        return None
+    return dict(w=w, r=r, key=key, a=a, b=b, flag=rc)
 
 
 def face_dir(face, s, t):

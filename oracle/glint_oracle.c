@@ -587,18 +587,26 @@ static void pcg4d(uint32_t v[4])
 static float to_unit(uint32_t h) { return ((float)(h >> 9) + 0.5f) * 1.1920928955078125e-07f; }
 
 /* One hash serves two tree nodes: nodes 2i and 2i+1 of a lattice vertex
- * take (x, y) and (z, w) of pcg4d(a, b, level << 16 | i, seed ^ surf * phi). */
-void orc_hash_xi(uint32_t seed, uint32_t surf, int32_t level, int64_t a, int64_t b, int node, float *xi1,
-                 float *xi2)
+ * take (x, y) and (z, w) of pcg4d(a, b, key | i, seed ^ surf * phi); the
+ * key names the lattice (its upper 16 bits: level << 16 for the lattices of
+ * vertices 1 and 6, the footprint cell vertex for the full grid). */
+static void hash_xi_key(uint32_t seed, uint32_t surf, uint32_t key, int64_t a, int64_t b, int node, float *xi1,
+                        float *xi2)
 {
     uint32_t v[4];
     v[0] = (uint32_t)a;
     v[1] = (uint32_t)b;
-    v[2] = (((uint32_t)level & 0xFFFFu) << 16) | (((uint32_t)node >> 1) & 0xFFFFu);
+    v[2] = key | (((uint32_t)node >> 1) & 0xFFFFu);
     v[3] = seed ^ (surf * 0x9E3779B9u);
     pcg4d(v);
     *xi1 = to_unit(v[(node & 1) ? 2 : 0]);
     *xi2 = to_unit(v[(node & 1) ? 3 : 1]);
+}
+
+void orc_hash_xi(uint32_t seed, uint32_t surf, int32_t level, int64_t a, int64_t b, int node, float *xi1,
+                 float *xi2)
+{
+    hash_xi_key(seed, surf, ((uint32_t)level & 0xFFFFu) << 16, a, b, node, xi1, xi2);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -769,8 +777,8 @@ static int near_int_flag(double v)
  * tree over the K bins, nodes numbered breadth first (heap order); node i
  * splits [lo,hi) at the midpoint; the left child receives the positive count
  * n, the right child the negative count nb.  p_node = S_left / S_node. */
-static int multinomial(int sampler, double NP, const double *p, int K, uint32_t seed, uint32_t surf, int32_t level,
-                       int64_t a, int64_t b, double *M, uint8_t *codes)
+static int multinomial(int sampler, double NP, int root_exact, const double *p, int K, uint32_t seed, uint32_t surf,
+                       uint32_t key, int64_t a, int64_t b, double *M, uint8_t *codes)
 {
     int nodes = K - 1;
     double Nn[32];
@@ -778,7 +786,7 @@ static int multinomial(int sampler, double NP, const double *p, int K, uint32_t 
     int flag = 0;
     /* exact[i]: node i's count is formed by exact operations on exact values
      * (the root product, then gating outcomes without a Gaussian draw). */
-    Nn[0] = NP; lo_[0] = 0; hi_[0] = K; exact[0] = 1;
+    Nn[0] = NP; lo_[0] = 0; hi_[0] = K; exact[0] = root_exact;
     for (int i = 0; i < nodes; ++i) {
         int lo = lo_[i], hi = hi_[i], mid = lo + (hi - lo) / 2;
         double sl = 0.0, sr = 0.0;
@@ -788,7 +796,7 @@ static int multinomial(int sampler, double NP, const double *p, int K, uint32_t 
         double pn = st > 0.0 ? sl / st : 0.0;
         if (pn > 1.0) pn = 1.0;
         float xi1, xi2;
-        orc_hash_xi(seed, surf, level, a, b, i, &xi1, &xi2);
+        hash_xi_key(seed, surf, key, a, b, i, &xi1, &xi2);
         node_out o;
         sample_node(sampler, Nn[i], pn, xi1, xi2, exact[i], &o);
         codes[i] = o.code;
@@ -878,7 +886,115 @@ typedef struct {
     const uint32_t *surf;
     const float *vis; /* optional visibility in [0, 1] (NULL: unoccluded) */
     const float *tx, *ty, *tz; /* optional tangent (the alpha_x axis) */
+    const float *dudx, *dudy, *dvdx, *dvdy; /* optional uv Jacobian of the pixel (footprint grid) */
 } gbuf_t;
+
+/* ------------------------------------------------------------------------ */
+/* Footprint grid (Sec. 3.3, "Binomial Sampling with Anisotropic Grids"):    */
+/* the pixel footprint is described by its length, anisotropy and            */
+/* orientation; its microfacets are distributed over the vertices of the     */
+/* tetrahedral cell around it in that space, and at each such vertex a       */
+/* triangle grid in uv interpolates the outcomes drawn at its vertices.      */
+/* The layout is this library's (the paper treats the grid as a black box):  */
+/*  - footprint: ellipse of J J^T, J = [[du/dx, du/dy], [dv/dx, dv/dy]]:      */
+/*    length s_maj = sqrt(largest eigenvalue), s_min = |det J| / s_maj,       */
+/*    clamped to s_maj / 16, anisotropy A = s_maj / s_min in [1, 16],         */
+/*    orientation theta of the major axis in [0, pi);                         */
+/*  - grid coordinates g = (log2 s_maj, log2 A, 8 theta / pi), orientation    */
+/*    periodic with 8 cells; Kuhn cell: axes sorted by decreasing fraction    */
+/*    (ties in axis order), weights (1 - f1, f1 - f2, f2 - f3, f3);            */
+/*  - vertex (l, a, o): footprint of length 2^l, anisotropy 2^a, orientation */
+/*    o pi / 8; its count is N_P times the ratio of its uv area 4^l / 2^a to  */
+/*    the pixel's s_maj s_min;                                                */
+/*  - uv triangle grid of that vertex: uv rotated by -theta_o and scaled by   */
+/*    (2^-l, 2^(a-l)) (one cell per footprint), unit squares split along the  */
+/*    diagonal, barycentric weights;                                          */
+/*  - random numbers keyed by (lattice x, lattice y, l, a, o).                */
+/* 12 draws per pixel; the output is normalised by the weighted count         */
+/* sum_i w_i N_i.  flag: a cell, triangle or ordering decision within 1e-9    */
+/* of its boundary (implementations may decide differently there).           */
+/* ------------------------------------------------------------------------ */
+#define FG_ORIENT 8
+#define FG_AMAX 16.0
+
+typedef struct {
+    int valid, flag;
+    double w[12], r[12];
+    uint32_t key[12];
+    int64_t a[12], b[12];
+} fgrid_t;
+
+static int near_int_1e9(double x)
+{
+    return fabs(x - floor(x + 0.5)) < 1e-9 * (1.0 + fabs(x));
+}
+
+static void footprint_grid(double uu, double vv, double j00, double j01, double j10, double j11, fgrid_t *G)
+{
+    double m11 = j00 * j00 + j01 * j01, m22 = j10 * j10 + j11 * j11, m12 = j00 * j10 + j01 * j11;
+    double h = 0.5 * (m11 - m22);
+    double disc = sqrt(h * h + m12 * m12);
+    double smaj = sqrt(0.5 * (m11 + m22) + disc);
+    G->flag = 0;
+    G->valid = isfinite(smaj) && smaj > 1e-12;
+    if (!G->valid) return;
+    double smin = fabs(j00 * j11 - j01 * j10) / smaj;
+    int clamped = !(smin > smaj / FG_AMAX);
+    double sminc = clamped ? smaj / FG_AMAX : smin;
+    double A = smaj / sminc;
+    double th = 0.5 * atan2(2.0 * m12, m11 - m22);
+    if (th < 0.0) th += M_PI;
+    /* a clamped anisotropy is exactly log2(16) = 4 on every implementation */
+    double g[3] = {log2(smaj), clamped ? 4.0 : log2(A), th * ((double)FG_ORIENT / M_PI)};
+    int base[3];
+    double f[3];
+    for (int c = 0; c < 3; ++c) {
+        double fl = floor(g[c]);
+        base[c] = (int)fl;
+        f[c] = g[c] - fl;
+        if (!(c == 1 && clamped)) G->flag |= near_int_1e9(g[c]);
+    }
+    int ord[3] = {0, 1, 2};
+    for (int i = 1; i < 3; ++i)
+        for (int j = i; j > 0 && f[ord[j]] > f[ord[j - 1]]; --j) {
+            int t = ord[j]; ord[j] = ord[j - 1]; ord[j - 1] = t;
+        }
+    G->flag |= fabs(f[ord[0]] - f[ord[1]]) < 1e-9 || fabs(f[ord[1]] - f[ord[2]]) < 1e-9;
+    double wt[4] = {1.0 - f[ord[0]], f[ord[0]] - f[ord[1]], f[ord[1]] - f[ord[2]], f[ord[2]]};
+    int cv[3] = {base[0], base[1], base[2]};
+    for (int i = 0; i < 4; ++i) {
+        if (i > 0) cv[ord[i - 1]] += 1;
+        int l = cv[0], ai = cv[1], o = ((cv[2] % FG_ORIENT) + FG_ORIENT) % FG_ORIENT;
+        double li = ldexp(1.0, l), Ai = ldexp(1.0, ai), thi = (double)o * (M_PI / (double)FG_ORIENT);
+        double ratio = (li * li / Ai) / (smaj * sminc);
+        uint32_t key = (((uint32_t)l & 0xFFu) << 24) | (((uint32_t)ai & 0xFu) << 20) | (((uint32_t)o & 0xFu) << 16);
+        double cs = cos(thi), sn = sin(thi);
+        double X = (cs * uu + sn * vv) / li;
+        double Y = (cs * vv - sn * uu) * Ai / li;
+        double fxl = floor(X), fyl = floor(Y);
+        double fx = X - fxl, fy = Y - fyl;
+        G->flag |= near_int_1e9(X) | near_int_1e9(Y) | (fabs(fx - fy) < 1e-9);
+        int64_t ix = (int64_t)fxl, iy = (int64_t)fyl;
+        for (int c = 0; c < 3; ++c) {
+            int64_t a, b;
+            double bw;
+            if (fx >= fy) {
+                if (c == 0) { a = ix; b = iy; bw = 1.0 - fx; }
+                else if (c == 1) { a = ix + 1; b = iy; bw = fx - fy; }
+                else { a = ix + 1; b = iy + 1; bw = fy; }
+            } else {
+                if (c == 0) { a = ix; b = iy; bw = 1.0 - fy; }
+                else if (c == 1) { a = ix; b = iy + 1; bw = fy - fx; }
+                else { a = ix + 1; b = iy + 1; bw = fx; }
+            }
+            G->w[3 * i + c] = wt[i] * bw;
+            G->r[3 * i + c] = ratio;
+            G->key[3 * i + c] = key;
+            G->a[3 * i + c] = a;
+            G->b[3 * i + c] = b;
+        }
+    }
+}
 
 /* Anisotropic lookup: the future work of Sec. 8 (several samples of the
  * prefiltered map for anisotropic distributions) as this library designs
@@ -948,21 +1064,24 @@ static void aniso_lookup(const pyr_src *ind, const pyr_src *rgbs, int R, int M, 
  * or integer part on this pixel: 1 = xi1 within the tolerance band of a
  * float gating threshold, 2 = a node probability on a float rounding
  * boundary, 4 = a node count on a float rounding boundary, 8 = a sampled
- * count within 1e-5 of an integer (without being one). */
+ * count within 1e-5 of an integer (without being one), 16 = a footprint
+ * grid decision (cell, ordering, triangle) within 1e-9 of its boundary. */
 static int shade_impl(const float *const *gb, const float *ind_pyr, const float *rgb_pyr, const double *levels,
                       const float *lut_S, const float *lut_E, int R, int K, int M, uint32_t seed, int V,
                       int sampler, int prob_mode, double gamma, int lobe_taps, const int64_t *pix, int64_t count,
                       const double *Fext, double *radiance, double *counts, uint8_t *codes, double *probs,
                       uint8_t *flags, int threads)
 {
-    if (R < 1 || K < 2 || K > 16 || (K & (K - 1)) || M < 1 || (R >> (M - 1)) < 1 || (V != 1 && V != 6) ||
+    if (R < 1 || K < 2 || K > 16 || (K & (K - 1)) || M < 1 || (R >> (M - 1)) < 1 || (V != 1 && V != 6 && V != 12) ||
+        (V == 12 && (!gb[20] || !gb[21] || !gb[22] || !gb[23])) ||
         sampler < 0 || sampler > 2 || prob_mode < 0 || prob_mode > 1 ||
         (prob_mode == 1 && !(gamma > 0.0 && gamma <= 1.0)) ||
         !(lobe_taps == 0 || lobe_taps == 2 || lobe_taps == 4 || lobe_taps == 8) ||
         (lobe_taps && (!gb[17] || !gb[18] || !gb[19])))
         return ORC_EINVAL;
     gbuf_t g = {gb[0], gb[1], gb[2], gb[3], gb[4], gb[5], gb[6], gb[7], gb[8], gb[9], gb[10], gb[11],
-                gb[12], gb[13], gb[14], (const uint32_t *)gb[15], gb[16], gb[17], gb[18], gb[19]};
+                gb[12], gb[13], gb[14], (const uint32_t *)gb[15], gb[16], gb[17], gb[18], gb[19],
+                gb[20], gb[21], gb[22], gb[23]};
     /* prob_mode 1 (the comparison of Sec. 7 "Comparison with Previous Work",
      * after Wang et al. 2020): every facet reflects with one probability
      * gamma, independent of the map; this is the two-bin case of the same
@@ -1040,17 +1159,38 @@ static int shade_impl(const float *const *gb, const float *ind_pyr, const float 
         pa[0] = 1.0 - rest;
         if (pr) for (int k = 0; k < K; ++k) pr[k] = pa[k];
         /* Sec. 3.3 Eq. (anisogrid): weighted sum of independent multinomial
-         * draws at lattice vertices, each with N_i = N_P. */
+         * draws at lattice vertices; vertices 1 and 6 draw N_i = N_P, the
+         * footprint grid (12) its vertices' own counts. */
         double lt;
         int l0 = lattice_level((double)g.area[i], &lt);
         double Msum[16] = {0};
         int flag = 0;
         double uu = (double)g.u[i], vv = (double)g.v[i];
+        fgrid_t fg;
+        double Nbar = NP; /* the normalisation's count */
+        if (V == 12) {
+            footprint_grid(uu, vv, g.dudx[i], g.dudy[i], g.dvdx[i], g.dvdy[i], &fg);
+            if (!fg.valid) { /* no footprint: nothing is drawn */
+                flags[q] = 0;
+                continue;
+            }
+            flag |= fg.flag << 4;
+            Nbar = 0.0;
+            for (int vi = 0; vi < 12; ++vi) Nbar += fg.w[vi] * (NP * fg.r[vi]);
+        }
         for (int vi = 0; vi < V; ++vi) {
-            int lev;
+            int lev = 0;
             int64_t a, b;
             double w;
-            if (V == 1) {
+            double Nv = NP;
+            uint32_t key;
+            if (V == 12) {
+                w = fg.w[vi];
+                Nv = NP * fg.r[vi];
+                key = fg.key[vi];
+                a = fg.a[vi];
+                b = fg.b[vi];
+            } else if (V == 1) {
                 lev = l0;
                 a = (int64_t)floor(ldexp(uu, -lev) + 0.5);
                 b = (int64_t)floor(ldexp(vv, -lev) + 0.5);
@@ -1074,9 +1214,10 @@ static int shade_impl(const float *const *gb, const float *ind_pyr, const float 
                 }
                 w = (side == 0 ? 1.0 - lt : lt) * bw;
             }
+            if (V != 12) key = ((uint32_t)lev & 0xFFFFu) << 16;
             double Mv[16];
             uint8_t cv[16];
-            flag |= multinomial(sampler, NP, pa, K, seed, surf, lev, a, b, Mv, cv);
+            flag |= multinomial(sampler, Nv, V != 12, pa, K, seed, surf, key, a, b, Mv, cv);
             for (int k = 0; k < K; ++k) Msum[k] += w * Mv[k];
             if (cnt) for (int k = 0; k < K; ++k) cnt[vi * K + k] = Mv[k];
             if (cod) for (int k = 0; k < K - 1; ++k) cod[vi * (K - 1) + k] = cv[k];
@@ -1085,7 +1226,7 @@ static int shade_impl(const float *const *gb, const float *ind_pyr, const float 
         double num = 0.0, den = 0.0;
         for (int k = 0; k < K; ++k) num += levels[k] * Msum[k];
         for (int k = 1; k < K; ++k) den += levels[k] * p[k];
-        den *= NP;
+        den *= Nbar;
         double gmod = (num > 0.0 && den > 0.0) ? num / den : 0.0;
         const float *f0[3] = {g.f0r, g.f0g, g.f0b};
         for (int c = 0; c < 3; ++c) {
@@ -1157,6 +1298,21 @@ int orc_sample_binomial(int sampler, const double *N, const double *p, const uin
     }
     (void)threads;
     return ORC_OK;
+}
+
+/* The footprint grid's 12 draws of one pixel (weights, count ratios, hash
+ * keys, lattice vertices); returns -1 for a degenerate Jacobian, else the
+ * boundary flag. */
+int orc_footprint_grid(double u, double v, double j00, double j01, double j10, double j11, double *w, double *r,
+                       uint32_t *key, int64_t *a, int64_t *b)
+{
+    fgrid_t G;
+    footprint_grid(u, v, j00, j01, j10, j11, &G);
+    if (!G.valid) return -1;
+    for (int i = 0; i < 12; ++i) {
+        w[i] = G.w[i]; r[i] = G.r[i]; key[i] = G.key[i]; a[i] = G.a[i]; b[i] = G.b[i];
+    }
+    return G.flag;
 }
 
 void orc_face_dir(int face, double s, double t, double *d) { face_to_dir(face, s, t, d); }

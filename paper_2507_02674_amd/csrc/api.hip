@@ -232,7 +232,7 @@ int glint_prefilter(glint_ctx ctx, const float *env, const uint8_t *ind_j, const
 static int check_shade_params(const glint_shade_params &sp, int view)
 {
     const char *what = nullptr;
-    if (sp.vertices != 1 && sp.vertices != 6) what = "vertices must be 1 or 6";
+    if (sp.vertices != 1 && sp.vertices != 6 && sp.vertices != 12) what = "vertices must be 1, 6 or 12";
     else if (sp.exact_gating != 0 && sp.exact_gating != 1) what = "exact_gating must be 0 or 1";
     else if (sp.sampler < GLINT_SAMPLER_DUAL || sp.sampler > GLINT_SAMPLER_SINGLE_FLOOR) what = "unknown sampler";
     else if (sp.prob_mode != GLINT_PROBS_ENV && sp.prob_mode != GLINT_PROBS_CONSTANT) what = "unknown prob_mode";
@@ -299,6 +299,10 @@ int glint_shade(glint_ctx ctx, const glint_gbuffer *g, int64_t P, const glint_en
     if (sp->lobe_taps > 0 && (env->dtype != GLINT_F32 || sp->sampler != GLINT_SAMPLER_DUAL || constant))
         return fail(GLINT_EUNSUPPORTED, "anisotropic lookups need a float32 pyramid, the dual gate and the map's "
                     "probabilities");
+    if (sp->vertices == 12 &&
+        (env->dtype != GLINT_F32 || sp->sampler != GLINT_SAMPLER_DUAL || constant || sp->lobe_taps != 0))
+        return fail(GLINT_EUNSUPPORTED, "the footprint grid needs a float32 pyramid, the dual gate, the map's "
+                    "probabilities and one lookup");
     if (P == 0) return ok();
     if (!radiance || !env->rgb_pyr || !env->lut_E ||
         (!constant && (!env->ind_pyr || !env->levels || !env->lut_S)))
@@ -306,6 +310,8 @@ int glint_shade(glint_ctx ctx, const glint_gbuffer *g, int64_t P, const glint_en
     if (int rc = check_gbuffer(g)) return rc;
     if (sp->lobe_taps > 0 && (!g->tx || !g->ty || !g->tz))
         return fail(GLINT_EINVAL, "anisotropic lookups need the G-buffer tangent");
+    if (sp->vertices == 12 && (!g->dudx || !g->dudy || !g->dvdx || !g->dvdy))
+        return fail(GLINT_EINVAL, "the footprint grid needs the G-buffer uv Jacobian");
     if (reinterpret_cast<uintptr_t>(env->rgb_pyr) % 16) return fail(GLINT_EINVAL, "rgb_pyr must be 16-byte aligned");
     if (P > ((int64_t)1 << 40)) return fail(GLINT_EINVAL, "num_pixels too large");
     return device_status(glint::launch_shade(*g, P, *env, *sp, nullptr, radiance, dbg, (hipStream_t)stream),
@@ -438,7 +444,7 @@ int glint_shade_surrogate(glint_ctx ctx, const glint_gbuffer *g, int64_t P, cons
     if (int rc = check_mips(env->R, env->num_mips)) return rc;
     if (int rc = check_surrogate(env->K, w, w_bf16)) return rc;
     if (int rc = check_shade_params(*sp, -1)) return rc;
-    if (sp->prob_mode != GLINT_PROBS_ENV || sp->lobe_taps != 0)
+    if (sp->prob_mode != GLINT_PROBS_ENV || sp->lobe_taps != 0 || sp->vertices == 12)
         return fail(GLINT_EUNSUPPORTED, "the surrogate form computes the map's probabilities with one lookup");
     if (P == 0) return ok();
     if (!radiance || !workspace || !env->rgb_pyr || !env->levels || !env->lut_S || !env->lut_E)
@@ -490,7 +496,8 @@ int glint_frame_batched(glint_ctx ctx, const glint_env_task *envs, int n_env, co
         if (w.num_pixels < 0 || w.num_pixels > ((int64_t)1 << 40))
             return fail(GLINT_EINVAL, "view %d: bad num_pixels", v);
         if (int rc = check_shade_params(w.shade, v)) return rc;
-        if (w.shade.sampler != GLINT_SAMPLER_DUAL || w.shade.prob_mode != GLINT_PROBS_ENV || w.shade.lobe_taps != 0)
+        if (w.shade.sampler != GLINT_SAMPLER_DUAL || w.shade.prob_mode != GLINT_PROBS_ENV || w.shade.lobe_taps != 0 ||
+            w.shade.vertices == 12)
             return fail(GLINT_EUNSUPPORTED, "view %d: batched frames use the dual-gated sampler and the map's "
                         "probabilities with one lookup", v);
         if (!w.radiance) return fail(GLINT_EINVAL, "view %d: null radiance", v);

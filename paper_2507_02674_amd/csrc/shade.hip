@@ -271,7 +271,7 @@ __device__ __forceinline__ void node_sample(int sampler, double N, double p, flo
 // child counts at the back, shifting with static indices, so no register
 // array is indexed dynamically.
 template <int K, bool SG>
-__device__ __forceinline__ void multinomial(double NP, const double (&p)[K], uint32_t seed_mix, int lev, int64_t a,
+__device__ __forceinline__ void multinomial(double NP, const double (&p)[K], uint32_t seed_mix, uint32_t key, int64_t a,
                                             int64_t b, const double *__restrict__ qtail, bool exact_gating,
                                             int sampler, double (&leaf)[K], uint8_t *codes)
 {
@@ -309,7 +309,7 @@ __device__ __forceinline__ void multinomial(double NP, const double (&p)[K], uin
             const int node = nd - 1 + j;
             uint32_t hx, hy;
             if ((node & 1) == 0) {
-                const u4 h = pcg4d({(uint32_t)a, (uint32_t)b, (((uint32_t)lev & 0xFFFFu) << 16) | ((uint32_t)node >> 1),
+                const u4 h = pcg4d({(uint32_t)a, (uint32_t)b, key | ((uint32_t)node >> 1),
                                     seed_mix});
                 hx = h.x;
                 hy = h.y;
@@ -333,6 +333,71 @@ __device__ __forceinline__ void multinomial(double NP, const double (&p)[K], uin
     }
 #pragma unroll
     for (int k = 0; k < K; ++k) leaf[k] = Q[k];
+}
+
+// Footprint grid (Sec. 3.3 "Binomial Sampling with Anisotropic Grids"; the
+// paper uses the grid as a black box, the layout is this library's): the
+// pixel footprint, the ellipse of J J^T for the uv Jacobian J, by length
+// log2 s_maj, anisotropy log2(s_maj / s_min) (s_min clamped to s_maj / 16)
+// and orientation 8 theta / pi (periodic); a Kuhn tetrahedron of that grid
+// (axes by decreasing fraction, ties in axis order) gives 4 vertices with
+// weights; each vertex (l, a, o) draws with its own count N_P 4^l 2^-a /
+// (s_maj s_min) on the uv triangle grid of its footprint (uv rotated by
+// -o pi/8, scaled by (2^-l, 2^(a-l))), 3 triangle vertices each.
+struct FootGrid {
+    bool valid;
+    double smaj, sminc;
+    double wt[4];
+    int l[4], a[4], o[4];
+};
+
+__device__ __forceinline__ FootGrid footprint_grid(double j00, double j01, double j10, double j11)
+{
+    FootGrid G;
+    const double m11 = j00 * j00 + j01 * j01, m22 = j10 * j10 + j11 * j11, m12 = j00 * j10 + j01 * j11;
+    const double h = 0.5 * (m11 - m22);
+    const double disc = sqrt(h * h + m12 * m12);
+    const double smaj = sqrt(0.5 * (m11 + m22) + disc);
+    G.valid = isfinite(smaj) && smaj > 1e-12;
+    if (!G.valid) return G;
+    const double smin = fabs(j00 * j11 - j01 * j10) / smaj;
+    const bool clamped = !(smin > smaj / 16.0);
+    const double sminc = clamped ? smaj / 16.0 : smin;
+    const double A = smaj / sminc;
+    double th = 0.5 * atan2(2.0 * m12, m11 - m22);
+    if (th < 0.0) th += M_PI;
+    const double g[3] = {log2(smaj), clamped ? 4.0 : log2(A), th * (8.0 / M_PI)};
+    int base[3];
+    double f[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const double fl = floor(g[c]);
+        base[c] = (int)fl;
+        f[c] = g[c] - fl;
+    }
+    // axes by decreasing fraction, ties in axis order (insertion sort)
+    int o0 = 0, o1 = 1, o2 = 2;
+    if (f[o1] > f[o0]) { const int t = o0; o0 = o1; o1 = t; }
+    if (f[o2] > f[o1]) {
+        const int t = o1; o1 = o2; o2 = t;
+        if (f[o1] > f[o0]) { const int t2 = o0; o0 = o1; o1 = t2; }
+    }
+    G.smaj = smaj;
+    G.sminc = sminc;
+    G.wt[0] = 1.0 - f[o0];
+    G.wt[1] = f[o0] - f[o1];
+    G.wt[2] = f[o1] - f[o2];
+    G.wt[3] = f[o2];
+    int cv[3] = {base[0], base[1], base[2]};
+    const int ord[3] = {o0, o1, o2};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        if (i > 0) cv[ord[i - 1]] += 1;
+        G.l[i] = cv[0];
+        G.a[i] = cv[1];
+        G.o[i] = ((cv[2] % 8) + 8) % 8;
+    }
+    return G;
 }
 
 // Shades pixel i of the view described by A (all of rows b1-b5).  SURR: the
@@ -466,12 +531,53 @@ __device__ __forceinline__ void shade_pixel(const ShadeArgs &A, int64_t i)
     double Msum[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) Msum[k] = 0.0;
-#pragma unroll
+    double Nbar = NP; // the normalisation's count
+    FootGrid fg;
+    if constexpr (V == 12) {
+        fg = footprint_grid((double)A.g.dudx[i], (double)A.g.dudy[i], (double)A.g.dvdx[i], (double)A.g.dvdy[i]);
+        if (!fg.valid) { // no footprint: nothing is drawn
+            A.radiance[3 * i] = 0.0f; A.radiance[3 * i + 1] = 0.0f; A.radiance[3 * i + 2] = 0.0f;
+            if (A.counts) for (int k = 0; k < V * K; ++k) A.counts[i * V * K + k] = 0.0;
+            if (A.codes) for (int k = 0; k < V * (K - 1); ++k) A.codes[i * V * (K - 1) + k] = 0;
+            return;
+        }
+    }
+    // the footprint grid's 12 draws run in a loop (code size); 1 and 6 unrolled
+    constexpr int kUnrollV = V == 12 ? 1 : V;
+#pragma unroll kUnrollV
     for (int vi = 0; vi < V; ++vi) {
-        int lev;
+        int lev = 0;
         int64_t a, b;
         double w;
-        if (V == 1) {
+        double Nv = NP;
+        uint32_t key;
+        if constexpr (V == 12) {
+            const int ti = vi / 3, corner = vi % 3;
+            const double li = ldexp(1.0, fg.l[ti]), Ai = ldexp(1.0, fg.a[ti]);
+            const double thi = (double)fg.o[ti] * (M_PI / 8.0);
+            const double ratio = (li * li / Ai) / (fg.smaj * fg.sminc);
+            key = (((uint32_t)fg.l[ti] & 0xFFu) << 24) | (((uint32_t)fg.a[ti] & 0xFu) << 20) |
+                  (((uint32_t)fg.o[ti] & 0xFu) << 16);
+            const double cs = cos(thi), sn = sin(thi);
+            const double X = (cs * uu + sn * vv) / li;
+            const double Y = (cs * vv - sn * uu) * Ai / li;
+            const double fxl = floor(X), fyl = floor(Y);
+            const double fx = X - fxl, fy = Y - fyl;
+            const int64_t ix = (int64_t)fxl, iy = (int64_t)fyl;
+            double bw;
+            if (fx >= fy) {
+                if (corner == 0) { a = ix; b = iy; bw = 1.0 - fx; }
+                else if (corner == 1) { a = ix + 1; b = iy; bw = fx - fy; }
+                else { a = ix + 1; b = iy + 1; bw = fy; }
+            } else {
+                if (corner == 0) { a = ix; b = iy; bw = 1.0 - fy; }
+                else if (corner == 1) { a = ix; b = iy + 1; bw = fy - fx; }
+                else { a = ix + 1; b = iy + 1; bw = fx; }
+            }
+            w = fg.wt[ti] * bw;
+            Nv = NP * ratio;
+            Nbar = vi == 0 ? w * Nv : Nbar + w * Nv;
+        } else if (V == 1) {
             lev = l0;
             a = (int64_t)floor(ldexp(uu, -lev) + 0.5);
             b = (int64_t)floor(ldexp(vv, -lev) + 0.5);
@@ -495,9 +601,10 @@ __device__ __forceinline__ void shade_pixel(const ShadeArgs &A, int64_t i)
             }
             w = (side == 0 ? 1.0 - lt : lt) * bw;
         }
+        if constexpr (V != 12) key = ((uint32_t)lev & 0xFFFFu) << 16;
         double Mv[K];
         uint8_t *cod = A.codes ? A.codes + (i * V + vi) * (K - 1) : nullptr;
-        multinomial<K, SG>(NP, p, seed_mix, lev, a, b, A.qtail, A.exact_gating != 0, A.sampler, Mv, cod);
+        multinomial<K, SG>(Nv, p, seed_mix, key, a, b, A.qtail, A.exact_gating != 0, A.sampler, Mv, cod);
 #pragma unroll
         for (int k = 0; k < K; ++k) Msum[k] += w * Mv[k];
         if (A.counts) {
@@ -514,7 +621,7 @@ __device__ __forceinline__ void shade_pixel(const ShadeArgs &A, int64_t i)
 #pragma unroll
         for (int k = 1; k < K; ++k) num += A.levels[k] * Msum[k];
     }
-    den *= NP;
+    den *= Nbar;
     const double gmod = (num > 0.0 && den > 0.0) ? num / den : 0.0;
     const double f0[3] = {(double)A.g.f0r[i], (double)A.g.f0g[i], (double)A.g.f0b[i]};
 #pragma unroll
@@ -554,6 +661,14 @@ template <int K, int DT>
 static hipError_t launch_shade_kd(const ShadeArgs &a, int V, hipStream_t stream)
 {
     const unsigned blocks = (unsigned)((a.P + kShadeThreads - 1) / kShadeThreads);
+    if (V == 12) {
+        // footprint grid: float32 pyramid, dual gate, one lookup (the API checks)
+        if constexpr (DT == 0) {
+            GLINT_LAUNCH("k_shade", (k_shade<K, 0, 12>), dim3(blocks), dim3(kShadeThreads), 0, stream, a);
+            return hipGetLastError();
+        }
+        return hipErrorInvalidValue;
+    }
     if (a.lobe_taps > 0) {
         // anisotropic lookups: float32 pyramid, dual gate (the API checks)
         if constexpr (DT == 0) {

@@ -21,7 +21,7 @@ LUT_N = 64
 
 GBUF_FIELDS = ("nx", "ny", "nz", "vx", "vy", "vz", "u", "v", "area", "ax", "ay", "density",
                "f0r", "f0g", "f0b", "surf_id")
-GBUF_OPTIONAL = ("visibility", "tx", "ty", "tz")  # float32, may be absent
+GBUF_OPTIONAL = ("visibility", "tx", "ty", "tz", "dudx", "dudy", "dvdx", "dvdy")  # float32, may be absent
 
 
 class GlintError(RuntimeError):

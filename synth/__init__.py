@@ -226,6 +226,71 @@ def contact_visibility(g: dict) -> np.ndarray:
     return vis
 
 
+def _camera_rays(W, H, px, py, eye, target, vfov_deg):
+    """Unit ray directions through image positions (px, py) in pixels."""
+    eye = np.array(eye, np.float64)
+    fwd = np.array(target, np.float64) - eye
+    fwd /= np.linalg.norm(fwd)
+    right = np.cross(fwd, np.array([0.0, 1.0, 0.0]))
+    right /= np.linalg.norm(right)
+    up = np.cross(right, fwd)
+    th = math.tan(math.radians(vfov_deg) * 0.5)
+    xs = (2.0 * px / W - 1.0) * th * W / H
+    ys = (1.0 - 2.0 * py / H) * th
+    d = fwd[None] + xs[:, None] * right[None] + ys[:, None] * up[None]
+    return d / np.linalg.norm(d, axis=1, keepdims=True)
+
+
+def _scene_uv(d, eye, plane_half):
+    """Surface id (1 sphere, 2 plane, 0 none) and uv of the first hit."""
+    eye = np.array(eye, np.float64)
+    b = d @ eye
+    disc = b * b - (eye @ eye - 1.0)
+    ts = np.where(disc > 0.0, -b - np.sqrt(np.clip(disc, 0.0, None)), np.inf)
+    ts = np.where(ts > 1e-6, ts, np.inf)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        tp = np.where(d[:, 1] < 0.0, (-1.0 - eye[1]) / d[:, 1], np.inf)
+    hp = eye[None] + np.where(np.isfinite(tp), tp, 0.0)[:, None] * d
+    inside = (np.abs(hp[:, 0]) <= plane_half) & (np.abs(hp[:, 2]) <= plane_half) & np.isfinite(tp)
+    tp = np.where(inside, tp, np.inf)
+    sid = np.zeros(len(d), np.int64)
+    on_s = np.isfinite(ts) & (ts <= tp)
+    on_p = np.isfinite(tp) & ~on_s
+    sid[on_s], sid[on_p] = 1, 2
+    uv = np.zeros((len(d), 2))
+    hs = eye[None] + ts[on_s][:, None] * d[on_s]
+    uv[on_s] = np.stack(_sphere_uv(hs / np.linalg.norm(hs, axis=1, keepdims=True)), -1)
+    hq = eye[None] + tp[on_p][:, None] * d[on_p]
+    uv[on_p] = hq[:, [0, 2]]
+    return sid, uv
+
+
+def uv_jacobian(g: dict, W: int, H: int, eye=(0.0, 0.6, 4.0), target=(0.0, -0.2, 0.0), vfov_deg: float = 40.0,
+                plane_half: float = 20.0):
+    """Pixel footprint of scene_frame's camera as the uv Jacobian (float32
+    dudx, dudy, dvdx, dvdy): differences of the uv hit by rays half a pixel
+    to either side (one-sided where a side leaves the surface, longitude
+    wrapped), zero where both sides do."""
+    j, i = np.meshgrid(np.arange(H), np.arange(W), indexing="ij")
+    i, j = i.ravel().astype(np.float64) + 0.5, j.ravel().astype(np.float64) + 0.5
+    sid0 = g["surf_id"].astype(np.int64)
+    sid0 = np.where(sid0 == NO_SURFACE, 0, sid0)
+    _, uv0 = _scene_uv(_camera_rays(W, H, i, j, eye, target, vfov_deg), eye, plane_half)
+    out = []
+    for dx, dy in ((0.5, 0.0), (0.0, 0.5)):
+        sp, uvp = _scene_uv(_camera_rays(W, H, i + dx, j + dy, eye, target, vfov_deg), eye, plane_half)
+        sm, uvm = _scene_uv(_camera_rays(W, H, i - dx, j - dy, eye, target, vfov_deg), eye, plane_half)
+        okp, okm = (sp == sid0) & (sid0 > 0), (sm == sid0) & (sid0 > 0)
+        dp, dm = uvp - uv0, uv0 - uvm
+        for dd in (dp, dm):
+            dd[:, 0] = np.where(sid0 == 1, (dd[:, 0] + 0.5) % 1.0 - 0.5, dd[:, 0])
+        deriv = np.where((okp & okm)[:, None], dp + dm, np.where(okp[:, None], 2 * dp, np.where(okm[:, None], 2 * dm, 0.0)))
+        out.append(deriv)
+    ddx, ddy = out
+    return (ddx[:, 0].astype(np.float32), ddy[:, 0].astype(np.float32), ddx[:, 1].astype(np.float32),
+            ddy[:, 1].astype(np.float32))
+
+
 def surface_tangents(g: dict):
     """Tangent of the alpha_x axis for the sphere-and-plane scene (float32
     tx, ty, tz): on the sphere the direction of increasing longitude u

@@ -48,7 +48,7 @@ def test_struct_layouts_match_header():
     # field order and sizes as declared in include/glint.h (LP64)
     assert C.sizeof(G.PartitionParams) == 24
     assert G.PartitionParams.ell.offset == 8
-    assert C.sizeof(G.GBuffer) == 20 * 8
+    assert C.sizeof(G.GBuffer) == 24 * 8
     assert C.sizeof(G.Env) == 5 * 8 + 4 * 4 + 8
     assert C.sizeof(G.ShadeParams) == 28
     assert C.sizeof(G.ShadeDebug) == 24

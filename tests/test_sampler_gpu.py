@@ -297,3 +297,45 @@ def test_anisotropic_lookup_arguments_rejected(ctx):
         G.glint_shade(ctx, G.make_gbuffer(fields), len(g["nx"]), envs,
                       G.ShadeParams(1, 1, 0, G.GLINT_SAMPLER_SINGLE, 0, 1.0, 4), rad)
     assert e.value.code == G.GLINT_EUNSUPPORTED
+
+
+# --- footprint grid (12 draws per pixel) ---------------------------------------------
+
+@pytest.mark.parametrize("K", [4, 8])
+def test_shade_footprint_grid_matches_oracle(ctx, qtail, K):
+    """The footprint grid (length x anisotropy x orientation cell, uv
+    triangle grid per cell vertex), every pixel against the oracle."""
+    R, M = 16, 5
+    U.log(f"shade footprint grid K={K}")
+    env = synth.make_env(R, 6)
+    levels, ind, rgb = oracle_env(env, K, M)
+    S, E = oracle.lut_tables()
+    W, H = 96, 54
+    g = synth.scene_frame(W, H, seed=3, density_decades=(0.0, 8.0))
+    g["dudx"], g["dudy"], g["dvdx"], g["dvdy"] = synth.uv_jacobian(g, W, H)
+    # a few degenerate footprints draw nothing
+    g["dudx"][:40] = g["dudy"][:40] = g["dvdx"][:40] = g["dvdy"][:40] = 0.0
+    gpu = U.shade(ctx, g, ind, rgb, levels, S, E, R, K, M, seed=7, vertices=12, qtail=qtail)
+    orc = oracle.shade(g, ind, rgb, levels, S, E, R, K, M, 7, 12)
+    check_pixels(gpu, orc, f"footprint grid K={K}", max_flagged=2e-2)
+
+
+def test_footprint_grid_arguments_rejected(ctx):
+    import torch
+    R, K, M = 16, 4, 5
+    env = synth.make_env(R, 2)
+    levels, ind, rgb = oracle_env(env, K, M)
+    S, E = oracle.lut_tables()
+    g = synth.scene_frame(32, 18, seed=1)
+    fields = U.gbuf_to_device(g)  # no Jacobian
+    envs = G.make_env(U.dev(ind), U.dev(rgb), U.dev(levels), U.dev(S), U.dev(E), R, K, M, G.GLINT_F32)
+    rad = torch.empty((len(g["nx"]), 3), dtype=torch.float32, device="cuda")
+    with pytest.raises(G.GlintError) as e:
+        G.glint_shade(ctx, G.make_gbuffer(fields), len(g["nx"]), envs, G.ShadeParams(1, 12), rad)
+    assert e.value.code == G.GLINT_EINVAL
+    g["dudx"], g["dudy"], g["dvdx"], g["dvdy"] = synth.uv_jacobian(g, 32, 18)
+    fields = U.gbuf_to_device(g)
+    with pytest.raises(G.GlintError) as e:
+        G.glint_shade(ctx, G.make_gbuffer(fields), len(g["nx"]), envs,
+                      G.ShadeParams(1, 12, 0, G.GLINT_SAMPLER_SINGLE), rad)
+    assert e.value.code == G.GLINT_EUNSUPPORTED
