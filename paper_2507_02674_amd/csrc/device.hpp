@@ -87,6 +87,7 @@ __host__ __device__ __forceinline__ int64_t level_offset(int R, int level)
 // texel across the edge); the texel off two edges (beyond a cube corner)
 // is the mean of the three texels meeting at that corner.  This keeps the
 // lookup continuous across edges and corners.
+
 __device__ __forceinline__ int64_t reproject_one(int face, int x, int y, int n)
 {
     const double inv = ldexp(1.0, -__builtin_ctz((unsigned)n)); // 1/n, exact for n a power of two
@@ -98,6 +99,106 @@ __device__ __forceinline__ int64_t reproject_one(int face, int x, int y, int n)
     a = a < 0 ? 0 : (a > n - 1 ? n - 1 : a);
     b = b < 0 ? 0 : (b > n - 1 ? n - 1 : b);
     return ((int64_t)f2 * n + b) * n + a;
+}
+
+// The same re-projection for a texel one step beyond an edge, in integer
+// form (the shading lookup's footprints cross edges often; the filter keeps
+// the form above, which measures faster in its kernel).
+// Scaled by n, the extended texel centre's direction has integer
+// components (face_dir with s = 2x+1-n, t = 2y+1-n and the major axis n),
+// so its owning face and texel follow exactly from integer arithmetic
+// (floor((num + den) n / (2 den)); the quotient is never an integer there,
+// so a floating-point evaluation of the same steps lands on the same
+// texel).  The result is affine in the position i along the
+// edge: texel (a1 i + an (n-1), b1 i + bn (n-1)) of face f2.  The 24 maps
+// (face, edge: 0 x = -1, 1 x = n, 2 y = -1, 3 y = n) are derived here at
+// compile time from this file's cube convention.
+struct EdgeMap {
+    int f2, a1, an, b1, bn;
+};
+
+struct EdgeTexel {
+    int f2, a, b;
+};
+
+constexpr EdgeTexel edge_texel_int(int face, int x, int y, long n)
+{
+    const long s = 2 * x + 1 - n, t = 2 * y + 1 - n, m = n;
+    long d[3] = {0, 0, 0};
+    switch (face) { // face_dir, scaled by n
+    case 0: d[0] = m; d[1] = -t; d[2] = -s; break;
+    case 1: d[0] = -m; d[1] = -t; d[2] = s; break;
+    case 2: d[0] = s; d[1] = m; d[2] = t; break;
+    case 3: d[0] = s; d[1] = -m; d[2] = -t; break;
+    case 4: d[0] = s; d[1] = -t; d[2] = m; break;
+    default: d[0] = -s; d[1] = -t; d[2] = -m; break;
+    }
+    const long ax = d[0] < 0 ? -d[0] : d[0], ay = d[1] < 0 ? -d[1] : d[1], az = d[2] < 0 ? -d[2] : d[2];
+    int f2 = 0;
+    long ma = 1, sc = 0, tc = 0;
+    if (ax >= ay && ax >= az) { // dir_face, numerators over the major magnitude
+        f2 = d[0] >= 0 ? 0 : 1; ma = ax; sc = d[0] >= 0 ? -d[2] : d[2]; tc = -d[1];
+    } else if (ay >= az) {
+        f2 = d[1] >= 0 ? 2 : 3; ma = ay; sc = d[0]; tc = d[1] >= 0 ? d[2] : -d[2];
+    } else {
+        f2 = d[2] >= 0 ? 4 : 5; ma = az; sc = d[2] >= 0 ? d[0] : -d[0]; tc = -d[1];
+    }
+    long a = (sc + ma) * n / (2 * ma), b = (tc + ma) * n / (2 * ma); // numerators >= 0: floor
+    a = a < 0 ? 0 : (a > n - 1 ? n - 1 : a);
+    b = b < 0 ? 0 : (b > n - 1 ? n - 1 : b);
+    return {f2, (int)a, (int)b};
+}
+
+constexpr EdgeMap derive_edge_map(int face, int e)
+{
+    const long n = 8; // the maps are affine in i; two positions fix them
+    const int x0 = e == 0 ? -1 : (e == 1 ? (int)n : 0), y0 = e == 2 ? -1 : (e == 3 ? (int)n : 0);
+    const int x1 = e <= 1 ? x0 : 1, y1 = e <= 1 ? 1 : y0;
+    const EdgeTexel p = edge_texel_int(face, x0, y0, n), q = edge_texel_int(face, x1, y1, n);
+    const int a1 = q.a - p.a, b1 = q.b - p.b;
+    return {p.f2, a1, p.a / (int)(n - 1), b1, p.b / (int)(n - 1)};
+}
+
+struct EdgeMaps {
+    EdgeMap m[24];
+};
+
+constexpr EdgeMaps derive_edge_maps()
+{
+    EdgeMaps t{};
+    for (int f = 0; f < 6; ++f)
+        for (int e = 0; e < 4; ++e) t.m[4 * f + e] = derive_edge_map(f, e);
+    return t;
+}
+
+constexpr EdgeMaps kEdgeMaps = derive_edge_maps();
+
+// a self-check of the affine form at another size
+constexpr bool edge_maps_consistent()
+{
+    for (int f = 0; f < 6; ++f)
+        for (int e = 0; e < 4; ++e)
+            for (int i = 0; i < 32; ++i) {
+                const long n = 32;
+                const int x = e == 0 ? -1 : (e == 1 ? (int)n : i), y = e == 2 ? -1 : (e == 3 ? (int)n : i);
+                const EdgeTexel r = edge_texel_int(f, x, y, n);
+                const EdgeMap m = kEdgeMaps.m[4 * f + e];
+                if (r.f2 != m.f2 || r.a != m.a1 * i + m.an * (int)(n - 1) || r.b != m.b1 * i + m.bn * (int)(n - 1))
+                    return false;
+            }
+    return true;
+}
+static_assert(edge_maps_consistent(), "edge maps are not affine in the position along the edge");
+
+// Flat index (within the level) of texel (x, y) of `face` one step beyond
+// exactly one edge (x or y in range).
+__device__ __forceinline__ int64_t reproject_edge(int face, int x, int y, int n)
+{
+    const int e = x < 0 ? 0 : (x >= n ? 1 : (y < 0 ? 2 : 3));
+    const int i = e <= 1 ? y : x;
+    const EdgeMap m = kEdgeMaps.m[4 * face + e];
+    const int a = m.a1 * i + m.an * (n - 1), b = m.b1 * i + m.bn * (n - 1);
+    return ((int64_t)m.f2 * n + b) * n + a;
 }
 
 // Resolves texel (x, y), x and y in [-1, n], of `face` to 1 or 3 flat

@@ -157,10 +157,21 @@ __device__ __forceinline__ void pyramid_trilinear(const ShadeArgs &A, const d3 &
         const int64_t base = level_offset(A.R, s);
         const double w4[4] = {lw * ((1.0 - bl.fy) * (1.0 - bl.fx)), lw * ((1.0 - bl.fy) * bl.fx),
                               lw * (bl.fy * (1.0 - bl.fx)), lw * (bl.fy * bl.fx)};
-        if (bl.x0 >= 0 && bl.x0 + 1 < ns && bl.y0 >= 0 && bl.y0 + 1 < ns) {
-            // footprint inside the face: four loads in flight
-            const int64_t t0 = base + ((int64_t)fs.face * ns + bl.y0) * ns + bl.x0;
-            const int64_t tt[4] = {t0, t0 + 1, t0 + ns, t0 + ns + 1};
+        // the four texels of the footprint; one beyond a face edge is the
+        // neighbouring face's texel (one index, as inside the face), one
+        // beyond a cube corner needs the three-texel mean below
+        int64_t tt[4];
+        bool corner = false;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int x = bl.x0 + (c & 1), y = bl.y0 + (c >> 1);
+            const bool xin = (unsigned)x < (unsigned)ns, yin = (unsigned)y < (unsigned)ns;
+            if (xin && yin) tt[c] = base + ((int64_t)fs.face * ns + y) * ns + x;
+            else if (xin || yin) tt[c] = base + reproject_edge(fs.face, x, y, ns);
+            else corner = true;
+        }
+        if (!corner) {
+            // four loads in flight
             double v[4][KL + 3];
 #pragma unroll
             for (int c = 0; c < 4; ++c) load_texel<KL, DT>(A.ind_pyr, A.rgb_pyr, tt[c], v[c]);
@@ -169,7 +180,7 @@ __device__ __forceinline__ void pyramid_trilinear(const ShadeArgs &A, const d3 &
 #pragma unroll
                 for (int k = 0; k < KL + 3; ++k) acc[k] += w4[c] * v[c][k];
         } else {
-            // across a seam: one copy of the seam rule
+            // a cube corner: one copy of the seam rule
 #pragma unroll 1
             for (int c = 0; c < 4; ++c)
                 accumulate_pyr<KL, DT>(A.ind_pyr, A.rgb_pyr, base, fs.face, bl.x0 + (c & 1), bl.y0 + (c >> 1), ns,
