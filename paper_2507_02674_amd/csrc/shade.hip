@@ -564,11 +564,16 @@ __device__ __forceinline__ void shade_pixel(const ShadeArgs &A, int64_t i)
         uint32_t key;
         if constexpr (V == 12) {
             const int ti = vi / 3, corner = vi % 3;
-            const double li = ldexp(1.0, fg.l[ti]), Ai = ldexp(1.0, fg.a[ti]);
-            const double thi = (double)fg.o[ti] * (M_PI / 8.0);
+            // the cell vertex's entries by selection (static indices: no
+            // private array for the runtime index)
+            const int gl = ti == 0 ? fg.l[0] : (ti == 1 ? fg.l[1] : (ti == 2 ? fg.l[2] : fg.l[3]));
+            const int ga = ti == 0 ? fg.a[0] : (ti == 1 ? fg.a[1] : (ti == 2 ? fg.a[2] : fg.a[3]));
+            const int go = ti == 0 ? fg.o[0] : (ti == 1 ? fg.o[1] : (ti == 2 ? fg.o[2] : fg.o[3]));
+            const double gw = ti == 0 ? fg.wt[0] : (ti == 1 ? fg.wt[1] : (ti == 2 ? fg.wt[2] : fg.wt[3]));
+            const double li = ldexp(1.0, gl), Ai = ldexp(1.0, ga);
+            const double thi = (double)go * (M_PI / 8.0);
             const double ratio = (li * li / Ai) / (fg.smaj * fg.sminc);
-            key = (((uint32_t)fg.l[ti] & 0xFFu) << 24) | (((uint32_t)fg.a[ti] & 0xFu) << 20) |
-                  (((uint32_t)fg.o[ti] & 0xFu) << 16);
+            key = (((uint32_t)gl & 0xFFu) << 24) | (((uint32_t)ga & 0xFu) << 20) | (((uint32_t)go & 0xFu) << 16);
             const double cs = cos(thi), sn = sin(thi);
             const double X = (cs * uu + sn * vv) / li;
             const double Y = (cs * vv - sn * uu) * Ai / li;
@@ -585,7 +590,7 @@ __device__ __forceinline__ void shade_pixel(const ShadeArgs &A, int64_t i)
                 else if (corner == 1) { a = ix; b = iy + 1; bw = fy - fx; }
                 else { a = ix + 1; b = iy + 1; bw = fx; }
             }
-            w = fg.wt[ti] * bw;
+            w = gw * bw;
             Nv = NP * ratio;
             Nbar = vi == 0 ? w * Nv : Nbar + w * Nv;
         } else if (V == 1) {
@@ -639,8 +644,10 @@ __device__ __forceinline__ void shade_pixel(const ShadeArgs &A, int64_t i)
     for (int c = 0; c < 3; ++c) A.radiance[3 * i + c] = (float)((f0[c] * EA + EB) * rgb[c] * gmod);
 }
 
+// The footprint grid and the anisotropic lookup carry more state per lane;
+// asking for two waves per SIMD keeps them at <= 256 registers.
 template <int K, int DT, int V, bool SURR = false, bool SG = false, bool PC = false, bool AN = false>
-__global__ void __launch_bounds__(kShadeThreads) k_shade(ShadeArgs A)
+__global__ void __launch_bounds__(kShadeThreads, (V == 12 || AN) ? 2 : 1) k_shade(ShadeArgs A)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= A.P) return;
