@@ -434,11 +434,22 @@ __global__ void __launch_bounds__(256) k_mlp_prepare(float *__restrict__ w, uint
 }
 
 // ---------------------------------------------------------------------------
-// inference: kInferWaves waves per block share the staged weights; wave w of
-// block b runs tiles (b * waves + w) + it * (grid * waves); every wave of a
-// block runs the same number of iterations (tiles past the end are masked),
-// so the block barriers line up.
+// inference: kInferWaves waves per block share the staged weights (one
+// block barrier after staging); wave w of block b then runs tiles
+// (b * waves + w) + it * (grid * waves) in its own LDS tile, so the layers
+// are ordered within the wave only.
 // ---------------------------------------------------------------------------
+// Orders a wave's LDS writes before its later LDS reads (all lanes of one
+// wave): the writes complete (lgkmcnt 0) and the compiler moves no memory
+// operation across.
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_s_waitcnt(0xC07F); // lgkmcnt(0), other counters unchanged
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 struct InferInput {
     const float *x;   // [B][5] features (src 0), or null
     glint_gbuffer g;  // G-buffer (src 1)
@@ -469,6 +480,7 @@ __global__ void __launch_bounds__(64 * kInferWaves) k_mlp_infer(InferInput in, i
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     InferTile &t = s_t[wave];
     stage_weights(wb, s_w);
+    __syncthreads(); // the staged weights are shared by the block's waves
     const uint16_t *W1 = s_w + sW1, *W2 = s_w + sW2, *W3 = s_w + sW3, *W4 = s_w + sW4;
     const int64_t tiles = (B + 31) / 32;
     const int64_t stride = (int64_t)gridDim.x * kInferWaves;
@@ -496,15 +508,15 @@ __global__ void __launch_bounds__(64 * kInferWaves) k_mlp_infer(InferInput in, i
             xr[1] = make_uint4(0u, 0u, 0u, 0u);
         }
         // a tile with no sample and no surface pixel (background) skips the
-        // network; the block's barriers are still reached by every wave
+        // network
         const bool active = __ballot(needed) != 0;
-        __syncthreads();
+        wave_lds_sync();
         if (active) dense_silu(t.x, kLdX, kIn, W1, kLdW1, w + ob1, t.h[0], nullptr);
-        __syncthreads();
+        wave_lds_sync();
         if (active) dense_silu(t.h[0], kLdH, kH, W2, kLdH, w + ob2, t.h[1], nullptr);
-        __syncthreads();
+        wave_lds_sync();
         if (active) dense_silu(t.h[1], kLdH, kH, W3, kLdH, w + ob3, t.h[0], nullptr);
-        __syncthreads();
+        wave_lds_sync();
         float logit[16], y[16];
 #pragma unroll
         for (int j = 0; j < 16; ++j) y[j] = 0.0f;
