@@ -339,3 +339,52 @@ def test_footprint_grid_arguments_rejected(ctx):
         G.glint_shade(ctx, G.make_gbuffer(fields), len(g["nx"]), envs,
                       G.ShadeParams(1, 12, 0, G.GLINT_SAMPLER_SINGLE), rad)
     assert e.value.code == G.GLINT_EUNSUPPORTED
+
+
+# --- every mode at the frame workload's size, sampled -------------------------------
+
+FRAME_MODES = {
+    "single": dict(sampler=G.GLINT_SAMPLER_SINGLE),
+    "single-floor": dict(sampler=G.GLINT_SAMPLER_SINGLE_FLOOR),
+    "constant": dict(prob_mode=G.GLINT_PROBS_CONSTANT, gamma=0.05),
+    "visibility": dict(extra="visibility"),
+    "lobe-taps-8": dict(lobe_taps=8, extra="tangent"),
+    "vertices-6": dict(vertices=6),
+    "vertices-12": dict(vertices=12, extra="jacobian"),
+}
+
+
+@pytest.fixture(scope="module")
+def frame_env(ctx):
+    w = synth.WORKLOADS["frame"]
+    env, g = w.env(), w.gbuf()
+    lv, ij, it = U.partition(ctx, env, w.K)
+    raw, rgb, _ = U.prefilter(ctx, env, ij, it, w.K, w.M, w.T)
+    S, E = U.luts(ctx)
+    return dict(w=w, g=g, lv=lv, raw=raw, rgb=rgb, S=S, E=E)
+
+
+@pytest.mark.parametrize("mode", list(FRAME_MODES))
+def test_frame_size_modes_sampled(ctx, qtail, frame_env, mode):
+    """1920x1080 frame, R=256, K=8, M=8, in the launch configuration the
+    benchmark times for the mode, with the GPU's own pyramid and LUTs fed to
+    both sides; 12k sampled pixels against the oracle."""
+    f, opts = frame_env, dict(FRAME_MODES[mode])
+    w, g = f["w"], dict(f["g"])
+    extra = opts.pop("extra", None)
+    if extra == "visibility":
+        g["visibility"] = synth.contact_visibility(g)
+    elif extra == "tangent":
+        g["tx"], g["ty"], g["tz"] = synth.surface_tangents(g)
+    elif extra == "jacobian":
+        g["dudx"], g["dudy"], g["dvdx"], g["dvdy"] = synth.uv_jacobian(g, w.W, w.H)
+    V = opts.pop("vertices", 1)
+    U.log(f"frame-size mode {mode}")
+    gpu = U.shade(ctx, g, f["raw"], f["rgb"], f["lv"], f["S"], f["E"], w.R, w.K, w.M, seed=w.hash_seed, vertices=V,
+                  qtail=qtail, **opts)
+    rng = np.random.default_rng(7)
+    hit = np.nonzero(g["surf_id"] != synth.NO_SURFACE)[0]
+    pix = np.sort(np.concatenate([rng.choice(hit, 12000, replace=False), np.arange(0, len(g["nx"]), 997)]))
+    orc = oracle.shade(g, f["raw"], f["rgb"], f["lv"], f["S"], f["E"], w.R, w.K, w.M, w.hash_seed, V, pixels=pix, **opts)
+    sub = {k: v[pix] for k, v in gpu.items()}
+    check_pixels(sub, orc, f"frame {mode}", max_flagged=2e-2)
