@@ -272,7 +272,8 @@ int glint_build_quantile_table(glint_ctx ctx, double *table, void *stream);
  *    probability 1 - (1-p)^N without bias, floor of the same clamped
  *    Gaussian.
  * Single-gated forms return nbar = max(N - n, 0).  Gates are evaluated in
- * float (powf), the Gaussian (AS 241) in double.
+ * float (the decisions of powf thresholds; exact_gating = 1 evaluates powf
+ * for every draw), the Gaussian (AS 241) in double.
  * All arrays are device memory of `count` elements; quantile_tail may be
  * NULL (see glint_build_quantile_table).  code: bits as in
  * glint_shade_debug for the dual form; 1 = gate passed, 16 = Gaussian for

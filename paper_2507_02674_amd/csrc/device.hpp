@@ -477,6 +477,37 @@ __device__ __forceinline__ float single_gate_threshold(int form, float Nf, float
     return 1.0f - powf(1.0f - pf, Nf);
 }
 
+// The single gate's decision xi1 < threshold, first from the power taken
+// with the hardware log2/exp2 (the bound of gate_decide: relative error
+// below 2^-17 above 2^-64, and the minimum with the exact N p moves the
+// threshold by no more than the power), falling back to powf within
+// 2^-14 P + 2^-22 of the approximate threshold.
+__device__ __forceinline__ bool single_gate_decide(int form, float Nf, float pf, float xi1, bool exact_only)
+{
+#pragma clang fp contract(off)
+    if (!exact_only) {
+        float base, ex;
+        if (form == 1) {
+            const float eps = 2.8840315031266055e-04f; // 10^-3.54
+            base = 1.0f - fmaxf(pf, eps);
+            ex = Nf * fminf(1.0f, pf / eps);
+        } else {
+            base = 1.0f - pf;
+            ex = Nf;
+        }
+        const float P = __builtin_amdgcn_exp2f(ex * __builtin_amdgcn_logf(base));
+        const float pany = 1.0f - P;
+        float th = pany;
+        if (form == 1) {
+            const float np = Nf * pf;
+            th = np < pany ? np : pany;
+        }
+        const float margin = 6.103515625e-05f * P + 2.384185791015625e-07f; // 2^-14 P + 2^-22
+        if (fabsf(xi1 - th) > margin) return xi1 < th;
+    }
+    return xi1 < single_gate_threshold(form, Nf, pf);
+}
+
 // Learned-surrogate inputs of a lookup (the project's extension, not the
 // paper's): the reflection direction, then (ln alpha - c) / h for alpha_x
 // and alpha_y, where c and h map [ln 0.02, ln 0.5] onto [-1, 1].

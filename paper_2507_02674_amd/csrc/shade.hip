@@ -233,15 +233,15 @@ __device__ __forceinline__ void dual_gated(double N, double p, float xi1, float 
 // (floor, no bias, no N < 1 generalisation).  The negative count is what
 // remains, max(N - n, 0).
 __device__ __forceinline__ void single_gated(int form, double N, double p, float xi1, float xi2, uint32_t h9,
-                                             const double *__restrict__ qtail, double &n, double &nb,
-                                             uint32_t &code)
+                                             const double *__restrict__ qtail, bool exact_gating, double &n,
+                                             double &nb, uint32_t &code)
 {
 #pragma clang fp contract(off)
     uint32_t tidx = 0;
     const bool tail = tail_index(h9, tidx);
     double ztab = 0.0;
     if (qtail && tail) ztab = qtail[tidx];
-    const bool hit = xi1 < single_gate_threshold(form, (float)N, (float)p);
+    const bool hit = single_gate_decide(form, (float)N, (float)p, xi1, exact_gating);
     const bool BG = hit && N > 1.0;
     double c = hit ? 1.0 : 0.0;
     if (BG) {
@@ -267,7 +267,7 @@ __device__ __forceinline__ void node_sample(int sampler, double N, double p, flo
                                             const double *__restrict__ qtail, bool exact_gating, double &n,
                                             double &nb, uint32_t &code)
 {
-    if constexpr (SG) single_gated(sampler, N, p, xi1, xi2, h9, qtail, n, nb, code);
+    if constexpr (SG) single_gated(sampler, N, p, xi1, xi2, h9, qtail, exact_gating, n, nb, code);
     else dual_gated(N, p, xi1, xi2, h9, qtail, exact_gating, n, nb, code);
 }
 

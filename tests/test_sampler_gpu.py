@@ -88,12 +88,17 @@ def test_sample_binomial_matches_oracle(ctx, qtail, sampler, with_table):
     check_draws(gpu, orc, f"sampler {sampler}")
 
 
-def test_sample_binomial_exact_gating_path(ctx, qtail):
-    """The dual gate's exact (powf everywhere) path gives the same draws."""
+@pytest.mark.parametrize("sampler", SAMPLERS)
+def test_sample_binomial_exact_gating_path(ctx, qtail, sampler):
+    """The gates' exact (powf everywhere) path gives the same draws as the
+    hardware log2/exp2 path with its powf fallback."""
     N, p, h1, h2 = inputs(50_000, 3)
-    a = gpu_draw(ctx, G.GLINT_SAMPLER_DUAL, N, p, h1, h2, qtail, exact_gating=1)
-    orc = oracle.sample_binomial(G.GLINT_SAMPLER_DUAL, N, p, h1, h2)
-    check_draws(a, orc, "exact gating")
+    a = gpu_draw(ctx, sampler, N, p, h1, h2, qtail, exact_gating=1)
+    b = gpu_draw(ctx, sampler, N, p, h1, h2, qtail, exact_gating=0)
+    orc = oracle.sample_binomial(sampler, N, p, h1, h2)
+    check_draws(a, orc, f"exact gating sampler {sampler}")
+    for k in ("n", "nb", "code"):
+        assert np.array_equal(a[k], b[k]), k
 
 
 def test_sample_binomial_edge_sizes_and_errors(ctx):
