@@ -393,3 +393,32 @@ def test_frame_size_modes_sampled(ctx, qtail, frame_env, mode):
     orc = oracle.shade(g, f["raw"], f["rgb"], f["lv"], f["S"], f["E"], w.R, w.K, w.M, w.hash_seed, V, pixels=pix, **opts)
     sub = {k: v[pix] for k, v in gpu.items()}
     check_pixels(sub, orc, f"frame {mode}", max_flagged=2e-2)
+
+
+@pytest.mark.parametrize("mode", list(FRAME_MODES))
+def test_modes_ragged_sizes_and_empty(ctx, qtail, mode):
+    """Every mode on 1 and 257 pixels against the oracle, and 0 pixels as a
+    no-op."""
+    R, K, M = 16, 8, 5
+    env = synth.make_env(R, 6)
+    levels, ind, rgb = oracle_env(env, K, M)
+    S, E = oracle.lut_tables()
+    W, H = 64, 36
+    g = synth.scene_frame(W, H, seed=9, density_decades=(0.0, 8.0))
+    opts = dict(FRAME_MODES[mode])
+    extra = opts.pop("extra", None)
+    if extra == "visibility":
+        g["visibility"] = synth.contact_visibility(g)
+    elif extra == "tangent":
+        g["tx"], g["ty"], g["tz"] = synth.surface_tangents(g)
+    elif extra == "jacobian":
+        g["dudx"], g["dudy"], g["dvdx"], g["dvdy"] = synth.uv_jacobian(g, W, H)
+    V = opts.pop("vertices", 1)
+    hit = np.nonzero(g["surf_id"] != synth.NO_SURFACE)[0]
+    for P in (1, 257):
+        sub = synth.subsample_gbuf(g, hit[:P])  # the optional fields too
+        gpu = U.shade(ctx, sub, ind, rgb, levels, S, E, R, K, M, seed=3, vertices=V, qtail=qtail, **opts)
+        orc = oracle.shade(sub, ind, rgb, levels, S, E, R, K, M, 3, V, **opts)
+        check_pixels(gpu, orc, f"{mode} P={P}", max_flagged=1.0)
+    out = U.shade(ctx, g, ind, rgb, levels, S, E, R, K, M, num_pixels=0, vertices=V, debug=False, qtail=qtail, **opts)
+    assert out["radiance"].shape[0] == 0
