@@ -14,6 +14,11 @@ numpy arrays into it and chains its steps in the paper's order:
   -> :func:`luts`
 * Sec. 3.2 (N_P), Sec. 4 Eq. (probhk) and Eq. (iblglints:fin), Sec. 6 and
   Alg. "Dual-gated Gaussian" -> :func:`shade`
+* Sec. 6 "Single-Gated Gaussians" / "Gating Generalization", Eq. (gated),
+  Eq. (oldgated) -> :func:`sample_binomial`, ``shade(sampler=...)``
+* Sec. 3.3 footprint grid -> :func:`footprint_grid`, ``shade(vertices=12)``;
+  Sec. 8 anisotropic lookup and occlusion, Sec. 7 comparison method ->
+  ``shade(lobe_taps=..., prob_mode=..., gbuf["visibility"])``
 
 Pins (tests/test_oracle_*.py): every step is checked against closed forms,
 invariants, library routines or brute force, except the per-footprint hash
