@@ -370,21 +370,46 @@ __device__ __forceinline__ bool mlp_pad(int p, int K)
     return false;
 }
 
-// Sums the per-block gradients in block order (deterministic), applies one
-// Adam step to the float master and refreshes the bf16 copy; pads stay zero.
-__global__ void __launch_bounds__(256) k_mlp_adam(const float *__restrict__ partial, int blocks, int K,
-                                                  float *__restrict__ w, uint16_t *__restrict__ wb,
-                                                  float *__restrict__ m, float *__restrict__ v, int step, float lr,
-                                                  const float *__restrict__ loss_partial, int B,
-                                                  float *__restrict__ loss_out)
+// Sum of the per-block partial gradients of parameter p: a block of 256
+// threads covers 64 parameters (lane) x 4 slices (wave); slice s adds the
+// partials s, s + 4, ... in order, and the four slice sums are combined as
+// (s0 + s1) + (s2 + s3) (a fixed order: results are deterministic).  Every
+// thread of the block must call it (a barrier); p >= kParams contribute 0.
+constexpr int kReduceParams = 64, kReduceSlices = 4;
+
+__device__ __forceinline__ float reduce_partials(const float *__restrict__ partial, int blocks, int p)
 {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p == 0) {
+    __shared__ float s_part[kReduceSlices][kReduceParams];
+    const int lane = threadIdx.x % kReduceParams, slice = threadIdx.x / kReduceParams;
+    float g = 0.0f;
+    if (p < kParams)
+        for (int b = slice; b < blocks; b += kReduceSlices) g += partial[(int64_t)b * kParams + p];
+    s_part[slice][lane] = g;
+    __syncthreads();
+    return (s_part[0][lane] + s_part[1][lane]) + (s_part[2][lane] + s_part[3][lane]);
+}
+
+__device__ __forceinline__ void reduce_loss(const float *__restrict__ loss_partial, int blocks, int B,
+                                            float *__restrict__ loss_out)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
         float s = 0.0f;
         for (int b = 0; b < blocks; ++b) s += loss_partial[b];
         *loss_out = s / (float)B;
     }
-    if (p >= kParams) return;
+}
+
+// Gradient reduction and one Adam step (beta 0.9, 0.999, eps 1e-8) on the
+// float master, then its bfloat16 copy; pad entries stay 0.
+__global__ void __launch_bounds__(kReduceParams * kReduceSlices) k_mlp_adam(
+    const float *__restrict__ partial, int blocks, int K, float *__restrict__ w, uint16_t *__restrict__ wb,
+    float *__restrict__ m, float *__restrict__ v, int step, float lr, const float *__restrict__ loss_partial, int B,
+    float *__restrict__ loss_out)
+{
+    reduce_loss(loss_partial, blocks, B, loss_out);
+    const int p = blockIdx.x * kReduceParams + (int)(threadIdx.x % kReduceParams);
+    const float g = reduce_partials(partial, blocks, p);
+    if (threadIdx.x >= kReduceParams || p >= kParams) return; // slice 0 writes
     if (mlp_pad(p, K)) {
         w[p] = 0.0f;
         wb[p] = 0;
@@ -392,8 +417,6 @@ __global__ void __launch_bounds__(256) k_mlp_adam(const float *__restrict__ part
         v[p] = 0.0f;
         return;
     }
-    float g = 0.0f;
-    for (int b = 0; b < blocks; ++b) g += partial[(int64_t)b * kParams + p];
     const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
     const float mm = b1 * m[p] + (1.0f - b1) * g;
     const float vv = b2 * v[p] + (1.0f - b2) * g * g;
@@ -406,21 +429,15 @@ __global__ void __launch_bounds__(256) k_mlp_adam(const float *__restrict__ part
     wb[p] = to_bf16(nw);
 }
 
-// Full-batch gradient (block-order sum of the partials) and mean loss.
-__global__ void __launch_bounds__(256) k_mlp_sum(const float *__restrict__ partial, int blocks,
-                                                 const float *__restrict__ loss_partial, int B,
-                                                 float *__restrict__ grad, float *__restrict__ loss_out)
+// Gradient reduction only (the gradient entry point).
+__global__ void __launch_bounds__(kReduceParams * kReduceSlices) k_mlp_sum(
+    const float *__restrict__ partial, int blocks, const float *__restrict__ loss_partial, int B,
+    float *__restrict__ grad, float *__restrict__ loss_out)
 {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p == 0) {
-        float s = 0.0f;
-        for (int b = 0; b < blocks; ++b) s += loss_partial[b];
-        *loss_out = s / (float)B;
-    }
-    if (p >= kParams) return;
-    float g = 0.0f;
-    for (int b = 0; b < blocks; ++b) g += partial[(int64_t)b * kParams + p];
-    grad[p] = g;
+    reduce_loss(loss_partial, blocks, B, loss_out);
+    const int p = blockIdx.x * kReduceParams + (int)(threadIdx.x % kReduceParams);
+    const float g = reduce_partials(partial, blocks, p);
+    if (threadIdx.x < kReduceParams && p < kParams) grad[p] = g;
 }
 
 // Zeroes the pad entries of the float master and writes the bf16 copy.
@@ -560,7 +577,8 @@ hipError_t launch_mlp_grad_step(const float *x, const float *target, int B, int 
         GLINT_LAUNCH("k_mlp_grad", k_mlp_grad, dim3(blocks), dim3(64), 0, stream, x, target, B, K, w, wb, partial,
                            loss_partial);
     }
-    GLINT_LAUNCH("k_mlp_adam", k_mlp_adam, dim3((kParams + 255) / 256), dim3(256), 0, stream, partial, blocks, K, w, wb, m,
+    GLINT_LAUNCH("k_mlp_adam", k_mlp_adam, dim3((kParams + kReduceParams - 1) / kReduceParams),
+                 dim3(kReduceParams * kReduceSlices), 0, stream, partial, blocks, K, w, wb, m,
                        v, step, lr, loss_partial, B, loss_out);
     return hipGetLastError();
 }
@@ -574,7 +592,8 @@ hipError_t launch_mlp_gradient(const float *x, const float *target, int B, int K
         GLINT_LAUNCH("k_mlp_grad", k_mlp_grad, dim3(blocks), dim3(64), 0, stream, x, target, B, K, w, wb, partial,
                            loss_partial);
     }
-    GLINT_LAUNCH("k_mlp_sum", k_mlp_sum, dim3((kParams + 255) / 256), dim3(256), 0, stream, partial, blocks, loss_partial, B,
+    GLINT_LAUNCH("k_mlp_sum", k_mlp_sum, dim3((kParams + kReduceParams - 1) / kReduceParams),
+                 dim3(kReduceParams * kReduceSlices), 0, stream, partial, blocks, loss_partial, B,
                        grad, loss_out);
     return hipGetLastError();
 }
