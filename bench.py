@@ -184,6 +184,9 @@ def parse():
     ap.add_argument("--env", default="dynamic", choices=["dynamic", "static"],
                     help="dynamic: the map is partitioned and prefiltered every frame (the headline); static: "
                          "prefiltered once, frames shade only (the paper's two runtime scenarios)")
+    ap.add_argument("--buffers", type=int, default=3,
+                    help="environment buffer sets of the overlapped frame pipeline (the environment work runs "
+                         "up to buffers - 1 frames ahead of the shading)")
     ap.add_argument("--no-overlap", action="store_true",
                     help="run frames back to back on one stream (no environment/shading overlap)")
     ap.add_argument("--cpu-sample", type=float, default=1.0 / 48.0,
@@ -420,7 +423,7 @@ def main():
                 shader.run(pipe.env_struct())
         frames = _Static()
     else:
-        frames = FramePipeline(new_env, shader, overlap=not a.no_overlap)
+        frames = FramePipeline(new_env, shader, overlap=not a.no_overlap, buffers=a.buffers)
         frames.build_luts()
     for _ in range(a.warmup):
         frames.step(env)

@@ -287,21 +287,24 @@ class SurrogateShader(Shader):
 
 
 class FramePipeline:
-    """Per-frame path with the environment work of frame f+1 overlapping the
-    shading of frame f: two sets of environment buffers used alternately, the
-    environment kernels on one stream and shading on another, ordered by
-    events (a buffer set is refilled only after the shading that read it).
+    """Per-frame path with the environment work of later frames overlapping
+    the shading of frame f: `buffers` sets of environment buffers used in
+    turn (three by default, so the environment stream can run up to two
+    frames ahead), the environment kernels on one stream and shading on
+    another, ordered by events (a buffer set is refilled only after the
+    shading that read it).
 
     env_factory() -> EnvPipeline, shader: Shader or SurrogateShader."""
 
-    def __init__(self, env_factory, shader, overlap=True):
-        self.pipes = [env_factory(), env_factory()] if overlap else [env_factory()]
+    def __init__(self, env_factory, shader, overlap=True, buffers=3):
+        self.nbuf = max(2, buffers) if overlap else 1
+        self.pipes = [env_factory() for _ in range(self.nbuf)]
         self.shader = shader
         self.overlap = overlap
         self.s_env = torch.cuda.Stream() if overlap else None
         self.s_shade = torch.cuda.Stream() if overlap else None
         self.frame = 0
-        self._shade_done = [None, None]
+        self._shade_done = [None] * self.nbuf
 
     def build_luts(self):
         for p in self.pipes:
@@ -315,7 +318,7 @@ class FramePipeline:
             self.shader.run(p.env_struct())
             self.frame += 1
             return
-        b = self.frame % 2
+        b = self.frame % self.nbuf
         p = self.pipes[b]
         with torch.cuda.stream(self.s_env):
             if self._shade_done[b] is not None:
