@@ -3,12 +3,14 @@
 // Sec. 3.4, Eq. (rtibl), n = v = r).
 //
 // Source mip chain: level 0 is virtual (dense weights 1-t, t expanded from
-// the packed indicator plus RGB from the map); levels >= 1 are stored float,
-// [texel][CP] with CP = K+3 rounded up to 4 (16-byte texel records), each
-// face with a one-texel border that holds the seam rule's value (the
-// adjacent face's texel beyond an edge, the mean of the three texels that
-// meet at a corner), so bilinear footprints on levels >= 1 never leave the
-// stored face:
+// the packed indicator plus RGB from the map); levels >= 1 are stored float
+// in CP/4 planes of float4 (CP = K+3 rounded up to 4): plane q of a level
+// holds channels 4q..4q+3 of every texel record, so lanes that read
+// neighbouring texels of one plane touch a third as many cache lines as with
+// 48-byte interleaved records.  Each face has a one-texel border that holds
+// the seam rule's value (the adjacent face's texel beyond an edge, the mean
+// of the three texels that meet at a corner), so bilinear footprints on
+// levels >= 1 never leave the stored face:
 //
 //   k_chain_tiles   per 32x32 tile of level 0: mip 0 of the output pyramid
 //                   (alpha = 0, the dense level) and chain levels 1..5 via
@@ -67,6 +69,28 @@ __host__ __device__ inline int64_t chain_level_base(int R, int s)
 __host__ __device__ inline int64_t chain_rec(int face, int x, int y, int n)
 {
     return ((int64_t)face * (n + 2) + (y + 1)) * (n + 2) + (x + 1);
+}
+
+// Floats per float4 plane of a stored level of face size n.
+__host__ __device__ inline int64_t chain_plane(int n)
+{
+    return 6LL * (n + 2) * (n + 2) * 4;
+}
+
+// Element k of record `rec` in a stored level (planes of `plane` floats).
+__device__ __forceinline__ int64_t chain_elem(int64_t plane, int64_t rec, int k)
+{
+    return (k >> 2) * plane + rec * 4 + (k & 3);
+}
+
+// Writes the CP floats of record `rec`.
+template <int CP>
+__device__ __forceinline__ void store_record(float *__restrict__ lvl, int64_t plane, int64_t rec, const float (&out)[CP])
+{
+#pragma unroll
+    for (int q = 0; q < CP / 4; ++q)
+        *reinterpret_cast<float4 *>(lvl + q * plane + rec * 4) =
+            make_float4(out[4 * q], out[4 * q + 1], out[4 * q + 2], out[4 * q + 3]);
 }
 
 // ---------------------------------------------------------------------------
@@ -147,53 +171,32 @@ struct Level0 {
 };
 
 template <int K>
-__device__ __forceinline__ void load_chain(const float *__restrict__ lvl, int64_t i, double (&v)[K + 3])
+__device__ __forceinline__ void load_chain(const float *__restrict__ lvl, int64_t plane, int64_t i,
+                                           double (&v)[K + 3])
 {
     constexpr int CP = chain_stride(K);
-    const float4 *p = reinterpret_cast<const float4 *>(lvl + i * CP);
     float buf[CP];
 #pragma unroll
     for (int q = 0; q < CP / 4; ++q) {
-        const float4 f = p[q];
+        const float4 f = *reinterpret_cast<const float4 *>(lvl + q * plane + i * 4);
         buf[4 * q] = f.x; buf[4 * q + 1] = f.y; buf[4 * q + 2] = f.z; buf[4 * q + 3] = f.w;
     }
 #pragma unroll
     for (int k = 0; k < K + 3; ++k) v[k] = (double)buf[k];
 }
 
-// acc += w * texel i of chain level s (level 0 expanded on the fly).
+// acc += w * (texel (x, y) of `face` on level 0, the virtual level) with the
+// seam rule: beyond a cube corner the texel is the mean of the three texels
+// meeting there, added as three terms of weight w/3.
 template <int K>
-__device__ __forceinline__ void add_texel(const Level0<K> &l0, const float *__restrict__ lvl, int s, int64_t i,
-                                          double w, double (&acc)[K + 3])
-{
-    constexpr int CP = chain_stride(K);
-    if (s == 0) {
-        l0.add(i, w, acc);
-    } else {
-        const float4 *q = reinterpret_cast<const float4 *>(lvl + i * CP);
-#pragma unroll
-        for (int q4 = 0; q4 < CP / 4; ++q4) {
-            const float4 f = q[q4];
-            const float fv[4] = {f.x, f.y, f.z, f.w};
-#pragma unroll
-            for (int e = 0; e < 4; ++e)
-                if (4 * q4 + e < K + 3) acc[4 * q4 + e] += w * (double)fv[e];
-        }
-    }
-}
-
-// acc += w * (texel (x, y) of `face` on level s) with the seam rule: beyond a
-// cube corner the texel is the mean of the three texels meeting there,
-// added as three terms of weight w/3.
-template <int K>
-__device__ __forceinline__ void accumulate_texel(const Level0<K> &l0, const float *__restrict__ lvl, int s, int face,
-                                                 int x, int y, int n, double w, double (&acc)[K + 3])
+__device__ __forceinline__ void accumulate_texel0(const Level0<K> &l0, int face, int x, int y, int n, double w,
+                                                  double (&acc)[K + 3])
 {
     int64_t idx[3];
     const int cnt = resolve_texel(face, x, y, n, idx);
     const double wc = cnt == 3 ? w / 3.0 : w;
 #pragma unroll 1
-    for (int e = 0; e < cnt; ++e) add_texel<K>(l0, lvl, s, e == 0 ? idx[0] : (e == 1 ? idx[1] : idx[2]), wc, acc);
+    for (int e = 0; e < cnt; ++e) l0.add(e == 0 ? idx[0] : (e == 1 ? idx[1] : idx[2]), wc, acc);
 }
 
 // ---------------------------------------------------------------------------
@@ -214,9 +217,9 @@ __global__ void __launch_bounds__(kChainThreads) k_chain_level(Level0<K> l0, con
         const int64_t c00 = ((int64_t)f * m + 2 * y) * m + 2 * x;
         l0.load(c00, a); l0.load(c00 + 1, b); l0.load(c00 + m, c); l0.load(c00 + m + 1, d);
     } else {
-        const int64_t c00 = chain_rec(f, 2 * x, 2 * y, m);
-        load_chain<K>(src, c00, a); load_chain<K>(src, c00 + 1, b);
-        load_chain<K>(src, c00 + m + 2, c); load_chain<K>(src, c00 + m + 3, d);
+        const int64_t c00 = chain_rec(f, 2 * x, 2 * y, m), ps = chain_plane(m);
+        load_chain<K>(src, ps, c00, a); load_chain<K>(src, ps, c00 + 1, b);
+        load_chain<K>(src, ps, c00 + m + 2, c); load_chain<K>(src, ps, c00 + m + 3, d);
     }
     float out[CP];
     {
@@ -226,9 +229,7 @@ __global__ void __launch_bounds__(kChainThreads) k_chain_level(Level0<K> l0, con
     }
 #pragma unroll
     for (int k = C; k < CP; ++k) out[k] = 0.0f;
-    float4 *q = reinterpret_cast<float4 *>(dst + chain_rec(f, x, y, n) * CP);
-#pragma unroll
-    for (int i = 0; i < CP / 4; ++i) q[i] = make_float4(out[4 * i], out[4 * i + 1], out[4 * i + 2], out[4 * i + 3]);
+    store_record<CP>(dst, chain_plane(n), chain_rec(f, x, y, n), out);
 }
 
 // ---------------------------------------------------------------------------
@@ -243,7 +244,7 @@ constexpr int kTile = 32;
 template <int K>
 __device__ __forceinline__ void mean4_store(const double (&a)[K + 3], const double (&b)[K + 3],
                                             const double (&c)[K + 3], const double (&d)[K + 3], float *lds_out,
-                                            float *__restrict__ gl_out)
+                                            float *__restrict__ gl_lvl, int64_t plane, int64_t rec)
 {
     constexpr int C = K + 3, CP = chain_stride(K);
     float out[CP];
@@ -256,9 +257,7 @@ __device__ __forceinline__ void mean4_store(const double (&a)[K + 3], const doub
     for (int k = C; k < CP; ++k) out[k] = 0.0f;
 #pragma unroll
     for (int k = 0; k < CP; ++k) lds_out[k] = out[k];
-    float4 *q = reinterpret_cast<float4 *>(gl_out);
-#pragma unroll
-    for (int i = 0; i < CP / 4; ++i) q[i] = make_float4(out[4 * i], out[4 * i + 1], out[4 * i + 2], out[4 * i + 3]);
+    store_record<CP>(gl_lvl, plane, rec, out);
 }
 
 template <int K>
@@ -284,7 +283,7 @@ __device__ __forceinline__ void reduce_lds_level(const float *src, float *dst, i
         lds_texel<K>(src + ((2 * y) * side + 2 * x + 1) * CP, b);
         lds_texel<K>(src + ((2 * y + 1) * side + 2 * x) * CP, c);
         lds_texel<K>(src + ((2 * y + 1) * side + 2 * x + 1) * CP, d);
-        mean4_store<K>(a, b, c, d, dst + o * CP, level_base + chain_rec(face, ox + x, oy + y, n) * CP);
+        mean4_store<K>(a, b, c, d, dst + o * CP, level_base, chain_plane(n), chain_rec(face, ox + x, oy + y, n));
     }
 }
 
@@ -320,7 +319,8 @@ __global__ void __launch_bounds__(256) k_chain_tiles(Level0<K> l0, int R, int M,
             const int64_t c00 = ((int64_t)face * R + gy) * R + gx;
             double a[K + 3], b[K + 3], c[K + 3], d[K + 3];
             l0.load(c00, a); l0.load(c00 + 1, b); l0.load(c00 + R, c); l0.load(c00 + R + 1, d);
-            mean4_store<K>(a, b, c, d, s_a + o * CP, base1 + chain_rec(face, tx * half + x, ty * half + y, n1) * CP);
+            mean4_store<K>(a, b, c, d, s_a + o * CP, base1, chain_plane(n1),
+                           chain_rec(face, tx * half + x, ty * half + y, n1));
         }
     }
     __syncthreads();
@@ -349,7 +349,7 @@ __global__ void __launch_bounds__(256) k_chain_faces(int R, int M, int first, fl
     const float *lvl0 = chain + chain_level_base(R, first - 1) * CP;
     for (int o = threadIdx.x; o < n0 * n0 * CP; o += blockDim.x) {
         const int tex = o / CP, k = o % CP;
-        src[o] = lvl0[chain_rec(face, tex % n0, tex / n0, n0) * CP + k];
+        src[o] = lvl0[chain_elem(chain_plane(n0), chain_rec(face, tex % n0, tex / n0, n0), k)];
     }
     __syncthreads();
     int side = n0;
@@ -406,23 +406,22 @@ __global__ void __launch_bounds__(256) k_chain_border(int R, int M, float *__res
         const int f = (int)(i / nn), rem = (int)(i % nn);
         rec[e] = chain_rec(f, rem % n, rem / n, n);
     }
+    const int64_t pl = chain_plane(n);
     float out[CP];
     if (cnt == 1) {
 #pragma unroll
-        for (int k = 0; k < CP; ++k) out[k] = lvl[rec[0] * CP + k];
+        for (int k = 0; k < CP; ++k) out[k] = lvl[chain_elem(pl, rec[0], k)];
     } else {
 #pragma clang fp contract(off)
 #pragma unroll
         for (int k = 0; k < C; ++k)
-            out[k] = (float)((((double)lvl[rec[0] * CP + k] + (double)lvl[rec[1] * CP + k]) +
-                              (double)lvl[rec[2] * CP + k]) /
+            out[k] = (float)((((double)lvl[chain_elem(pl, rec[0], k)] + (double)lvl[chain_elem(pl, rec[1], k)]) +
+                              (double)lvl[chain_elem(pl, rec[2], k)]) /
                              3.0);
 #pragma unroll
         for (int k = C; k < CP; ++k) out[k] = 0.0f;
     }
-    float4 *q = reinterpret_cast<float4 *>(lvl + chain_rec(face, x, y, n) * CP);
-#pragma unroll
-    for (int i = 0; i < CP / 4; ++i) q[i] = make_float4(out[4 * i], out[4 * i + 1], out[4 * i + 2], out[4 * i + 3]);
+    store_record<CP>(lvl, pl, chain_rec(face, x, y, n), out);
 }
 
 // ---------------------------------------------------------------------------
@@ -500,13 +499,15 @@ __device__ __forceinline__ void accumulate_tap(const Tap &tp, const d3 &r, const
                               lw1 * (b1.fy * (1.0 - b1.fx)),         lw1 * (b1.fy * b1.fx)};
         const float *lv0 = chain + lvl_off[s0], *lv1 = chain + lvl_off[s1];
         const int64_t a0 = chain_rec(fs.face, b0.x0, b0.y0, n0), a1 = chain_rec(fs.face, b1.x0, b1.y0, n1);
-        const float *src[8] = {lv0 + a0 * CP, lv0 + (a0 + 1) * CP, lv0 + (a0 + n0 + 2) * CP, lv0 + (a0 + n0 + 3) * CP,
-                               lv1 + a1 * CP, lv1 + (a1 + 1) * CP, lv1 + (a1 + n1 + 2) * CP, lv1 + (a1 + n1 + 3) * CP};
+        const int64_t p0 = chain_plane(n0), p1 = chain_plane(n1);
+        const float *src[8] = {lv0 + a0 * 4, lv0 + (a0 + 1) * 4, lv0 + (a0 + n0 + 2) * 4, lv0 + (a0 + n0 + 3) * 4,
+                               lv1 + a1 * 4, lv1 + (a1 + 1) * 4, lv1 + (a1 + n1 + 2) * 4, lv1 + (a1 + n1 + 3) * 4};
         float4 raw[8][CP / 4];
 #pragma unroll
         for (int c = 0; c < 8; ++c)
 #pragma unroll
-            for (int q4 = 0; q4 < CP / 4; ++q4) raw[c][q4] = reinterpret_cast<const float4 *>(src[c])[q4];
+            for (int q4 = 0; q4 < CP / 4; ++q4)
+                raw[c][q4] = *reinterpret_cast<const float4 *>(src[c] + q4 * (c < 4 ? p0 : p1));
 #pragma unroll
         for (int c = 0; c < 8; ++c) {
             const float *f = reinterpret_cast<const float *>(raw[c]);
@@ -527,13 +528,14 @@ __device__ __forceinline__ void accumulate_tap(const Tap &tp, const d3 &r, const
         const float *lvl = chain + lvl_off[s]; // global pointer arithmetic: global loads
         if (s > 0) {
             // stored level: the bordered face holds the whole footprint
-            const int64_t t0 = chain_rec(fs.face, bl.x0, bl.y0, ns);
+            const int64_t t0 = chain_rec(fs.face, bl.x0, bl.y0, ns), pl = chain_plane(ns);
             const int64_t tt[4] = {t0, t0 + 1, t0 + ns + 2, t0 + ns + 3};
             float4 raw[4][CP / 4];
 #pragma unroll
             for (int c = 0; c < 4; ++c)
 #pragma unroll
-                for (int q4 = 0; q4 < CP / 4; ++q4) raw[c][q4] = reinterpret_cast<const float4 *>(lvl + tt[c] * CP)[q4];
+                for (int q4 = 0; q4 < CP / 4; ++q4)
+                    raw[c][q4] = *reinterpret_cast<const float4 *>(lvl + q4 * pl + tt[c] * 4);
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
                 const float *f = reinterpret_cast<const float *>(raw[c]);
@@ -550,8 +552,8 @@ __device__ __forceinline__ void accumulate_tap(const Tap &tp, const d3 &r, const
             // level 0 across a seam: one copy of the seam rule
 #pragma unroll 1
             for (int c = 0; c < 4; ++c)
-                accumulate_texel<K>(l0, lvl, 0, fs.face, bl.x0 + (c & 1), bl.y0 + (c >> 1), ns,
-                                    c == 0 ? w4[0] : (c == 1 ? w4[1] : (c == 2 ? w4[2] : w4[3])), acc);
+                accumulate_texel0<K>(l0, fs.face, bl.x0 + (c & 1), bl.y0 + (c >> 1), ns,
+                                     c == 0 ? w4[0] : (c == 1 ? w4[1] : (c == 2 ? w4[2] : w4[3])), acc);
         }
     }
 }

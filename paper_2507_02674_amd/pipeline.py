@@ -292,7 +292,10 @@ class FramePipeline:
     turn (three by default, so the environment stream can run up to two
     frames ahead), the environment kernels on one stream and shading on
     another, ordered by events (a buffer set is refilled only after the
-    shading that read it).
+    shading that read it).  Both streams are non-blocking pool streams: each
+    frame first waits for the work already enqueued on the caller's current
+    stream (the lookup tables of build_luts, the map, the G-buffer), and
+    the frame's radiance is complete once s_shade reaches it.
 
     env_factory() -> EnvPipeline, shader: Shader or SurrogateShader."""
 
@@ -320,6 +323,9 @@ class FramePipeline:
             return
         b = self.frame % self.nbuf
         p = self.pipes[b]
+        caller = torch.cuda.current_stream()
+        self.s_env.wait_stream(caller)
+        self.s_shade.wait_stream(caller)
         with torch.cuda.stream(self.s_env):
             if self._shade_done[b] is not None:
                 self.s_env.wait_event(self._shade_done[b])

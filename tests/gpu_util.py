@@ -47,16 +47,19 @@ def prefilter(ctx, env, ind_j, ind_t, K, M, T=64, dtype=G.GLINT_F32):
 
 
 def chain_levels(ws, R, K, M, borders=False):
-    """Chain levels 1..M-1 from the prefilter workspace: each level is stored
-    as 6 faces of (n+2)^2 records of CP floats (a one-texel border around
-    each face).  Returns the interiors concatenated [texels, K+3] (the
-    oracle's layout), or with borders=True the list of [6, n+2, n+2, K+3]."""
+    """Chain levels 1..M-1 from the prefilter workspace: each level holds
+    6 faces of (n+2)^2 texel records (a one-texel border around each face)
+    of CP floats, stored as CP/4 planes of float4 (plane q: channels
+    4q..4q+3 of every record).  Returns the interiors concatenated
+    [texels, K+3] (the oracle's layout), or with borders=True the list of
+    [6, n+2, n+2, K+3]."""
     CP = (K + 3 + 3) & ~3
     out, o = [], 0
     for s in range(1, M):
         n = R >> s
         cnt = 6 * (n + 2) * (n + 2) * CP
-        lvl = ws[o:o + cnt].reshape(6, n + 2, n + 2, CP)[..., : K + 3]
+        planes = ws[o:o + cnt].reshape(CP // 4, 6, n + 2, n + 2, 4)
+        lvl = np.moveaxis(planes, 0, 3).reshape(6, n + 2, n + 2, CP)[..., : K + 3]
         out.append(lvl if borders else lvl[:, 1:-1, 1:-1].reshape(-1, K + 3))
         o += cnt
     if borders:
