@@ -163,8 +163,9 @@ SAMPLERS = {"dual": 0, "single": 1, "single-floor": 2}
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=100,
+                    help="untimed frames first (the GPU reaches its steady clocks after ~50 ms of work)")
     ap.add_argument("--workload", default="frame")
     ap.add_argument("--form", default="plain", choices=["plain", "surrogate"])
     ap.add_argument("--dtype", default="f32", choices=["f32", "f16", "bf16", "unorm16"])

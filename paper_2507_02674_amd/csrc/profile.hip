@@ -39,6 +39,15 @@ hipEvent_t Profiler::event()
     return e;
 }
 
+void Profiler::reserve(size_t n)
+{
+    while (pool.size() < n) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return;
+        pool.push_back(e);
+    }
+}
+
 hipError_t Profiler::collect()
 {
     hipError_t err = hipSuccess;

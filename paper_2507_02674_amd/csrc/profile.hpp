@@ -37,6 +37,9 @@ struct Profiler {
     std::vector<ProfSummary> summary;
     ~Profiler();
     hipEvent_t event();
+    // Creates events until the pool holds n (so that timed launches do not
+    // create events themselves).
+    void reserve(size_t n);
     // Waits for every recorded event, folds the records into `summary`
     // (adding to what it holds) and recycles the events.
     hipError_t collect();

@@ -307,7 +307,13 @@ class FramePipeline:
         self.s_env = torch.cuda.Stream() if overlap else None
         self.s_shade = torch.cuda.Stream() if overlap else None
         self.frame = 0
-        self._shade_done = [None] * self.nbuf
+        # events reused frame after frame (creating them costs host time):
+        # a wait enqueued on a stream waits for the event's latest record
+        self._caller_ev = torch.cuda.Event()
+        self._env_done = [torch.cuda.Event() for _ in range(self.nbuf)]
+        self._shade_done = [torch.cuda.Event() for _ in range(self.nbuf)]
+        self._recorded = [False] * self.nbuf
+        self._env_structs = [p.env_struct() for p in self.pipes]
 
     def build_luts(self):
         for p in self.pipes:
@@ -323,21 +329,18 @@ class FramePipeline:
             return
         b = self.frame % self.nbuf
         p = self.pipes[b]
-        caller = torch.cuda.current_stream()
-        self.s_env.wait_stream(caller)
-        self.s_shade.wait_stream(caller)
-        with torch.cuda.stream(self.s_env):
-            if self._shade_done[b] is not None:
-                self.s_env.wait_event(self._shade_done[b])
-            p.run(env, stream=self.s_env)
-            env_done = torch.cuda.Event()
-            env_done.record(self.s_env)
-        with torch.cuda.stream(self.s_shade):
-            self.s_shade.wait_event(env_done)
-            self.shader.run(p.env_struct(), stream=self.s_shade)
-            done = torch.cuda.Event()
-            done.record(self.s_shade)
-        self._shade_done[b] = done
+        self._caller_ev.record(torch.cuda.current_stream())
+        self.s_env.wait_event(self._caller_ev)
+        self.s_shade.wait_event(self._caller_ev)
+        if self._recorded[b]:
+            # the buffer set is refilled only after the shading that read it
+            self.s_env.wait_event(self._shade_done[b])
+        p.run(env, stream=self.s_env)
+        self._env_done[b].record(self.s_env)
+        self.s_shade.wait_event(self._env_done[b])
+        self.shader.run(self._env_structs[b], stream=self.s_shade)
+        self._shade_done[b].record(self.s_shade)
+        self._recorded[b] = True
         self.frame += 1
 
     def streams(self):

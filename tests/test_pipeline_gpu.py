@@ -50,3 +50,38 @@ def test_overlapped_frames_equal_serial_frames(ctx, buffers):
         assert torch.equal(got[f], ref_sh.radiance), f
     # consecutive frames differ (the maps differ), so equality is not vacuous
     assert not torch.equal(got[0], got[1])
+
+
+def test_frames_wait_for_the_callers_stream(ctx):
+    """Tables built on the caller's stream behind a long-running kernel are
+    complete before any frame reads them (the pipeline's streams do not
+    synchronise with the caller's stream by themselves)."""
+    import torch
+    from paper_2507_02674_amd.pipeline import EnvPipeline, FramePipeline, Shader
+    R, K, M, T = 32, 8, 6, 64
+    U.log("frame pipeline behind a busy caller stream")
+    env = torch.from_numpy(synth.make_env(R, 3)).cuda()
+    g = synth.scene_frame(192, 108, seed=2, density_decades=(2.0, 8.0))
+    shader = Shader(ctx, g, seed=5)
+    frames = FramePipeline(lambda: EnvPipeline(ctx, R, K, M, T), shader, overlap=True, buffers=3)
+    # finite but wrong tables (S = 0 reflects nothing) until build_luts runs
+    for p in frames.pipes:
+        for t in (p.lut_S, p.lut_E, p.qtail):
+            t.zero_()
+    torch.cuda.synchronize()
+    torch.cuda._sleep(50_000_000)  # a bounded spin on the caller's stream (~20 ms)
+    frames.build_luts()
+    got = []
+    for f in range(3):
+        frames.step(env)
+        with torch.cuda.stream(frames.s_shade):
+            got.append(shader.radiance.clone())
+    torch.cuda.synchronize()
+    ref_pipe = EnvPipeline(ctx, R, K, M, T)
+    ref_pipe.build_luts()
+    ref_pipe.run(env)
+    ref_sh = Shader(ctx, g, seed=5)
+    ref_sh.run(ref_pipe.env_struct())
+    torch.cuda.synchronize()
+    for f in range(3):
+        assert torch.equal(got[f], ref_sh.radiance), f
