@@ -79,6 +79,9 @@ def _declare(L):
     L.orc_sample_binomial.argtypes = [C.c_int, f64p, f64p, u32p, u32p, C.c_int64, f64p, f64p, u8p, u8p, C.c_int]
     L.orc_gate_probs.argtypes = [C.c_float, C.c_float, f32p]
     L.orc_dual_gated.argtypes = [C.c_double, C.c_double, C.c_float, C.c_float, f64p, f64p, u8p]
+    L.orc_multinomial.argtypes = [C.c_int, C.c_double, f64p, C.c_int, C.c_uint32, C.c_uint32, C.c_int32,
+                                  C.c_int64, C.c_int64, f64p, u8p]
+    L.orc_multinomial.restype = C.c_int
     L.orc_face_dir.argtypes = [C.c_int, C.c_double, C.c_double, f64p]
     L.orc_dir_face.argtypes = [f64p, f64p]
     L.orc_dir_face.restype = C.c_int
@@ -294,6 +297,21 @@ def dual_gated(N: float, p: float, xi1: float, xi2: float):
     n, nb, code = C.c_double(), C.c_double(), C.c_uint8()
     lib().orc_dual_gated(N, p, xi1, xi2, C.byref(n), C.byref(nb), C.byref(code))
     return n.value, nb.value, code.value
+
+
+def multinomial(sampler: int, NP: float, p, seed: int, surf: int, level: int, a: int, b: int):
+    """One hierarchical multinomial draw (Sec. 6) of N_P facets over the
+    given probabilities, hashed as a V = 1 shading draw at lattice vertex
+    (a, b) of `level`.  Returns (counts [K], codes [K-1], flags)."""
+    p = np.ascontiguousarray(p, dtype=np.float64)
+    K = len(p)
+    M = np.zeros(K)
+    codes = np.zeros(K - 1, np.uint8)
+    fl = lib().orc_multinomial(sampler, float(NP), _p(p, C.c_double), K, seed, surf, level, a, b,
+                               _p(M, C.c_double), _p(codes, C.c_uint8))
+    if fl < 0:
+        raise ValueError("orc_multinomial rejected its arguments")
+    return M, codes, fl
 
 
 def sample_binomial(sampler: int, N, p, h1, h2, threads=None):

@@ -673,12 +673,18 @@ typedef struct {
     double n, nb;
     uint8_t code;
     int flag;
+    /* the count varies continuously with the value of a Gaussian draw (of
+     * this node or above), whose last bits follow those of p: such a count
+     * can land on an integer on one implementation and just below it on
+     * another.  Counts formed from gating constants, clamp bounds, the
+     * floor of the prior single gate and N_P do not. */
+    int n_cont, nb_cont;
 } node_out;
 
 /* N_exact: N is computed exactly on every conforming implementation (the
  * root count N_P = density * area, an exact double product of two floats),
  * so its float rounding cannot differ. */
-static void dual_gated(double N, double p, float xi1, float xi2, int N_exact, node_out *o)
+static void dual_gated(double N, double p, float xi1, float xi2, int N_exact, int N_cont, node_out *o)
 {
     float Nf = (float)N, pf = (float)p;
     gate_t g;
@@ -696,6 +702,22 @@ static void dual_gated(double N, double p, float xi1, float xi2, int N_exact, no
     double Gb = N2 - G;
     o->n = (B_nN ? N2 - 1.0 : 0.0) + (B_n1N ? 1.0 : 0.0) + (B_G ? G : 0.0);
     o->nb = (B_nbN ? N2 - 1.0 : 0.0) + (B_nb1N ? 1.0 : 0.0) + (B_G ? Gb : 0.0);
+    /* per term: N2 follows N above 2; G and N2 - G follow the draw unless
+     * G is clamped (G = 1, N2 - G = N2 - 1; or G = N2 - 1, N2 - G = 1) or
+     * degenerate (N2 = 2: mean 1, spread 0, G = 1) */
+    int N2_cont = N_cont && N > 2.0;
+    int G_cont, Gb_cont;
+    if (x < 1.0 || N2 <= 2.0) {
+        G_cont = 0;
+        Gb_cont = N2_cont;
+    } else if (x > N2 - 1.0) {
+        G_cont = N2_cont;
+        Gb_cont = 0;
+    } else {
+        G_cont = Gb_cont = 1;
+    }
+    o->n_cont = (B_nN && N2_cont) || (B_G && G_cont);
+    o->nb_cont = (B_nbN && N2_cont) || (B_G && Gb_cont);
     o->code = (uint8_t)(B_nN | (B_n1N << 1) | (B_nbN << 2) | (B_nb1N << 3) | (B_G << 4));
     o->flag = gate_band_flag(&g, xi1) | (round_flag(p) << 1) | ((!N_exact && round_flag(N)) << 2);
 }
@@ -712,7 +734,8 @@ static void dual_gated(double N, double p, float xi1, float xi2, int N_exact, no
  * clamped Gaussian.
  * Both forms: the negative count is what remains, max(N - n, 0).  The gate
  * is evaluated in float, as the dual gate; the Gaussian in double. */
-static void single_gated(int form, double N, double p, float xi1, float xi2, int N_exact, node_out *o)
+static void single_gated(int form, double N, double p, float xi1, float xi2, int N_exact, int N_cont,
+                         node_out *o)
 {
     const float eps = (float)EPS_GATE;
     float Nf = (float)N, pf = (float)p;
@@ -748,6 +771,13 @@ static void single_gated(int form, double N, double p, float xi1, float xi2, int
     double r = N - n;
     o->n = n;
     o->nb = r > 0.0 ? r : 0.0;
+    /* past the gate: n is exact when clamped to a bound or floored (the
+     * floor's own ambiguity is flagged above) */
+    /* n: a gate constant, the floor (its own ambiguity flagged above) or a
+     * clamp bound, else the draw; the rest N - n follows both (0 when n
+     * reaches N) */
+    o->n_cont = gauss && form != 2 && n != 1.0 && (n != N1 || N_cont);
+    o->nb_cont = o->nb > 0.0 && (N_cont || o->n_cont);
     o->code = (uint8_t)(hit | (gauss << 4));
     double bandg = 9.5367431640625e-07 * (double)th + 5.9604644775390625e-08;
     fl |= fabs((double)xi1 - (double)th) <= bandg;
@@ -756,21 +786,24 @@ static void single_gated(int form, double N, double p, float xi1, float xi2, int
 
 /* The binomial approximation selected by `sampler`: 0 dual-gated (Alg.
  * "Dual-gated Gaussian"), 1 single-gated Eq. (gated), 2 Eq. (oldgated). */
-static void sample_node(int sampler, double N, double p, float xi1, float xi2, int N_exact, node_out *o)
+static void sample_node(int sampler, double N, double p, float xi1, float xi2, int N_exact, int N_cont,
+                        node_out *o)
 {
-    if (sampler == 0) dual_gated(N, p, xi1, xi2, N_exact, o);
-    else single_gated(sampler, N, p, xi1, xi2, N_exact, o);
+    if (sampler == 0) dual_gated(N, p, xi1, xi2, N_exact, N_cont, o);
+    else single_gated(sampler, N, p, xi1, xi2, N_exact, N_cont, o);
 }
 
 /* A sampled count is "near an integer" if it lies within 1e-5 of one
  * without being one, or, for counts so large that a double's spacing
  * approaches that band (beyond ~1e10), within 8 units in the last place:
- * there the evaluation order alone moves a count by a few ulps. */
-static int near_int_flag(double v)
+ * there the evaluation order alone moves a count by a few ulps.  A count
+ * that varies with a Gaussian draw (node_out.n_cont) and is itself an
+ * integer is near one too: another evaluation order lands just below it. */
+static int near_int_flag(double v, int cont)
 {
     double d = fabs(v - floor(v + 0.5));
     double band = 8.0 * (nextafter(fabs(v), INFINITY) - fabs(v));
-    return d > 0.0 && d < (band > 1e-5 ? band : 1e-5);
+    return (d > 0.0 || cont) && d < (band > 1e-5 ? band : 1e-5);
 }
 
 /* Sec. 6 (hierarchical multinomial from recursive binomials): balanced binary
@@ -782,11 +815,12 @@ static int multinomial(int sampler, double NP, int root_exact, const double *p, 
 {
     int nodes = K - 1;
     double Nn[32];
-    int lo_[32], hi_[32], exact[32];
+    int lo_[32], hi_[32], exact[32], cont[32];
     int flag = 0;
     /* exact[i]: node i's count is formed by exact operations on exact values
-     * (the root product, then gating outcomes without a Gaussian draw). */
-    Nn[0] = NP; lo_[0] = 0; hi_[0] = K; exact[0] = root_exact;
+     * (the root product, then gating outcomes without a Gaussian draw);
+     * cont[i]: it varies with a Gaussian draw's value (node_out). */
+    Nn[0] = NP; lo_[0] = 0; hi_[0] = K; exact[0] = root_exact; cont[0] = 0;
     for (int i = 0; i < nodes; ++i) {
         int lo = lo_[i], hi = hi_[i], mid = lo + (hi - lo) / 2;
         double sl = 0.0, sr = 0.0;
@@ -798,19 +832,21 @@ static int multinomial(int sampler, double NP, int root_exact, const double *p, 
         float xi1, xi2;
         hash_xi_key(seed, surf, key, a, b, i, &xi1, &xi2);
         node_out o;
-        sample_node(sampler, Nn[i], pn, xi1, xi2, exact[i], &o);
+        sample_node(sampler, Nn[i], pn, xi1, xi2, exact[i], cont[i], &o);
         codes[i] = o.code;
         flag |= o.flag;
         int c1 = 2 * i + 1, c2 = 2 * i + 2;
         Nn[c1] = o.n; lo_[c1] = lo; hi_[c1] = mid;
         Nn[c2] = o.nb; lo_[c2] = mid; hi_[c2] = hi;
         exact[c1] = exact[c2] = exact[i] && !(o.code & 16);
+        cont[c1] = o.n_cont;
+        cont[c2] = o.nb_cont;
     }
     /* leaves: heap slots nodes .. 2K-2 hold single bins, in order, for a
      * power-of-two K */
     for (int k = 0; k < K; ++k) {
         M[k] = Nn[nodes + k];
-        flag |= near_int_flag(M[k]) << 3;
+        flag |= near_int_flag(M[k], cont[nodes + k]) << 3;
     }
     return flag;
 }
@@ -1273,8 +1309,18 @@ void orc_gate_probs(float N, float p, float *out4)
 void orc_dual_gated(double N, double p, float xi1, float xi2, double *n, double *nb, uint8_t *code)
 {
     node_out o;
-    dual_gated(N, p, xi1, xi2, 0, &o);
+    dual_gated(N, p, xi1, xi2, 0, 1, &o);
     *n = o.n; *nb = o.nb; *code = o.code;
+}
+
+/* The hierarchical multinomial of one draw (Sec. 6) on given probabilities
+ * p[K] (K a power of two <= 16): leaf counts M[K], node codes[K-1]; returns
+ * the draw's flags (bit 8: a count near an integer). */
+int orc_multinomial(int sampler, double NP, const double *p, int K, uint32_t seed, uint32_t surf, int32_t level,
+                    int64_t a, int64_t b, double *M, uint8_t *codes)
+{
+    if (sampler < 0 || sampler > 2 || K < 2 || K > 16 || (K & (K - 1))) return -1;
+    return multinomial(sampler, NP, 1, p, K, seed, surf, ((uint32_t)level & 0xFFFFu) << 16, a, b, M, codes);
 }
 
 /* One binomial draw per element with the given random words: xi1 from h1,
@@ -1290,7 +1336,7 @@ int orc_sample_binomial(int sampler, const double *N, const double *p, const uin
 #endif
     for (int64_t i = 0; i < count; ++i) {
         node_out o;
-        sample_node(sampler, N[i], p[i], to_unit(h1[i]), to_unit(h2[i]), 1, &o);
+        sample_node(sampler, N[i], p[i], to_unit(h1[i]), to_unit(h2[i]), 1, 0, &o);
         n[i] = o.n;
         nb[i] = o.nb;
         code[i] = o.code;

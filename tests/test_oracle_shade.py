@@ -210,3 +210,38 @@ def test_given_F_path_equals_pyramid_path_and_is_scale_free():
     ok = (scaled["flags"] == 0) & (given["flags"] == 0)
     np.testing.assert_allclose(scaled["probs"], given["probs"], rtol=1e-13, atol=1e-15)
     np.testing.assert_allclose(scaled["radiance"][ok], given["radiance"][ok], rtol=1e-9)
+
+
+def test_integral_gaussian_count_is_flagged():
+    """At N_P = 1e12 a count that came from a Gaussian draw lands on an exact
+    integer now and then (a double's spacing there is ~3e-5).  Another
+    evaluation order of p moves it by a few ulps, possibly just below the
+    integer, so the oracle flags it like a count near an integer; a count
+    formed from gating constants, clamp bounds and N_P is not flagged."""
+    p = np.array([0.0118, 0.1343, 0.2137, 0.3402, 0.2175, 0.0706, 0.01175, 1.87e-5])
+    p /= p.sum()
+    NP = 1e12
+    hits = flagged = 0
+    moved = False
+    for a in range(40000):
+        M, codes, fl = oracle.multinomial(0, NP, p, 5, 7, -7, a, 11)
+        assert np.all(codes == 16)  # every node draws its Gaussian
+        flagged += (fl & 8) != 0
+        if np.any(M == np.floor(M)):
+            hits += 1
+            assert fl & 8, (a, M)
+            # a few ulps of p (bins moved in mixed directions) move an
+            # integral count's integer part
+            for pattern in ([1, -1] * 4, [1] * 4 + [-1] * 4, [1, 0, 0, 0, 0, 0, 0, 0], [0, 0, 0, 0, 1, 0, 0, 0]):
+                for sgn in (-1, 1):
+                    q = p.copy()
+                    for _ in range(4):
+                        q = np.nextafter(q, q + sgn * np.asarray(pattern, np.float64))
+                    M2, _, _ = oracle.multinomial(0, NP, q, 5, 7, -7, a, 11)
+                    moved |= bool(np.any(np.floor(M2) != np.floor(M)))
+    assert hits >= 3 and moved, (hits, moved)
+    assert flagged / 40000 < 1e-2
+    # degenerate and clamped draws give exact integers that are not flagged
+    for a in range(2000):
+        M, codes, fl = oracle.multinomial(0, 1.5, p, 5, 7, 0, a, 3)
+        assert not fl & 8
