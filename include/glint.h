@@ -125,8 +125,10 @@ int glint_partition_env(glint_ctx ctx, const float *env, int R, const glint_part
  * beyond a face edge is the nearest texel of the face that owns its centre's
  * direction (the adjacent texel); the texel beyond a cube corner is the mean
  * of the three texels meeting there, so lookups are continuous.  Shading
- * reads the pyramid with the same rule.  Sums run in double; results are
- * rounded once to the stored type.
+ * reads the pyramid with the same rule.  The eight weighted corners of one
+ * tap's trilinear lookup are summed in float (non-negative terms: relative
+ * error below 9 * 2^-24), the taps and the normalisation in double; results
+ * are rounded once to the stored type.
  * ------------------------------------------------------------------------ */
 typedef struct glint_prefilter_params {
     int num_mips;      /* M, 1 <= M <= log2(R) + 1 */

@@ -21,8 +21,9 @@
 //                   texels that the tiles did not reach, R >= 2048);
 //   k_chain_border  the border rings of every stored level;
 //   k_prefilter     mips >= 1: a group of G lanes per output texel splits
-//                   the T taps, accumulates in double, reduces across the
-//                   group with cross-lane shuffles; the tap table of the
+//                   the T taps, sums each tap's trilinear corners in float
+//                   and the taps in double, reduces across the group with
+//                   cross-lane shuffles; the tap table of the
 //                   block's mip lives in LDS.  Blocks are mip-homogeneous and
 //                   remapped so consecutive tiles share an XCD's L2.
 #include "device.hpp"
@@ -508,12 +509,21 @@ __device__ __forceinline__ void accumulate_tap(const Tap &tp, const d3 &r, const
 #pragma unroll
             for (int q4 = 0; q4 < CP / 4; ++q4)
                 raw[c][q4] = *reinterpret_cast<const float4 *>(src[c] + q4 * (c < 4 ? p0 : p1));
+        // the tap's eight weighted corners are summed in float (eight
+        // non-negative terms, weights rounded once: relative error below
+        // 9 * 2^-24), the taps in double
+        float tsum[C];
+#pragma unroll
+        for (int k = 0; k < C; ++k) tsum[k] = 0.0f;
 #pragma unroll
         for (int c = 0; c < 8; ++c) {
             const float *f = reinterpret_cast<const float *>(raw[c]);
+            const float wf = (float)w8[c];
 #pragma unroll
-            for (int k = 0; k < C; ++k) acc[k] += w8[c] * (double)f[k];
+            for (int k = 0; k < C; ++k) tsum[k] = __builtin_fmaf(wf, f[k], tsum[k]);
         }
+#pragma unroll
+        for (int k = 0; k < C; ++k) acc[k] += (double)tsum[k];
         return;
     }
 #endif

@@ -113,6 +113,12 @@ def test_partition_rejects_bad_arguments(ctx):
 
 # --- a4-a5 prefilter -----------------------------------------------------------
 
+# Pyramid texels against the oracle's double sums: the kernel sums the eight
+# weighted corners of each tap in float (non-negative terms, weights rounded
+# once: relative error below 9 * 2^-24, i.e. below 9 ulp of the result) and
+# the taps in double, then rounds once: at most 10 ulp.
+PYR_ULP = 10
+
 @pytest.mark.parametrize("R,K,M", [(32, 4, 6), (16, 16, 5), (8, 2, 4), (4, 8, 3)])
 def test_prefilter_full_pyramid(ctx, R, K, M):
     U.log(f"prefilter full R={R} K={K} M={M}")
@@ -124,9 +130,10 @@ def test_prefilter_full_pyramid(ctx, R, K, M):
         assert np.array_equal(chain, ochain[: len(chain)])  # same sums in the same order
     opyr = oracle.prefilter(env, ij, it, ochain, K, M, 64)
     d = U.ulp_diff(raw, opyr[:, :K])
-    assert d.max() <= 1 and (d > 0).mean() < 1e-3, (d.max(), (d > 0).mean())
+    U.log(f"  indicator ulp: max {d.max()}, mean {d.mean():.3f}, > 2: {(d > 2).mean():.4f}")
+    assert d.max() <= PYR_ULP and d.mean() < 1.0, (d.max(), d.mean())
     d = U.ulp_diff(rgb[:, :3], opyr[:, K:])
-    assert d.max() <= 1 and np.all(rgb[:, 3] == 0)
+    assert d.max() <= PYR_ULP and d.mean() < 1.0 and np.all(rgb[:, 3] == 0)
 
 
 def seam_texel(level, face, x, y, n):
@@ -183,6 +190,9 @@ def test_prefilter_storage_types(ctx, dtype):
         d = np.abs(raw.view(np.int16).astype(np.int64) - want.view(np.int16).astype(np.int64))
     else:
         d = np.abs(raw.astype(np.int64) - want.astype(np.int64))
+    # the float result is within PYR_ULP float ulps of the oracle's, far below
+    # one 16-bit step: the stored codes differ by at most one, rarely
+    U.log(f"  code diff: max {d.max()}, > 0: {(d > 0).mean():.5f}")
     assert d.max() <= 1 and (d > 0).mean() < 1e-3
 
 
@@ -204,8 +214,9 @@ def test_prefilter_frame_size_sampled(ctx):
     ids = np.concatenate(ids)
     opyr = oracle.prefilter(env, ij, it, ochain, w.K, w.M, w.T, texel_ids=ids)
     d = U.ulp_diff(raw[ids], opyr[:, :w.K])
-    assert d.max() <= 1 and (d > 0).mean() < 1e-3
-    assert U.ulp_diff(rgb[ids, :3], opyr[:, w.K:]).max() <= 1
+    U.log(f"  indicator ulp: max {d.max()}, mean {d.mean():.3f}, > 2: {(d > 2).mean():.4f}")
+    assert d.max() <= PYR_ULP and d.mean() < 1.0
+    assert U.ulp_diff(rgb[ids, :3], opyr[:, w.K:]).max() <= PYR_ULP
 
 
 def test_prefilter_rejects_bad_arguments(ctx):
@@ -364,7 +375,7 @@ def test_precision_workload_sampled(ctx):
     ids = np.concatenate([oracle.level_offset(w.R, m) + rng.choice(6 * (w.R >> m) ** 2, min(6 * (w.R >> m) ** 2, 300),
                                                                    replace=False) for m in range(w.M)])
     opyr = oracle.prefilter(env, ij, it, ochain, w.K, w.M, w.T, texel_ids=ids)
-    assert U.ulp_diff(raw[ids], opyr[:, :w.K]).max() <= 1
+    assert U.ulp_diff(raw[ids], opyr[:, :w.K]).max() <= PYR_ULP
     S, E = U.luts(ctx)
     gpu = U.shade(ctx, g, raw, rgb, lv, S, E, w.R, w.K, w.M, seed=w.hash_seed)
     hit = np.nonzero(g["surf_id"] != synth.NO_SURFACE)[0]
