@@ -329,10 +329,14 @@ class FramePipeline:
             return
         b = self.frame % self.nbuf
         p = self.pipes[b]
-        self._caller_ev.record(torch.cuda.current_stream())
-        self.s_env.wait_event(self._caller_ev)
-        self.s_shade.wait_event(self._caller_ev)
-        if self._recorded[b]:
+        # a wait that the host already sees satisfied is not enqueued: each
+        # costs the queue a barrier packet
+        caller = torch.cuda.current_stream()
+        if not caller.query():
+            self._caller_ev.record(caller)
+            self.s_env.wait_event(self._caller_ev)
+            self.s_shade.wait_event(self._caller_ev)
+        if self._recorded[b] and not self._shade_done[b].query():
             # the buffer set is refilled only after the shading that read it
             self.s_env.wait_event(self._shade_done[b])
         p.run(env, stream=self.s_env)
