@@ -221,6 +221,26 @@ __device__ __forceinline__ int resolve_texel(int face, int x, int y, int n, int6
     return 3;
 }
 
+// resolve_texel with the integer edge maps (texels one step beyond an edge:
+// the same indices as reproject_one).
+__device__ __forceinline__ int resolve_texel_edge(int face, int x, int y, int n, int64_t (&idx)[3])
+{
+    const bool xin = (unsigned)x < (unsigned)n, yin = (unsigned)y < (unsigned)n;
+    if (xin && yin) {
+        idx[0] = ((int64_t)face * n + y) * n + x;
+        return 1;
+    }
+    if (xin || yin) {
+        idx[0] = reproject_edge(face, x, y, n);
+        return 1;
+    }
+    const int xc = x < 0 ? 0 : n - 1, yc = y < 0 ? 0 : n - 1;
+    idx[0] = ((int64_t)face * n + yc) * n + xc;
+    idx[1] = reproject_edge(face, x, yc, n);
+    idx[2] = reproject_edge(face, xc, y, n);
+    return 3;
+}
+
 // Footprint of a direction on one level: face coordinates are computed once
 // per direction (dir_face) and shared by every level.
 struct face_st {

@@ -398,7 +398,7 @@ __global__ void __launch_bounds__(256) k_chain_border(int R, int M, float *__res
     }
     float *lvl = chain + chain_level_base(R, s) * CP;
     int64_t idx[3];
-    const int cnt = resolve_texel(face, x, y, n, idx);
+    const int cnt = resolve_texel_edge(face, x, y, n, idx);
     int64_t rec[3];
     const int64_t nn = (int64_t)n * n;
 #pragma unroll
