@@ -339,6 +339,9 @@ class FramePipeline:
         if self._recorded[b] and not self._shade_done[b].query():
             # the buffer set is refilled only after the shading that read it
             self.s_env.wait_event(self._shade_done[b])
+        # the caller may drop the map once step returns: its memory is not
+        # reused before the environment stream has read it
+        env.record_stream(self.s_env)
         p.run(env, stream=self.s_env)
         self._env_done[b].record(self.s_env)
         self.s_shade.wait_event(self._env_done[b])

@@ -85,3 +85,40 @@ def test_frames_wait_for_the_callers_stream(ctx):
     torch.cuda.synchronize()
     for f in range(3):
         assert torch.equal(got[f], ref_sh.radiance), f
+
+
+def test_frames_keep_the_callers_map_alive(ctx):
+    """A map dropped by the caller right after step() is not overwritten
+    before the environment stream has read it (the frame equals the serial
+    frame of the same map), with many frames over freshly uploaded maps."""
+    import torch
+    from paper_2507_02674_amd.pipeline import EnvPipeline, FramePipeline, Shader
+    R, K, M, T = 32, 8, 6, 64
+    U.log("frame pipeline over dropped maps")
+    maps = [synth.make_env(R, s) for s in (3, 4)]
+    g = synth.scene_frame(96, 54, seed=2, density_decades=(2.0, 8.0))
+    shader = Shader(ctx, g, seed=5)
+    frames = FramePipeline(lambda: EnvPipeline(ctx, R, K, M, T), shader, overlap=True, buffers=3)
+    frames.build_luts()
+    got = []
+    for f in range(40):
+        env = torch.from_numpy(maps[f % 2]).cuda()
+        frames.step(env)
+        del env
+        # allocations on the caller's stream that would reuse a freed map
+        junk = torch.full((6, R, R, 3), -1.0, device="cuda")
+        del junk
+        with torch.cuda.stream(frames.s_shade):
+            got.append(shader.radiance.clone())
+    torch.cuda.synchronize()
+    ref = []
+    for m in maps:
+        p = EnvPipeline(ctx, R, K, M, T)
+        p.build_luts()
+        p.run(torch.from_numpy(m).cuda())
+        sh = Shader(ctx, g, seed=5)
+        sh.run(p.env_struct())
+        torch.cuda.synchronize()
+        ref.append(sh.radiance.clone())
+    for f in range(40):
+        assert torch.equal(got[f], ref[f % 2]), f
