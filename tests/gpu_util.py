@@ -67,6 +67,20 @@ def chain_levels(ws, R, K, M, borders=False):
     return np.concatenate(out) if out else np.zeros((0, K + 3), np.float32)
 
 
+def chain_sample(ws, R, K, s, face, x, y):
+    """Records (x, y) of `face` on stored chain level s >= 1 gathered on the
+    device from the prefilter workspace `ws` (float32 tensor; layout as in
+    chain_levels): [len(x), K+3] float32 on the host."""
+    CP = (K + 3 + 3) & ~3
+    base = sum(6 * ((R >> q) + 2) ** 2 * CP for q in range(1, s))
+    n = R >> s
+    plane = 6 * (n + 2) ** 2 * 4
+    rec = (np.asarray(face, np.int64) * (n + 2) + np.asarray(y, np.int64) + 1) * (n + 2) + np.asarray(x, np.int64) + 1
+    k = np.arange(K + 3)
+    idx = base + (k[None, :] // 4) * plane + rec[:, None] * 4 + (k[None, :] % 4)
+    return host(ws[torch.from_numpy(idx.reshape(-1)).cuda()]).reshape(len(rec), K + 3)
+
+
 def decode(raw, dtype):
     if dtype == G.GLINT_F32:
         return raw.astype(np.float32)

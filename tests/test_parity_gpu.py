@@ -196,6 +196,46 @@ def test_prefilter_storage_types(ctx, dtype):
     assert d.max() <= 1 and (d > 0).mean() < 1e-3
 
 
+@pytest.mark.parametrize("R,K", [(1024, 8), (2048, 8), (4096, 4)])
+def test_prefilter_largest_faces_sampled(ctx, R, K):
+    """Face sizes whose coarser chain levels are built one level per launch
+    (faces above 16 texels once the 32x32 tiles are done: R >= 1024), up to
+    the largest accepted face size R = 4096, all mips: partition, sampled
+    chain records (bit-exact) and sampled pyramid texels against the oracle,
+    gathered on the device."""
+    import torch
+    from paper_2507_02674_amd.pipeline import EnvPipeline
+    M, T = int(np.log2(R)) + 1, 64
+    U.log(f"prefilter largest faces R={R} K={K} M={M}")
+    env = synth.make_env(R, 5)
+    pipe = EnvPipeline(ctx, R, K, M, T)
+    pipe.run(torch.from_numpy(env).cuda())
+    olv, oij, oit = oracle.partition(env, K)
+    np.testing.assert_allclose(U.host(pipe.levels), olv, rtol=1e-14, atol=0)
+    assert np.array_equal(U.host(pipe.ind_j), oij) and U.ulp_diff(U.host(pipe.ind_t), oit).max() <= 1
+    ochain = oracle.mipchain(env, oij, oit, K, M)
+    rng = np.random.default_rng(R)
+    off = 0
+    for s in range(1, M):
+        n = R >> s
+        c = min(6 * n * n, 400)
+        t = rng.choice(6 * n * n, c, replace=False)
+        f, y, x = t // (n * n), (t // n) % n, t % n
+        got = U.chain_sample(pipe.filt_ws, R, K, s, f, x, y)
+        assert np.array_equal(got, ochain[off + t]), s
+        off += 6 * n * n
+    ids = np.concatenate([oracle.level_offset(R, m) + rng.choice(6 * (R >> m) ** 2, min(6 * (R >> m) ** 2, 150),
+                                                                 replace=False) for m in range(M)])
+    opyr = oracle.prefilter(env, oij, oit, ochain, K, M, T, texel_ids=ids)
+    sel = torch.from_numpy(ids).cuda()
+    raw = U.host(pipe.ind_pyr[sel])
+    rgb = U.host(pipe.rgb_pyr[sel])
+    d = U.ulp_diff(raw, opyr[:, :K])
+    U.log(f"  indicator ulp: max {d.max()}, mean {d.mean():.3f}")
+    assert d.max() <= PYR_ULP and d.mean() < 1.0
+    assert U.ulp_diff(rgb[:, :3], opyr[:, K:]).max() <= PYR_ULP and np.all(rgb[:, 3] == 0)
+
+
 def test_prefilter_frame_size_sampled(ctx):
     """R=256, K=8, M=8 (the frame workload's map), in the launch configuration the
     benchmark times; 4000 texels sampled over all mips against the oracle."""
