@@ -196,6 +196,25 @@ def test_prefilter_storage_types(ctx, dtype):
     assert d.max() <= 1 and (d > 0).mean() < 1e-3
 
 
+@pytest.mark.parametrize("R,K,M,T", [(1, 4, 1, 64), (2, 4, 2, 64), (32, 4, 1, 64), (16, 8, 5, 1), (16, 8, 5, 1024),
+                                     (64, 2, 7, 64)])
+def test_prefilter_degenerate_sizes(ctx, R, K, M, T):
+    """One-texel and two-texel faces, a single mip (no filtered level), one
+    tap and the largest tap count, every mip down to 1x1 faces: the whole
+    pyramid against the oracle."""
+    U.log(f"prefilter degenerate R={R} K={K} M={M} T={T}")
+    env = synth.make_env(R, 7)
+    lv, ij, it = U.partition(ctx, env, K)
+    raw, rgb, chain = U.prefilter(ctx, env, ij, it, K, M, T)
+    ochain = oracle.mipchain(env, ij, it, K, M)
+    if M > 1:
+        assert np.array_equal(chain, ochain[: len(chain)])
+    opyr = oracle.prefilter(env, ij, it, ochain, K, M, T)
+    assert raw.shape[0] == opyr.shape[0] == G.glint_pyramid_texels(R, M)
+    assert U.ulp_diff(raw, opyr[:, :K]).max() <= PYR_ULP
+    assert U.ulp_diff(rgb[:, :3], opyr[:, K:]).max() <= PYR_ULP and np.all(rgb[:, 3] == 0)
+
+
 @pytest.mark.parametrize("R,K", [(1024, 8), (2048, 8), (4096, 4)])
 def test_prefilter_largest_faces_sampled(ctx, R, K):
     """Face sizes whose coarser chain levels are built one level per launch
