@@ -663,10 +663,16 @@ __global__ void __launch_bounds__(512) k_shade_views(const ShadeArgs *__restrict
 {
     __shared__ int s_view;
     const int64_t b = blockIdx.x;
-    if (threadIdx.x == 0) {
+    if (threadIdx.x < 64) {
+        // the view is the number of views v >= 1 whose first tile is <= b
+        // (tile0 ascending, tile0[0] = 0): one load per lane and a ballot
+        // per 64 views instead of a serial scan
         int v = 0;
-        while (v + 1 < n_views && tile0[v + 1] <= b) ++v;
-        s_view = v;
+        for (int base = 1; base < n_views; base += 64) {
+            const int u = base + (int)threadIdx.x;
+            v += __popcll(__ballot(u < n_views && tile0[u] <= b));
+        }
+        if (threadIdx.x == 0) s_view = v;
     }
     __syncthreads();
     const ShadeArgs A = views[s_view];
@@ -749,6 +755,8 @@ void make_shade_args(void *out, const glint_gbuffer &g, int64_t P, const glint_e
 hipError_t launch_shade_views(int K, int dtype, int V, bool surrogate, const void *views, const int64_t *tile0,
                               int n_views, int64_t tiles, int tile_px, hipStream_t stream)
 {
+    // k_shade_views finds a block's view with its first wave
+    if (tile_px < 64 || tile_px % 64 != 0 || tile_px > 512) return hipErrorInvalidValue;
     const ShadeArgs *va = static_cast<const ShadeArgs *>(views);
     if (surrogate) {
         // the indicator pyramid is not read, so its storage type does not matter
