@@ -22,7 +22,7 @@ namespace glint {
 
 namespace {
 
-constexpr int kTileCandidates[] = {64, 128, 256, 512};
+constexpr int kTileCandidates[] = {64, 128, 256}; // pixels per block (multiples of one wave, <= 256)
 
 struct Group {
     int K, V;

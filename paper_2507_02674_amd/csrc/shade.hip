@@ -135,10 +135,53 @@ struct ShadeArgs {
     int lobe_taps;       // anisotropic lookup taps (2, 4, 8; 0: isotropic lookup)
 };
 
+// The same arguments with every pointer typed as global memory.  Pointers
+// read from memory (the batched launch's per-view table) have no known
+// address space, so loads through them would be generic (flat) loads with
+// 64-bit addresses in vector registers; read through this layout they are
+// global loads, as for kernel arguments.
+#define GLINT_GLOBAL(T) __attribute__((address_space(1))) T
+struct GBufferG {
+    const GLINT_GLOBAL(float) *nx, *ny, *nz, *vx, *vy, *vz, *u, *v, *area, *ax, *ay, *density, *f0r, *f0g, *f0b;
+    const GLINT_GLOBAL(uint32_t) *surf_id;
+    const GLINT_GLOBAL(float) *visibility, *tx, *ty, *tz, *dudx, *dudy, *dvdx, *dvdy;
+};
+
+struct ShadeArgsG {
+    GBufferG g;
+    int64_t P;
+    const GLINT_GLOBAL(void) *ind_pyr;
+    const GLINT_GLOBAL(float) *rgb_pyr;
+    const GLINT_GLOBAL(double) *levels;
+    const GLINT_GLOBAL(float) *lut_S;
+    const GLINT_GLOBAL(float) *lut_E;
+    int R, M;
+    uint32_t seed;
+    GLINT_GLOBAL(float) *radiance;
+    GLINT_GLOBAL(double) *counts;
+    GLINT_GLOBAL(uint8_t) *codes;
+    GLINT_GLOBAL(double) *probs;
+    const GLINT_GLOBAL(float) *F;
+    const GLINT_GLOBAL(double) *qtail;
+    int exact_gating;
+    int sampler;
+    double gamma;
+    int lobe_taps;
+};
+static_assert(sizeof(GBufferG) == sizeof(glint_gbuffer) && offsetof(GBufferG, dvdy) == offsetof(glint_gbuffer, dvdy) &&
+                  offsetof(GBufferG, surf_id) == offsetof(glint_gbuffer, surf_id),
+              "GBufferG mirrors glint_gbuffer");
+static_assert(sizeof(ShadeArgsG) == sizeof(ShadeArgs) && offsetof(ShadeArgsG, P) == offsetof(ShadeArgs, P) &&
+                  offsetof(ShadeArgsG, seed) == offsetof(ShadeArgs, seed) &&
+                  offsetof(ShadeArgsG, qtail) == offsetof(ShadeArgs, qtail) &&
+                  offsetof(ShadeArgsG, gamma) == offsetof(ShadeArgs, gamma) &&
+                  offsetof(ShadeArgsG, lobe_taps) == offsetof(ShadeArgs, lobe_taps),
+              "ShadeArgsG mirrors ShadeArgs");
+
 // acc += w * trilinear lookup of the pyramid (KL indicator channels, then
 // RGB) in direction dir at lod (clamped to [0, M-1]).
-template <int KL, int DT>
-__device__ __forceinline__ void pyramid_trilinear(const ShadeArgs &A, const d3 &dir, double lod, double w,
+template <int KL, int DT, class Args>
+__device__ __forceinline__ void pyramid_trilinear(const Args &A, const d3 &dir, double lod, double w,
                                                   double (&acc)[KL + 3])
 {
     lod = lod < 0.0 ? 0.0 : (lod > (double)(A.M - 1) ? (double)(A.M - 1) : lod);
@@ -174,7 +217,7 @@ __device__ __forceinline__ void pyramid_trilinear(const ShadeArgs &A, const d3 &
             // four loads in flight
             double v[4][KL + 3];
 #pragma unroll
-            for (int c = 0; c < 4; ++c) load_texel<KL, DT>(A.ind_pyr, A.rgb_pyr, tt[c], v[c]);
+            for (int c = 0; c < 4; ++c) load_texel<KL, DT>((const void *)A.ind_pyr, (const float *)A.rgb_pyr, tt[c], v[c]);
 #pragma unroll
             for (int c = 0; c < 4; ++c)
 #pragma unroll
@@ -183,7 +226,7 @@ __device__ __forceinline__ void pyramid_trilinear(const ShadeArgs &A, const d3 &
             // a cube corner: one copy of the seam rule
 #pragma unroll 1
             for (int c = 0; c < 4; ++c)
-                accumulate_pyr<KL, DT>(A.ind_pyr, A.rgb_pyr, base, fs.face, bl.x0 + (c & 1), bl.y0 + (c >> 1), ns,
+                accumulate_pyr<KL, DT>((const void *)A.ind_pyr, (const float *)A.rgb_pyr, base, fs.face, bl.x0 + (c & 1), bl.y0 + (c >> 1), ns,
                                        c == 0 ? w4[0] : (c == 1 ? w4[1] : (c == 2 ? w4[2] : w4[3])), acc);
         }
     }
@@ -415,8 +458,9 @@ __device__ __forceinline__ FootGrid footprint_grid(double j00, double j01, doubl
 // K filtered indicator values come from A.F (a learned surrogate's output)
 // and only RGB is read from the pyramid.  PC: constant reflection
 // probability A.gamma (K = 2, levels (0, 1)), no indicator lookup.
-template <int K, int DT, int V, bool SURR = false, bool SG = false, bool PC = false, bool AN = false>
-__device__ __forceinline__ void shade_pixel(const ShadeArgs &A, int64_t i)
+template <int K, int DT, int V, bool SURR = false, bool SG = false, bool PC = false, bool AN = false,
+          class Args = ShadeArgs>
+__device__ __forceinline__ void shade_pixel(const Args &A, int64_t i)
 {
     static_assert(!PC || (K == 2 && !SURR), "constant probabilities use two bins");
     constexpr int KL = (SURR || PC) ? 0 : K; // indicator channels read from the pyramid
@@ -485,8 +529,8 @@ __device__ __forceinline__ void shade_pixel(const ShadeArgs &A, int64_t i)
         pyramid_trilinear<KL, DT>(A, wr, sa * (double)(A.M - 1), 1.0, acc);
     }
     const double rgb[3] = {acc[KL], acc[KL + 1], acc[KL + 2]};
-    const double EA = lut_bilinear(A.lut_E, 2, 0, mu, sa);
-    const double EB = lut_bilinear(A.lut_E, 2, 1, mu, sa);
+    const double EA = lut_bilinear((const float *)A.lut_E, 2, 0, mu, sa);
+    const double EB = lut_bilinear((const float *)A.lut_E, 2, 1, mu, sa);
 
     // Sec. 4 Eq. (probhk) with Sec. 5 Eq. (rtiblndf); the normalisation of
     // Eq. (iblglints:fin) uses these (unattenuated) probabilities
@@ -507,7 +551,7 @@ __device__ __forceinline__ void shade_pixel(const ShadeArgs &A, int64_t i)
         double sumF = 0.0;
 #pragma unroll
         for (int k = 0; k < K; ++k) sumF += F[k];
-        const double S = lut_bilinear(A.lut_S, 1, 0, mu, sa);
+        const double S = lut_bilinear((const float *)A.lut_S, 1, 0, mu, sa);
         const double scale = sumF > 0.0 ? S / sumF : 0.0;
 #pragma unroll
         for (int k = 1; k < K; ++k) {
@@ -619,8 +663,9 @@ __device__ __forceinline__ void shade_pixel(const ShadeArgs &A, int64_t i)
         }
         if constexpr (V != 12) key = ((uint32_t)lev & 0xFFFFu) << 16;
         double Mv[K];
-        uint8_t *cod = A.codes ? A.codes + (i * V + vi) * (K - 1) : nullptr;
-        multinomial<K, SG>(Nv, p, seed_mix, key, a, b, A.qtail, A.exact_gating != 0, A.sampler, Mv, cod);
+        uint8_t *cod = A.codes ? (uint8_t *)A.codes + (i * V + vi) * (K - 1) : nullptr;
+        multinomial<K, SG>(Nv, p, seed_mix, key, a, b, (const double *)A.qtail, A.exact_gating != 0, A.sampler, Mv,
+                           cod);
 #pragma unroll
         for (int k = 0; k < K; ++k) Msum[k] += w * Mv[k];
         if (A.counts) {
@@ -658,7 +703,7 @@ __global__ void __launch_bounds__(kShadeThreads, (V == 12 || AN) ? 2 : 1) k_shad
 // concatenated views (tile = blockDim.x pixels); tile0[v] is the first tile
 // of view v (ascending), so the view is found by a scan of <= n_views entries.
 template <int K, int DT, int V, bool SURR = false>
-__global__ void __launch_bounds__(512) k_shade_views(const ShadeArgs *__restrict__ views,
+__global__ void __launch_bounds__(kShadeThreads, 1) k_shade_views(const ShadeArgs *__restrict__ views,
                                                      const int64_t *__restrict__ tile0, int n_views)
 {
     __shared__ int s_view;
@@ -675,10 +720,11 @@ __global__ void __launch_bounds__(512) k_shade_views(const ShadeArgs *__restrict
         if (threadIdx.x == 0) s_view = v;
     }
     __syncthreads();
-    const ShadeArgs A = views[s_view];
+    // uniform across the block: the view's arguments go to scalar registers
+    const ShadeArgsG A = reinterpret_cast<const ShadeArgsG *>(views)[__builtin_amdgcn_readfirstlane(s_view)];
     const int64_t i = (b - tile0[s_view]) * blockDim.x + threadIdx.x;
     if (i >= A.P) return;
-    shade_pixel<K, DT, V, SURR>(A, i);
+    shade_pixel<K, DT, V, SURR, false, false, false, ShadeArgsG>(A, i);
 }
 
 template <int K, int DT>
@@ -756,7 +802,7 @@ hipError_t launch_shade_views(int K, int dtype, int V, bool surrogate, const voi
                               int n_views, int64_t tiles, int tile_px, hipStream_t stream)
 {
     // k_shade_views finds a block's view with its first wave
-    if (tile_px < 64 || tile_px % 64 != 0 || tile_px > 512) return hipErrorInvalidValue;
+    if (tile_px < 64 || tile_px % 64 != 0 || tile_px > kShadeThreads) return hipErrorInvalidValue;
     const ShadeArgs *va = static_cast<const ShadeArgs *>(views);
     if (surrogate) {
         // the indicator pyramid is not read, so its storage type does not matter
