@@ -33,7 +33,7 @@ constexpr int sW1 = 0, sW2 = sW1 + kH * kLdW1, sW3 = sW2 + kH * kLdH, sW4 = sW3 
               kWLds = sW4 + kOut * kLdH; // bf16 weights staged in LDS (no biases)
 
 constexpr int kInferWaves = 4;     // waves per block of the inference kernels
-constexpr int kInferMaxBlocks = 1024;
+constexpr int kInferMaxBlocks = 768; // one round at 3 blocks per CU (256 CUs)
 
 __device__ __forceinline__ uint16_t to_bf16(float f)
 {
@@ -208,12 +208,36 @@ __device__ __forceinline__ void softmax_pair(const float (&logit)[16], int K, fl
     for (int j = 0; j < 16; ++j) y[j] *= inv;
 }
 
-// Per-wave LDS of the inference kernels: inputs and two ping-pong hidden
-// buffers (the output layer and softmax stay in registers).
+// Per-wave LDS of the inference kernels: one buffer of 32 rows that holds
+// the inputs (columns 0..15), then each hidden layer in turn (the output
+// layer and softmax stay in registers).  One buffer instead of three keeps
+// the block at 3 per CU.
 struct InferTile {
-    uint16_t x[32 * kLdX];
-    uint16_t h[2][32 * kLdH];
+    uint16_t h[32 * kLdH];
 };
+
+// One hidden layer in place: both 32-unit tiles are computed from the
+// buffer before any output is written back into it (the wave's LDS
+// operations complete in order).
+__device__ __forceinline__ void dense_silu_inplace(uint16_t *buf, int Kd, const uint16_t *W, int ldw,
+                                                   const float *__restrict__ bias)
+{
+    const int r = threadIdx.x & 31, h = (threadIdx.x & 63) >> 5;
+    f32x16 acc[2];
+    unit_tile(W, ldw, buf, kLdH, Kd, 0, acc[0]);
+    unit_tile(W, ldw, buf, kLdH, Kd, 32, acc[1]);
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int n = 32 * t + 8 * q + 4 * h;
+            const float4 b4 = *reinterpret_cast<const float4 *>(bias + n);
+            const float z0 = acc[t][4 * q] + b4.x, z1 = acc[t][4 * q + 1] + b4.y, z2 = acc[t][4 * q + 2] + b4.z,
+                        z3 = acc[t][4 * q + 3] + b4.w;
+            *reinterpret_cast<uint2 *>(buf + r * kLdH + n) = pack_bf16x4(silu(z0), silu(z1), silu(z2), silu(z3));
+        }
+    }
+}
 
 // Per-wave LDS of the training kernel (one wave per block).
 struct TrainTile {
@@ -505,6 +529,7 @@ __global__ void __launch_bounds__(64 * kInferWaves) k_mlp_infer(InferInput in, i
     const int64_t iters = first < tiles ? (tiles - first + stride - 1) / stride : 0;
     for (int64_t it = 0; it < iters; ++it) {
         const int64_t row0 = (first + wave + it * stride) * 32;
+        wave_lds_sync(); // the previous tile's output layer has read the buffer
         bool needed = false; // this lane's row is a sample or a surface pixel
         if (lane < 32) {
             const int64_t i = row0 + lane;
@@ -519,7 +544,7 @@ __global__ void __launch_bounds__(64 * kInferWaves) k_mlp_infer(InferInput in, i
                     if (needed) pixel_features(in.g, i, f);
                 }
             }
-            uint4 *xr = reinterpret_cast<uint4 *>(t.x + lane * kLdX);
+            uint4 *xr = reinterpret_cast<uint4 *>(t.h + lane * kLdH);
             const uint2 lo = pack_bf16x4(f[0], f[1], f[2], f[3]);
             xr[0] = make_uint4(lo.x, lo.y, (uint32_t)to_bf16(f[4]), 0u);
             xr[1] = make_uint4(0u, 0u, 0u, 0u);
@@ -528,17 +553,17 @@ __global__ void __launch_bounds__(64 * kInferWaves) k_mlp_infer(InferInput in, i
         // network
         const bool active = __ballot(needed) != 0;
         wave_lds_sync();
-        if (active) dense_silu(t.x, kLdX, kIn, W1, kLdW1, w + ob1, t.h[0], nullptr);
+        if (active) dense_silu_inplace(t.h, kIn, W1, kLdW1, w + ob1);
         wave_lds_sync();
-        if (active) dense_silu(t.h[0], kLdH, kH, W2, kLdH, w + ob2, t.h[1], nullptr);
+        if (active) dense_silu_inplace(t.h, kH, W2, kLdH, w + ob2);
         wave_lds_sync();
-        if (active) dense_silu(t.h[1], kLdH, kH, W3, kLdH, w + ob3, t.h[0], nullptr);
+        if (active) dense_silu_inplace(t.h, kH, W3, kLdH, w + ob3);
         wave_lds_sync();
         float logit[16], y[16];
 #pragma unroll
         for (int j = 0; j < 16; ++j) y[j] = 0.0f;
         if (active) {
-            dense_out(t.h[0], W4, w + ob4, logit);
+            dense_out(t.h, W4, w + ob4, logit);
             softmax_pair(logit, K, y);
         }
         const int64_t i = row0 + (lane & 31);
