@@ -447,17 +447,21 @@ int glint_shade_surrogate(glint_ctx ctx, const glint_gbuffer *gbuf, int64_t num_
  *
  * The first call for a given argument set (compared byte-wise, including
  * the pointers) is a set-up call: it times the shading launch for each
- * candidate tile size (pixels per workgroup: 64, 128, 256, 512; results do
- * not depend on the choice) and keeps the fastest per (K, dtype, vertices,
- * size class) in the context, uploads the view descriptors into
+ * candidate tile size (pixels per workgroup: 64, 128, 256; results do not
+ * depend on the choice) and keeps the fastest per (K, dtype, vertices,
+ * form, size class) in the context, uploads the view descriptors into
  * `workspace`, and captures the frame into a HIP graph: one branch per
  * environment on the context's side streams (the maps are filtered
- * concurrently), joined before one shading launch per (K, vertices) group
- * that covers all views of the group.  The set-up call synchronises the
- * stream and lets the HIP runtime allocate graph objects.  Later calls with
- * the same arguments enqueue exactly one hipGraphLaunch and allocate
- * nothing.  Every environment's outputs and every view's radiance must be
- * distinct buffers; env_index selects the environment a view is lit by.
+ * concurrently), joined before one shading launch per (K, vertices,
+ * plain/surrogate) group that covers all views of the group.  The set-up
+ * call synchronises the stream and lets the HIP runtime allocate graph
+ * objects.  Later calls with the same arguments enqueue exactly one
+ * hipGraphLaunch and allocate nothing.  A workspace holds the descriptors of
+ * one argument set: a set-up call drops every graph captured on the same
+ * workspace, so alternating argument sets on one workspace repeats the
+ * set-up each time (give each set its own workspace to keep both graphs).
+ * Every environment's outputs and every view's radiance must be distinct
+ * buffers; env_index selects the environment a view is lit by.
  * ------------------------------------------------------------------------ */
 typedef struct glint_env_task {
     const float *env;               /* device [6][R][R][3] */
@@ -490,7 +494,8 @@ typedef struct glint_view {
                                        view's environment has a surrogate (else ignored) */
 } glint_view;
 
-/* Device workspace (bytes, 16-byte aligned) for n_views views. */
+/* Device workspace (bytes) for n_views views; the workspace passed to
+ * glint_frame_batched must be 256-byte aligned. */
 size_t glint_batched_workspace_bytes(int n_views);
 
 /* GLINT_EINVAL for null pointers, n_env outside 1..64, n_views outside

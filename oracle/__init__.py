@@ -21,10 +21,13 @@ numpy arrays into it and chains its steps in the paper's order:
   ``shade(lobe_taps=..., prob_mode=..., gbuf["visibility"])``
 
 Pins (tests/test_oracle_*.py): every step is checked against closed forms,
-invariants, library routines or brute force, except the per-footprint hash
-(pcg4d, Jarzynski & Olano 2020), for which no published test vectors are at
-hand: its values are *parity unpinned* (checked only for exactness of the
-float mapping and chi^2 uniformity); the GPU path implements the same
+invariants, library routines or brute force.  The per-footprint hash (pcg4d,
+Jarzynski & Olano 2020) has no published output values to compare with; it
+is pinned by the properties the method relies on (tests/test_oracle_hash.py:
+avalanche of the upper output bits, the carry structure of its multiply-add
+and xorshift steps, 2-D chi^2 independence of a node's two uniforms, of the
+two nodes sharing one hash and of neighbouring vertices), which reject the
+plausible slips in its definition; the GPU path implements the same
 published definition independently.
 """
 from __future__ import annotations
@@ -67,6 +70,7 @@ def _declare(L):
     L.orc_ppnd16.restype = C.c_double
     L.orc_hash_xi.argtypes = [C.c_uint32, C.c_uint32, C.c_int32, C.c_int64, C.c_int64, C.c_int,
                               f32p, f32p]
+    L.orc_pcg4d.argtypes = [C.POINTER(C.c_uint32), C.POINTER(C.c_uint32), C.c_int64]
     L.orc_shade_pixels.argtypes = [C.POINTER(f32p), f32p, f32p, f64p, f32p, f32p, C.c_int, C.c_int, C.c_int,
                                    C.c_uint32, C.c_int, C.c_int, C.c_int, C.c_double, C.c_int, i64p, C.c_int64, f64p,
                                    f64p, u8p, f64p, u8p, C.c_int]
@@ -285,6 +289,14 @@ def hash_xi(seed, surf, level, a, b, node):
     x1, x2 = C.c_float(), C.c_float()
     lib().orc_hash_xi(seed, surf, level, a, b, node, C.byref(x1), C.byref(x2))
     return x1.value, x2.value
+
+
+def pcg4d(words):
+    """The per-footprint hash on an [n, 4] array of 32-bit words."""
+    a = np.ascontiguousarray(words, dtype=np.uint32).reshape(-1, 4)
+    out = np.empty_like(a)
+    lib().orc_pcg4d(_p(a, C.c_uint32), _p(out, C.c_uint32), a.shape[0])
+    return out
 
 
 def gate_probs(N: float, p: float):

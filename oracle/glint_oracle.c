@@ -609,6 +609,17 @@ void orc_hash_xi(uint32_t seed, uint32_t surf, int32_t level, int64_t a, int64_t
     hash_xi_key(seed, surf, ((uint32_t)level & 0xFFFFu) << 16, a, b, node, xi1, xi2);
 }
 
+/* The raw hash on n 4-word inputs (in and out [n][4]), for the quality
+ * checks of the hash itself. */
+void orc_pcg4d(const uint32_t *in, uint32_t *out, int64_t n)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        uint32_t v[4] = {in[4 * i], in[4 * i + 1], in[4 * i + 2], in[4 * i + 3]};
+        pcg4d(v);
+        for (int k = 0; k < 4; ++k) out[4 * i + k] = v[k];
+    }
+}
+
 /* ------------------------------------------------------------------------ */
 /* Sec. 6, Alg. "Dual-gated Gaussian".  Gating probabilities and masks in    */
 /* float (the paper's precision for them); the Gaussian in double.  The      */

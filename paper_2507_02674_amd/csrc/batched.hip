@@ -164,6 +164,21 @@ hipError_t frame_batched(BatchedCache &c, const glint_env_task *envs, int n_env,
     if (err != hipSuccess) return err;
     const int dtype = (int)envs[0].prefilter.dtype;
 
+    // A graph reads its descriptors and tile tables from the workspace, where
+    // this set-up call writes its own: a workspace holds one argument set, so
+    // every graph captured on it is dropped (it would read the new set with
+    // its old grid sizes).  Earlier launches of those graphs on `stream` are
+    // ordered before the uploads below; the wait lets them finish first.
+    if ((err = hipStreamSynchronize(stream)) != hipSuccess) return err;
+    for (auto g = c.graphs.begin(); g != c.graphs.end();) {
+        if (g->second.workspace == workspace) {
+            hipGraphExecDestroy(g->second.exec);
+            g = c.graphs.erase(g);
+        } else {
+            ++g;
+        }
+    }
+
     // groups by (K, V, form), views in caller order
     std::vector<Group> groups;
     for (int v = 0; v < n_views; ++v) {
@@ -269,7 +284,7 @@ hipError_t frame_batched(BatchedCache &c, const glint_env_task *envs, int n_env,
         hipGraphExecDestroy(c.graphs.begin()->second.exec);
         c.graphs.erase(c.graphs.begin());
     }
-    c.graphs[key] = BatchedCache::Entry{exec};
+    c.graphs[key] = BatchedCache::Entry{exec, workspace};
     return hipGraphLaunch(exec, stream);
 }
 

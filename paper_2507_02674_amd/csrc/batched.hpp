@@ -17,6 +17,7 @@ struct BatchedCache {
     static constexpr int kSideStreams = 4;
     struct Entry {
         hipGraphExec_t exec = nullptr;
+        void *workspace = nullptr; // the workspace its descriptors and tile tables live in
     };
     std::mutex mu;
     hipStream_t side[kSideStreams] = {};

@@ -65,7 +65,7 @@ def test_batched_equals_per_call_path_and_replays(ctx):
     for e, (bp, rp) in enumerate(zip(bf.pipes, pipes)):
         for name in ("levels", "ind_j", "ind_t", "ind_pyr", "rgb_pyr"):
             assert torch.equal(getattr(bp, name), getattr(rp, name)), (e, name)
-    assert G.glint_batched_tile_px(ctx) in (64, 128, 256, 512)
+    assert G.glint_batched_tile_px(ctx) in (64, 128, 256)
     # replays: one graph launch each, with eager work and syncs in between
     for rep in range(3):
         for sh in bf.shaders:
@@ -138,3 +138,26 @@ def test_batched_surrogate_form_equals_per_call_path(ctx):
                  bf.view_structs[0].radiance, None)
     with pytest.raises(G.GlintError):
         G.glint_frame_batched(ctx, bf.tasks, [bad], bf.ws)
+
+
+def test_batched_two_argument_sets_share_one_workspace(ctx):
+    """Two argument sets alternating on one workspace: each set-up call drops
+    the graphs captured on that workspace (their descriptors are
+    overwritten), so every call, set-up or replay, gives the per-call path's
+    radiance bit for bit."""
+    import torch
+    U.log("batched: two argument sets on one workspace")
+    envs, views = small_setup()
+    A = BatchedFrame(ctx, envs, views[:5])
+    B = BatchedFrame(ctx, envs, views[3:])
+    ws = A.ws if A.ws.numel() >= B.ws.numel() else B.ws
+    _, ref = reference(ctx, envs, views)
+    ref_a, ref_b = ref[:5], ref[3:]
+    for rep in range(3):
+        for frame, expect in ((A, ref_a), (B, ref_b), (A, ref_a), (A, ref_a), (B, ref_b)):
+            for sh in frame.shaders:
+                sh.radiance.fill_(-1.0)
+            G.glint_frame_batched(ctx, frame.tasks, frame.view_structs, ws)
+            torch.cuda.synchronize()
+            for v, sh in enumerate(frame.shaders):
+                assert np.array_equal(U.host(sh.radiance), expect[v]), (rep, v)
