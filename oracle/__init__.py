@@ -70,6 +70,7 @@ def _declare(L):
     L.orc_ppnd16.restype = C.c_double
     L.orc_hash_xi.argtypes = [C.c_uint32, C.c_uint32, C.c_int32, C.c_int64, C.c_int64, C.c_int,
                               f32p, f32p]
+    L.orc_quantile_levels.argtypes = [f32p, C.c_int, C.c_int, C.c_double, f64p, f64p]
     L.orc_pcg4d.argtypes = [C.POINTER(C.c_uint32), C.POINTER(C.c_uint32), C.c_int64]
     L.orc_shade_pixels.argtypes = [C.POINTER(f32p), f32p, f32p, f64p, f32p, f32p, C.c_int, C.c_int, C.c_int,
                                    C.c_uint32, C.c_int, C.c_int, C.c_int, C.c_double, C.c_int, i64p, C.c_int64, f64p,
@@ -262,6 +263,18 @@ def shade(gbuf: dict, ind_pyr, rgb_pyr, levels, lut_S, lut_E, R: int, K: int, M:
     if rc:
         raise ValueError("orc_shade_pixels rejected its arguments")
     return out
+
+
+def quantile_levels(env: np.ndarray, K: int, ell: float = 1e-3):
+    """Quantile levels (level_mode 1) and, per level, the margin of its
+    weighted distribution function to q W, over W."""
+    env = np.ascontiguousarray(env, dtype=np.float32)
+    R = env.shape[1]
+    levels = np.zeros(K, np.float64)
+    margin = np.zeros(K, np.float64)
+    if lib().orc_quantile_levels(_p(env, C.c_float), R, K, ell, _p(levels, C.c_double), _p(margin, C.c_double)):
+        raise ValueError("orc_quantile_levels rejected its arguments")
+    return levels, margin
 
 
 def frame(env, gbuf, K, M, T=64, ell=1e-3, seed=1, vertices=1, level_mode=0, weight_space=0, pixels=None,

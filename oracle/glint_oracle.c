@@ -107,10 +107,88 @@ static void radiance_levels(double lmin, double lmax, int K, int level_mode, dou
     L[K - 1] = lmax;
 }
 
+/* Exact solid angle of texel (x, y) of a cube face of size R: the area
+ * element dA / (1 + s^2 + t^2)^(3/2) of the unit cube face integrated over
+ * the texel, from its antiderivative atan2(s t, sqrt(s^2 + t^2 + 1)). */
+static double corner_F(double s, double t) { return atan2(s * t, sqrt(s * s + t * t + 1.0)); }
+
+static double texel_solid_angle(int R, int x, int y)
+{
+    double s0 = 2.0 * x / R - 1.0, s1 = 2.0 * (x + 1) / R - 1.0;
+    double t0 = 2.0 * y / R - 1.0, t1 = 2.0 * (y + 1) / R - 1.0;
+    return corner_F(s1, t1) - corner_F(s0, t1) - corner_F(s1, t0) + corner_F(s0, t0);
+}
+
+typedef struct {
+    double y, w;
+} yw_t;
+
+static int cmp_yw(const void *a, const void *b)
+{
+    double ya = ((const yw_t *)a)->y, yb = ((const yw_t *)b)->y;
+    return (ya > yb) - (ya < yb);
+}
+
+/* Quantile levels: the configuration's wording "regions by radiance
+ * quantiles" (the paper's own levels are the log-lerp above).  Level k,
+ * 1 <= k <= K-2 (zero-based), is the solid-angle-weighted quantile of the
+ * texel luminance at q = k/(K-1): the smallest texel luminance y whose
+ * weighted distribution function C(y) = sum of the solid angles of the
+ * texels with Y <= y reaches q W (W the total), clipped to [lmin, lmax]
+ * like the log-lerp levels; L(0) = 0 and L(K-1) = lmax.  margin[k]
+ * (optional) is the distance of q W to the nearer of C(L(k)) and
+ * C(just below L(k)), over W: the room a differently rounded sum has before
+ * it would pick another texel value. */
+static int quantile_levels(const float *env, int R, int K, double lmin, double lmax, double *L, double *margin)
+{
+    int64_t n = 6LL * R * R;
+    yw_t *a = (yw_t *)malloc(sizeof(yw_t) * (size_t)n);
+    if (!a) return ORC_EINVAL;
+    for (int f = 0; f < 6; ++f)
+        for (int y = 0; y < R; ++y)
+            for (int x = 0; x < R; ++x) {
+                int64_t i = ((int64_t)f * R + y) * R + x;
+                a[i].y = luminance(env + 3 * i);
+                a[i].w = texel_solid_angle(R, x, y);
+            }
+    qsort(a, (size_t)n, sizeof(yw_t), cmp_yw);
+    double W = 0.0;
+    for (int64_t i = 0; i < n; ++i) W += a[i].w;
+    L[0] = 0.0;
+    if (margin) margin[0] = INFINITY;
+    for (int k = 1; k <= K - 2; ++k) {
+        double tau = (double)k / (double)(K - 1) * W;
+        double cum = 0.0, below = 0.0;
+        int64_t i = 0;
+        /* walk runs of equal luminance: C jumps by the whole run */
+        while (i < n) {
+            int64_t j = i;
+            double run = 0.0;
+            while (j < n && a[j].y == a[i].y) run += a[j++].w;
+            below = cum;
+            cum += run;
+            if (cum >= tau || j == n) break;
+            i = j;
+        }
+        double q = a[i].y;
+        if (q < lmin) q = lmin;
+        if (q > lmax) q = lmax;
+        L[k] = q;
+        if (margin) {
+            double m1 = (cum - tau) / W, m2 = (tau - below) / W;
+            margin[k] = m1 < m2 ? m1 : m2;
+        }
+    }
+    L[K - 1] = lmax;
+    if (margin) margin[K - 1] = INFINITY;
+    free(a);
+    return ORC_OK;
+}
+
 int orc_partition(const float *env, int R, int K, double ell, int level_mode, int weight_space,
                   double *levels, uint8_t *ind_j, float *ind_t)
 {
-    if (R < 1 || K < 2 || K > 16 || !(ell > 0.0)) return ORC_EINVAL;
+    if (R < 1 || K < 2 || K > 16 || !(ell > 0.0) || level_mode < 0 || level_mode > 2) return ORC_EINVAL;
     int64_t n = 6LL * R * R;
     double ymin = INFINITY, ymax = 0.0;
     for (int64_t i = 0; i < n; ++i) {
@@ -121,7 +199,11 @@ int orc_partition(const float *env, int R, int K, double ell, int level_mode, in
     double lmin = ymin > ell ? ymin : ell;
     double lmax = ymax;
     if (lmax < lmin) lmax = lmin;
-    radiance_levels(lmin, lmax, K, level_mode, levels);
+    if (level_mode == 1) {
+        if (quantile_levels(env, R, K, lmin, lmax, levels, NULL)) return ORC_EINVAL;
+    } else {
+        radiance_levels(lmin, lmax, K, level_mode, levels);
+    }
     for (int64_t i = 0; i < n; ++i) {
         double y = luminance(env + 3 * i);
         if (y > levels[K - 1]) y = levels[K - 1];
@@ -144,6 +226,22 @@ int orc_partition(const float *env, int R, int K, double ell, int level_mode, in
         ind_t[i] = (float)t;
     }
     return ORC_OK;
+}
+
+/* Quantile levels with their margins (for the tests). */
+int orc_quantile_levels(const float *env, int R, int K, double ell, double *levels, double *margin)
+{
+    if (R < 1 || K < 2 || K > 16 || !(ell > 0.0)) return ORC_EINVAL;
+    int64_t n = 6LL * R * R;
+    double ymin = INFINITY, ymax = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        double y = luminance(env + 3 * i);
+        if (y < ymin) ymin = y;
+        if (y > ymax) ymax = y;
+    }
+    double lmin = ymin > ell ? ymin : ell;
+    double lmax = ymax < lmin ? lmin : ymax;
+    return quantile_levels(env, R, K, lmin, lmax, levels, margin);
 }
 
 /* ------------------------------------------------------------------------ */
