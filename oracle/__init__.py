@@ -73,18 +73,18 @@ def _declare(L):
     L.orc_quantile_levels.argtypes = [f32p, C.c_int, C.c_int, C.c_double, f64p, f64p]
     L.orc_pcg4d.argtypes = [C.POINTER(C.c_uint32), C.POINTER(C.c_uint32), C.c_int64]
     L.orc_shade_pixels.argtypes = [C.POINTER(f32p), f32p, f32p, f64p, f32p, f32p, C.c_int, C.c_int, C.c_int,
-                                   C.c_uint32, C.c_int, C.c_int, C.c_int, C.c_double, C.c_int, i64p, C.c_int64, f64p,
-                                   f64p, u8p, f64p, u8p, C.c_int]
+                                   C.c_uint32, C.c_int, C.c_int, C.c_int, C.c_int, C.c_double, C.c_int, i64p,
+                                   C.c_int64, f64p, f64p, u8p, f64p, u8p, C.c_int]
     L.orc_shade_pixels_given_F.argtypes = [C.POINTER(f32p), f64p, f32p, f64p, f32p, f32p, C.c_int, C.c_int,
-                                           C.c_int, C.c_uint32, C.c_int, C.c_int, i64p, C.c_int64, f64p, f64p,
-                                           u8p, f64p, u8p, C.c_int]
+                                           C.c_int, C.c_uint32, C.c_int, C.c_int, C.c_int, i64p, C.c_int64, f64p,
+                                           f64p, u8p, f64p, u8p, C.c_int]
     u32p = C.POINTER(C.c_uint32)
     L.orc_footprint_grid.argtypes = [C.c_double] * 6 + [f64p, f64p, u32p, i64p, i64p]
     L.orc_footprint_grid.restype = C.c_int
     L.orc_sample_binomial.argtypes = [C.c_int, f64p, f64p, u32p, u32p, C.c_int64, f64p, f64p, u8p, u8p, C.c_int]
     L.orc_gate_probs.argtypes = [C.c_float, C.c_float, f32p]
     L.orc_dual_gated.argtypes = [C.c_double, C.c_double, C.c_float, C.c_float, f64p, f64p, u8p]
-    L.orc_multinomial.argtypes = [C.c_int, C.c_double, f64p, C.c_int, C.c_uint32, C.c_uint32, C.c_int32,
+    L.orc_multinomial.argtypes = [C.c_int, C.c_int, C.c_double, f64p, C.c_int, C.c_uint32, C.c_uint32, C.c_int32,
                                   C.c_int64, C.c_int64, f64p, u8p]
     L.orc_multinomial.restype = C.c_int
     L.orc_face_dir.argtypes = [C.c_int, C.c_double, C.c_double, f64p]
@@ -197,12 +197,14 @@ SAMPLERS = {"dual": 0, "single": 1, "single-floor": 2}
 
 def shade(gbuf: dict, ind_pyr, rgb_pyr, levels, lut_S, lut_E, R: int, K: int, M: int, seed: int,
           vertices: int = 1, pixels=None, threads=None, F=None, sampler: int = 0, prob_mode: int = 0,
-          gamma: float = 1.0, lobe_taps: int = 0):
+          gamma: float = 1.0, lobe_taps: int = 0, tree: int = 0):
     """Glint radiance of the requested pixels (all when None).
 
     sampler: binomial approximation of every tree node, 0 dual-gated (Sec. 6
     Alg. "Dual-gated Gaussian"), 1 single-gated Eq. (gated), 2 the prior
     single-gated form Eq. (oldgated).
+    tree: shape of the hierarchical multinomial, 0 balanced binary tree,
+    1 sequential chain (bin i against the bins after it).
     prob_mode 1: one reflection probability gamma for every facet (the
     comparison method of Sec. 7), outputs laid out for K = 2.
     gbuf may carry "visibility" (float32 in [0, 1]) to attenuate the
@@ -247,7 +249,8 @@ def shade(gbuf: dict, ind_pyr, rgb_pyr, levels, lut_S, lut_E, R: int, K: int, M:
         F = np.ascontiguousarray(F, dtype=np.float64).reshape(n, K)
         rc = lib().orc_shade_pixels_given_F(arr, _p(F, C.c_double), _p(rgb_pyr, C.c_float), _p(levels, C.c_double),
                                             _p(lut_S, C.c_float), _p(lut_E, C.c_float), R, K, M, seed, vertices,
-                                            sampler, _p(pixels, C.c_int64), n, _p(out["radiance"], C.c_double),
+                                            sampler, tree, _p(pixels, C.c_int64), n,
+                                            _p(out["radiance"], C.c_double),
                                             _p(out["counts"], C.c_double), _p(out["codes"], C.c_uint8),
                                             _p(out["probs"], C.c_double), _p(out["flags"], C.c_uint8),
                                             threads or threads_default())
@@ -256,7 +259,8 @@ def shade(gbuf: dict, ind_pyr, rgb_pyr, levels, lut_S, lut_E, R: int, K: int, M:
         return out
     rc = lib().orc_shade_pixels(arr, _p(ind_pyr, C.c_float), _p(rgb_pyr, C.c_float), _p(levels, C.c_double),
                                 _p(lut_S, C.c_float), _p(lut_E, C.c_float), R, K, M, seed, vertices,
-                                sampler, prob_mode, gamma, lobe_taps, _p(pixels, C.c_int64), n, _p(out["radiance"], C.c_double),
+                                sampler, tree, prob_mode, gamma, lobe_taps, _p(pixels, C.c_int64), n,
+                                _p(out["radiance"], C.c_double),
                                 _p(out["counts"], C.c_double), _p(out["codes"], C.c_uint8),
                                 _p(out["probs"], C.c_double), _p(out["flags"], C.c_uint8),
                                 threads or threads_default())
@@ -324,15 +328,16 @@ def dual_gated(N: float, p: float, xi1: float, xi2: float):
     return n.value, nb.value, code.value
 
 
-def multinomial(sampler: int, NP: float, p, seed: int, surf: int, level: int, a: int, b: int):
+def multinomial(sampler: int, NP: float, p, seed: int, surf: int, level: int, a: int, b: int, tree: int = 0):
     """One hierarchical multinomial draw (Sec. 6) of N_P facets over the
     given probabilities, hashed as a V = 1 shading draw at lattice vertex
-    (a, b) of `level`.  Returns (counts [K], codes [K-1], flags)."""
+    (a, b) of `level`; tree 0 balanced binary tree, 1 sequential chain.
+    Returns (counts [K], codes [K-1], flags)."""
     p = np.ascontiguousarray(p, dtype=np.float64)
     K = len(p)
     M = np.zeros(K)
     codes = np.zeros(K - 1, np.uint8)
-    fl = lib().orc_multinomial(sampler, float(NP), _p(p, C.c_double), K, seed, surf, level, a, b,
+    fl = lib().orc_multinomial(sampler, tree, float(NP), _p(p, C.c_double), K, seed, surf, level, a, b,
                                _p(M, C.c_double), _p(codes, C.c_uint8))
     if fl < 0:
         raise ValueError("orc_multinomial rejected its arguments")

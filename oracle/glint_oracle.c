@@ -915,13 +915,50 @@ static int near_int_flag(double v, int cont)
     return (d > 0.0 || cont) && d < (band > 1e-5 ? band : 1e-5);
 }
 
+/* Sec. 6 (a multinomial drawn "hierarchically" from binomials), second
+ * shape: a sequential chain.  Node i (0 <= i <= K-2) draws the facets of
+ * bin i out of the N_i that reach it, with p_node = p_i / S_i, S_i the
+ * suffix sum p_i + S_{i+1} (S_{K-1} = p_{K-1}, evaluated from the last bin
+ * down), p_node = 0 when S_i = 0; bin i receives the positive count n and
+ * the negative count nb goes on to node i+1 (N_0 = N_P); bin K-1 receives
+ * what reaches it. */
+static int multinomial_chain(int sampler, double NP, int root_exact, const double *p, int K, uint32_t seed,
+                             uint32_t surf, uint32_t key, int64_t a, int64_t b, double *M, uint8_t *codes)
+{
+    double S[16];
+    S[K - 1] = p[K - 1];
+    for (int k = K - 2; k >= 0; --k) S[k] = p[k] + S[k + 1];
+    double N = NP;
+    int exact = root_exact, cont = 0, flag = 0;
+    for (int i = 0; i < K - 1; ++i) {
+        double pn = S[i] > 0.0 ? p[i] / S[i] : 0.0;
+        if (pn > 1.0) pn = 1.0;
+        float xi1, xi2;
+        hash_xi_key(seed, surf, key, a, b, i, &xi1, &xi2);
+        node_out o;
+        sample_node(sampler, N, pn, xi1, xi2, exact, cont, &o);
+        codes[i] = o.code;
+        flag |= o.flag;
+        M[i] = o.n;
+        flag |= near_int_flag(M[i], o.n_cont) << 3;
+        N = o.nb;
+        exact = exact && !(o.code & 16);
+        cont = o.nb_cont;
+    }
+    M[K - 1] = N;
+    flag |= near_int_flag(N, cont) << 3;
+    return flag;
+}
+
 /* Sec. 6 (hierarchical multinomial from recursive binomials): balanced binary
  * tree over the K bins, nodes numbered breadth first (heap order); node i
  * splits [lo,hi) at the midpoint; the left child receives the positive count
- * n, the right child the negative count nb.  p_node = S_left / S_node. */
-static int multinomial(int sampler, double NP, int root_exact, const double *p, int K, uint32_t seed, uint32_t surf,
-                       uint32_t key, int64_t a, int64_t b, double *M, uint8_t *codes)
+ * n, the right child the negative count nb.  p_node = S_left / S_node.
+ * tree = 1 selects the sequential chain above instead. */
+static int multinomial(int sampler, int tree, double NP, int root_exact, const double *p, int K, uint32_t seed,
+                       uint32_t surf, uint32_t key, int64_t a, int64_t b, double *M, uint8_t *codes)
 {
+    if (tree == 1) return multinomial_chain(sampler, NP, root_exact, p, K, seed, surf, key, a, b, M, codes);
     int nodes = K - 1;
     double Nn[32];
     int lo_[32], hi_[32], exact[32], cont[32];
@@ -1213,13 +1250,13 @@ static void aniso_lookup(const pyr_src *ind, const pyr_src *rgbs, int R, int M, 
  * grid decision (cell, ordering, triangle) within 1e-9 of its boundary. */
 static int shade_impl(const float *const *gb, const float *ind_pyr, const float *rgb_pyr, const double *levels,
                       const float *lut_S, const float *lut_E, int R, int K, int M, uint32_t seed, int V,
-                      int sampler, int prob_mode, double gamma, int lobe_taps, const int64_t *pix, int64_t count,
+                      int sampler, int tree, int prob_mode, double gamma, int lobe_taps, const int64_t *pix, int64_t count,
                       const double *Fext, double *radiance, double *counts, uint8_t *codes, double *probs,
                       uint8_t *flags, int threads)
 {
     if (R < 1 || K < 2 || K > 16 || (K & (K - 1)) || M < 1 || (R >> (M - 1)) < 1 || (V != 1 && V != 6 && V != 12) ||
         (V == 12 && (!gb[20] || !gb[21] || !gb[22] || !gb[23])) ||
-        sampler < 0 || sampler > 2 || prob_mode < 0 || prob_mode > 1 ||
+        sampler < 0 || sampler > 2 || tree < 0 || tree > 1 || prob_mode < 0 || prob_mode > 1 ||
         (prob_mode == 1 && !(gamma > 0.0 && gamma <= 1.0)) ||
         !(lobe_taps == 0 || lobe_taps == 2 || lobe_taps == 4 || lobe_taps == 8) ||
         (lobe_taps && (!gb[17] || !gb[18] || !gb[19])))
@@ -1362,7 +1399,7 @@ static int shade_impl(const float *const *gb, const float *ind_pyr, const float 
             if (V != 12) key = ((uint32_t)lev & 0xFFFFu) << 16;
             double Mv[16];
             uint8_t cv[16];
-            flag |= multinomial(sampler, Nv, V != 12, pa, K, seed, surf, key, a, b, Mv, cv);
+            flag |= multinomial(sampler, tree, Nv, V != 12, pa, K, seed, surf, key, a, b, Mv, cv);
             for (int k = 0; k < K; ++k) Msum[k] += w * Mv[k];
             if (cnt) for (int k = 0; k < K; ++k) cnt[vi * K + k] = Mv[k];
             if (cod) for (int k = 0; k < K - 1; ++k) cod[vi * (K - 1) + k] = cv[k];
@@ -1386,10 +1423,10 @@ static int shade_impl(const float *const *gb, const float *ind_pyr, const float 
 
 int orc_shade_pixels(const float *const *gb, const float *ind_pyr, const float *rgb_pyr, const double *levels,
                      const float *lut_S, const float *lut_E, int R, int K, int M, uint32_t seed, int V, int sampler,
-                     int prob_mode, double gamma, int lobe_taps, const int64_t *pix, int64_t count,
+                     int tree, int prob_mode, double gamma, int lobe_taps, const int64_t *pix, int64_t count,
                      double *radiance, double *counts, uint8_t *codes, double *probs, uint8_t *flags, int threads)
 {
-    return shade_impl(gb, ind_pyr, rgb_pyr, levels, lut_S, lut_E, R, K, M, seed, V, sampler, prob_mode, gamma,
+    return shade_impl(gb, ind_pyr, rgb_pyr, levels, lut_S, lut_E, R, K, M, seed, V, sampler, tree, prob_mode, gamma,
                       lobe_taps, pix, count, NULL, radiance, counts, codes, probs, flags, threads);
 }
 
@@ -1399,11 +1436,12 @@ int orc_shade_pixels(const float *const *gb, const float *ind_pyr, const float *
  * ind_pyr is not read. */
 int orc_shade_pixels_given_F(const float *const *gb, const double *F, const float *rgb_pyr, const double *levels,
                              const float *lut_S, const float *lut_E, int R, int K, int M, uint32_t seed, int V,
-                             int sampler, const int64_t *pix, int64_t count, double *radiance, double *counts,
-                             uint8_t *codes, double *probs, uint8_t *flags, int threads)
+                             int sampler, int tree, const int64_t *pix, int64_t count, double *radiance,
+                             double *counts, uint8_t *codes, double *probs, uint8_t *flags, int threads)
 {
     if (!F) return ORC_EINVAL;
-    return shade_impl(gb, NULL, rgb_pyr, levels, lut_S, lut_E, R, K, M, seed, V, sampler, 0, 1.0, 0, pix, count, F,
+    return shade_impl(gb, NULL, rgb_pyr, levels, lut_S, lut_E, R, K, M, seed, V, sampler, tree, 0, 1.0, 0, pix,
+                      count, F,
                       radiance, counts, codes, probs, flags, threads);
 }
 
@@ -1425,11 +1463,12 @@ void orc_dual_gated(double N, double p, float xi1, float xi2, double *n, double 
 /* The hierarchical multinomial of one draw (Sec. 6) on given probabilities
  * p[K] (K a power of two <= 16): leaf counts M[K], node codes[K-1]; returns
  * the draw's flags (bit 8: a count near an integer). */
-int orc_multinomial(int sampler, double NP, const double *p, int K, uint32_t seed, uint32_t surf, int32_t level,
-                    int64_t a, int64_t b, double *M, uint8_t *codes)
+int orc_multinomial(int sampler, int tree, double NP, const double *p, int K, uint32_t seed, uint32_t surf,
+                    int32_t level, int64_t a, int64_t b, double *M, uint8_t *codes)
 {
-    if (sampler < 0 || sampler > 2 || K < 2 || K > 16 || (K & (K - 1))) return -1;
-    return multinomial(sampler, NP, 1, p, K, seed, surf, ((uint32_t)level & 0xFFFFu) << 16, a, b, M, codes);
+    if (sampler < 0 || sampler > 2 || tree < 0 || tree > 1 || K < 2 || K > 16 || (tree == 0 && (K & (K - 1))))
+        return -1;
+    return multinomial(sampler, tree, NP, 1, p, K, seed, surf, ((uint32_t)level & 0xFFFFu) << 16, a, b, M, codes);
 }
 
 /* One binomial draw per element with the given random words: xi1 from h1,
