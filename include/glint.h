@@ -79,10 +79,19 @@ int glint_sync(glint_ctx ctx);
  *
  * Brightness of a texel is Rec. 709 luminance of its RGB (non-finite or
  * negative channels count as 0).  With Lmin = max(ell, min Y) and
- * Lmax = max Y: levels[0] = 0 and, for k >= 1,
- * levels[k] = min(Lmax, exp(lerp(ln Lmin, ln Lmax, k/(K-1)))) with
- * levels[K-1] = Lmax (level_mode 0, the paper's; level_mode 2 uses
- * (k-1)/(K-2) so that levels[1] = Lmin).  Each texel stores the interval
+ * Lmax = max(max Y, Lmin): levels[0] = 0, levels[K-1] = Lmax and, for
+ * 1 <= k <= K-2:
+ *   level_mode 0 (the paper's): min(Lmax, exp(lerp(ln Lmin, ln Lmax, k/(K-1))));
+ *   level_mode 2: the same with (k-1)/(K-2), so that levels[1] = Lmin;
+ *   level_mode 1 (regions by radiance quantiles): the solid-angle-weighted
+ *     quantile of Y at q = k/(K-1), i.e. the smallest texel luminance y
+ *     with C(y) >= q W, C(y) the total solid angle of the texels with
+ *     Y <= y and W that of the sphere, clipped to [Lmin, Lmax].  Solid
+ *     angles are exact per texel (from the antiderivative
+ *     atan2(s t, sqrt(s^2 + t^2 + 1)) of the cube face's area element)
+ *     and summed in 2^-55 fixed point, so the result does not depend on
+ *     the summation order.
+ * Each texel stores the interval
  * index j (largest j <= K-2 with levels[j] <= min(Y, Lmax)) and the lerp
  * factor t in [0,1] (linear space, weight_space 0, the paper's choice; log
  * space for j >= 1 with weight_space 1); the fuzzy indicator weights are
@@ -91,11 +100,13 @@ int glint_sync(glint_ctx ctx);
 typedef struct glint_partition_params {
     int K;            /* number of radiance levels, 2..16 */
     double ell;       /* lower clip of the minimum radiance (> 0), e.g. 1e-3 */
-    int level_mode;   /* 0 (paper) or 2 */
+    int level_mode;   /* 0 (paper), 1 (radiance quantiles) or 2 */
     int weight_space; /* 0 linear (paper) or 1 log */
 } glint_partition_params;
 
-/* Device workspace (bytes) glint_partition_env needs for a face size R. */
+/* Device workspace (bytes) glint_partition_env needs for a face size R
+ * (any level mode; the quantile mode's solid-angle table of one face
+ * quadrant grows as R^2 / 4 * 8 bytes: 128 KB at R = 256, 32 MB at 4096). */
 size_t glint_partition_workspace_bytes(int R);
 
 /* env: device [6][R][R][3] float32.  workspace: device, at least
@@ -302,7 +313,13 @@ int glint_sample_binomial(glint_ctx ctx, int sampler, int exact_gating, const do
  * in breadth-first order), node probability S_left / S_node, the left child
  * receiving the positive count n and the right child the negative count
  * nbar of the dual-gated Gaussian (or of the single-gated forms, selected
- * by params->sampler, see glint_sample_binomial).  Gating probabilities and masks are
+ * by params->sampler, see glint_sample_binomial).  With tree =
+ * GLINT_TREE_CHAIN the multinomial is a sequential chain instead (Sec. 6
+ * does not fix the shape): node i (0..K-2) draws bin i's count out of the
+ * N_i facets that reach it with probability p_i / S_i, S_i = p_i + S_{i+1}
+ * (S_{K-1} = p_{K-1}), nbar goes on to node i+1 (N_0 = N_P) and bin K-1
+ * keeps what reaches it; the node ids of the hash are 0..K-2 in chain
+ * order.  Gating probabilities and masks are
  * evaluated in float with the bias c = max(1, eps/p), eps = 10^-3.54
  * (Sec. 6 "Numeric Gating Issues"); the Gaussian quantile (AS 241) and all
  * other arithmetic in double.  Random numbers per (surface, lattice vertex,
@@ -402,10 +419,16 @@ typedef struct glint_shade_params {
     int lobe_taps;    /* 0: one lookup at alpha = sqrt(alpha_x alpha_y); 2, 4 or 8: anisotropic
                          lookup with that many taps along the lobe (see glint_shade; needs the
                          G-buffer tangent; float32 pyramid, dual-gated sampler, GLINT_PROBS_ENV) */
+    int tree;         /* shape of the hierarchical multinomial: GLINT_TREE_BALANCED (binary tree,
+                         the default) or GLINT_TREE_CHAIN (sequential chain; float32 pyramid,
+                         dual-gated sampler, GLINT_PROBS_ENV, one lookup, vertices 1 or 6, plain
+                         form; not in glint_frame_batched) */
 } glint_shade_params;
 
 #define GLINT_PROBS_ENV 0
 #define GLINT_PROBS_CONSTANT 1
+#define GLINT_TREE_BALANCED 0
+#define GLINT_TREE_CHAIN 1
 
 /* Optional per-pixel outputs for verification (each pointer may be NULL). */
 typedef struct glint_shade_debug {

@@ -93,9 +93,7 @@ int check_partition(const float *env, int R, const glint_partition_params *pp, c
     if (int rc = check_R(R)) return rc;
     if (pp->K < 2 || pp->K > 16) return fail(GLINT_EINVAL, "K=%d must be in [2, 16]", pp->K);
     if (!(pp->ell > 0.0)) return fail(GLINT_EINVAL, "ell must be > 0");
-    if (pp->level_mode != 0 && pp->level_mode != 2)
-        return fail(pp->level_mode == 1 ? GLINT_EUNSUPPORTED : GLINT_EINVAL, "level_mode %d not available",
-                    pp->level_mode);
+    if (pp->level_mode < 0 || pp->level_mode > 2) return fail(GLINT_EINVAL, "level_mode %d not available", pp->level_mode);
     if (pp->level_mode == 2 && pp->K < 3) return fail(GLINT_EINVAL, "level_mode 2 needs K >= 3");
     if (pp->weight_space != 0 && pp->weight_space != 1) return fail(GLINT_EINVAL, "weight_space must be 0 or 1");
     if (reinterpret_cast<uintptr_t>(workspace) % 8) return fail(GLINT_EINVAL, "workspace must be 8-byte aligned");
@@ -189,7 +187,7 @@ int glint_sync(glint_ctx ctx)
 size_t glint_partition_workspace_bytes(int R)
 {
     if (!pow2(R) || R > 4096) return 0;
-    return sizeof(double) * 2 * (size_t)glint::partition_blocks(R);
+    return glint::partition_workspace_bytes(R);
 }
 
 int glint_partition_env(glint_ctx ctx, const float *env, int R, const glint_partition_params *pp, void *workspace,
@@ -240,6 +238,8 @@ static int check_shade_params(const glint_shade_params &sp, int view)
         what = "gamma must be in (0, 1]";
     else if (sp.lobe_taps != 0 && sp.lobe_taps != 2 && sp.lobe_taps != 4 && sp.lobe_taps != 8)
         what = "lobe_taps must be 0, 2, 4 or 8";
+    else if (sp.tree != GLINT_TREE_BALANCED && sp.tree != GLINT_TREE_CHAIN)
+        what = "tree must be GLINT_TREE_BALANCED or GLINT_TREE_CHAIN";
     if (!what) return GLINT_OK;
     if (view >= 0) return fail(GLINT_EINVAL, "view %d: %s", view, what);
     return fail(GLINT_EINVAL, "%s", what);
@@ -303,6 +303,11 @@ int glint_shade(glint_ctx ctx, const glint_gbuffer *g, int64_t P, const glint_en
         (env->dtype != GLINT_F32 || sp->sampler != GLINT_SAMPLER_DUAL || constant || sp->lobe_taps != 0))
         return fail(GLINT_EUNSUPPORTED, "the footprint grid needs a float32 pyramid, the dual gate, the map's "
                     "probabilities and one lookup");
+    if (sp->tree == GLINT_TREE_CHAIN &&
+        (env->dtype != GLINT_F32 || sp->sampler != GLINT_SAMPLER_DUAL || constant || sp->lobe_taps != 0 ||
+         sp->vertices == 12))
+        return fail(GLINT_EUNSUPPORTED, "the sequential chain needs a float32 pyramid, the dual gate, the map's "
+                    "probabilities, one lookup and 1 or 6 vertices");
     if (P == 0) return ok();
     if (!radiance || !env->rgb_pyr || !env->lut_E ||
         (!constant && (!env->ind_pyr || !env->levels || !env->lut_S)))
@@ -444,8 +449,10 @@ int glint_shade_surrogate(glint_ctx ctx, const glint_gbuffer *g, int64_t P, cons
     if (int rc = check_mips(env->R, env->num_mips)) return rc;
     if (int rc = check_surrogate(env->K, w, w_bf16)) return rc;
     if (int rc = check_shade_params(*sp, -1)) return rc;
-    if (sp->prob_mode != GLINT_PROBS_ENV || sp->lobe_taps != 0 || sp->vertices == 12)
-        return fail(GLINT_EUNSUPPORTED, "the surrogate form computes the map's probabilities with one lookup");
+    if (sp->prob_mode != GLINT_PROBS_ENV || sp->lobe_taps != 0 || sp->vertices == 12 ||
+        sp->tree != GLINT_TREE_BALANCED)
+        return fail(GLINT_EUNSUPPORTED, "the surrogate form computes the map's probabilities with one lookup and "
+                    "the balanced tree");
     if (P == 0) return ok();
     if (!radiance || !workspace || !env->rgb_pyr || !env->levels || !env->lut_S || !env->lut_E)
         return fail(GLINT_EINVAL, "null pointer argument");
@@ -497,9 +504,9 @@ int glint_frame_batched(glint_ctx ctx, const glint_env_task *envs, int n_env, co
             return fail(GLINT_EINVAL, "view %d: bad num_pixels", v);
         if (int rc = check_shade_params(w.shade, v)) return rc;
         if (w.shade.sampler != GLINT_SAMPLER_DUAL || w.shade.prob_mode != GLINT_PROBS_ENV || w.shade.lobe_taps != 0 ||
-            w.shade.vertices == 12)
-            return fail(GLINT_EUNSUPPORTED, "view %d: batched frames use the dual-gated sampler and the map's "
-                        "probabilities with one lookup", v);
+            w.shade.vertices == 12 || w.shade.tree != GLINT_TREE_BALANCED)
+            return fail(GLINT_EUNSUPPORTED, "view %d: batched frames use the dual-gated sampler, the balanced tree "
+                        "and the map's probabilities with one lookup", v);
         if (!w.radiance) return fail(GLINT_EINVAL, "view %d: null radiance", v);
         if (envs[w.env_index].surrogate_w &&
             (!w.surrogate_F || reinterpret_cast<uintptr_t>(w.surrogate_F) % 16))

@@ -172,7 +172,7 @@ hipError_t frame_batched(BatchedCache &c, const glint_env_task *envs, int n_env,
     if ((err = hipStreamSynchronize(stream)) != hipSuccess) return err;
     for (auto g = c.graphs.begin(); g != c.graphs.end();) {
         if (g->second.workspace == workspace) {
-            hipGraphExecDestroy(g->second.exec);
+            (void)hipGraphExecDestroy(g->second.exec);
             g = c.graphs.erase(g);
         } else {
             ++g;
@@ -281,7 +281,7 @@ hipError_t frame_batched(BatchedCache &c, const glint_env_task *envs, int n_env,
     hipGraphDestroy(graph);
     if (err != hipSuccess) return err;
     if (c.graphs.size() >= 16) { // bounded cache: drop one entry
-        hipGraphExecDestroy(c.graphs.begin()->second.exec);
+        (void)hipGraphExecDestroy(c.graphs.begin()->second.exec);
         c.graphs.erase(c.graphs.begin());
     }
     c.graphs[key] = BatchedCache::Entry{exec, workspace};

@@ -389,6 +389,64 @@ __device__ __forceinline__ void multinomial(double NP, const double (&p)[K], uin
     for (int k = 0; k < K; ++k) leaf[k] = Q[k];
 }
 
+// The second shape of the hierarchical multinomial (tree = 1): a sequential
+// chain.  Node i draws bin i's facets out of those that reach it with
+// probability p_i / S_i, S_i = p_i + S_{i+1} the suffix sum (from the last
+// bin down); the negative count goes on to node i+1 and bin K-1 keeps what
+// reaches it.  One copy of the sampler in a loop that is not unrolled; the
+// node probabilities and the bins' counts move through register queues with
+// static indices.
+template <int K, bool SG>
+__device__ __forceinline__ void multinomial_chain(double NP, const double (&p)[K], uint32_t seed_mix, uint32_t key,
+                                                  int64_t a, int64_t b, const double *__restrict__ qtail,
+                                                  bool exact_gating, int sampler, double (&leaf)[K], uint8_t *codes)
+{
+    double S[K];
+    S[K - 1] = p[K - 1];
+#pragma unroll
+    for (int k = K - 2; k >= 0; --k) S[k] = p[k] + S[k + 1];
+    double P[K - 1];
+#pragma unroll
+    for (int k = 0; k < K - 1; ++k) {
+        const double q = S[k] > 0.0 ? p[k] / S[k] : 0.0;
+        P[k] = q > 1.0 ? 1.0 : q;
+    }
+    double Mq[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) Mq[k] = 0.0;
+    double N = NP;
+    uint32_t carry_z = 0, carry_w = 0;
+#pragma unroll 1
+    for (int node = 0; node < K - 1; ++node) {
+        const double pj = P[0];
+#pragma unroll
+        for (int k = 0; k + 1 < K - 1; ++k) P[k] = P[k + 1];
+        uint32_t hx, hy;
+        if ((node & 1) == 0) {
+            const u4 h = pcg4d({(uint32_t)a, (uint32_t)b, key | ((uint32_t)node >> 1), seed_mix});
+            hx = h.x;
+            hy = h.y;
+            carry_z = h.z;
+            carry_w = h.w;
+        } else {
+            hx = carry_z;
+            hy = carry_w;
+        }
+        double n, nb;
+        uint32_t code;
+        node_sample<SG>(sampler, N, pj, hash_unit(hx), hash_unit(hy), hy >> 9, qtail, exact_gating, n, nb, code);
+        if (codes) codes[node] = (uint8_t)code;
+#pragma unroll
+        for (int k = 0; k + 1 < K; ++k) Mq[k] = Mq[k + 1];
+        Mq[K - 1] = n;
+        N = nb;
+    }
+    // Mq[1..K-1] hold the counts of bins 0..K-2 in order
+#pragma unroll
+    for (int k = 0; k + 1 < K; ++k) leaf[k] = Mq[k + 1];
+    leaf[K - 1] = N;
+}
+
 // Footprint grid (Sec. 3.3 "Binomial Sampling with Anisotropic Grids"; the
 // paper uses the grid as a black box, the layout is this library's): the
 // pixel footprint, the ellipse of J J^T for the uv Jacobian J, by length
@@ -459,7 +517,7 @@ __device__ __forceinline__ FootGrid footprint_grid(double j00, double j01, doubl
 // and only RGB is read from the pyramid.  PC: constant reflection
 // probability A.gamma (K = 2, levels (0, 1)), no indicator lookup.
 template <int K, int DT, int V, bool SURR = false, bool SG = false, bool PC = false, bool AN = false,
-          class Args = ShadeArgs>
+          bool CH = false, class Args = ShadeArgs>
 __device__ __forceinline__ void shade_pixel(const Args &A, int64_t i)
 {
     static_assert(!PC || (K == 2 && !SURR), "constant probabilities use two bins");
@@ -664,8 +722,12 @@ __device__ __forceinline__ void shade_pixel(const Args &A, int64_t i)
         if constexpr (V != 12) key = ((uint32_t)lev & 0xFFFFu) << 16;
         double Mv[K];
         uint8_t *cod = A.codes ? (uint8_t *)A.codes + (i * V + vi) * (K - 1) : nullptr;
-        multinomial<K, SG>(Nv, p, seed_mix, key, a, b, (const double *)A.qtail, A.exact_gating != 0, A.sampler, Mv,
-                           cod);
+        if constexpr (CH)
+            multinomial_chain<K, SG>(Nv, p, seed_mix, key, a, b, (const double *)A.qtail, A.exact_gating != 0,
+                                     A.sampler, Mv, cod);
+        else
+            multinomial<K, SG>(Nv, p, seed_mix, key, a, b, (const double *)A.qtail, A.exact_gating != 0, A.sampler,
+                               Mv, cod);
 #pragma unroll
         for (int k = 0; k < K; ++k) Msum[k] += w * Mv[k];
         if (A.counts) {
@@ -691,12 +753,13 @@ __device__ __forceinline__ void shade_pixel(const Args &A, int64_t i)
 
 // The footprint grid and the anisotropic lookup carry more state per lane;
 // asking for two waves per SIMD keeps them at <= 256 registers.
-template <int K, int DT, int V, bool SURR = false, bool SG = false, bool PC = false, bool AN = false>
+template <int K, int DT, int V, bool SURR = false, bool SG = false, bool PC = false, bool AN = false,
+          bool CH = false>
 __global__ void __launch_bounds__(kShadeThreads, (V == 12 || AN) ? 2 : 1) k_shade(ShadeArgs A)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= A.P) return;
-    shade_pixel<K, DT, V, SURR, SG, PC, AN>(A, i);
+    shade_pixel<K, DT, V, SURR, SG, PC, AN, CH>(A, i);
 }
 
 // All views of one (K, V) group in one launch: block b shades tile b of the
@@ -724,7 +787,7 @@ __global__ void __launch_bounds__(kShadeThreads, 1) k_shade_views(const ShadeArg
     const ShadeArgsG A = reinterpret_cast<const ShadeArgsG *>(views)[__builtin_amdgcn_readfirstlane(s_view)];
     const int64_t i = (b - tile0[s_view]) * blockDim.x + threadIdx.x;
     if (i >= A.P) return;
-    shade_pixel<K, DT, V, SURR, false, false, false, ShadeArgsG>(A, i);
+    shade_pixel<K, DT, V, SURR, false, false, false, false, ShadeArgsG>(A, i);
 }
 
 template <int K, int DT>
@@ -859,6 +922,27 @@ hipError_t launch_shade(const glint_gbuffer &g, int64_t P, const glint_env &env,
     a.gamma = (double)sp.gamma;
     a.lobe_taps = sp.lobe_taps;
     const int K = env.K, DT = (int)env.dtype, V = sp.vertices;
+    if (sp.tree == GLINT_TREE_CHAIN) {
+        // sequential chain: float32 pyramid, dual gate, map probabilities, one
+        // lookup, 1 or 6 vertices (the API checks)
+        const unsigned blocks = (unsigned)((P + kShadeThreads - 1) / kShadeThreads);
+#define GLINT_CH(KK)                                                                                         \
+    if (K == KK) {                                                                                           \
+        if (V == 1)                                                                                          \
+            GLINT_LAUNCH("k_shade", (k_shade<KK, 0, 1, false, false, false, false, true>), dim3(blocks),     \
+                         dim3(kShadeThreads), 0, stream, a);                                                 \
+        else                                                                                                 \
+            GLINT_LAUNCH("k_shade", (k_shade<KK, 0, 6, false, false, false, false, true>), dim3(blocks),     \
+                         dim3(kShadeThreads), 0, stream, a);                                                 \
+        return hipGetLastError();                                                                            \
+    }
+        GLINT_CH(2)
+        GLINT_CH(4)
+        GLINT_CH(8)
+        GLINT_CH(16)
+#undef GLINT_CH
+        return hipErrorInvalidValue;
+    }
     if (sp.prob_mode == GLINT_PROBS_CONSTANT) {
         // two bins, indicator pyramid not read
         const unsigned blocks = (unsigned)((P + kShadeThreads - 1) / kShadeThreads);

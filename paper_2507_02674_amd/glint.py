@@ -16,6 +16,7 @@ GLINT_OK, GLINT_EINVAL, GLINT_EUNSUPPORTED, GLINT_EDEVICE, GLINT_ENOMEM = 0, 1, 
 GLINT_F32, GLINT_F16, GLINT_BF16, GLINT_UNORM16 = 0, 1, 2, 3
 GLINT_SAMPLER_DUAL, GLINT_SAMPLER_SINGLE, GLINT_SAMPLER_SINGLE_FLOOR = 0, 1, 2
 GLINT_PROBS_ENV, GLINT_PROBS_CONSTANT = 0, 1
+GLINT_TREE_BALANCED, GLINT_TREE_CHAIN = 0, 1
 GLINT_NO_SURFACE = 0xFFFFFFFF
 LUT_N = 64
 
@@ -50,7 +51,7 @@ class Env(C.Structure):
 
 class ShadeParams(C.Structure):
     _fields_ = [("seed", C.c_uint32), ("vertices", C.c_int), ("exact_gating", C.c_int), ("sampler", C.c_int),
-                ("prob_mode", C.c_int), ("gamma", C.c_float), ("lobe_taps", C.c_int)]
+                ("prob_mode", C.c_int), ("gamma", C.c_float), ("lobe_taps", C.c_int), ("tree", C.c_int)]
 
 
 class ShadeDebug(C.Structure):

@@ -65,7 +65,7 @@ class Shader:
     """Per-pixel glint shading of a fixed G-buffer."""
 
     def __init__(self, ctx, gbuf: dict, seed=1, vertices=1, device="cuda", sampler=G.GLINT_SAMPLER_DUAL,
-                 prob_mode=G.GLINT_PROBS_ENV, gamma=1.0, lobe_taps=0):
+                 prob_mode=G.GLINT_PROBS_ENV, gamma=1.0, lobe_taps=0, tree=G.GLINT_TREE_BALANCED):
         self.ctx = ctx
         self.fields = {k: (v if isinstance(v, torch.Tensor) else torch.from_numpy(v)).to(device)
                        for k, v in gbuf.items()}
@@ -74,7 +74,7 @@ class Shader:
                 if self.fields["surf_id"].dtype == torch.uint32 else self.fields["surf_id"].to(torch.int32)
         self.P = int(self.fields["nx"].numel())
         self.gb = G.make_gbuffer(self.fields)
-        self.sp = G.ShadeParams(seed, vertices, 0, sampler, prob_mode, gamma, lobe_taps)
+        self.sp = G.ShadeParams(seed, vertices, 0, sampler, prob_mode, gamma, lobe_taps, tree)
         self.vertices = vertices
         self.radiance = torch.empty((self.P, 3), dtype=torch.float32, device=device)
 

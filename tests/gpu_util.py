@@ -126,7 +126,7 @@ def gbuf_to_device(gbuf):
 
 def shade(ctx, gbuf, ind_raw, rgb, levels, lut_S, lut_E, R, K, M, dtype=G.GLINT_F32, seed=1, vertices=1,
           debug=True, num_pixels=None, qtail=None, exact_gating=0, sampler=0, prob_mode=0, gamma=1.0,
-          lobe_taps=0):
+          lobe_taps=0, tree=0):
     fields = gbuf_to_device(gbuf)
     P = len(gbuf["nx"]) if num_pixels is None else num_pixels
     tdt, ndt = STORAGE[dtype]
@@ -142,7 +142,7 @@ def shade(ctx, gbuf, ind_raw, rgb, levels, lut_S, lut_E, R, K, M, dtype=G.GLINT_
                    codes=torch.empty((max(P, 1), vertices, Kd - 1), dtype=torch.uint8, device="cuda"),
                    probs=torch.empty((max(P, 1), Kd), dtype=torch.float64, device="cuda"))
     G.glint_shade(ctx, G.make_gbuffer(fields), P, env,
-                  G.ShadeParams(seed, vertices, exact_gating, sampler, prob_mode, gamma, lobe_taps), rad, dbg)
+                  G.ShadeParams(seed, vertices, exact_gating, sampler, prob_mode, gamma, lobe_taps, tree), rad, dbg)
     out = dict(radiance=host(rad)[:P])
     if debug:
         for k, v in dbg.items():

@@ -50,7 +50,7 @@ def test_struct_layouts_match_header():
     assert G.PartitionParams.ell.offset == 8
     assert C.sizeof(G.GBuffer) == 24 * 8
     assert C.sizeof(G.Env) == 5 * 8 + 4 * 4 + 8
-    assert C.sizeof(G.ShadeParams) == 28
+    assert C.sizeof(G.ShadeParams) == 32
     assert C.sizeof(G.ShadeDebug) == 24
 
 

@@ -422,3 +422,48 @@ def test_modes_ragged_sizes_and_empty(ctx, qtail, mode):
         check_pixels(gpu, orc, f"{mode} P={P}", max_flagged=1.0)
     out = U.shade(ctx, g, ind, rgb, levels, S, E, R, K, M, num_pixels=0, vertices=V, debug=False, qtail=qtail, **opts)
     assert out["radiance"].shape[0] == 0
+
+
+# --- the sequential-chain multinomial (tree = 1) ----------------------------------
+
+@pytest.mark.parametrize("K", [2, 4, 8, 16])
+@pytest.mark.parametrize("vertices", [1, 6])
+def test_shade_with_sequential_chain(ctx, qtail, K, vertices):
+    """tree = GLINT_TREE_CHAIN: every pixel against the oracle's chain
+    (densities over 9 decades: gated, small and Gaussian nodes)."""
+    R, M = 16, 5
+    U.log(f"shade chain K={K} V={vertices}")
+    env = synth.make_env(R, 6)
+    levels, ind, rgb = oracle_env(env, K, M)
+    S, E = oracle.lut_tables()
+    g = synth.scene_frame(96, 54, seed=3, density_decades=(0.0, 9.0))
+    gpu = U.shade(ctx, g, ind, rgb, levels, S, E, R, K, M, seed=7, vertices=vertices, qtail=qtail, tree=1)
+    orc = oracle.shade(g, ind, rgb, levels, S, E, R, K, M, 7, vertices, tree=1)
+    check_pixels(gpu, orc, f"chain K={K} V={vertices}")
+    # without the tail table the chain gives the same bits
+    nt = U.shade(ctx, g, ind, rgb, levels, S, E, R, K, M, seed=7, vertices=vertices, tree=1)
+    for k in ("radiance", "counts", "codes"):
+        assert np.array_equal(nt[k], gpu[k]), k
+
+
+def test_sequential_chain_options_are_checked(ctx):
+    import torch
+    R, K, M = 16, 4, 5
+    env = synth.make_env(R, 2)
+    levels, ind, rgb = oracle_env(env, K, M)
+    S, E = oracle.lut_tables()
+    g = synth.scene_frame(32, 18, seed=1)
+    fields = U.gbuf_to_device(g)
+    envs = G.make_env(U.dev(ind), U.dev(rgb), U.dev(levels), U.dev(S), U.dev(E), R, K, M, G.GLINT_F32)
+    ind16 = U.dev(U.encode(ind, G.GLINT_F16).view(np.int16))
+    env16 = G.make_env(ind16, U.dev(rgb), U.dev(levels), U.dev(S), U.dev(E), R, K, M, G.GLINT_F16)
+    rad = torch.empty((len(g["nx"]), 3), dtype=torch.float32, device="cuda")
+    gb = G.make_gbuffer(fields)
+    P = len(g["nx"])
+    for e, sp, code in ((env16, G.ShadeParams(1, 1, 0, 0, 0, 1.0, 0, 1), G.GLINT_EUNSUPPORTED),
+                        (envs, G.ShadeParams(1, 1, 0, G.GLINT_SAMPLER_SINGLE, 0, 1.0, 0, 1), G.GLINT_EUNSUPPORTED),
+                        (envs, G.ShadeParams(1, 1, 0, 0, G.GLINT_PROBS_CONSTANT, 0.5, 0, 1), G.GLINT_EUNSUPPORTED),
+                        (envs, G.ShadeParams(1, 1, 0, 0, 0, 1.0, 0, 2), G.GLINT_EINVAL)):
+        with pytest.raises(G.GlintError) as ex:
+            G.glint_shade(ctx, gb, P, e, sp, rad)
+        assert ex.value.code == code
