@@ -118,6 +118,21 @@ size_t glint_partition_workspace_bytes(int R);
 int glint_partition_env(glint_ctx ctx, const float *env, int R, const glint_partition_params *params,
                         void *workspace, double *levels, uint8_t *ind_j, float *ind_t, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * operation as glint_partition_env without the workspace argument.  Its
+ * workspace is a scratch array of 2,359,296 bytes that the library holds on
+ * each GPU until the process ends (looked up per device by glint_create);
+ * this call allocates nothing.  Every call on one GPU shares that array and
+ * leaves its contents behind (each call rebuilds what it reads), so calls
+ * that overlap on one GPU -- on different streams, threads or contexts --
+ * race and must be ordered by the caller.  Arguments, outputs and errors as
+ * glint_partition_env; GLINT_EINVAL also when the face size needs more
+ * scratch than the array holds (level_mode 1 above R = 1024; levels modes 0
+ * and 2 fit every R). */
+int glint_partition_env_noalloc(glint_ctx ctx, const float *env, int R, const glint_partition_params *params,
+                                double *levels, uint8_t *ind_j, float *ind_t, void *stream);
+
 /* ------------------------------------------------------------------------
  * Prefilter (Sec. 5 "Integrated NDF", Eq. (rtiblndf) with the real-time IBL
  * kernel of Sec. 3.4, Eq. (rtibl), assuming n = v = r).  The K indicator

@@ -4,6 +4,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 
 #include "batched.hpp"
@@ -13,11 +14,46 @@
 struct glint_ctx_s {
     int device;
     int num_cu;
+    void *scratch; // device address of this GPU's copy of `scratch` below
     glint::BatchedCache batched;
     glint::Profiler prof;
 };
 
+// Workspace of glint_partition_env_noalloc: a file-scope device array, one
+// copy per GPU, held until the process ends.  Host code uses the device
+// address that hipGetSymbolAddress returns for the current GPU (kept per
+// device below), never the array's name.  Every call on one GPU shares it.
+constexpr size_t kNoallocScratchBytes = 2304 * 1024;
+static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
+
 namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on `device` (looked up once per device, with
+// that device current).
+hipError_t scratch_address(int device, void **out)
+{
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        int prev = -1;
+        hipError_t e = hipGetDevice(&prev);
+        if (e != hipSuccess) return e;
+        if (prev != device && (e = hipSetDevice(device)) != hipSuccess) return e;
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (prev != device) {
+            const hipError_t e2 = hipSetDevice(prev);
+            if (e == hipSuccess) e = e2;
+        }
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[device] = p;
+    }
+    *out = g_scratch_ptr[device];
+    return hipSuccess;
+}
 
 thread_local char g_err[512] = "";
 
@@ -167,10 +203,15 @@ int glint_create(int device, glint_ctx *out)
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) != hipSuccess)
         return fail(GLINT_EDEVICE, "hipGetDeviceProperties(%d) failed", device);
+    if (device >= kMaxDevices) return fail(GLINT_EINVAL, "device %d beyond the library's %d", device, kMaxDevices);
+    void *scr = nullptr;
+    if (hipError_t e = scratch_address(device, &scr); e != hipSuccess)
+        return fail(GLINT_EDEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", device, hipGetErrorString(e));
     glint_ctx c = new (std::nothrow) glint_ctx_s;
     if (!c) return fail(GLINT_ENOMEM, "context allocation failed");
     c->device = device;
     c->num_cu = prop.multiProcessorCount;
+    c->scratch = scr;
     *out = c;
     return ok();
 }
@@ -199,6 +240,21 @@ int glint_partition_env(glint_ctx ctx, const float *env, int R, const glint_part
     return device_status(glint::launch_partition(env, R, pp->K, pp->ell, pp->level_mode, pp->weight_space,
                                                  workspace, levels, ind_j, ind_t, (hipStream_t)stream),
                          "glint_partition_env launch");
+}
+
+int glint_partition_env_noalloc(glint_ctx ctx, const float *env, int R, const glint_partition_params *pp,
+                                double *levels, uint8_t *ind_j, float *ind_t, void *stream)
+{
+    if (int rc = check_ctx(ctx)) return rc;
+    glint::ProfScope prof_scope(&ctx->prof);
+    if (int rc = check_partition(env, R, pp, ctx->scratch, levels, ind_j, ind_t)) return rc;
+    const size_t need = glint::partition_workspace_bytes_mode(R, pp->level_mode);
+    if (need > kNoallocScratchBytes)
+        return fail(GLINT_EINVAL, "R=%d with level_mode %d needs %zu bytes of scratch; the allocation-free call "
+                    "holds %zu (level_mode 1 up to R = 1024)", R, pp->level_mode, need, kNoallocScratchBytes);
+    return device_status(glint::launch_partition(env, R, pp->K, pp->ell, pp->level_mode, pp->weight_space,
+                                                 ctx->scratch, levels, ind_j, ind_t, (hipStream_t)stream),
+                         "glint_partition_env_noalloc launch");
 }
 
 int64_t glint_pyramid_texels(int R, int num_mips)

@@ -13,6 +13,7 @@ constexpr int kMaxPartitionBlocks = 1024;
 
 int partition_blocks(int R);
 size_t partition_workspace_bytes(int R); // every level mode
+size_t partition_workspace_bytes_mode(int R, int level_mode);
 hipError_t launch_partition(const float *env, int R, int K, double ell, int level_mode, int weight_space,
                             void *workspace, double *levels, uint8_t *ind_j, float *ind_t, hipStream_t stream);
 

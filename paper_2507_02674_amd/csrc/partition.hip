@@ -355,6 +355,14 @@ int partition_blocks(int R)
 
 size_t partition_workspace_bytes(int R) { return quantile_layout(R).total; }
 
+size_t partition_workspace_bytes_mode(int R, int level_mode)
+{
+    // the log-lerp modes use the (min, max) pairs only; the selection state
+    // that follows them is addressed but not read
+    const QLayout q = quantile_layout(R);
+    return (level_mode == 1) ? q.total : q.hist;
+}
+
 hipError_t launch_partition(const float *env, int R, int K, double ell, int level_mode, int weight_space,
                             void *workspace, double *levels, uint8_t *ind_j, float *ind_t, hipStream_t stream)
 {

@@ -82,6 +82,8 @@ EXPORTS = {
     "glint_partition_workspace_bytes": ([C.c_int], C.c_size_t),
     "glint_partition_env": ([C.c_void_p, C.c_void_p, C.c_int, C.POINTER(PartitionParams), C.c_void_p, C.c_void_p,
                              C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
+    "glint_partition_env_noalloc": ([C.c_void_p, C.c_void_p, C.c_int, C.POINTER(PartitionParams), C.c_void_p,
+                                     C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     "glint_pyramid_texels": ([C.c_int, C.c_int], C.c_int64),
     "glint_prefilter_workspace_bytes": ([C.c_int, C.c_int, C.POINTER(PrefilterParams)], C.c_size_t),
     "glint_prefilter": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_int,
@@ -199,6 +201,12 @@ def glint_partition_env(ctx, env, R, params: PartitionParams, workspace, levels,
     _require_cuda(env, workspace, levels, ind_j, ind_t)
     _check(lib().glint_partition_env(ctx, _ptr(env), R, C.byref(params), _ptr(workspace), _ptr(levels),
                                      _ptr(ind_j), _ptr(ind_t), _stream(stream)))
+
+
+def glint_partition_env_noalloc(ctx, env, R, params: PartitionParams, levels, ind_j, ind_t, stream=None):
+    _require_cuda(env, levels, ind_j, ind_t)
+    _check(lib().glint_partition_env_noalloc(ctx, _ptr(env), R, C.byref(params), _ptr(levels), _ptr(ind_j),
+                                             _ptr(ind_t), _stream(stream)))
 
 
 def glint_pyramid_texels(R: int, num_mips: int) -> int:
