@@ -210,12 +210,49 @@ def copy_probe(mib: int) -> None:
     print(json.dumps({"copy_probe_mib": mib, "launches": 3}), flush=True)
 
 
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_share() -> int:
+    """Host threads this process may use: OMP_NUM_THREADS when set (the
+    process's CPU share), else the visible CPUs."""
+    try:
+        n = int(os.environ.get("OMP_NUM_THREADS", "0"))
+    except ValueError:
+        n = 0
+    if n <= 0:
+        try:
+            n = len(os.sched_getaffinity(0))
+        except AttributeError:
+            n = os.cpu_count() or 1
+    return max(1, n)
+
+
 def cpu_baseline(w, env, gbuf, glint_pixels, frac, shade_inputs):
-    """Times the oracle (as it stands) on a stratified sample of the same frame
-    and scales to Mpix/s of whole frames.  shade_inputs: the frame's pyramid,
-    levels and LUTs (host copies), so the sampled pixels shade real values."""
+    """Times the oracle (as it stands) on a stratified sample of the same
+    frame, once on one thread and once on every thread of the process's CPU
+    share, and scales to Mpix/s of whole frames.  shade_inputs: the frame's
+    pyramid, levels and LUTs (host copies), so the sampled pixels shade real
+    values."""
+    share = cpu_share()
+    multi = cpu_baseline_leg(w, env, gbuf, glint_pixels, frac, shade_inputs, share)
+    single = cpu_baseline_leg(w, env, gbuf, glint_pixels, frac, shade_inputs, 1)
+    multi["single_thread"] = {k: single[k] for k in ("value", "cores", "prefilter_s_per_frame",
+                                                      "shade_s_per_frame")}
+    multi["cpu_model"] = cpu_model()
+    multi["host_cpus_visible"] = os.cpu_count()
+    return multi
+
+
+def cpu_baseline_leg(w, env, gbuf, glint_pixels, frac, shade_inputs, threads):
     import oracle
-    threads = min(os.cpu_count() or 1, 16)
     t0 = time.perf_counter()
     levels, ij, it = oracle.partition(env, w.K, w.ell)
     chain = oracle.mipchain(env, ij, it, w.K, w.M)

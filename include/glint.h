@@ -12,7 +12,8 @@
  *
  * Conventions for every entry point:
  *   - Returns GLINT_OK (0) or a positive error code; nothing is thrown.
- *     glint_last_error() returns a message for the calling thread.
+ *     glint_last_error(ctx) returns the message of the calling thread's
+ *     last failed call on ctx (glint_last_error(NULL): of any call).
  *   - Pointers marked "device" are HIP device pointers (e.g. torch CUDA
  *     tensors' data_ptr()); the caller owns every buffer.  Entry points that
  *     take a stream never allocate device memory and never synchronise:
@@ -46,7 +47,8 @@ enum glint_status {
     GLINT_EINVAL = 1,       /* invalid argument (size, null pointer, option) */
     GLINT_EUNSUPPORTED = 2, /* valid but not implemented (option value) */
     GLINT_EDEVICE = 3,      /* HIP runtime error (launch, device query) */
-    GLINT_ENOMEM = 4        /* host allocation failed (context only) */
+    GLINT_ENOMEM = 4,       /* host allocation failed (context only) */
+    GLINT_ENOTTRAINED = 5   /* surrogate parameters never prepared or trained in this context */
 };
 
 typedef enum glint_dtype {
@@ -61,8 +63,11 @@ typedef struct glint_ctx_s *glint_ctx;
 /* Library version (GLINT_VERSION of the build). */
 int glint_version(void);
 
-/* Message of the last failed call on this thread ("" if none). */
-const char *glint_last_error(void);
+/* Message of the calling thread's last failed call on ctx ("" if its last
+ * call on ctx succeeded or it made none); with ctx = NULL, of the thread's
+ * last call of any entry point (including glint_create).  The string stays
+ * valid until the thread's next call on the same context. */
+const char *glint_last_error(glint_ctx ctx);
 
 /* Creates a context bound to HIP device `device` (queries its properties).
  * *out receives the context.  GLINT_EINVAL for a bad device index or a null
@@ -233,7 +238,11 @@ int glint_surrogate_params(void);
 size_t glint_surrogate_workspace_bytes(int batch);
 
 /* Zeroes the pad entries of the master w (device) and writes the bfloat16
- * copy w_bf16 (device).  Call after writing or loading w. */
+ * copy w_bf16 (device).  Call after writing or loading w.  The context
+ * records w_bf16 (its address) and K: the calls below that read the
+ * network return GLINT_ENOTTRAINED for a w_bf16 that was never prepared or
+ * updated by glint_surrogate_train_step in this context, or was prepared
+ * for another K (a host-side check of the address, not of the contents). */
 int glint_surrogate_prepare(glint_ctx ctx, int K, float *w, uint16_t *w_bf16, void *stream);
 
 /* Forward pass: x device [B][5] float32 -> probs device [B][K] float32.

@@ -4,8 +4,10 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <map>
 #include <mutex>
 #include <new>
+#include <string>
 
 #include "batched.hpp"
 #include "device.hpp"
@@ -17,6 +19,10 @@ struct glint_ctx_s {
     void *scratch; // device address of this GPU's copy of `scratch` below
     glint::BatchedCache batched;
     glint::Profiler prof;
+    // bf16 parameter copies written in this context (glint_surrogate_prepare
+    // or glint_surrogate_train_step), with their K
+    std::mutex sur_mu;
+    std::map<const void *, int> prepared;
 };
 
 // Workspace of glint_partition_env_noalloc: a file-scope device array, one
@@ -55,7 +61,21 @@ hipError_t scratch_address(int device, void **out)
     return hipSuccess;
 }
 
+// Error messages: per thread the last one of any call, and per (thread,
+// context) the last one of a call on that context.  Every entry point that
+// takes a context names it first (check_ctx or enter), so fail() and ok()
+// know where to record.
 thread_local char g_err[512] = "";
+thread_local glint_ctx g_cur = nullptr;
+thread_local std::map<glint_ctx, std::string> *g_ctx_err = nullptr;
+
+void enter(glint_ctx ctx) { g_cur = ctx; }
+
+std::map<glint_ctx, std::string> &ctx_errors()
+{
+    if (!g_ctx_err) g_ctx_err = new std::map<glint_ctx, std::string>(); // lives as long as the thread
+    return *g_ctx_err;
+}
 
 int fail(int code, const char *fmt, ...)
 {
@@ -63,12 +83,17 @@ int fail(int code, const char *fmt, ...)
     va_start(ap, fmt);
     vsnprintf(g_err, sizeof(g_err), fmt, ap);
     va_end(ap);
+    if (g_cur) ctx_errors()[g_cur] = g_err;
     return code;
 }
 
 int ok()
 {
     g_err[0] = '\0';
+    if (g_cur && g_ctx_err) {
+        auto it = g_ctx_err->find(g_cur);
+        if (it != g_ctx_err->end()) it->second.clear();
+    }
     return GLINT_OK;
 }
 
@@ -89,6 +114,7 @@ int log2i(int x)
 
 int check_ctx(glint_ctx ctx)
 {
+    enter(ctx);
     if (!ctx) return fail(GLINT_EINVAL, "null context");
     int cur = -1;
     if (hipGetDevice(&cur) != hipSuccess) return fail(GLINT_EDEVICE, "hipGetDevice failed");
@@ -171,6 +197,26 @@ int check_surrogate(int K, const void *w, const void *w_bf16)
     return GLINT_OK;
 }
 
+void mark_prepared(glint_ctx ctx, const void *w_bf16, int K)
+{
+    std::lock_guard<std::mutex> lock(ctx->sur_mu);
+    ctx->prepared[w_bf16] = K;
+}
+
+// GLINT_ENOTTRAINED unless w_bf16 was written for K in this context.
+int check_prepared(glint_ctx ctx, const void *w_bf16, int K)
+{
+    std::lock_guard<std::mutex> lock(ctx->sur_mu);
+    auto it = ctx->prepared.find(w_bf16);
+    if (it == ctx->prepared.end())
+        return fail(GLINT_ENOTTRAINED, "surrogate parameters at %p were never prepared (glint_surrogate_prepare) "
+                    "or trained (glint_surrogate_train_step) in this context", w_bf16);
+    if (it->second != K)
+        return fail(GLINT_ENOTTRAINED, "surrogate parameters at %p were prepared for K=%d, not K=%d", w_bf16,
+                    it->second, K);
+    return GLINT_OK;
+}
+
 int check_batch(int B, const float *x, const float *target, const void *workspace)
 {
     if (B < 1 || B > (1 << 20)) return fail(GLINT_EINVAL, "batch size %d must be in [1, 2^20]", B);
@@ -191,10 +237,17 @@ extern "C" {
 
 int glint_version(void) { return GLINT_VERSION; }
 
-const char *glint_last_error(void) { return g_err; }
+const char *glint_last_error(glint_ctx ctx)
+{
+    if (!ctx) return g_err;
+    if (!g_ctx_err) return "";
+    auto it = g_ctx_err->find(ctx);
+    return it == g_ctx_err->end() ? "" : it->second.c_str();
+}
 
 int glint_create(int device, glint_ctx *out)
 {
+    enter(nullptr);
     if (!out) return fail(GLINT_EINVAL, "null output pointer");
     *out = nullptr;
     int count = 0;
@@ -216,7 +269,12 @@ int glint_create(int device, glint_ctx *out)
     return ok();
 }
 
-void glint_destroy(glint_ctx ctx) { delete ctx; }
+void glint_destroy(glint_ctx ctx)
+{
+    if (g_ctx_err) g_ctx_err->erase(ctx); // this thread's record (others keep a stale entry, never read)
+    if (g_cur == ctx) g_cur = nullptr;
+    delete ctx;
+}
 
 int glint_sync(glint_ctx ctx)
 {
@@ -433,8 +491,10 @@ int glint_surrogate_prepare(glint_ctx ctx, int K, float *w, uint16_t *w_bf16, vo
     if (int rc = check_ctx(ctx)) return rc;
     glint::ProfScope prof_scope(&ctx->prof);
     if (int rc = check_surrogate(K, w, w_bf16)) return rc;
-    return device_status(glint::launch_mlp_prepare(w, w_bf16, K, (hipStream_t)stream),
-                         "glint_surrogate_prepare launch");
+    const int rc = device_status(glint::launch_mlp_prepare(w, w_bf16, K, (hipStream_t)stream),
+                                 "glint_surrogate_prepare launch");
+    if (rc == GLINT_OK) mark_prepared(ctx, w_bf16, K);
+    return rc;
 }
 
 int glint_surrogate_forward(glint_ctx ctx, int K, const float *w, const uint16_t *w_bf16, const float *x,
@@ -444,6 +504,7 @@ int glint_surrogate_forward(glint_ctx ctx, int K, const float *w, const uint16_t
     glint::ProfScope prof_scope(&ctx->prof);
     if (int rc = check_surrogate(K, w, w_bf16)) return rc;
     if (B < 0 || B > ((int64_t)1 << 36)) return fail(GLINT_EINVAL, "bad batch size %lld", (long long)B);
+    if (int rc = check_prepared(ctx, w_bf16, K)) return rc;
     if (B == 0) return ok();
     if (!x || !probs) return fail(GLINT_EINVAL, "null pointer argument");
     return device_status(glint::launch_mlp_forward(x, B, K, w, w_bf16, probs, (hipStream_t)stream),
@@ -458,6 +519,7 @@ int glint_surrogate_gradient(glint_ctx ctx, int K, const float *w, const uint16_
     if (int rc = check_surrogate(K, w, w_bf16)) return rc;
     if (int rc = check_batch(B, x, target, workspace)) return rc;
     if (!grad || !loss) return fail(GLINT_EINVAL, "null pointer argument");
+    if (int rc = check_prepared(ctx, w_bf16, K)) return rc;
     const size_t blocks = (size_t)(B + 31) / 32;
     float *partial = static_cast<float *>(workspace);
     float *loss_partial = reinterpret_cast<float *>(static_cast<char *>(workspace) + surrogate_partial_bytes(blocks));
@@ -477,6 +539,7 @@ int glint_surrogate_train_step(glint_ctx ctx, int K, float *w, uint16_t *w_bf16,
     if (!m || !v || !loss) return fail(GLINT_EINVAL, "null pointer argument");
     if (step < 1) return fail(GLINT_EINVAL, "step must be >= 1");
     if (!(lr >= 0.0f) || !(lr < 1.0f)) return fail(GLINT_EINVAL, "learning rate must be in [0, 1)");
+    if (int rc = check_prepared(ctx, w_bf16, K)) return rc;
     const size_t blocks = (size_t)(B + 31) / 32;
     float *partial = static_cast<float *>(workspace);
     float *loss_partial = reinterpret_cast<float *>(static_cast<char *>(workspace) + surrogate_partial_bytes(blocks));
@@ -509,6 +572,7 @@ int glint_shade_surrogate(glint_ctx ctx, const glint_gbuffer *g, int64_t P, cons
         sp->tree != GLINT_TREE_BALANCED)
         return fail(GLINT_EUNSUPPORTED, "the surrogate form computes the map's probabilities with one lookup and "
                     "the balanced tree");
+    if (int rc = check_prepared(ctx, w_bf16, env->K)) return rc;
     if (P == 0) return ok();
     if (!radiance || !workspace || !env->rgb_pyr || !env->levels || !env->lut_S || !env->lut_E)
         return fail(GLINT_EINVAL, "null pointer argument");
@@ -550,8 +614,10 @@ int glint_frame_batched(glint_ctx ctx, const glint_env_task *envs, int n_env, co
             return fail(GLINT_EINVAL, "all environments of one call must share the pyramid dtype");
         if ((t.surrogate_w == nullptr) != (t.surrogate_w_bf16 == nullptr))
             return fail(GLINT_EINVAL, "environment %d: surrogate weights and their bf16 copy go together", e);
-        if (t.surrogate_w)
+        if (t.surrogate_w) {
             if (int rc = check_surrogate(t.partition.K, t.surrogate_w, t.surrogate_w_bf16)) return rc;
+            if (int rc = check_prepared(ctx, t.surrogate_w_bf16, t.partition.K)) return rc;
+        }
     }
     for (int v = 0; v < n_views; ++v) {
         const glint_view &w = views[v];
@@ -575,7 +641,11 @@ int glint_frame_batched(glint_ctx ctx, const glint_env_task *envs, int n_env, co
                          "glint_frame_batched");
 }
 
-int glint_batched_tile_px(glint_ctx ctx) { return ctx ? ctx->batched.last_tile_px : 0; }
+int glint_batched_tile_px(glint_ctx ctx)
+{
+    enter(ctx);
+    return ctx ? ctx->batched.last_tile_px : 0;
+}
 
 int glint_profile_enable(glint_ctx ctx, int enable)
 {
@@ -590,6 +660,7 @@ int glint_profile_enable(glint_ctx ctx, int enable)
 
 int glint_profile_select(glint_ctx ctx, const char *kernels)
 {
+    enter(ctx);
     if (!ctx) return fail(GLINT_EINVAL, "null context");
     ctx->prof.only = kernels ? kernels : "";
     return ok();
@@ -606,6 +677,7 @@ int glint_profile_collect(glint_ctx ctx, int *n_kernels)
 
 int glint_profile_entry(glint_ctx ctx, int i, const char **name, double *total_ms, int64_t *launches)
 {
+    enter(ctx);
     if (!ctx) return fail(GLINT_EINVAL, "null context");
     if (i < 0 || i >= (int)ctx->prof.summary.size()) return fail(GLINT_EINVAL, "profile entry %d out of range", i);
     if (!name || !total_ms || !launches) return fail(GLINT_EINVAL, "null pointer argument");

@@ -12,7 +12,7 @@ import os
 
 from . import build as _build
 
-GLINT_OK, GLINT_EINVAL, GLINT_EUNSUPPORTED, GLINT_EDEVICE, GLINT_ENOMEM = 0, 1, 2, 3, 4
+GLINT_OK, GLINT_EINVAL, GLINT_EUNSUPPORTED, GLINT_EDEVICE, GLINT_ENOMEM, GLINT_ENOTTRAINED = 0, 1, 2, 3, 4, 5
 GLINT_F32, GLINT_F16, GLINT_BF16, GLINT_UNORM16 = 0, 1, 2, 3
 GLINT_SAMPLER_DUAL, GLINT_SAMPLER_SINGLE, GLINT_SAMPLER_SINGLE_FLOOR = 0, 1, 2
 GLINT_PROBS_ENV, GLINT_PROBS_CONSTANT = 0, 1
@@ -75,7 +75,7 @@ _LIB = None
 
 EXPORTS = {
     "glint_version": ([], C.c_int),
-    "glint_last_error": ([], C.c_char_p),
+    "glint_last_error": ([C.c_void_p], C.c_char_p),
     "glint_create": ([C.c_int, C.POINTER(C.c_void_p)], C.c_int),
     "glint_destroy": ([C.c_void_p], None),
     "glint_sync": ([C.c_void_p], C.c_int),
@@ -149,7 +149,7 @@ def library_path() -> str:
 
 def _check(rc):
     if rc != GLINT_OK:
-        raise GlintError(rc, lib().glint_last_error().decode())
+        raise GlintError(rc, lib().glint_last_error(None).decode())
 
 
 def _ptr(t):
@@ -177,6 +177,10 @@ def _require_cuda(*tensors):
 
 def glint_version() -> int:
     return lib().glint_version()
+
+
+def glint_last_error(ctx=None) -> str:
+    return lib().glint_last_error(ctx).decode()
 
 
 def glint_create(device: int = 0) -> C.c_void_p:

@@ -88,7 +88,7 @@ def test_calls_validate_before_touching_the_device():
     # a null context is rejected with EINVAL, not a crash
     rc = lib.glint_partition_env(None, None, 32, None, None, None, None, None, None)
     assert rc == G.GLINT_EINVAL
-    assert "context" in lib.glint_last_error().decode()
+    assert "context" in lib.glint_last_error(None).decode()
     rc = lib.glint_shade(None, None, 10, None, None, None, None, None)
     assert rc == G.GLINT_EINVAL
     rc = lib.glint_sample_binomial(None, 0, 0, None, None, None, None, 10, None, None, None, None, None)

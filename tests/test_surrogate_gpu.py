@@ -308,6 +308,31 @@ def test_surrogate_rejects_bad_arguments(ctx):
         G.glint_surrogate_train_step(ctx, K, wt, wb, m, m.clone(), 0, 1e-3, x, t, ws, loss)
     # empty batch is a no-op for the forward pass
     G.glint_surrogate_forward(ctx, K, wt, wb, x[:0], probs)
+    # parameters never prepared in this context, or prepared for another K
+    raw = torch.zeros_like(wb)
+    for call in (lambda: G.glint_surrogate_forward(ctx, K, wt, raw, x, probs),
+                 lambda: G.glint_surrogate_forward(ctx, 4, wt, wb, x, probs[:, :4].contiguous()),
+                 lambda: G.glint_surrogate_train_step(ctx, K, wt, raw, m, m.clone(), 1, 1e-3, x, t, ws, loss),
+                 lambda: G.glint_surrogate_gradient(ctx, K, wt, raw, x, t, ws, m.clone(), loss)):
+        with pytest.raises(G.GlintError) as e:
+            call()
+        assert e.value.code == G.GLINT_ENOTTRAINED
+    other = G.glint_create(0)
+    try:
+        with pytest.raises(G.GlintError) as e:
+            G.glint_surrogate_forward(other, K, wt, wb, x, probs)
+        assert e.value.code == G.GLINT_ENOTTRAINED
+        # per-context messages: the failure stays recorded on `other`, the
+        # successful call below clears ctx's record only
+        assert "never prepared" in G.glint_last_error(other)
+        G.glint_surrogate_forward(ctx, K, wt, wb, x, probs)
+        assert G.glint_last_error(ctx) == ""
+        assert "never prepared" in G.glint_last_error(other)
+        G.glint_surrogate_prepare(other, K, wt, wb)
+        G.glint_surrogate_forward(other, K, wt, wb, x, probs)
+        assert G.glint_last_error(other) == ""
+    finally:
+        G.glint_destroy(other)
 
 
 def test_checkpoint_resume_reproduces_training(ctx, tmp_path):
