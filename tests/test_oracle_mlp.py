@@ -62,3 +62,42 @@ def test_bf16_rounding():
     assert mlp.bf16(1.0 + 3 * 2 ** -9) == 1.0 + 2 ** -7
     x = np.random.default_rng(3).normal(size=1000)
     assert np.all(np.abs(mlp.bf16(x) - x) <= 2 ** -8 * np.abs(x))
+
+
+def _perturbed(K, seed, scale=0.05):
+    rng = np.random.default_rng(seed)
+    w = mlp.init(K, seed=seed + 1).astype(np.float64)
+    mask = mlp.pack(mlp.unpack(np.ones(mlp.N_PARAMS), K), K) != 0
+    return (w + rng.normal(scale=scale, size=w.shape) * mask).astype(np.float32).astype(np.float64), rng
+
+
+@pytest.mark.parametrize("K,B", [(8, 600), (4, 64), (16, 37), (8, 4096)])
+def test_bfloat16_mirror_fits_the_rounding_error_model(K, B):
+    """The tolerance model of the GPU parity tests (tests/mlp_bounds.py)
+    against the bfloat16 mirror of the kernels, which rounds exactly where
+    they round: the deviations from FP64 are of the order of the model's
+    sigma (root-mean-square ratio between 0.05 and 2) and never beyond the
+    8 sigma the GPU tests allow."""
+    from tests import mlp_bounds as MB
+    w, rng = _perturbed(K, 5)
+    d = rng.normal(size=(B, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    la = rng.uniform(np.log(0.02), np.log(0.5), size=(B, 2))
+    x = mlp.features(d, np.exp(la[:, 0]), np.exp(la[:, 1])).astype(np.float32).astype(np.float64)
+    t = rng.dirichlet(np.ones(K) * 0.5, size=B)
+    y64, sy, _ = MB.forward_sigma(w, x, K)
+    ref, _ = mlp.forward(w, x, K, bf=False)
+    np.testing.assert_allclose(y64, ref, rtol=1e-12, atol=1e-15)
+    ybf, _ = mlp.forward(w, x, K, bf=True)
+    r = np.abs(ybf - y64) / sy
+    rms = float(np.sqrt(np.mean(r * r)))
+    assert r.max() < 8 and 0.05 < rms < 2, (r.max(), rms)
+    g64, sg = MB.gradient_sigma(w, x, t, K)
+    _, gref = mlp.loss_and_grad(w, x, t, K, bf=False)
+    np.testing.assert_allclose(g64, gref, rtol=1e-10, atol=1e-14)
+    _, gbf = mlp.loss_and_grad(w, x, t, K, bf=True)
+    nz = sg > 0
+    assert np.all(gbf[~nz] == 0) and np.all(g64[~nz] == 0)
+    r = np.abs(gbf - g64)[nz] / sg[nz]
+    rms = float(np.sqrt(np.mean(r * r)))
+    assert r.max() < 8 and 0.02 < rms < 2, (r.max(), rms)

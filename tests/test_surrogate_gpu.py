@@ -4,10 +4,12 @@
   at arbitrary (direction, alpha) (float outputs of double sums: 1e-5
   relative); at a mip's roughness and a texel's centre direction the sampler
   reproduces the stored pyramid texel.
-* glint_surrogate_forward / _gradient against the FP64 definition
-  (oracle/mlp.py) rounded at the same points as the matrix cores are fed
-  (bf16=True); what remains is float accumulation order and a rare
-  bfloat16 rounding-boundary flip, hence the tolerances below.
+* glint_surrogate_forward / _gradient / _train_step against the plain FP64
+  definition (oracle/mlp.py, bf=False), element by element, within 8
+  standard deviations of a bfloat16 rounding-error model of that definition
+  (tests/mlp_bounds.py); and, tighter, against the same definition rounded
+  at the points where the matrix cores are fed (bf=True), where only float
+  accumulation order and a rare bfloat16 rounding-boundary flip remain.
 * glint_surrogate_train_step = the gradient followed by Adam.
 * glint_shade_surrogate: the network's per-pixel outputs against the
   oracle's forward pass, and the shading given those outputs against the
@@ -192,6 +194,87 @@ def test_gradient_matches_oracle(ctx, K, B):
     grad2 = torch.empty_like(grad)
     G.glint_surrogate_gradient(ctx, K, wt, wb, U.dev(x), U.dev(t), ws, grad2, loss)
     assert np.array_equal(U.host(grad2), U.host(grad))
+
+
+# --- against the plain FP64 definition (bf=False), element by element ----------------
+
+def _fp64_case(K, B, seed):
+    rng = np.random.default_rng(seed)
+    w = mlp.init(K, seed=seed + 1).astype(np.float64)
+    mask = mlp.pack(mlp.unpack(np.ones(mlp.N_PARAMS), K), K) != 0
+    w = (w + rng.normal(scale=0.05, size=w.shape) * mask).astype(np.float32)
+    x = random_inputs(B, seed + 2)
+    t = rng.dirichlet(np.ones(K) * 0.5, size=B).astype(np.float32)
+    return w, x, t, mask
+
+
+@pytest.mark.parametrize("K,B", [(8, 4096), (4, 1000), (16, 33)])
+def test_forward_matches_fp64_definition(ctx, K, B):
+    """Every output within 8 sigma of the bfloat16 rounding-error model
+    (tests/mlp_bounds.py) of the plain FP64 network."""
+    import torch
+    from tests import mlp_bounds as MB
+    w, x, _, _ = _fp64_case(K, B, 41)
+    wt, wb = upload_params(ctx, w, K)
+    probs = torch.empty((B, K), dtype=torch.float32, device="cuda")
+    G.glint_surrogate_forward(ctx, K, wt, wb, U.dev(x), probs)
+    got = U.host(probs).astype(np.float64)
+    y64, sy, _ = MB.forward_sigma(w.astype(np.float64), x.astype(np.float64), K)
+    r = np.abs(got - y64) / (sy + 6e-8 * y64)
+    U.log(f"  forward vs FP64: max {r.max():.2f} sigma, rms {np.sqrt(np.mean(r * r)):.3f}")
+    assert r.max() < 8.0
+
+
+@pytest.mark.parametrize("K,B", [(8, 1000), (4, 64), (16, 37), (8, 4096)])
+def test_gradient_matches_fp64_definition(ctx, K, B):
+    """Every gradient entry within 8 sigma of the rounding-error model of the
+    plain FP64 gradient (pads exactly zero); the loss within 1e-3."""
+    import torch
+    from tests import mlp_bounds as MB
+    w, x, t, mask = _fp64_case(K, B, 51)
+    wt, wb = upload_params(ctx, w, K)
+    ws = torch.empty(G.glint_surrogate_workspace_bytes(B) // 4, dtype=torch.float32, device="cuda")
+    grad = torch.empty(mlp.N_PARAMS, dtype=torch.float32, device="cuda")
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    G.glint_surrogate_gradient(ctx, K, wt, wb, U.dev(x), U.dev(t), ws, grad, loss)
+    g = U.host(grad).astype(np.float64)
+    g64, sg = MB.gradient_sigma(w.astype(np.float64), x.astype(np.float64), t.astype(np.float64), K)
+    l64, _ = mlp.loss_and_grad(w.astype(np.float64), x.astype(np.float64), t.astype(np.float64), K)
+    assert float(U.host(loss)[0]) == pytest.approx(l64, rel=1e-3)
+    assert np.all(g[~mask] == 0)
+    r = np.abs(g - g64)[mask] / (sg[mask] + 6e-8 * np.abs(g64[mask]) + 1e-30)
+    U.log(f"  gradient vs FP64: max {r.max():.2f} sigma, rms {np.sqrt(np.mean(r * r)):.3f}")
+    assert r.max() < 8.0
+
+
+def test_adam_step_matches_fp64_definition(ctx):
+    """One training step (step 1) against FP64 Adam on the FP64 gradient:
+    the first step moves every weight by lr sign(g) (|g| >> eps), so where
+    the model makes the gradient's sign certain (|g64| > 8 sigma) the step
+    agrees to float rounding; elsewhere it is within 2 lr."""
+    import torch
+    from tests import mlp_bounds as MB
+    K, B, lr = 8, 2048, 1e-3
+    w, x, t, mask = _fp64_case(K, B, 61)
+    wt, wb = upload_params(ctx, w, K)
+    ws = torch.empty(G.glint_surrogate_workspace_bytes(B) // 4, dtype=torch.float32, device="cuda")
+    m = torch.zeros(mlp.N_PARAMS, dtype=torch.float32, device="cuda")
+    v = torch.zeros_like(m)
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    G.glint_surrogate_train_step(ctx, K, wt, wb, m, v, 1, lr, U.dev(x), U.dev(t), ws, loss)
+    got = U.host(wt).astype(np.float64)
+    g64, sg = MB.gradient_sigma(w.astype(np.float64), x.astype(np.float64), t.astype(np.float64), K)
+    w64, _, _ = mlp.adam(w.astype(np.float64), np.zeros(mlp.N_PARAMS), np.zeros(mlp.N_PARAMS), g64, 1, lr)
+    sure = mask & (np.abs(g64) > 8.0 * sg) & (np.abs(g64) > 1e-6)
+    assert sure.sum() > 0.5 * mask.sum()
+    err = np.abs(got - w64)
+    # float rounding of the update and of w, plus the update's sensitivity
+    # lr eps / (|g| + eps)^2 to the gradient's deviation (eps = 1e-8)
+    fl = 2.0 ** -23 * np.abs(w64) + lr * 1e-5 + lr * 1e-8 * 8.0 * sg / (np.abs(g64) + 1e-8) ** 2
+    assert np.all(err[sure] <= fl[sure]), err[sure].max()
+    assert np.all(err[mask] <= 2 * lr + fl[mask])
+    assert np.all(got[~mask] == 0)
+    U.log(f"  Adam step 1: {int(sure.sum())}/{int(mask.sum())} weights with a certain sign agree to float rounding")
 
 
 def test_train_step_is_gradient_then_adam(ctx):
