@@ -226,7 +226,13 @@ int glint_surrogate_samples(glint_ctx ctx, const float *env, const uint8_t *ind_
  *   W3 [64][64], b3 [64], W4 [32][64] (rows K..31 zero), b4 [32] (K.. zero)
  * and a bfloat16 copy (uint16_t bit patterns, same layout, 16-byte aligned)
  * that the matrix cores read.  Loss: mean over the batch of the soft-label
- * cross-entropy -sum_k t_k ln y_k.
+ * cross-entropy -sum_k t_k ln y_k, plus, with the radiance levels L given
+ * and weight lam > 0, lam times the cross-entropy -sum_{k>=1} t'_k ln y'_k
+ * of the radiance-weighted distributions over the bins k >= 1,
+ * y'_k = L_k y_k / sum_{j>=1} L_j y_j and t'_k likewise (samples with
+ * sum_{j>=1} L_j t_j = 0 add no such term).  The glint radiance of a pixel
+ * moves with sum_k L_k |dp_k| / sum_k L_k p_k (Eq. (iblglints:fin)), so the
+ * second term weights each bin's relative error by its radiance.
  * ------------------------------------------------------------------------ */
 
 /* Entries of the padded parameter layout (11488). */
@@ -252,11 +258,14 @@ int glint_surrogate_forward(glint_ctx ctx, int K, const float *w, const uint16_t
 
 /* Gradient of the mean loss over the batch: grad device [params] float32
  * (pad entries 0), loss device float32 scalar.  x [B][5], target [B][K];
- * workspace device, >= glint_surrogate_workspace_bytes(B), 16-byte aligned.
- * The per-block partial gradients are summed in a fixed order, so results
- * are deterministic. */
+ * levels: device [K] double (e.g. from glint_partition_env) or NULL, used
+ * when radiance_weight (lam, in [0, 1000]) is > 0; workspace device,
+ * >= glint_surrogate_workspace_bytes(B), 16-byte aligned.  The per-block
+ * partial gradients are summed in a fixed order, so results are
+ * deterministic. */
 int glint_surrogate_gradient(glint_ctx ctx, int K, const float *w, const uint16_t *w_bf16, const float *x,
-                             const float *target, int B, void *workspace, float *grad, float *loss, void *stream);
+                             const float *target, const double *levels, float radiance_weight, int B,
+                             void *workspace, float *grad, float *loss, void *stream);
 
 /* One training step: the gradient as above, then Adam (beta1 0.9, beta2
  * 0.999, eps 1e-8, bias correction with step >= 1) on the master w with
@@ -264,8 +273,8 @@ int glint_surrogate_gradient(glint_ctx ctx, int K, const float *w, const uint16_
  * bfloat16 copy is refreshed.  loss receives the batch loss before the
  * update.  lr: the step's learning rate (schedules are the caller's). */
 int glint_surrogate_train_step(glint_ctx ctx, int K, float *w, uint16_t *w_bf16, float *m, float *v, int step,
-                               float lr, const float *x, const float *target, int B, void *workspace, float *loss,
-                               void *stream);
+                               float lr, const float *x, const float *target, const double *levels,
+                               float radiance_weight, int B, void *workspace, float *loss, void *stream);
 
 /* ------------------------------------------------------------------------
  * Lookup tables, once per BRDF model (isotropic GGX, Schlick Fresnel,
@@ -483,6 +492,19 @@ size_t glint_shade_surrogate_workspace_bytes(int64_t num_pixels, int K);
 int glint_shade_surrogate(glint_ctx ctx, const glint_gbuffer *gbuf, int64_t num_pixels, const glint_env *env,
                           const float *w, const uint16_t *w_bf16, const glint_shade_params *params,
                           void *workspace, float *radiance, const glint_shade_debug *debug, void *stream);
+
+/* Shading with the K filtered indicator values of every pixel given
+ * (F [num_pixels][K] float32, device; any positive scale): p_k =
+ * S F_k / sum F as in glint_shade, RGB, S and E_rho read from env, the
+ * indicator pyramid not read (env->ind_pyr may be NULL, env->dtype is
+ * ignored).  This is the second step of glint_shade_surrogate; with F from
+ * glint_sample_filter at each pixel's reflection direction and
+ * sqrt(alpha_x alpha_y) it shades with the plain filter itself (no mip
+ * interpolation), the reference the surrogate and the pyramid are judged
+ * against.  Errors as glint_shade_surrogate. */
+int glint_shade_given_F(glint_ctx ctx, const glint_gbuffer *gbuf, int64_t num_pixels, const glint_env *env,
+                        const float *F, const glint_shade_params *params, float *radiance,
+                        const glint_shade_debug *debug, void *stream);
 
 /* ------------------------------------------------------------------------
  * Batched frame: several environment maps and many views of uneven size,

@@ -7,7 +7,9 @@ Not from the paper: the network, its inputs and its training are the
 project's own.
 
 Network: x (5) -> 64 -> 64 -> 64 -> K, SiLU hidden units, softmax output,
-soft-label cross-entropy against the filter's normalised outputs.
+soft-label cross-entropy against the filter's normalised outputs, plus an
+optional cross-entropy of the radiance-weighted distributions (the glint
+radiance of Eq. (iblglints:fin) weights each bin's error by its level).
 Inputs: (w_x, w_y, w_z, (ln alpha_x - c)/h, (ln alpha_y - c)/h) with c, h
 mapping [ln 0.02, ln 0.5] to [-1, 1].
 
@@ -128,14 +130,37 @@ def forward(w, x, K, bf=False):
     return y, dict(a0=a0, z1=z1, h1=h1, z2=z2, h2=h2, z3=z3, h3=h3, W=W, y=y)
 
 
-def loss_and_grad(w, x, t, K, bf=False):
-    """Mean soft-label cross-entropy over the batch and its gradient (flat,
-    padded layout; pad entries 0)."""
+def radiance_weighted(y, t, levels):
+    """The radiance-weighted distributions over the bins k >= 1:
+    y'_k = L_k y_k / sum_{j>=1} L_j y_j and t' likewise, and the mask of the
+    samples for which both sums are positive (the others get no term)."""
+    L = np.asarray(levels, dtype=np.float64)[1:]
+    yw, tw = y[:, 1:] * L, t[:, 1:] * L
+    ys, ts = yw.sum(1, keepdims=True), tw.sum(1, keepdims=True)
+    ok = (ys[:, 0] > 0) & (ts[:, 0] > 0)
+    return yw / np.where(ys > 0, ys, 1.0), tw / np.where(ts > 0, ts, 1.0), ok
+
+
+def loss_and_grad(w, x, t, K, bf=False, levels=None, lam=0.0):
+    """Mean loss over the batch and its gradient (flat, padded layout; pad
+    entries 0).  The loss is the soft-label cross-entropy -sum_k t_k ln y_k
+    plus, with levels and lam > 0, lam times the cross-entropy of the
+    radiance-weighted distributions, -sum_{k>=1} t'_k ln y'_k (see
+    radiance_weighted).  Its gradient with respect to the logits is
+    (y - t) + lam (y' - t') on the bins k >= 1: y' is the softmax of
+    z_k + ln L_k over those bins."""
     r = bf16 if bf else (lambda a: np.asarray(a, dtype=np.float64))
     y, c = forward(w, x, K, bf)
     B = len(x)
+    t = np.asarray(t, dtype=np.float64)
     loss = -np.sum(t * np.log(np.maximum(y, 1e-300))) / B
-    dz4 = r((y - t) / B)
+    dz = y - t
+    if levels is not None and lam > 0:
+        yp, tp, ok = radiance_weighted(y, t, levels)
+        loss += lam * -np.sum(tp[ok] * np.log(np.maximum(yp[ok], 1e-300))) / B
+        dz = dz.copy()
+        dz[ok, 1:] += lam * (yp[ok] - tp[ok])
+    dz4 = r(dz / B)
     g = {}
     g["W4"] = dz4.T @ c["h3"]
     g["b4"] = dz4.sum(0)

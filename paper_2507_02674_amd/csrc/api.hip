@@ -511,26 +511,36 @@ int glint_surrogate_forward(glint_ctx ctx, int K, const float *w, const uint16_t
                          "glint_surrogate_forward launch");
 }
 
+static int check_radiance_weight(const double *levels, float lam)
+{
+    if (!(lam >= 0.0f) || !(lam <= 1e3f)) return fail(GLINT_EINVAL, "radiance_weight must be in [0, 1000]");
+    if (lam > 0.0f && !levels) return fail(GLINT_EINVAL, "a radiance weight needs the levels");
+    return GLINT_OK;
+}
+
 int glint_surrogate_gradient(glint_ctx ctx, int K, const float *w, const uint16_t *w_bf16, const float *x,
-                             const float *target, int B, void *workspace, float *grad, float *loss, void *stream)
+                             const float *target, const double *levels, float radiance_weight, int B,
+                             void *workspace, float *grad, float *loss, void *stream)
 {
     if (int rc = check_ctx(ctx)) return rc;
     glint::ProfScope prof_scope(&ctx->prof);
     if (int rc = check_surrogate(K, w, w_bf16)) return rc;
     if (int rc = check_batch(B, x, target, workspace)) return rc;
     if (!grad || !loss) return fail(GLINT_EINVAL, "null pointer argument");
+    if (int rc = check_radiance_weight(levels, radiance_weight)) return rc;
     if (int rc = check_prepared(ctx, w_bf16, K)) return rc;
     const size_t blocks = (size_t)(B + 31) / 32;
     float *partial = static_cast<float *>(workspace);
     float *loss_partial = reinterpret_cast<float *>(static_cast<char *>(workspace) + surrogate_partial_bytes(blocks));
-    return device_status(glint::launch_mlp_gradient(x, target, B, K, w, w_bf16, partial, loss_partial, grad, loss,
-                                                    (hipStream_t)stream),
+    return device_status(glint::launch_mlp_gradient(x, target, radiance_weight > 0.0f ? levels : nullptr,
+                                                    radiance_weight, B, K, w, w_bf16, partial, loss_partial, grad,
+                                                    loss, (hipStream_t)stream),
                          "glint_surrogate_gradient launch");
 }
 
 int glint_surrogate_train_step(glint_ctx ctx, int K, float *w, uint16_t *w_bf16, float *m, float *v, int step,
-                               float lr, const float *x, const float *target, int B, void *workspace, float *loss,
-                               void *stream)
+                               float lr, const float *x, const float *target, const double *levels,
+                               float radiance_weight, int B, void *workspace, float *loss, void *stream)
 {
     if (int rc = check_ctx(ctx)) return rc;
     glint::ProfScope prof_scope(&ctx->prof);
@@ -539,11 +549,13 @@ int glint_surrogate_train_step(glint_ctx ctx, int K, float *w, uint16_t *w_bf16,
     if (!m || !v || !loss) return fail(GLINT_EINVAL, "null pointer argument");
     if (step < 1) return fail(GLINT_EINVAL, "step must be >= 1");
     if (!(lr >= 0.0f) || !(lr < 1.0f)) return fail(GLINT_EINVAL, "learning rate must be in [0, 1)");
+    if (int rc = check_radiance_weight(levels, radiance_weight)) return rc;
     if (int rc = check_prepared(ctx, w_bf16, K)) return rc;
     const size_t blocks = (size_t)(B + 31) / 32;
     float *partial = static_cast<float *>(workspace);
     float *loss_partial = reinterpret_cast<float *>(static_cast<char *>(workspace) + surrogate_partial_bytes(blocks));
-    return device_status(glint::launch_mlp_grad_step(x, target, B, K, w, w_bf16, m, v, step, lr, partial,
+    return device_status(glint::launch_mlp_grad_step(x, target, radiance_weight > 0.0f ? levels : nullptr,
+                                                     radiance_weight, B, K, w, w_bf16, m, v, step, lr, partial,
                                                      loss_partial, loss, (hipStream_t)stream),
                          "glint_surrogate_train_step launch");
 }
@@ -585,6 +597,32 @@ int glint_shade_surrogate(glint_ctx ctx, const glint_gbuffer *g, int64_t P, cons
     if (e != hipSuccess) return device_status(e, "glint_shade_surrogate network launch");
     return device_status(glint::launch_shade(*g, P, *env, *sp, F, radiance, dbg, (hipStream_t)stream),
                          "glint_shade_surrogate launch");
+}
+
+int glint_shade_given_F(glint_ctx ctx, const glint_gbuffer *g, int64_t P, const glint_env *env, const float *F,
+                        const glint_shade_params *sp, float *radiance, const glint_shade_debug *dbg, void *stream)
+{
+    if (int rc = check_ctx(ctx)) return rc;
+    glint::ProfScope prof_scope(&ctx->prof);
+    if (!g || !env || !sp) return fail(GLINT_EINVAL, "null pointer argument");
+    if (P < 0) return fail(GLINT_EINVAL, "num_pixels must be >= 0");
+    if (int rc = check_R(env->R)) return rc;
+    if (int rc = check_tree_K(env->K)) return rc;
+    if (int rc = check_mips(env->R, env->num_mips)) return rc;
+    if (int rc = check_shade_params(*sp, -1)) return rc;
+    if (sp->prob_mode != GLINT_PROBS_ENV || sp->lobe_taps != 0 || sp->vertices == 12 ||
+        sp->tree != GLINT_TREE_BALANCED)
+        return fail(GLINT_EUNSUPPORTED, "given filtered values are one lookup's, shaded with the map's "
+                    "probabilities and the balanced tree");
+    if (P == 0) return ok();
+    if (!radiance || !F || !env->rgb_pyr || !env->levels || !env->lut_S || !env->lut_E)
+        return fail(GLINT_EINVAL, "null pointer argument");
+    if (int rc = check_gbuffer(g)) return rc;
+    if (reinterpret_cast<uintptr_t>(env->rgb_pyr) % 16 || reinterpret_cast<uintptr_t>(F) % 4)
+        return fail(GLINT_EINVAL, "rgb_pyr must be 16-byte and F 4-byte aligned");
+    if (P > ((int64_t)1 << 40)) return fail(GLINT_EINVAL, "num_pixels too large");
+    return device_status(glint::launch_shade(*g, P, *env, *sp, F, radiance, dbg, (hipStream_t)stream),
+                         "glint_shade_given_F launch");
 }
 
 size_t glint_batched_workspace_bytes(int n_views)

@@ -33,12 +33,14 @@ hipError_t launch_quantile_table(double *table, hipStream_t stream);
 // learned surrogate
 int mlp_params();
 hipError_t launch_mlp_prepare(float *w, uint16_t *wb, int K, hipStream_t stream);
-hipError_t launch_mlp_grad_step(const float *x, const float *target, int B, int K, float *w, uint16_t *wb,
-                                float *m, float *v, int step, float lr, float *partial, float *loss_partial,
-                                float *loss_out, hipStream_t stream);
-hipError_t launch_mlp_gradient(const float *x, const float *target, int B, int K, const float *w,
-                               const uint16_t *wb, float *partial, float *loss_partial, float *grad, float *loss_out,
-                               hipStream_t stream);
+// levels: null (soft-label cross-entropy only) or the K radiance levels of
+// the radiance-weighted term, with weight lam
+hipError_t launch_mlp_grad_step(const float *x, const float *target, const double *levels, float lam, int B, int K,
+                                float *w, uint16_t *wb, float *m, float *v, int step, float lr, float *partial,
+                                float *loss_partial, float *loss_out, hipStream_t stream);
+hipError_t launch_mlp_gradient(const float *x, const float *target, const double *levels, float lam, int B, int K,
+                               const float *w, const uint16_t *wb, float *partial, float *loss_partial, float *grad,
+                               float *loss_out, hipStream_t stream);
 hipError_t launch_mlp_forward(const float *x, int64_t B, int K, const float *w, const uint16_t *wb, float *probs,
                               hipStream_t stream);
 hipError_t launch_mlp_lookup(const glint_gbuffer &g, int64_t P, int K, const float *w, const uint16_t *wb, float *F,

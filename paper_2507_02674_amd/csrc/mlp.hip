@@ -254,9 +254,9 @@ struct TrainTile {
 // training: one wave per 32 samples; per-block partial gradients
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(64) k_mlp_grad(const float *__restrict__ x, const float *__restrict__ target,
-                                                 int B, int K, const float *__restrict__ w,
-                                                 const uint16_t *__restrict__ wb, float *__restrict__ partial,
-                                                 float *__restrict__ loss_partial)
+                                                 const double *__restrict__ levels, float lam, int B, int K,
+                                                 const float *__restrict__ w, const uint16_t *__restrict__ wb,
+                                                 float *__restrict__ partial, float *__restrict__ loss_partial)
 {
     __shared__ __attribute__((aligned(16))) uint16_t s_w[kWLds];
     __shared__ __attribute__((aligned(16))) TrainTile t;
@@ -275,8 +275,11 @@ __global__ void __launch_bounds__(64) k_mlp_grad(const float *__restrict__ x, co
     __syncthreads();
     dense_silu(t.h[1], kLdH, kH, W3, kLdH, w + ob3, t.h[2], t.z[2]);
     __syncthreads();
-    // output layer, softmax, loss and the output error signal (y - t) / B,
-    // in registers (sample r = lane % 32, 16 of its outputs per lane)
+    // output layer, softmax, loss and the output error signal, in registers
+    // (sample r = lane % 32, 16 of its outputs per lane, the other 16 in
+    // lane ^ 32): (y - t) / B, plus, with levels, lam (y' - t') / B for the
+    // radiance-weighted distributions y'_k = L_k y_k / sum_{j>=1} L_j y_j,
+    // t' likewise, over the bins k >= 1
     float logit[16], y[16];
     dense_out(t.h[2], W4, w + ob4, logit);
     softmax_pair(logit, K, y);
@@ -284,15 +287,35 @@ __global__ void __launch_bounds__(64) k_mlp_grad(const float *__restrict__ x, co
     {
         const int r = lane & 31;
         const bool valid = row0 + r < B;
+        float tv[16], Lk[16];
+        float tws = 0.0f, yws = 0.0f;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const int o = out_unit(j);
+            tv[j] = (o < K && valid) ? target[(int64_t)(row0 + r) * K + o] : 0.0f;
+            Lk[j] = (levels && o >= 1 && o < K) ? (float)levels[o] : 0.0f;
+            tws += tv[j] * Lk[j];
+            yws += y[j] * Lk[j];
+        }
+        tws += __shfl_xor(tws, 32, 64);
+        yws += __shfl_xor(yws, 32, 64);
+        const bool rad = levels && valid && tws > 0.0f && yws > 0.0f;
+        const float itw = rad ? 1.0f / tws : 0.0f, iyw = rad ? 1.0f / yws : 0.0f;
         float d[16];
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
             const int o = out_unit(j);
             d[j] = 0.0f;
             if (o < K && valid) {
-                const float tk = target[(int64_t)(row0 + r) * K + o];
-                d[j] = (y[j] - tk) / (float)B;
+                const float tk = tv[j];
+                float dj = y[j] - tk;
                 loss -= tk * logf(fmaxf(y[j], 1e-30f));
+                if (rad && o >= 1) {
+                    const float yp = y[j] * Lk[j] * iyw, tp = tk * Lk[j] * itw;
+                    dj += lam * (yp - tp);
+                    loss -= lam * tp * logf(fmaxf(yp, 1e-30f));
+                }
+                d[j] = dj / (float)B;
             }
         }
 #pragma unroll
@@ -593,14 +616,14 @@ hipError_t launch_mlp_prepare(float *w, uint16_t *wb, int K, hipStream_t stream)
     return hipGetLastError();
 }
 
-hipError_t launch_mlp_grad_step(const float *x, const float *target, int B, int K, float *w, uint16_t *wb,
-                                float *m, float *v, int step, float lr, float *partial, float *loss_partial,
-                                float *loss_out, hipStream_t stream)
+hipError_t launch_mlp_grad_step(const float *x, const float *target, const double *levels, float lam, int B, int K,
+                                float *w, uint16_t *wb, float *m, float *v, int step, float lr, float *partial,
+                                float *loss_partial, float *loss_out, hipStream_t stream)
 {
     const int blocks = (B + 31) / 32;
     {
-        GLINT_LAUNCH("k_mlp_grad", k_mlp_grad, dim3(blocks), dim3(64), 0, stream, x, target, B, K, w, wb, partial,
-                           loss_partial);
+        GLINT_LAUNCH("k_mlp_grad", k_mlp_grad, dim3(blocks), dim3(64), 0, stream, x, target, levels, lam, B, K, w,
+                     wb, partial, loss_partial);
     }
     GLINT_LAUNCH("k_mlp_adam", k_mlp_adam, dim3((kParams + kReduceParams - 1) / kReduceParams),
                  dim3(kReduceParams * kReduceSlices), 0, stream, partial, blocks, K, w, wb, m,
@@ -608,14 +631,14 @@ hipError_t launch_mlp_grad_step(const float *x, const float *target, int B, int 
     return hipGetLastError();
 }
 
-hipError_t launch_mlp_gradient(const float *x, const float *target, int B, int K, const float *w,
-                               const uint16_t *wb, float *partial, float *loss_partial, float *grad, float *loss_out,
-                               hipStream_t stream)
+hipError_t launch_mlp_gradient(const float *x, const float *target, const double *levels, float lam, int B, int K,
+                               const float *w, const uint16_t *wb, float *partial, float *loss_partial, float *grad,
+                               float *loss_out, hipStream_t stream)
 {
     const int blocks = (B + 31) / 32;
     {
-        GLINT_LAUNCH("k_mlp_grad", k_mlp_grad, dim3(blocks), dim3(64), 0, stream, x, target, B, K, w, wb, partial,
-                           loss_partial);
+        GLINT_LAUNCH("k_mlp_grad", k_mlp_grad, dim3(blocks), dim3(64), 0, stream, x, target, levels, lam, B, K, w,
+                     wb, partial, loss_partial);
     }
     GLINT_LAUNCH("k_mlp_sum", k_mlp_sum, dim3((kParams + kReduceParams - 1) / kReduceParams),
                  dim3(kReduceParams * kReduceSlices), 0, stream, partial, blocks, loss_partial, B,

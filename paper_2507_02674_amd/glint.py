@@ -106,15 +106,17 @@ EXPORTS = {
     "glint_surrogate_prepare": ([C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     "glint_surrogate_forward": ([C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,
                                  C.c_void_p], C.c_int),
-    "glint_surrogate_gradient": ([C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int,
-                                  C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
+    "glint_surrogate_gradient": ([C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                  C.c_float, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     "glint_surrogate_train_step": ([C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int,
-                                    C.c_float, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p,
-                                    C.c_void_p], C.c_int),
+                                    C.c_float, C.c_void_p, C.c_void_p, C.c_void_p, C.c_float, C.c_int, C.c_void_p,
+                                    C.c_void_p, C.c_void_p], C.c_int),
     "glint_shade_surrogate_workspace_bytes": ([C.c_int64, C.c_int], C.c_size_t),
     "glint_shade_surrogate": ([C.c_void_p, C.POINTER(GBuffer), C.c_int64, C.POINTER(Env), C.c_void_p, C.c_void_p,
                                C.POINTER(ShadeParams), C.c_void_p, C.c_void_p, C.POINTER(ShadeDebug), C.c_void_p],
                               C.c_int),
+    "glint_shade_given_F": ([C.c_void_p, C.POINTER(GBuffer), C.c_int64, C.POINTER(Env), C.c_void_p,
+                             C.POINTER(ShadeParams), C.c_void_p, C.POINTER(ShadeDebug), C.c_void_p], C.c_int),
     "glint_batched_workspace_bytes": ([C.c_int], C.c_size_t),
     "glint_frame_batched": ([C.c_void_p, C.POINTER(EnvTask), C.c_int, C.POINTER(View), C.c_int, C.c_void_p,
                              C.c_void_p], C.c_int),
@@ -330,18 +332,22 @@ def glint_surrogate_forward(ctx, K, w, w_bf16, x, probs, stream=None):
     _check(lib().glint_surrogate_forward(ctx, K, _ptr(w), _ptr(w_bf16), _ptr(x), B, _ptr(probs), _stream(stream)))
 
 
-def glint_surrogate_gradient(ctx, K, w, w_bf16, x, target, workspace, grad, loss, stream=None):
-    _require_cuda(w, w_bf16, x, target, workspace, grad, loss)
+def glint_surrogate_gradient(ctx, K, w, w_bf16, x, target, workspace, grad, loss, stream=None, levels=None,
+                             radiance_weight=0.0):
+    _require_cuda(w, w_bf16, x, target, workspace, grad, loss, levels)
     B = int(x.shape[0])
-    _check(lib().glint_surrogate_gradient(ctx, K, _ptr(w), _ptr(w_bf16), _ptr(x), _ptr(target), B, _ptr(workspace),
-                                          _ptr(grad), _ptr(loss), _stream(stream)))
+    _check(lib().glint_surrogate_gradient(ctx, K, _ptr(w), _ptr(w_bf16), _ptr(x), _ptr(target), _ptr(levels),
+                                          radiance_weight, B, _ptr(workspace), _ptr(grad), _ptr(loss),
+                                          _stream(stream)))
 
 
-def glint_surrogate_train_step(ctx, K, w, w_bf16, m, v, step, lr, x, target, workspace, loss, stream=None):
-    _require_cuda(w, w_bf16, m, v, x, target, workspace, loss)
+def glint_surrogate_train_step(ctx, K, w, w_bf16, m, v, step, lr, x, target, workspace, loss, stream=None,
+                               levels=None, radiance_weight=0.0):
+    _require_cuda(w, w_bf16, m, v, x, target, workspace, loss, levels)
     B = int(x.shape[0])
     _check(lib().glint_surrogate_train_step(ctx, K, _ptr(w), _ptr(w_bf16), _ptr(m), _ptr(v), step, lr, _ptr(x),
-                                            _ptr(target), B, _ptr(workspace), _ptr(loss), _stream(stream)))
+                                            _ptr(target), _ptr(levels), radiance_weight, B, _ptr(workspace),
+                                            _ptr(loss), _stream(stream)))
 
 
 def glint_shade_surrogate_workspace_bytes(num_pixels: int, K: int) -> int:
@@ -355,6 +361,14 @@ def glint_shade_surrogate(ctx, gbuf: GBuffer, num_pixels: int, env: Env, w, w_bf
     _check(lib().glint_shade_surrogate(ctx, C.byref(gbuf), num_pixels, C.byref(env), _ptr(w), _ptr(w_bf16),
                                        C.byref(params), _ptr(workspace), _ptr(radiance),
                                        C.byref(dbg) if dbg is not None else None, _stream(stream)))
+
+
+def glint_shade_given_F(ctx, gbuf: GBuffer, num_pixels: int, env: Env, F, params: ShadeParams, radiance,
+                        debug=None, stream=None):
+    _require_cuda(F, radiance)
+    dbg = _debug(debug)
+    _check(lib().glint_shade_given_F(ctx, C.byref(gbuf), num_pixels, C.byref(env), _ptr(F), C.byref(params),
+                                     _ptr(radiance), C.byref(dbg) if dbg is not None else None, _stream(stream)))
 
 
 def glint_batched_workspace_bytes(n_views: int) -> int:

@@ -200,16 +200,18 @@ class Surrogate:
         G.glint_surrogate_forward(self.ctx, self.K, self.w, self.wb, x, probs)
         return probs
 
-    def gradient(self, x, target):
+    def gradient(self, x, target, levels=None, lam=0.0):
+        """Gradient of the loss; levels (device [K] double) and lam > 0 add
+        the radiance-weighted term."""
         grad = torch.empty(self.n, dtype=torch.float32, device=self.device)
         G.glint_surrogate_gradient(self.ctx, self.K, self.w, self.wb, x, target, self._workspace(x.shape[0]), grad,
-                                   self.loss)
+                                   self.loss, levels=levels, radiance_weight=lam)
         return grad, self.loss
 
-    def train_step(self, x, target, lr):
+    def train_step(self, x, target, lr, levels=None, lam=0.0):
         self.step += 1
         G.glint_surrogate_train_step(self.ctx, self.K, self.w, self.wb, self.m, self.v, self.step, lr, x, target,
-                                     self._workspace(x.shape[0]), self.loss)
+                                     self._workspace(x.shape[0]), self.loss, levels=levels, radiance_weight=lam)
         return self.loss
 
     @staticmethod
@@ -234,10 +236,12 @@ class Surrogate:
                                   ax, ay, x, t)
         return x, t
 
-    def fit(self, x, t, epochs=1, batch=4096, lr=1e-3, lr_min=1e-5, seed=7, log_every=0, steps=None):
+    def fit(self, x, t, epochs=1, batch=4096, lr=1e-3, lr_min=1e-5, seed=7, log_every=0, steps=None, levels=None,
+            lam=0.0):
         """Adam over shuffled mini-batches with a cosine learning-rate
         schedule; returns the list of (step, loss) read back every
-        log_every steps (the device loss is read only then)."""
+        log_every steps (the device loss is read only then).  levels and
+        lam > 0: the radiance-weighted loss term."""
         n = x.shape[0]
         per_epoch = max(1, n // batch)
         total = steps if steps is not None else epochs * per_epoch
@@ -251,7 +255,7 @@ class Surrogate:
                 if s >= total:
                     break
                 lr_s = lr_min + 0.5 * (lr - lr_min) * (1.0 + math.cos(math.pi * s / max(1, total)))
-                self.train_step(xs[b * batch:(b + 1) * batch], ts[b * batch:(b + 1) * batch], lr_s)
+                self.train_step(xs[b * batch:(b + 1) * batch], ts[b * batch:(b + 1) * batch], lr_s, levels, lam)
                 s += 1
                 if log_every and (s % log_every == 0 or s == total):
                     curve.append((s, float(self.loss.item())))

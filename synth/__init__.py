@@ -41,18 +41,22 @@ def _face_dirs(R: int) -> np.ndarray:
     return d / np.linalg.norm(d, axis=-1, keepdims=True)
 
 
-def make_env(R: int, seed: int, suns: int = 3) -> np.ndarray:
-    """Sky gradient + ground + seeded sun lobes; returns [6,R,R,3] float32."""
+def make_env(R: int, seed: int, suns: int = 3, frame: int = 0) -> np.ndarray:
+    """Sky gradient + ground + seeded sun lobes; returns [6,R,R,3] float32.
+
+    frame > 0: the rotating-sun sequence of the surrogate workload, sun s's
+    azimuth advanced by 2 (s + 1) degrees per frame (each sun at its own
+    rate, so the map changes non-rigidly); frame 0 is the static map."""
     rng = np.random.default_rng(seed)
     d = _face_dirs(R)
     y = d[..., 1]
     sky = np.array([0.20, 0.35, 0.80]) * (0.25 + 0.75 * np.clip(y, 0.0, 1.0))[..., None]
     ground = np.broadcast_to(np.array([0.04, 0.035, 0.03]), d.shape)
     env = np.where((y >= 0.0)[..., None], sky, ground).astype(np.float64)
-    for _ in range(suns):
+    for sun in range(suns):
         amp = 10.0 ** rng.uniform(1.0, 3.0)
         el = math.radians(rng.uniform(10.0, 70.0))
-        az = math.radians(rng.uniform(0.0, 360.0))
+        az = math.radians(rng.uniform(0.0, 360.0) + 2.0 * (sun + 1) * frame)
         sigma = rng.uniform(1.5, 4.0) * (math.pi / 2.0) / R
         sd = np.array([math.cos(el) * math.sin(az), math.sin(el), math.cos(el) * math.cos(az)])
         cos_t = d @ sd

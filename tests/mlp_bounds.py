@@ -79,25 +79,38 @@ def forward_sigma(w, x, K):
     y = np.exp(zz)
     y /= y.sum(axis=1, keepdims=True)
 
-    def soft(V):
-        y2 = y * y
-        return y2 * ((1.0 - y) ** 2 * V + (y2 * V).sum(axis=1, keepdims=True) - y2 * V)
-
-    Vyi, Vys = soft(Vzi), soft(Vzs)
-    cache.update(y=y, Vyi=Vyi, Vys=Vys)
+    Vyi, Vys = _soft_var(y, Vzi), _soft_var(y, Vzs)
+    cache.update(y=y, Vyi=Vyi, Vys=Vys, Vz4i=Vzi, Vz4s=Vzs)
     return y, np.sqrt(Vyi + Vys) + FREL * y, cache
 
 
-def gradient_sigma(w, x, t, K):
-    """(g64, sigma_g): the FP64 gradient of the mean soft-label
-    cross-entropy (flat padded layout) and the model's standard deviation
-    of a bfloat16 evaluation's deviation from it, per element."""
+def _soft_var(y, V):
+    """Variance of softmax outputs y for independent logit errors of variance V."""
+    y2 = y * y
+    return y2 * ((1.0 - y) ** 2 * V + (y2 * V).sum(axis=1, keepdims=True) - y2 * V)
+
+
+def gradient_sigma(w, x, t, K, levels=None, lam=0.0):
+    """(g64, sigma_g): the FP64 gradient of the mean loss (flat padded
+    layout; with levels and lam the radiance-weighted term of
+    mlp.loss_and_grad) and the model's standard deviation of a bfloat16
+    evaluation's deviation from it, per element.  The two terms' errors
+    are correlated: their standard deviations add."""
     y, _, c = forward_sigma(w, x, K)
     p = c["p"]
     B = len(x)
-    d = (y - np.asarray(t, dtype=np.float64)) / B
-    Vi = c["Vyi"] / B ** 2 + Q * d * d
-    Vs = c["Vys"] / B ** 2
+    t = np.asarray(t, dtype=np.float64)
+    d = (y - t) / B
+    sdi, sds = np.sqrt(c["Vyi"]) / B, np.sqrt(c["Vys"]) / B
+    if levels is not None and lam > 0:
+        yp, tp, ok = mlp.radiance_weighted(y, t, levels)
+        d = d.copy()
+        d[ok, 1:] += lam * (yp[ok] - tp[ok]) / B
+        for sd, V in ((sdi, c["Vz4i"]), (sds, c["Vz4s"])):
+            add = lam * np.sqrt(_soft_var(yp, V[:, 1:])) / B
+            sd[ok, 1:] += add[ok]
+    Vi = sdi * sdi + Q * d * d
+    Vs = sds * sds
     g, S = {}, {}
     for l in (4, 3, 2, 1):
         a, Vai, Vas = c["a"][l - 1], c["Vi"][l - 1], c["Vs"][l - 1]

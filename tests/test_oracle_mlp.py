@@ -18,6 +18,42 @@ def test_layout_and_parameter_count():
 
 
 @pytest.mark.parametrize("K", [4, 8])
+def test_radiance_weighted_loss_gradient_matches_finite_differences(K):
+    """The loss with the radiance-weighted term: its gradient against central
+    differences of the loss itself; a sample whose target reflects nothing
+    above level 0 contributes only the plain term."""
+    rng = np.random.default_rng(7)
+    w = mlp.init(K, seed=8).astype(np.float64)
+    w += rng.normal(scale=0.05, size=w.shape) * (mlp.pack(mlp.unpack(np.ones(mlp.N_PARAMS), K), K) != 0)
+    x = rng.normal(size=(12, 5))
+    t = rng.dirichlet(np.ones(K), size=12)
+    t[3] = 0.0
+    t[3, 0] = 1.0
+    levels = np.concatenate([[0.0], np.sort(10.0 ** rng.uniform(-2, 3, K - 1))])
+    lam = 0.7
+    loss, g = mlp.loss_and_grad(w, x, t, K, levels=levels, lam=lam)
+    idx = np.nonzero(g)[0]
+    pick = rng.choice(idx, 60, replace=False)
+    h = 1e-6
+    for i in pick:
+        wp, wm = w.copy(), w.copy()
+        wp[i] += h
+        wm[i] -= h
+        fd = (mlp.loss_and_grad(wp, x, t, K, levels=levels, lam=lam)[0] -
+              mlp.loss_and_grad(wm, x, t, K, levels=levels, lam=lam)[0]) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(fd)), (i, fd, g[i])
+    # the term is the cross-entropy of the L-weighted distributions: zero
+    # gradient contribution when the network matches the target exactly
+    y, _ = mlp.forward(w, x, K)
+    _, g_self = mlp.loss_and_grad(w, x, y, K, levels=levels, lam=lam)
+    assert np.abs(g_self).max() < 1e-12
+    base, _ = mlp.loss_and_grad(w, x, t, K)
+    yp, tp, ok = mlp.radiance_weighted(y, t, levels)
+    assert not ok[3] and ok.sum() == 11
+    assert loss == pytest.approx(base - lam * np.sum(tp[ok] * np.log(yp[ok])) / 12, rel=1e-12)
+
+
+@pytest.mark.parametrize("K", [4, 8])
 def test_gradient_matches_finite_differences(K):
     rng = np.random.default_rng(1)
     w = mlp.init(K, seed=3).astype(np.float64)
@@ -92,12 +128,14 @@ def test_bfloat16_mirror_fits_the_rounding_error_model(K, B):
     r = np.abs(ybf - y64) / sy
     rms = float(np.sqrt(np.mean(r * r)))
     assert r.max() < 8 and 0.05 < rms < 2, (r.max(), rms)
-    g64, sg = MB.gradient_sigma(w, x, t, K)
-    _, gref = mlp.loss_and_grad(w, x, t, K, bf=False)
-    np.testing.assert_allclose(g64, gref, rtol=1e-10, atol=1e-14)
-    _, gbf = mlp.loss_and_grad(w, x, t, K, bf=True)
-    nz = sg > 0
-    assert np.all(gbf[~nz] == 0) and np.all(g64[~nz] == 0)
-    r = np.abs(gbf - g64)[nz] / sg[nz]
-    rms = float(np.sqrt(np.mean(r * r)))
-    assert r.max() < 8 and 0.02 < rms < 2, (r.max(), rms)
+    levels = np.concatenate([[0.0], np.sort(10.0 ** rng.uniform(-2, 3, K - 1))])
+    for lv, lam in ((None, 0.0), (levels, 1.0)):
+        g64, sg = MB.gradient_sigma(w, x, t, K, levels=lv, lam=lam)
+        _, gref = mlp.loss_and_grad(w, x, t, K, bf=False, levels=lv, lam=lam)
+        np.testing.assert_allclose(g64, gref, rtol=1e-10, atol=1e-14)
+        _, gbf = mlp.loss_and_grad(w, x, t, K, bf=True, levels=lv, lam=lam)
+        nz = sg > 0
+        assert np.all(gbf[~nz] == 0) and np.all(g64[~nz] == 0)
+        r = np.abs(gbf - g64)[nz] / sg[nz]
+        rms = float(np.sqrt(np.mean(r * r)))
+        assert r.max() < 8 and 0.02 < rms < 2, (lam, r.max(), rms)

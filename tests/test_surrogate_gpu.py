@@ -225,21 +225,34 @@ def test_forward_matches_fp64_definition(ctx, K, B):
     assert r.max() < 8.0
 
 
-@pytest.mark.parametrize("K,B", [(8, 1000), (4, 64), (16, 37), (8, 4096)])
-def test_gradient_matches_fp64_definition(ctx, K, B):
+def _levels(K, seed):
+    rng = np.random.default_rng(seed)
+    return np.concatenate([[0.0], np.sort(10.0 ** rng.uniform(-2, 3, K - 1))])
+
+
+@pytest.mark.parametrize("K,B,lam", [(8, 1000, 0.0), (4, 64, 0.0), (16, 37, 0.0), (8, 4096, 0.0), (8, 1000, 1.0),
+                                     (16, 300, 2.5)])
+def test_gradient_matches_fp64_definition(ctx, K, B, lam):
     """Every gradient entry within 8 sigma of the rounding-error model of the
-    plain FP64 gradient (pads exactly zero); the loss within 1e-3."""
+    plain FP64 gradient (pads exactly zero); the loss within 1e-3; with
+    lam > 0 the loss carries the radiance-weighted term."""
     import torch
     from tests import mlp_bounds as MB
     w, x, t, mask = _fp64_case(K, B, 51)
+    t[5] = 0.0
+    t[5, 0] = 1.0  # reflects nothing above level 0: no radiance-weighted term
+    lv = _levels(K, 52) if lam > 0 else None
     wt, wb = upload_params(ctx, w, K)
     ws = torch.empty(G.glint_surrogate_workspace_bytes(B) // 4, dtype=torch.float32, device="cuda")
     grad = torch.empty(mlp.N_PARAMS, dtype=torch.float32, device="cuda")
     loss = torch.empty(1, dtype=torch.float32, device="cuda")
-    G.glint_surrogate_gradient(ctx, K, wt, wb, U.dev(x), U.dev(t), ws, grad, loss)
+    G.glint_surrogate_gradient(ctx, K, wt, wb, U.dev(x), U.dev(t), ws, grad, loss,
+                               levels=U.dev(lv) if lv is not None else None, radiance_weight=lam)
     g = U.host(grad).astype(np.float64)
-    g64, sg = MB.gradient_sigma(w.astype(np.float64), x.astype(np.float64), t.astype(np.float64), K)
-    l64, _ = mlp.loss_and_grad(w.astype(np.float64), x.astype(np.float64), t.astype(np.float64), K)
+    g64, sg = MB.gradient_sigma(w.astype(np.float64), x.astype(np.float64), t.astype(np.float64), K, levels=lv,
+                                lam=lam)
+    l64, _ = mlp.loss_and_grad(w.astype(np.float64), x.astype(np.float64), t.astype(np.float64), K, levels=lv,
+                               lam=lam)
     assert float(U.host(loss)[0]) == pytest.approx(l64, rel=1e-3)
     assert np.all(g[~mask] == 0)
     r = np.abs(g - g64)[mask] / (sg[mask] + 6e-8 * np.abs(g64[mask]) + 1e-30)
@@ -389,6 +402,11 @@ def test_surrogate_rejects_bad_arguments(ctx):
     t = torch.full((64, K), 1.0 / K, dtype=torch.float32, device="cuda")
     with pytest.raises(G.GlintError):
         G.glint_surrogate_train_step(ctx, K, wt, wb, m, m.clone(), 0, 1e-3, x, t, ws, loss)
+    for lv, lam in ((None, 1.0), (U.dev(_levels(K, 3)), -1.0)):  # a radiance weight needs levels; lam >= 0
+        with pytest.raises(G.GlintError) as e:
+            G.glint_surrogate_train_step(ctx, K, wt, wb, m, m.clone(), 1, 1e-3, x, t, ws, loss, levels=lv,
+                                         radiance_weight=lam)
+        assert e.value.code == G.GLINT_EINVAL
     # empty batch is a no-op for the forward pass
     G.glint_surrogate_forward(ctx, K, wt, wb, x[:0], probs)
     # parameters never prepared in this context, or prepared for another K
