@@ -180,7 +180,11 @@ def parse():
                     help="anisotropic lookup with this many taps along the lobe (0: one lookup)")
     ap.add_argument("--visibility", default="none", choices=["none", "contact"],
                     help="occlusion that attenuates the probabilities (contact: the scene's AO-like field)")
-    ap.add_argument("--train-steps", type=int, default=400, help="surrogate training steps before timing")
+    ap.add_argument("--train-epochs", type=int, default=20,
+                    help="surrogate training epochs over 2^22 filter samples (batch 4096) before timing")
+    ap.add_argument("--rotate-frames", type=int, default=8,
+                    help="surrogate form: frames of the rotating-sun study after the timed region (frozen, "
+                         "fine-tuned and retrained network against the plain filter)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--env", default="dynamic", choices=["dynamic", "static"],
                     help="dynamic: the map is partitioned and prefiltered every frame (the headline); static: "
@@ -312,7 +316,7 @@ def batched(a):
             pipe = EnvPipeline(ctx, int(env.shape[1]), K, M, T)
             pipe.build_luts()
             pipe.run(env)
-            sur, info = train_surrogate(G, ctx, pipe, env, K, a.train_steps)
+            sur, info = train_surrogate(G, ctx, pipe, env, K, a.train_epochs)
             surrogates.append(sur)
             train_info.append(info)
     bf = BatchedFrame(ctx, envs, views, surrogates=surrogates)
@@ -344,33 +348,124 @@ def batched(a):
     print(json.dumps(out), flush=True)
 
 
-def train_surrogate(G, ctx, pipe, env, K, steps, batch=4096):
-    """Trains the surrogate on the plain filter of the current map (not
-    timed as part of a frame); then times training steps on their own."""
+def train_surrogate(G, ctx, pipe, env, K, epochs, batch=4096):
+    """Trains the surrogate on the plain filter of the current map with the
+    workload's schedule (2^22 samples, `epochs` epochs, not timed as part of
+    a frame); then times training steps on their own."""
     import torch
     from paper_2507_02674_amd.pipeline import Surrogate
     sur = Surrogate(ctx, K)
     sur.init(seed=7)
-    x, t = sur.samples(pipe, env, 1 << 20, seed=1)
-    sur.fit(x, t, batch=batch, lr=3e-3, lr_min=1e-4, steps=steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    curve = sur.train(pipe, env, epochs=epochs, log_every=2048)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    steps = sur.step
     xv, tv = sur.samples(pipe, env, 1 << 14, seed=2)
-    loss = float(sur.gradient(xv, tv)[1].item())
+    loss = float(sur.gradient(xv, tv, pipe.levels, Surrogate.TRAIN["lam"])[1].item())
     err = float((sur.forward(xv) - tv).abs().mean().item())
     # training-step throughput (b7): 50 steps at the training batch
-    xs, ts = x[:batch].contiguous(), t[:batch].contiguous()
+    xs, ts = xv[:batch].contiguous(), tv[:batch].contiguous()
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for _ in range(50):
-        sur.train_step(xs, ts, 1e-5)
+        sur.train_step(xs, ts, 1e-5, pipe.levels, Surrogate.TRAIN["lam"])
     e1.record()
     torch.cuda.synchronize()
     step_ms = e0.elapsed_time(e1) / 50
     flops = 3.0 * mlp_flops_per_row(K) * batch
-    info = {"train_steps": steps, "batch": batch, "heldout_loss": round(loss, 5), "heldout_mean_abs_F_err": err,
+    info = {"train_steps": steps, "batch": batch, "schedule": dict(Surrogate.TRAIN, epochs=epochs),
+            "train_s": round(train_s, 3), "loss_curve": [(st, round(l, 5)) for st, l in curve],
+            "heldout_loss": round(loss, 5), "heldout_mean_abs_F_err": err,
             "train_step_ms": round(step_ms, 4), "train_samples_per_s": round(batch / (step_ms * 1e-3), 1),
             "train_tflops_algorithmic": round(flops / (step_ms * 1e-3) / 1e12, 3)}
     return sur, info
+
+
+ACCURACY_METRIC = ("mean relative radiance error: sum |L - L_ref| / sum |L_ref| over the glint pixels and the RGB "
+                   "channels, same hash draws; L_ref shaded with the plain filter evaluated at each pixel's "
+                   "lookup (glint_filter_pixels, no mip interpolation)")
+
+
+def filter_accuracy(G, ctx, w, pipe, env, gbuf_np, shader, envs):
+    """The form under test and the plain f32 pyramid, each against shading
+    with the plain filter at every pixel's lookup."""
+    import torch
+    from paper_2507_02674_amd.pipeline import EnvPipeline, FilterShader, Shader, relative_l1
+    g = {k: v for k, v in gbuf_np.items() if k not in G.GBUF_OPTIONAL}
+    ref = FilterShader(ctx, g, w.K, seed=w.hash_seed)
+    f32 = EnvPipeline(ctx, w.R, w.K, w.M, w.T, G.GLINT_F32, w.ell)
+    f32.build_luts()
+    f32.run(env)
+    ref.run(f32, env)
+    pyr = Shader(ctx, g, seed=w.hash_seed)
+    pyr.run(f32.env_struct())
+    shader.run(envs)
+    torch.cuda.synchronize()
+    hit = torch.from_numpy(gbuf_np["surf_id"] != 0xFFFFFFFF).cuda()
+    return {"metric": ACCURACY_METRIC,
+            "form_vs_filter": relative_l1(shader.radiance, ref.radiance, hit),
+            "pyramid_f32_vs_filter": relative_l1(pyr.radiance, ref.radiance, hit),
+            "form_vs_pyramid_f32": relative_l1(shader.radiance, pyr.radiance, hit)}
+
+
+def rotating_study(G, ctx, w, env_np, gbuf_np, sur, frames, epochs):
+    """Rotating suns (sun s's azimuth +2 (s+1) degrees per frame): per
+    frame, the network trained on frame 0 (frozen), the same network
+    fine-tuned frame after frame (200 steps on 2^18 fresh samples of each
+    frame's filter) and the f32 pyramid, each against the plain filter of
+    that frame; at the last frame also a network retrained from scratch."""
+    import torch
+    import synth
+    from paper_2507_02674_amd.pipeline import (EnvPipeline, FilterShader, Shader, Surrogate, SurrogateShader,
+                                               relative_l1)
+    g = {k: v for k, v in gbuf_np.items() if k not in G.GBUF_OPTIONAL}
+    hit = torch.from_numpy(gbuf_np["surf_id"] != 0xFFFFFFFF).cuda()
+    frozen = Surrogate(ctx, w.K)
+    frozen.restore(sur.state())
+    tuned = Surrogate(ctx, w.K)
+    tuned.restore(sur.state())
+    pipe = EnvPipeline(ctx, w.R, w.K, w.M, w.T, G.GLINT_F32, w.ell)
+    pipe.build_luts()
+    ref = FilterShader(ctx, g, w.K, seed=w.hash_seed)
+    pyr = Shader(ctx, g, seed=w.hash_seed)
+    sh_frozen = SurrogateShader(ctx, g, frozen, seed=w.hash_seed)
+    sh_tuned = SurrogateShader(ctx, g, tuned, seed=w.hash_seed)
+    rows, tune_ms = [], []
+    for f in range(1, frames + 1):
+        env = torch.from_numpy(synth.make_env(w.R, w.env_seed, frame=f)).cuda()
+        pipe.run(env)
+        ref.run(pipe, env)
+        pyr.run(pipe.env_struct())
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        tuned.fine_tune(pipe, env, seed=100 + f)
+        torch.cuda.synchronize()
+        tune_ms.append(1e3 * (time.perf_counter() - t0))
+        sh_frozen.run(pipe.env_struct())
+        sh_tuned.run(pipe.env_struct())
+        torch.cuda.synchronize()
+        rows.append({"frame": f, "frozen": relative_l1(sh_frozen.radiance, ref.radiance, hit),
+                     "fine_tuned": relative_l1(sh_tuned.radiance, ref.radiance, hit),
+                     "pyramid_f32": relative_l1(pyr.radiance, ref.radiance, hit)})
+    fresh = Surrogate(ctx, w.K)
+    fresh.init(seed=7)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fresh.train(pipe, env, epochs=epochs)
+    torch.cuda.synchronize()
+    retrain_s = time.perf_counter() - t0
+    sh_fresh = SurrogateShader(ctx, g, fresh, seed=w.hash_seed)
+    sh_fresh.run(pipe.env_struct())
+    torch.cuda.synchronize()
+    mean = lambda k: float(np.mean([r[k] for r in rows]))
+    return {"metric": ACCURACY_METRIC, "frames": rows,
+            "mean": {k: mean(k) for k in ("frozen", "fine_tuned", "pyramid_f32")},
+            "fine_tune": dict(Surrogate.FINE_TUNE, ms_per_frame=round(float(np.mean(tune_ms)), 2)),
+            "retrained_last_frame": {"vs_filter": relative_l1(sh_fresh.radiance, ref.radiance, hit),
+                                     "train_s": round(retrain_s, 3), "epochs": epochs}}
 
 
 def roofline_records(kernels, w, a, shader, glint_pixels, config_tag):
@@ -448,7 +543,7 @@ def main():
     pipe.run(env)
     extra = {}
     if a.form == "surrogate":
-        sur, extra["surrogate"] = train_surrogate(G, ctx, pipe, env, w.K, a.train_steps)
+        sur, extra["surrogate"] = train_surrogate(G, ctx, pipe, env, w.K, a.train_epochs)
         shader = SurrogateShader(ctx, gbuf_np, sur, seed=w.hash_seed, vertices=a.vertices,
                                  sampler=SAMPLERS[a.sampler])
     else:
@@ -558,6 +653,10 @@ def main():
             if Kd == w.K else None,
             "radiance_mean_rel_err": float(rel[lit].mean().item()),
             "frame_mean_radiance_ratio": float((r1.mean() / r0.mean()).item())}
+    if a.form == "surrogate" or (a.dtype != "f32" and default_path):
+        out["vs_plain_filter"] = filter_accuracy(G, ctx, w, pipe, env, gbuf_np, shader, envs)
+    if a.form == "surrogate" and a.rotate_frames > 0:
+        out["rotating_suns"] = rotating_study(G, ctx, w, env_np, gbuf_np, sur, a.rotate_frames, a.train_epochs)
     if not a.no_cpu_baseline and a.form == "plain" and default_path:
         if a.dtype == "f32":
             ind_h = pipe.ind_pyr.cpu().numpy()

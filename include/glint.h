@@ -493,6 +493,18 @@ int glint_shade_surrogate(glint_ctx ctx, const glint_gbuffer *gbuf, int64_t num_
                           const float *w, const uint16_t *w_bf16, const glint_shade_params *params,
                           void *workspace, float *radiance, const glint_shade_debug *debug, void *stream);
 
+/* The filter at the lookup of every G-buffer pixel: reflection direction
+ * 2<n,v>n - v and alpha = sqrt(alpha_x alpha_y), computed as glint_shade
+ * computes them, at that continuous roughness (no mip interpolation).
+ * F: device [P][K] float32, the K filtered indicator values per pixel (0
+ * for background pixels).  With glint_shade_given_F this shades with the
+ * plain filter itself: the reference that the pyramid's and the
+ * surrogate's errors are measured against.  Errors as glint_sample_filter,
+ * plus GLINT_EINVAL for a G-buffer with a null field. */
+int glint_filter_pixels(glint_ctx ctx, const float *env, const uint8_t *ind_j, const float *ind_t, int R, int K,
+                        const glint_prefilter_params *params, const void *workspace, const glint_gbuffer *gbuf,
+                        int64_t num_pixels, float *F, void *stream);
+
 /* Shading with the K filtered indicator values of every pixel given
  * (F [num_pixels][K] float32, device; any positive scale): p_k =
  * S F_k / sum F as in glint_shade, RGB, S and E_rho read from env, the

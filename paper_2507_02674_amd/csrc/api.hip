@@ -453,7 +453,8 @@ int glint_sample_filter(glint_ctx ctx, const float *env, const uint8_t *ind_j, c
     if (n == 0) return ok();
     if (!dirs || !alphas || !out) return fail(GLINT_EINVAL, "null pointer argument");
     return device_status(glint::launch_sample_filter(env, ind_j, ind_t, workspace, R, K, fp->num_mips, fp->taps, 0,
-                                                     dirs, alphas, nullptr, n, out, nullptr, (hipStream_t)stream),
+                                                     dirs, alphas, nullptr, nullptr, n, out, nullptr,
+                                                     (hipStream_t)stream),
                          "glint_sample_filter launch");
 }
 
@@ -473,8 +474,30 @@ int glint_surrogate_samples(glint_ctx ctx, const float *env, const uint8_t *ind_
     if (n == 0) return ok();
     if (!dirs || !ax || !ay || !x || !target) return fail(GLINT_EINVAL, "null pointer argument");
     return device_status(glint::launch_sample_filter(env, ind_j, ind_t, workspace, R, K, fp->num_mips, fp->taps, 1,
-                                                     dirs, ax, ay, n, x, target, (hipStream_t)stream),
+                                                     dirs, ax, ay, nullptr, n, x, target, (hipStream_t)stream),
                          "glint_surrogate_samples launch");
+}
+
+int glint_filter_pixels(glint_ctx ctx, const float *env, const uint8_t *ind_j, const float *ind_t, int R, int K,
+                        const glint_prefilter_params *fp, const void *workspace, const glint_gbuffer *g, int64_t P,
+                        float *F, void *stream)
+{
+    if (int rc = check_ctx(ctx)) return rc;
+    glint::ProfScope prof_scope(&ctx->prof);
+    if (!fp || !env || !ind_j || !ind_t || !workspace) return fail(GLINT_EINVAL, "null pointer argument");
+    if (int rc = check_R(R)) return rc;
+    if (int rc = check_tree_K(K)) return rc;
+    if (int rc = check_mips(R, fp->num_mips)) return rc;
+    if (fp->taps < 1 || fp->taps > 1024) return fail(GLINT_EINVAL, "taps=%d must be in [1, 1024]", fp->taps);
+    if (P < 0 || P > ((int64_t)1 << 36)) return fail(GLINT_EINVAL, "bad pixel count %lld", (long long)P);
+    if (reinterpret_cast<uintptr_t>(workspace) % 16) return fail(GLINT_EINVAL, "workspace must be 16-byte aligned");
+    if (P == 0) return ok();
+    if (!F) return fail(GLINT_EINVAL, "null pointer argument");
+    if (int rc = check_gbuffer(g)) return rc;
+    return device_status(glint::launch_sample_filter(env, ind_j, ind_t, workspace, R, K, fp->num_mips, fp->taps, 2,
+                                                     nullptr, nullptr, nullptr, g, P, F, nullptr,
+                                                     (hipStream_t)stream),
+                         "glint_filter_pixels launch");
 }
 
 int glint_surrogate_params(void) { return glint::mlp_params(); }

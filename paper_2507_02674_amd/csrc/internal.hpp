@@ -22,10 +22,12 @@ hipError_t launch_prefilter(const float *env, const uint8_t *ind_j, const float 
                             int dtype, void *workspace, void *ind_pyr, float *rgb_pyr, hipStream_t stream);
 
 // mode 0: filter at alpha = a0 -> out0 [n][K+3]; mode 1: training pairs at
-// alpha = sqrt(a0 a1) -> out0 features [n][5], out1 targets [n][K].
+// alpha = sqrt(a0 a1) -> out0 features [n][5], out1 targets [n][K]; mode 2:
+// the lookups of the G-buffer g's pixels -> out0 [n][K].
 hipError_t launch_sample_filter(const float *env, const uint8_t *ind_j, const float *ind_t, const void *workspace,
                                 int R, int K, int M, int T, int mode, const float *dirs, const float *a0,
-                                const float *a1, int64_t n, float *out0, float *out1, hipStream_t stream);
+                                const float *a1, const glint_gbuffer *g, int64_t n, float *out0, float *out1,
+                                hipStream_t stream);
 
 hipError_t launch_luts(float *lut_S, float *lut_E, hipStream_t stream);
 hipError_t launch_quantile_table(double *table, hipStream_t stream);

@@ -649,13 +649,17 @@ __global__ void __launch_bounds__(kFilterThreads, GLINT_FILTER_MIN_WAVES) k_pref
 //   MODE 0: a0 = alpha [n]; out0 = filtered values [n][K+3].
 //   MODE 1: a0 = alpha_x, a1 = alpha_y [n], filtered at sqrt(alpha_x alpha_y);
 //           out0 = surrogate inputs [n][5], out1 = F_k / sum F [n][K].
+//   MODE 2: the lookups of G-buffer pixels (reflection direction
+//           2<n,v>n - v and sqrt(alpha_x alpha_y), as shading computes
+//           them); out0 = filtered indicator values [n][K] (0 for
+//           background pixels).
 template <int K, int MODE>
 __global__ void __launch_bounds__(kFilterThreads) k_sample_filter(int R, int M, int T, Level0<K> l0,
                                                                    const float *__restrict__ chain,
                                                                    const float *__restrict__ dirs,
                                                                    const float *__restrict__ a0,
-                                                                   const float *__restrict__ a1, int64_t n,
-                                                                   float *__restrict__ out0,
+                                                                   const float *__restrict__ a1, glint_gbuffer g,
+                                                                   int64_t n, float *__restrict__ out0,
                                                                    float *__restrict__ out1)
 {
     constexpr int C = K + 3, CP = chain_stride(K);
@@ -664,19 +668,28 @@ __global__ void __launch_bounds__(kFilterThreads) k_sample_filter(int R, int M, 
     __syncthreads();
     const int64_t q = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kGroup;
     const int sub = threadIdx.x % kGroup;
-    const bool active = q < n;
+    const bool active = q < n && (MODE != 2 || g.surf_id[q] != GLINT_NO_SURFACE);
     double acc[C];
 #pragma unroll
     for (int k = 0; k < C; ++k) acc[k] = 0.0;
     double wsum = 0.0;
     d3 r = {0.0, 0.0, 1.0};
     if (active) {
-        r = {(double)dirs[3 * q], (double)dirs[3 * q + 1], (double)dirs[3 * q + 2]};
+        double alpha;
+        if constexpr (MODE == 2) {
+            const d3 nn = {(double)g.nx[q], (double)g.ny[q], (double)g.nz[q]};
+            const d3 vv = {(double)g.vx[q], (double)g.vy[q], (double)g.vz[q]};
+            const double mu = nn.x * vv.x + nn.y * vv.y + nn.z * vv.z;
+            r = {2.0 * mu * nn.x - vv.x, 2.0 * mu * nn.y - vv.y, 2.0 * mu * nn.z - vv.z};
+            alpha = sqrt((double)g.ax[q] * (double)g.ay[q]);
+        } else {
+            r = {(double)dirs[3 * q], (double)dirs[3 * q + 1], (double)dirs[3 * q + 2]};
+            alpha = MODE == 0 ? (double)a0[q] : sqrt((double)a0[q] * (double)a1[q]);
+        }
         const double len = sqrt(r.x * r.x + r.y * r.y + r.z * r.z);
         const d3 u = {r.x / len, r.y / len, r.z / len};
         d3 t1, t2;
         onb(u, t1, t2);
-        const double alpha = MODE == 0 ? (double)a0[q] : sqrt((double)a0[q] * (double)a1[q]);
 #pragma unroll 1
         for (int j = sub; j < T; j += kGroup) {
             Tap tp;
@@ -692,6 +705,13 @@ __global__ void __launch_bounds__(kFilterThreads) k_sample_filter(int R, int M, 
         for (int o = kGroup / 2; o >= 1; o >>= 1) acc[k] += __shfl_xor(acc[k], o, kGroup);
     }
     for (int o = kGroup / 2; o >= 1; o >>= 1) wsum += __shfl_xor(wsum, o, kGroup);
+    if constexpr (MODE == 2) {
+        if (q < n && sub == 0) {
+#pragma unroll
+            for (int k = 0; k < K; ++k) out0[q * K + k] = active ? (float)(acc[k] / wsum) : 0.0f;
+        }
+        return;
+    }
     if (!active || sub != 0) return;
     if constexpr (MODE == 0) {
 #pragma unroll
@@ -712,19 +732,25 @@ __global__ void __launch_bounds__(kFilterThreads) k_sample_filter(int R, int M, 
 
 hipError_t launch_sample_filter(const float *env, const uint8_t *ind_j, const float *ind_t, const void *workspace,
                                 int R, int K, int M, int T, int mode, const float *dirs, const float *a0,
-                                const float *a1, int64_t n, float *out0, float *out1, hipStream_t stream)
+                                const float *a1, const glint_gbuffer *g, int64_t n, float *out0, float *out1,
+                                hipStream_t stream)
 {
     const float *chain = static_cast<const float *>(workspace);
     const unsigned blocks = (unsigned)((n * kGroup + kFilterThreads - 1) / kFilterThreads);
+    glint_gbuffer gb{};
+    if (g) gb = *g;
 #define GLINT_SF(KK)                                                                                          \
     if (K == KK) {                                                                                            \
         Level0<KK> l0{env, ind_j, ind_t};                                                                     \
         if (mode == 0)                                                                                        \
             GLINT_LAUNCH("k_sample_filter", (k_sample_filter<KK, 0>), dim3(blocks), dim3(kFilterThreads), 0,  \
-                         stream, R, M, T, l0, chain, dirs, a0, a1, n, out0, out1);                            \
-        else                                                                                                  \
+                         stream, R, M, T, l0, chain, dirs, a0, a1, gb, n, out0, out1);                        \
+        else if (mode == 1)                                                                                   \
             GLINT_LAUNCH("k_sample_filter", (k_sample_filter<KK, 1>), dim3(blocks), dim3(kFilterThreads), 0,  \
-                         stream, R, M, T, l0, chain, dirs, a0, a1, n, out0, out1);                            \
+                         stream, R, M, T, l0, chain, dirs, a0, a1, gb, n, out0, out1);                        \
+        else                                                                                                  \
+            GLINT_LAUNCH("k_filter_pixels", (k_sample_filter<KK, 2>), dim3(blocks), dim3(kFilterThreads), 0,  \
+                         stream, R, M, T, l0, chain, dirs, a0, a1, gb, n, out0, out1);                        \
         return hipGetLastError();                                                                             \
     }
     GLINT_SF(2)

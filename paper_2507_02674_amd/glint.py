@@ -101,6 +101,9 @@ EXPORTS = {
     "glint_surrogate_samples": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_int,
                                  C.POINTER(PrefilterParams), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                  C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
+    "glint_filter_pixels": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_int,
+                             C.POINTER(PrefilterParams), C.c_void_p, C.POINTER(GBuffer), C.c_int64, C.c_void_p,
+                             C.c_void_p], C.c_int),
     "glint_surrogate_params": ([], C.c_int),
     "glint_surrogate_workspace_bytes": ([C.c_int], C.c_size_t),
     "glint_surrogate_prepare": ([C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
@@ -311,6 +314,13 @@ def glint_surrogate_samples(ctx, env, ind_j, ind_t, R, K, params: PrefilterParam
     _check(lib().glint_surrogate_samples(ctx, _ptr(env), _ptr(ind_j), _ptr(ind_t), R, K, C.byref(params),
                                          _ptr(workspace), _ptr(dirs), _ptr(ax), _ptr(ay), n, _ptr(x), _ptr(target),
                                          _stream(stream)))
+
+
+def glint_filter_pixels(ctx, env, ind_j, ind_t, R, K, params: PrefilterParams, workspace, gbuf: GBuffer,
+                        num_pixels: int, F, stream=None):
+    _require_cuda(env, ind_j, ind_t, workspace, F)
+    _check(lib().glint_filter_pixels(ctx, _ptr(env), _ptr(ind_j), _ptr(ind_t), R, K, C.byref(params),
+                                     _ptr(workspace), C.byref(gbuf), num_pixels, _ptr(F), _stream(stream)))
 
 
 def glint_surrogate_params() -> int:

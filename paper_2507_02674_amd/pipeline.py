@@ -261,6 +261,30 @@ class Surrogate:
                     curve.append((s, float(self.loss.item())))
         return curve
 
+    # Training schedule of the surrogate workload: 2^22 filter samples, 20
+    # epochs of batch 4096 (20,480 Adam steps), cosine learning rate
+    # 5e-3 -> 1e-5, radiance-weighted loss term of weight 1.
+    TRAIN = dict(samples=1 << 22, epochs=20, batch=4096, lr=5e-3, lr_min=1e-5, lam=1.0)
+    FINE_TUNE = dict(samples=1 << 18, steps=200, batch=4096, lr=5e-4, lr_min=1e-5, lam=1.0)
+
+    def train(self, pipe, env, seed=1, log_every=0, **over):
+        """Trains on the plain filter of pipe's current map (fresh weights
+        not implied: call init first).  Returns the loss curve."""
+        c = dict(self.TRAIN, **over)
+        x, t = self.samples(pipe, env, c["samples"], seed=seed)
+        steps = c["epochs"] * max(1, c["samples"] // c["batch"])
+        return self.fit(x, t, batch=c["batch"], lr=c["lr"], lr_min=c["lr_min"], steps=steps, seed=seed,
+                        log_every=log_every, levels=pipe.levels, lam=c["lam"])
+
+    def fine_tune(self, pipe, env, seed=1, **over):
+        """A few Adam steps on fresh samples of pipe's current map (the
+        map moved since the weights were trained): by default 200 steps
+        over 2^18 samples, learning rate 5e-4 -> 1e-5."""
+        c = dict(self.FINE_TUNE, **over)
+        x, t = self.samples(pipe, env, c["samples"], seed=seed)
+        return self.fit(x, t, batch=c["batch"], lr=c["lr"], lr_min=c["lr_min"], steps=c["steps"], seed=seed,
+                        levels=pipe.levels, lam=c["lam"])
+
     def state(self):
         """Host copy of (w, m, v, step) for checkpoints."""
         return dict(w=self.w.cpu(), m=self.m.cpu(), v=self.v.cpu(), step=self.step, K=self.K)
@@ -288,6 +312,33 @@ class SurrogateShader(Shader):
     def run(self, env: G.Env, stream=None, debug=None):
         G.glint_shade_surrogate(self.ctx, self.gb, self.P, env, self.sur.w, self.sur.wb, self.sp, self.F,
                                 self.radiance, debug, stream)
+
+
+class FilterShader(Shader):
+    """Shading with the plain filter evaluated at every pixel's lookup
+    (glint_filter_pixels + glint_shade_given_F): no mip interpolation, the
+    reference the pyramid and the surrogate are judged against."""
+
+    def __init__(self, ctx, gbuf: dict, K, seed=1, vertices=1, device="cuda"):
+        super().__init__(ctx, gbuf, seed=seed, vertices=vertices, device=device)
+        self.K = K
+        self.F = torch.empty((max(self.P, 1), K), dtype=torch.float32, device=device)
+
+    def run(self, pipe: EnvPipeline, env, stream=None, debug=None):
+        G.glint_filter_pixels(self.ctx, env, pipe.ind_j, pipe.ind_t, pipe.R, pipe.K, pipe.fp, pipe.filt_ws, self.gb,
+                              self.P, self.F, stream)
+        G.glint_shade_given_F(self.ctx, self.gb, self.P, pipe.env_struct(), self.F, self.sp, self.radiance, debug,
+                              stream)
+
+
+def relative_l1(a, b, mask=None):
+    """Mean relative radiance error sum |a - b| / sum |b| over the masked
+    pixels and the three channels (a: radiance to judge, b: reference)."""
+    a, b = a.double(), b.double()
+    if mask is not None:
+        a, b = a[mask], b[mask]
+    den = b.abs().sum()
+    return float((a - b).abs().sum() / den) if float(den) > 0 else 0.0
 
 
 class FramePipeline:
