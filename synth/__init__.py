@@ -367,12 +367,25 @@ class Workload:
     extra: dict = field(default_factory=dict)
 
     def env(self) -> np.ndarray:
-        return make_env(self.R, self.env_seed)
+        key = ("env", self.name)
+        if key not in _CACHE:
+            _CACHE[key] = make_env(self.R, self.env_seed)
+        return _CACHE[key].copy()
 
     def gbuf(self) -> dict:
-        if self.scene == "tiny":
-            return scene_tiny(self.W, self.H)
-        return scene_frame(self.W, self.H, seed=self.env_seed + 5, density_decades=self.density_decades)
+        """The workload's G-buffer (generated once per process; every call
+        returns fresh copies of the arrays)."""
+        key = ("gbuf", self.name)
+        if key not in _CACHE:
+            if self.scene == "tiny":
+                _CACHE[key] = scene_tiny(self.W, self.H)
+            else:
+                _CACHE[key] = scene_frame(self.W, self.H, seed=self.env_seed + 5,
+                                          density_decades=self.density_decades)
+        return {k: v.copy() for k, v in _CACHE[key].items()}
+
+
+_CACHE = {}
 
 
 WORKLOADS = {

@@ -510,6 +510,66 @@ def test_precision_workload_sampled(ctx):
     check_shade({k: v[pix] for k, v in gpu.items()}, orc, w.K, "precision workload sampled")
 
 
+@pytest.mark.parametrize("dtype", [G.GLINT_F16, G.GLINT_BF16, G.GLINT_UNORM16])
+def test_precision_workload_storage_types_at_size(ctx, dtype):
+    """The precision workload's map (R = 512, M = 9, K = 8) stored in 16
+    bits: 2,700 sampled texels over every mip against the oracle's double
+    sums rounded to the same type (at most one 16-bit step apart, rarely)."""
+    w = synth.WORKLOADS["precision"]
+    U.log(f"precision workload storage dtype={dtype}")
+    env = w.env()
+    lv, ij, it = U.partition(ctx, env, w.K)
+    raw, rgb, chain = U.prefilter(ctx, env, ij, it, w.K, w.M, w.T, dtype=dtype)
+    rng = np.random.default_rng(11)
+    ids = np.concatenate([oracle.level_offset(w.R, m) + rng.choice(6 * (w.R >> m) ** 2, min(6 * (w.R >> m) ** 2, 300),
+                                                                   replace=False) for m in range(w.M)])
+    ochain = oracle.mipchain(env, ij, it, w.K, w.M)
+    opyr = oracle.prefilter(env, ij, it, ochain, w.K, w.M, w.T, texel_ids=ids)
+    want = U.encode(opyr[:, :w.K], dtype)
+    got = raw[ids]
+    if dtype == G.GLINT_F16:
+        d = np.abs(got.view(np.int16).astype(np.int64) - want.view(np.int16).astype(np.int64))
+    else:
+        d = np.abs(got.astype(np.int64) - want.astype(np.int64))
+    U.log(f"  code diff: max {d.max()}, > 0: {(d > 0).mean():.5f}")
+    assert d.max() <= 1 and (d > 0).mean() < 2e-3
+    assert U.ulp_diff(rgb[ids, :3], opyr[:, w.K:]).max() <= PYR_ULP
+
+
+def test_precision_workload_radiance_error_vs_fp64_oracle(ctx):
+    """Sec. 7 "Texture Precision" at 2560x1440 (R = 512, densities up to
+    1e10): the whole GPU frame with the pyramid stored as f32, f16, bf16 and
+    unorm16 against the FP64 oracle's frame (its own partition, pyramid, LUTs
+    and counts): mean relative radiance error sum |L - L_64| / sum |L_64|
+    over the glint pixels; f32 within 1e-3, the 16-bit types within 1e-2."""
+    import torch
+    from paper_2507_02674_amd.pipeline import EnvPipeline, Shader
+    w = synth.WORKLOADS["precision"]
+    U.log("precision workload radiance vs FP64 oracle, full frame")
+    env, g = w.env(), w.gbuf()
+    orc = oracle.frame(env, g, w.K, w.M, w.T, seed=w.hash_seed, lut=oracle_luts())
+    hit = g["surf_id"] != synth.NO_SURFACE
+    L64 = orc["radiance"][hit]
+    sh = Shader(ctx, g, seed=w.hash_seed)
+    errs = {}
+    for dt in (G.GLINT_F32, G.GLINT_F16, G.GLINT_BF16, G.GLINT_UNORM16):
+        pipe = EnvPipeline(ctx, w.R, w.K, w.M, w.T, dt)
+        pipe.build_luts()
+        pipe.run(U.dev(env))
+        sh.run(pipe.env_struct())
+        L = U.host(sh.radiance)[hit].astype(np.float64)
+        rel = np.abs(L - L64).sum() / np.abs(L64).sum()
+        lit = L64.sum(1) > 0
+        per_px = np.abs(L - L64).sum(1)[lit] / L64.sum(1)[lit]
+        errs[dt] = rel
+        U.log(f"  dtype {dt}: mean relative radiance error {rel:.3e}; per pixel: median {np.median(per_px):.2e}, "
+              f"99th percentile {np.percentile(per_px, 99):.2e}, exact {np.mean(per_px == 0):.3f}")
+        del pipe
+    assert errs[G.GLINT_F32] <= 1e-3
+    for dt in (G.GLINT_F16, G.GLINT_BF16, G.GLINT_UNORM16):
+        assert errs[dt] <= 1e-2
+
+
 def test_quantile_tail_table(ctx):
     """The tail table holds AS 241 of every tail uniform the hash can give
     (against the oracle's quantile), and shading with it is bit-identical to
@@ -559,23 +619,85 @@ def test_fast_gating_equals_exact_gating(ctx, vertices):
         U.shade(ctx, g, raw, rgb, lv, S, E, w.R, w.K, w.M, exact_gating=2)
 
 
+def _perturbed(a, ulps, rng):
+    """float32 values moved by up to `ulps` units in the last place each
+    (relative), at random."""
+    a = np.asarray(a, dtype=np.float32)
+    u = rng.uniform(-1.0, 1.0, a.shape) * ulps * 2.0 ** -23
+    return (a.astype(np.float64) * (1.0 + u)).astype(np.float32)
+
+
+def end_to_end(ctx, w, pixels, tag, runs=2):
+    """The GPU frame in the benchmark's launch configuration (EnvPipeline +
+    Shader, the GPU's own pyramid and LUTs) against the oracle run on its own
+    (its own partition, chain, pyramid and LUTs) on the given pixels.
+
+    The GPU pyramid lies within 10 ulp of the oracle's and the LUTs within 1
+    ulp, so where a count's integer part or a gating decision is that
+    sensitive the two may differ legitimately.  Such pixels are found by
+    re-running the oracle with its pyramid moved by up to 10 ulp and its S
+    table by 1 ulp at random (`runs` times): a pixel is stable when every
+    run gives its codes and integer counts.  Bar: on pixels the oracle does
+    not flag and that are stable, codes and integer parts of counts
+    bit-exact and radiance within 1e-3 relative; the other pixels are
+    counted and reported."""
+    import torch
+    from paper_2507_02674_amd.pipeline import EnvPipeline, Shader
+    env, g = w.env(), w.gbuf()
+    pipe = EnvPipeline(ctx, w.R, w.K, w.M, w.T)
+    pipe.build_luts()
+    pipe.run(U.dev(env))
+    sh = Shader(ctx, g, seed=w.hash_seed)
+    P, K = sh.P, w.K
+    dbg = dict(counts=torch.empty((P, 1, K), dtype=torch.float64, device="cuda"),
+               codes=torch.empty((P, 1, K - 1), dtype=torch.uint8, device="cuda"))
+    sh.run(pipe.env_struct(), debug=dbg)
+    gpu = dict(radiance=U.host(sh.radiance)[pixels], counts=U.host(dbg["counts"])[pixels],
+               codes=U.host(dbg["codes"])[pixels])
+    levels, ij, it = oracle.partition(env, K)
+    assert np.array_equal(levels, U.host(pipe.levels)) or np.allclose(levels, U.host(pipe.levels), rtol=1e-14)
+    chain = oracle.mipchain(env, ij, it, K, w.M)
+    ind, rgb = oracle.split_pyramid(oracle.prefilter(env, ij, it, chain, K, w.M, w.T), K)
+    S, E = oracle_luts()
+    orc = oracle.shade(g, ind, rgb, levels, S, E, w.R, K, w.M, w.hash_seed, 1, pixels=pixels)
+    rng = np.random.default_rng(17)
+    stable = np.ones(len(pixels), bool)
+    for _ in range(runs):
+        o2 = oracle.shade(g, _perturbed(ind, 10, rng), _perturbed(rgb, 10, rng), levels, _perturbed(S, 1, rng), E,
+                          w.R, K, w.M, w.hash_seed, 1, pixels=pixels)
+        stable &= np.all(o2["codes"] == orc["codes"], axis=(1, 2))
+        stable &= np.all(np.floor(o2["counts"]) == np.floor(orc["counts"]), axis=(1, 2))
+    unflagged = orc["flags"] == 0
+    same = np.all(gpu["codes"] == orc["codes"], axis=(1, 2)) & np.all(np.floor(gpu["counts"]) ==
+                                                                       np.floor(orc["counts"]), axis=(1, 2))
+    ok = unflagged & stable
+    rel = np.abs(gpu["radiance"].astype(np.float64) - orc["radiance"]) / np.maximum(np.abs(orc["radiance"]), 1e-30)
+    U.log(f"{tag}: {len(pixels)} px; oracle-flagged {(~unflagged).mean():.2e}; unstable under the 10-ulp "
+          f"pyramid band {(~stable).mean():.2e}; signature mismatch on unflagged px {(~same[unflagged]).mean():.2e}, "
+          f"on stable unflagged px {(~same[ok]).mean():.2e}; max rel radiance err on those {rel[ok].max():.2e}")
+    assert np.all(same[ok]), tag
+    assert np.all(rel[ok] <= 1e-3), tag
+    assert ok.mean() > 0.9, tag
+    return dict(flagged=(~unflagged).mean(), unstable=(~stable).mean(), mismatch_unflagged=(~same[unflagged]).mean())
+
+
 def test_end_to_end_tiny(ctx):
-    """GPU partition -> prefilter -> LUTs -> shade against the oracle run on its
-    own from the same map and G-buffer."""
+    """Every pixel of the tiny workload, GPU against the oracle run on its own."""
     w = synth.WORKLOADS["tiny"]
     U.log("end to end tiny")
-    env, g = w.env(), w.gbuf()
-    lv, ij, it = U.partition(ctx, env, w.K)
-    raw, rgb, _ = U.prefilter(ctx, env, ij, it, w.K, w.M, w.T)
-    S, E = U.luts(ctx)
-    gpu = U.shade(ctx, g, raw, rgb, lv, S, E, w.R, w.K, w.M, seed=w.hash_seed)
-    orc = oracle.frame(env, g, w.K, w.M, w.T, seed=w.hash_seed, lut=oracle_luts())
-    ok = orc["flags"] == 0
-    same_codes = np.all(gpu["codes"] == orc["codes"], axis=(1, 2))
-    assert same_codes[ok].mean() > 0.999
-    rel = np.abs(gpu["radiance"] - orc["radiance"]) / np.maximum(np.abs(orc["radiance"]), 1e-30)
-    good = ok & same_codes
-    assert np.all(rel[good] <= 1e-3)
+    g = w.gbuf()
+    end_to_end(ctx, w, np.arange(len(g["nx"])), "end to end tiny", runs=3)
+
+
+def test_end_to_end_frame_sampled(ctx):
+    """The frame workload (1920x1080, R = 256, K = 8), 20,000 sampled glint
+    pixels, GPU against the oracle run on its own."""
+    w = synth.WORKLOADS["frame"]
+    U.log("end to end frame, 20000 sampled pixels")
+    g = w.gbuf()
+    hit = np.nonzero(g["surf_id"] != synth.NO_SURFACE)[0]
+    pix = np.sort(np.random.default_rng(8).choice(hit, 20000, replace=False))
+    end_to_end(ctx, w, pix, "end to end frame")
 
 
 @pytest.mark.parametrize("dtype", [G.GLINT_F16, G.GLINT_BF16, G.GLINT_UNORM16])
