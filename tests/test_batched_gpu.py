@@ -161,3 +161,54 @@ def test_batched_two_argument_sets_share_one_workspace(ctx):
             torch.cuda.synchronize()
             for v, sh in enumerate(frame.shaders):
                 assert np.array_equal(U.host(sh.radiance), expect[v]), (rep, v)
+
+
+def test_batched_full_configuration_against_the_oracle(ctx):
+    """The full batched workload (64 views of 256^2 to 1920x1080 pixels, 4
+    maps 6x256x256 with K = 4, 8, 16, 8) in one graph launch, against the
+    oracle run on its own (its own partition, pyramid and LUTs per map) on
+    250 sampled glint pixels of every view.  Bar as for the single frame
+    end to end: radiance within 1e-3 relative on pixels the oracle does not
+    flag and whose outcome stays put when the oracle's pyramid moves by up
+    to 10 ulp (the GPU pyramid's distance from the oracle's)."""
+    import torch
+    from tests.test_parity_gpu import _perturbed, oracle_luts
+    import oracle
+    U.log("batched full configuration: synthesising 64 views")
+    views = synth.batched_views(64)
+    envs_np = [(synth.make_env(256, seed), K) for (seed, K) in synth.BATCHED_ENVS]
+    envs = [(torch.from_numpy(e).cuda(), K, 8, 64) for (e, K) in envs_np]
+    bf = BatchedFrame(ctx, envs, views)
+    bf.run()
+    bf.run()  # a replay
+    torch.cuda.synchronize()
+    U.log(f"  {bf.total_pixels} pixels shaded; oracle pyramids")
+    S, E = oracle_luts()
+    rng = np.random.default_rng(23)
+    orc_env = []
+    for (e, K) in envs_np:
+        lv, ij, it = oracle.partition(e, K)
+        chain = oracle.mipchain(e, ij, it, K, 8)
+        ind, rgb = oracle.split_pyramid(oracle.prefilter(e, ij, it, chain, K, 8, 64), K)
+        orc_env.append((lv, ind, rgb, K))
+    n_ok = n_all = 0
+    worst = 0.0
+    for v, (gb, ei, seed, V) in enumerate(views):
+        lv, ind, rgb, K = orc_env[ei]
+        hit = np.nonzero(gb["surf_id"] != synth.NO_SURFACE)[0]
+        pix = np.sort(rng.choice(hit, min(250, len(hit)), replace=False))
+        orc = oracle.shade(gb, ind, rgb, lv, S, E, 256, K, 8, seed, V, pixels=pix)
+        stable = orc["flags"] == 0
+        for _ in range(2):
+            o2 = oracle.shade(gb, _perturbed(ind, 10, rng), _perturbed(rgb, 10, rng), lv, _perturbed(S, 1, rng), E,
+                              256, K, 8, seed, V, pixels=pix)
+            stable &= np.all(o2["codes"] == orc["codes"], axis=(1, 2))
+            stable &= np.all(np.floor(o2["counts"]) == np.floor(orc["counts"]), axis=(1, 2))
+        got = U.host(bf.shaders[v].radiance)[pix].astype(np.float64)
+        rel = np.abs(got - orc["radiance"]) / np.maximum(np.abs(orc["radiance"]), 1e-30)
+        assert np.all(rel[stable] <= 1e-3), (v, rel[stable].max())
+        worst = max(worst, float(rel[stable].max()) if stable.any() else 0.0)
+        n_ok += int(stable.sum())
+        n_all += len(pix)
+    U.log(f"  {n_all} sampled pixels over 64 views, {n_ok} unflagged and stable, max rel radiance err {worst:.2e}")
+    assert n_ok > 0.95 * n_all
