@@ -83,6 +83,7 @@ def _declare(L):
     L.orc_footprint_grid.restype = C.c_int
     L.orc_sample_binomial.argtypes = [C.c_int, f64p, f64p, u32p, u32p, C.c_int64, f64p, f64p, u8p, u8p, C.c_int]
     L.orc_gate_probs.argtypes = [C.c_float, C.c_float, f32p]
+    L.orc_gate_probs_symmetric.argtypes = [C.c_float, C.c_float, C.c_float, f32p]
     L.orc_dual_gated.argtypes = [C.c_double, C.c_double, C.c_float, C.c_float, f64p, f64p, u8p]
     L.orc_multinomial.argtypes = [C.c_int, C.c_int, C.c_double, f64p, C.c_int, C.c_uint32, C.c_uint32, C.c_int32,
                                   C.c_int64, C.c_int64, f64p, u8p]
@@ -192,7 +193,7 @@ GBUF_FIELDS = ("nx", "ny", "nz", "vx", "vy", "vz", "u", "v", "area", "ax", "ay",
                "f0r", "f0g", "f0b", "surf_id")
 
 
-SAMPLERS = {"dual": 0, "single": 1, "single-floor": 2}
+SAMPLERS = {"dual": 0, "single": 1, "single-floor": 2, "dual-symmetric": 3}
 
 
 def shade(gbuf: dict, ind_pyr, rgb_pyr, levels, lut_S, lut_E, R: int, K: int, M: int, seed: int,
@@ -202,7 +203,9 @@ def shade(gbuf: dict, ind_pyr, rgb_pyr, levels, lut_S, lut_E, R: int, K: int, M:
 
     sampler: binomial approximation of every tree node, 0 dual-gated (Sec. 6
     Alg. "Dual-gated Gaussian"), 1 single-gated Eq. (gated), 2 the prior
-    single-gated form Eq. (oldgated).
+    single-gated form Eq. (oldgated), 3 dual-gated with the bias of
+    "Numeric Gating Issues" on both powers (the node's right-side
+    probability computed on its own).
     tree: shape of the hierarchical multinomial, 0 balanced binary tree,
     1 sequential chain (bin i against the bins after it).
     prob_mode 1: one reflection probability gamma for every facet (the
@@ -320,6 +323,14 @@ def gate_probs(N: float, p: float):
     out = np.zeros(4, np.float32)
     lib().orc_gate_probs(N, p, _p(out, C.c_float))
     return out  # P(n=N), P(n=1), P(nb=N), P(nb=1)
+
+
+def gate_probs_symmetric(N: float, p: float, q: float):
+    """Gating probabilities with the bias on both powers (q = 1 - p computed
+    on its own): P(n=N), P(n=1), P(nb=N), P(nb=1)."""
+    out = np.zeros(4, np.float32)
+    lib().orc_gate_probs_symmetric(N, p, q, _p(out, C.c_float))
+    return out
 
 
 def dual_gated(N: float, p: float, xi1: float, xi2: float):

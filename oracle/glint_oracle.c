@@ -733,7 +733,11 @@ typedef struct {
     float th_scale[4];/* magnitude of the terms behind each threshold */
 } gate_t;
 
-static void gate_probs(float Nf, float pf, gate_t *g)
+/* sym = 0: Alg. "Dual-gated Gaussian" as printed, where only the power
+ * (1-p)^N2 carries the bias.  sym = 1: the bias on both powers, P(n=N)
+ * taken as (1 - max(q, eps))^(N2 min(1, q/eps)) with q = 1 - p the other
+ * side's probability computed on its own (not as 1 - float(p)). */
+static void gate_probs(float Nf, float pf, float qf, int sym, gate_t *g)
 {
     const float eps = (float)EPS_GATE;
     float N2 = fmaxf(2.0f, Nf);
@@ -741,7 +745,7 @@ static void gate_probs(float Nf, float pf, gate_t *g)
     float cp = fmaxf(pf, eps);
     float ex = N2 * fminf(1.0f, pf / eps);
     float d1 = fmaxf(0.0f, 1.0f - fabsf(1.0f - Nf));
-    float pow_n = powf(pf, N2);
+    float pow_n = sym ? powf(1.0f - fmaxf(qf, eps), N2 * fminf(1.0f, qf / eps)) : powf(pf, N2);
     float pow_nb = powf(1.0f - cp, ex);
     g->P_nN = cN * pow_n;
     g->P_nbN = cN * pow_nb;
@@ -793,11 +797,12 @@ typedef struct {
 /* N_exact: N is computed exactly on every conforming implementation (the
  * root count N_P = density * area, an exact double product of two floats),
  * so its float rounding cannot differ. */
-static void dual_gated(double N, double p, float xi1, float xi2, int N_exact, int N_cont, node_out *o)
+static void dual_gated(double N, double p, double q, int sym, float xi1, float xi2, int N_exact, int N_cont,
+                       node_out *o)
 {
-    float Nf = (float)N, pf = (float)p;
+    float Nf = (float)N, pf = (float)p, qf = (float)q;
     gate_t g;
-    gate_probs(Nf, pf, &g);
+    gate_probs(Nf, pf, qf, sym, &g);
     int B_nN = xi1 < g.th[0];
     int B_n1N = xi1 < g.th[1];
     int B_nbN = g.th[2] <= xi1;
@@ -828,7 +833,8 @@ static void dual_gated(double N, double p, float xi1, float xi2, int N_exact, in
     o->n_cont = (B_nN && N2_cont) || (B_G && G_cont);
     o->nb_cont = (B_nbN && N2_cont) || (B_G && Gb_cont);
     o->code = (uint8_t)(B_nN | (B_n1N << 1) | (B_nbN << 2) | (B_nb1N << 3) | (B_G << 4));
-    o->flag = gate_band_flag(&g, xi1) | (round_flag(p) << 1) | ((!N_exact && round_flag(N)) << 2);
+    o->flag = gate_band_flag(&g, xi1) | ((round_flag(p) | (sym && round_flag(q))) << 1) |
+              ((!N_exact && round_flag(N)) << 2);
 }
 
 /* Sec. 6 paragraphs "Single-Gated Gaussians" and "Gating Generalization".
@@ -894,11 +900,13 @@ static void single_gated(int form, double N, double p, float xi1, float xi2, int
 }
 
 /* The binomial approximation selected by `sampler`: 0 dual-gated (Alg.
- * "Dual-gated Gaussian"), 1 single-gated Eq. (gated), 2 Eq. (oldgated). */
-static void sample_node(int sampler, double N, double p, float xi1, float xi2, int N_exact, int N_cont,
+ * "Dual-gated Gaussian"), 1 single-gated Eq. (gated), 2 Eq. (oldgated),
+ * 3 dual-gated with the bias on both powers (q: the negative side's
+ * probability, 1 - p in exact arithmetic). */
+static void sample_node(int sampler, double N, double p, double q, float xi1, float xi2, int N_exact, int N_cont,
                         node_out *o)
 {
-    if (sampler == 0) dual_gated(N, p, xi1, xi2, N_exact, N_cont, o);
+    if (sampler == 0 || sampler == 3) dual_gated(N, p, q, sampler == 3, xi1, xi2, N_exact, N_cont, o);
     else single_gated(sampler, N, p, xi1, xi2, N_exact, N_cont, o);
 }
 
@@ -933,10 +941,12 @@ static int multinomial_chain(int sampler, double NP, int root_exact, const doubl
     for (int i = 0; i < K - 1; ++i) {
         double pn = S[i] > 0.0 ? p[i] / S[i] : 0.0;
         if (pn > 1.0) pn = 1.0;
+        double qn = S[i] > 0.0 ? S[i + 1] / S[i] : 0.0; /* the bins after i */
+        if (qn > 1.0) qn = 1.0;
         float xi1, xi2;
         hash_xi_key(seed, surf, key, a, b, i, &xi1, &xi2);
         node_out o;
-        sample_node(sampler, N, pn, xi1, xi2, exact, cont, &o);
+        sample_node(sampler, N, pn, qn, xi1, xi2, exact, cont, &o);
         codes[i] = o.code;
         flag |= o.flag;
         M[i] = o.n;
@@ -975,10 +985,12 @@ static int multinomial(int sampler, int tree, double NP, int root_exact, const d
         double st = sl + sr;
         double pn = st > 0.0 ? sl / st : 0.0;
         if (pn > 1.0) pn = 1.0;
+        double qn = st > 0.0 ? sr / st : 0.0; /* the right child's share */
+        if (qn > 1.0) qn = 1.0;
         float xi1, xi2;
         hash_xi_key(seed, surf, key, a, b, i, &xi1, &xi2);
         node_out o;
-        sample_node(sampler, Nn[i], pn, xi1, xi2, exact[i], cont[i], &o);
+        sample_node(sampler, Nn[i], pn, qn, xi1, xi2, exact[i], cont[i], &o);
         codes[i] = o.code;
         flag |= o.flag;
         int c1 = 2 * i + 1, c2 = 2 * i + 2;
@@ -1256,7 +1268,7 @@ static int shade_impl(const float *const *gb, const float *ind_pyr, const float 
 {
     if (R < 1 || K < 2 || K > 16 || (K & (K - 1)) || M < 1 || (R >> (M - 1)) < 1 || (V != 1 && V != 6 && V != 12) ||
         (V == 12 && (!gb[20] || !gb[21] || !gb[22] || !gb[23])) ||
-        sampler < 0 || sampler > 2 || tree < 0 || tree > 1 || prob_mode < 0 || prob_mode > 1 ||
+        sampler < 0 || sampler > 3 || tree < 0 || tree > 1 || prob_mode < 0 || prob_mode > 1 ||
         (prob_mode == 1 && !(gamma > 0.0 && gamma <= 1.0)) ||
         !(lobe_taps == 0 || lobe_taps == 2 || lobe_taps == 4 || lobe_taps == 8) ||
         (lobe_taps && (!gb[17] || !gb[18] || !gb[19])))
@@ -1449,14 +1461,22 @@ int orc_shade_pixels_given_F(const float *const *gb, const double *F, const floa
 void orc_gate_probs(float N, float p, float *out4)
 {
     gate_t g;
-    gate_probs(N, p, &g);
+    gate_probs(N, p, 1.0f - p, 0, &g);
+    out4[0] = g.P_nN; out4[1] = g.P_n1; out4[2] = g.P_nbN; out4[3] = g.P_nb1;
+}
+
+/* The gating probabilities with the bias on both powers (q given). */
+void orc_gate_probs_symmetric(float N, float p, float q, float *out4)
+{
+    gate_t g;
+    gate_probs(N, p, q, 1, &g);
     out4[0] = g.P_nN; out4[1] = g.P_n1; out4[2] = g.P_nbN; out4[3] = g.P_nb1;
 }
 
 void orc_dual_gated(double N, double p, float xi1, float xi2, double *n, double *nb, uint8_t *code)
 {
     node_out o;
-    dual_gated(N, p, xi1, xi2, 0, 1, &o);
+    dual_gated(N, p, 1.0 - p, 0, xi1, xi2, 0, 1, &o);
     *n = o.n; *nb = o.nb; *code = o.code;
 }
 
@@ -1466,7 +1486,7 @@ void orc_dual_gated(double N, double p, float xi1, float xi2, double *n, double 
 int orc_multinomial(int sampler, int tree, double NP, const double *p, int K, uint32_t seed, uint32_t surf,
                     int32_t level, int64_t a, int64_t b, double *M, uint8_t *codes)
 {
-    if (sampler < 0 || sampler > 2 || tree < 0 || tree > 1 || K < 2 || K > 16 || (tree == 0 && (K & (K - 1))))
+    if (sampler < 0 || sampler > 3 || tree < 0 || tree > 1 || K < 2 || K > 16 || (tree == 0 && (K & (K - 1))))
         return -1;
     return multinomial(sampler, tree, NP, 1, p, K, seed, surf, ((uint32_t)level & 0xFFFFu) << 16, a, b, M, codes);
 }
@@ -1478,13 +1498,13 @@ int orc_multinomial(int sampler, int tree, double NP, const double *p, int K, ui
 int orc_sample_binomial(int sampler, const double *N, const double *p, const uint32_t *h1, const uint32_t *h2,
                         int64_t count, double *n, double *nb, uint8_t *code, uint8_t *flags, int threads)
 {
-    if (sampler < 0 || sampler > 2 || count < 0) return ORC_EINVAL;
+    if (sampler < 0 || sampler > 3 || count < 0) return ORC_EINVAL;
 #ifdef _OPENMP
 #pragma omp parallel for schedule(static) num_threads(threads > 0 ? threads : 1)
 #endif
     for (int64_t i = 0; i < count; ++i) {
         node_out o;
-        sample_node(sampler, N[i], p[i], to_unit(h1[i]), to_unit(h2[i]), 1, 0, &o);
+        sample_node(sampler, N[i], p[i], 1.0 - p[i], to_unit(h1[i]), to_unit(h2[i]), 1, 0, &o);
         n[i] = o.n;
         nb[i] = o.nb;
         code[i] = o.code;

@@ -228,3 +228,59 @@ def test_lattice_level_is_floor_of_half_log2_area():
         assert l0 == math.floor(lam) or (abs(lam - round(lam)) < 1e-12 and l0 in (round(lam) - 1, round(lam)))
         assert 0.0 <= frac <= 1.0
         assert abs((l0 + frac) - lam) < 1e-12 or frac in (0.0, 1.0)
+
+
+# --- the bias on both powers (sampler 3) ------------------------------------------
+
+def test_symmetric_gate_small_integer_N_is_exact_binomial():
+    """N in {0, 1, 2}: the same exact binomial outcomes as the dual gate."""
+    for N in (0.0, 1.0, 2.0):
+        for p in (0.0, 0.1, 0.5, 0.93, 1.0):
+            a = oracle.gate_probs(N, p)
+            b = oracle.gate_probs_symmetric(N, p, float(np.float32(1.0 - p)))
+            if N != 2.0:
+                np.testing.assert_array_equal(a, b)
+            else:  # P(n=2) = p^2 either way, within float rounding
+                assert abs(a[0] - b[0]) <= 2e-7 * max(a[0], 1e-30) + 1e-7 and np.array_equal(a[1:], b[1:])
+
+
+def test_symmetric_gate_fixes_the_mirrored_small_probability():
+    """When the node's negative side has a probability q below 2^-25, p = 1 - q
+    rounds to 1 in float: the printed algorithm then gives P(n = N) = p^N = 1
+    (no facet ever goes to the negative side, whatever N), while the exact
+    value is (1 - q)^N.  With the bias on that power too the error stays
+    within the paper's bound (about 1e-4 over N in [1, 1e16])."""
+    worst_sym = worst_lit = 0.0
+    for lq in np.arange(-16.0, -7.6, 0.25):
+        for lN in np.arange(0.5, 16.0, 0.5):
+            q, N = 10.0 ** lq, 10.0 ** lN
+            qf, Nf = float(np.float32(q)), float(np.float32(N))
+            exact = math.exp(Nf * math.log1p(-qf))
+            sym = float(oracle.gate_probs_symmetric(Nf, float(np.float32(1.0 - q)), qf)[0])
+            lit = float(oracle.gate_probs(Nf, float(np.float32(1.0 - q)))[0])
+            worst_sym = max(worst_sym, abs(sym - exact))
+            worst_lit = max(worst_lit, abs(lit - exact))
+    assert worst_sym <= 2e-4, worst_sym
+    assert worst_lit > 0.5, worst_lit  # e.g. q = 1e-9, N = 1e10: 1 instead of exp(-10)
+
+
+def test_symmetric_gate_negative_counts_follow_N_q():
+    """N = 1e10, q = 1e-9 (N q = 10 facets on the negative side): the printed
+    algorithm puts every facet on the positive side; with the bias on both
+    powers the Gaussian branch runs and the negative count N - G has the
+    mean 1 + (N - 2) q of Alg. "Dual-gated Gaussian" (G has mean
+    1 + (N - 2) p)."""
+    rng = np.random.default_rng(9)
+    m = 4000
+    N = np.full(m, 1e10)
+    q = 1e-9
+    p = np.full(m, 1.0 - q)
+    h1 = rng.integers(0, 2 ** 32, m, dtype=np.uint32)
+    h2 = rng.integers(0, 2 ** 32, m, dtype=np.uint32)
+    lit = oracle.sample_binomial(0, N, p, h1, h2)
+    sym = oracle.sample_binomial(3, N, p, h1, h2)
+    assert np.all(lit["nb"] == 0)
+    mean = sym["nb"].mean()
+    expect = 1.0 + (1e10 - 2.0) * q
+    assert abs(mean - expect) < 4 * math.sqrt(expect / m), mean
+    assert np.allclose(sym["n"] + sym["nb"], 1e10, rtol=1e-15)
