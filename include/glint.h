@@ -317,6 +317,16 @@ int glint_build_quantile_table(glint_ctx ctx, double *table, void *stream);
  *  GLINT_SAMPLER_SINGLE_FLOOR: Eq. (oldgated), the prior form: gate
  *    probability 1 - (1-p)^N without bias, floor of the same clamped
  *    Gaussian.
+ *  GLINT_SAMPLER_DUAL_SYMMETRIC: the dual gate with the bias of "Numeric
+ *    Gating Issues" on both powers: P(n = N) = (1 - max(q, eps))^(N2
+ *    min(1, q/eps)) with q the negative side's probability computed on its
+ *    own (here 1 - p in double; in shading the tree node's right share
+ *    S_right / S), instead of p^N2.  The printed algorithm biases only
+ *    (1 - p)^N2; in a multinomial tree the rare side of a node may be
+ *    either child (the bright bins sit on the right), and for q < 2^-25
+ *    float(p) = 1 makes p^N2 = 1: no facet ever reaches that side, however
+ *    large N.  This form keeps those draws within the paper's error
+ *    bound.
  * Single-gated forms return nbar = max(N - n, 0).  Gates are evaluated in
  * float (the decisions of powf thresholds; exact_gating = 1 evaluates powf
  * for every draw), the Gaussian (AS 241) in double.
@@ -329,6 +339,7 @@ int glint_build_quantile_table(glint_ctx ctx, double *table, void *stream);
 #define GLINT_SAMPLER_DUAL 0
 #define GLINT_SAMPLER_SINGLE 1
 #define GLINT_SAMPLER_SINGLE_FLOOR 2
+#define GLINT_SAMPLER_DUAL_SYMMETRIC 3
 int glint_sample_binomial(glint_ctx ctx, int sampler, int exact_gating, const double *N, const double *p,
                           const uint32_t *h1, const uint32_t *h2, int64_t count, const double *quantile_tail,
                           double *n, double *nbar, uint8_t *code, void *stream);
@@ -441,9 +452,9 @@ typedef struct glint_shade_params {
                          only within a safety margin of a threshold (same decisions); 1: always
                          powf (for verification) */
     int sampler;      /* binomial approximation at every tree node (see glint_sample_binomial):
-                         GLINT_SAMPLER_DUAL (the paper's method), GLINT_SAMPLER_SINGLE,
-                         GLINT_SAMPLER_SINGLE_FLOOR; the single-gated forms need a float32
-                         pyramid and are not available in glint_frame_batched
+                         GLINT_SAMPLER_DUAL (the paper's method), GLINT_SAMPLER_DUAL_SYMMETRIC,
+                         GLINT_SAMPLER_SINGLE, GLINT_SAMPLER_SINGLE_FLOOR; the single-gated forms
+                         need a float32 pyramid and are not available in glint_frame_batched
                          (GLINT_EUNSUPPORTED) */
     int prob_mode;    /* GLINT_PROBS_ENV: p_k from the map (the paper's method);
                          GLINT_PROBS_CONSTANT: every facet reflects with probability gamma,

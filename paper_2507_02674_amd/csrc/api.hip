@@ -340,13 +340,15 @@ int glint_prefilter(glint_ctx ctx, const float *env, const uint8_t *ind_j, const
                          "glint_prefilter launch");
 }
 
+static bool dual_sampler(int s) { return s == GLINT_SAMPLER_DUAL || s == GLINT_SAMPLER_DUAL_SYMMETRIC; }
+
 // view >= 0 names the batched view in the message
 static int check_shade_params(const glint_shade_params &sp, int view)
 {
     const char *what = nullptr;
     if (sp.vertices != 1 && sp.vertices != 6 && sp.vertices != 12) what = "vertices must be 1, 6 or 12";
     else if (sp.exact_gating != 0 && sp.exact_gating != 1) what = "exact_gating must be 0 or 1";
-    else if (sp.sampler < GLINT_SAMPLER_DUAL || sp.sampler > GLINT_SAMPLER_SINGLE_FLOOR) what = "unknown sampler";
+    else if (sp.sampler < GLINT_SAMPLER_DUAL || sp.sampler > GLINT_SAMPLER_DUAL_SYMMETRIC) what = "unknown sampler";
     else if (sp.prob_mode != GLINT_PROBS_ENV && sp.prob_mode != GLINT_PROBS_CONSTANT) what = "unknown prob_mode";
     else if (sp.prob_mode == GLINT_PROBS_CONSTANT && !(sp.gamma > 0.0f && sp.gamma <= 1.0f))
         what = "gamma must be in (0, 1]";
@@ -384,7 +386,7 @@ int glint_sample_binomial(glint_ctx ctx, int sampler, int exact_gating, const do
 {
     if (int rc = check_ctx(ctx)) return rc;
     glint::ProfScope prof_scope(&ctx->prof);
-    if (sampler < GLINT_SAMPLER_DUAL || sampler > GLINT_SAMPLER_SINGLE_FLOOR)
+    if (sampler < GLINT_SAMPLER_DUAL || sampler > GLINT_SAMPLER_DUAL_SYMMETRIC)
         return fail(GLINT_EINVAL, "unknown sampler %d", sampler);
     if (exact_gating != 0 && exact_gating != 1) return fail(GLINT_EINVAL, "exact_gating must be 0 or 1");
     if (count < 0 || count > ((int64_t)1 << 40)) return fail(GLINT_EINVAL, "bad count %lld", (long long)count);
@@ -408,17 +410,17 @@ int glint_shade(glint_ctx ctx, const glint_gbuffer *g, int64_t P, const glint_en
     if (int rc = check_dtype(env->dtype)) return rc;
     if (int rc = check_shade_params(*sp, -1)) return rc;
     const bool constant = sp->prob_mode == GLINT_PROBS_CONSTANT;
-    if (sp->sampler != GLINT_SAMPLER_DUAL && env->dtype != GLINT_F32 && !constant)
+    if (!dual_sampler(sp->sampler) && env->dtype != GLINT_F32 && !constant)
         return fail(GLINT_EUNSUPPORTED, "single-gated samplers need a float32 pyramid");
-    if (sp->lobe_taps > 0 && (env->dtype != GLINT_F32 || sp->sampler != GLINT_SAMPLER_DUAL || constant))
+    if (sp->lobe_taps > 0 && (env->dtype != GLINT_F32 || !dual_sampler(sp->sampler) || constant))
         return fail(GLINT_EUNSUPPORTED, "anisotropic lookups need a float32 pyramid, the dual gate and the map's "
                     "probabilities");
     if (sp->vertices == 12 &&
-        (env->dtype != GLINT_F32 || sp->sampler != GLINT_SAMPLER_DUAL || constant || sp->lobe_taps != 0))
+        (env->dtype != GLINT_F32 || !dual_sampler(sp->sampler) || constant || sp->lobe_taps != 0))
         return fail(GLINT_EUNSUPPORTED, "the footprint grid needs a float32 pyramid, the dual gate, the map's "
                     "probabilities and one lookup");
     if (sp->tree == GLINT_TREE_CHAIN &&
-        (env->dtype != GLINT_F32 || sp->sampler != GLINT_SAMPLER_DUAL || constant || sp->lobe_taps != 0 ||
+        (env->dtype != GLINT_F32 || !dual_sampler(sp->sampler) || constant || sp->lobe_taps != 0 ||
          sp->vertices == 12))
         return fail(GLINT_EUNSUPPORTED, "the sequential chain needs a float32 pyramid, the dual gate, the map's "
                     "probabilities, one lookup and 1 or 6 vertices");
@@ -686,7 +688,7 @@ int glint_frame_batched(glint_ctx ctx, const glint_env_task *envs, int n_env, co
         if (w.num_pixels < 0 || w.num_pixels > ((int64_t)1 << 40))
             return fail(GLINT_EINVAL, "view %d: bad num_pixels", v);
         if (int rc = check_shade_params(w.shade, v)) return rc;
-        if (w.shade.sampler != GLINT_SAMPLER_DUAL || w.shade.prob_mode != GLINT_PROBS_ENV || w.shade.lobe_taps != 0 ||
+        if (!dual_sampler(w.shade.sampler) || w.shade.prob_mode != GLINT_PROBS_ENV || w.shade.lobe_taps != 0 ||
             w.shade.vertices == 12 || w.shade.tree != GLINT_TREE_BALANCED)
             return fail(GLINT_EUNSUPPORTED, "view %d: batched frames use the dual-gated sampler, the balanced tree "
                         "and the map's probabilities with one lookup", v);

@@ -411,7 +411,10 @@ struct gate_f {
     float th_nb1N; // (1 - P(nbar = N)) - P(nbar = 1)
 };
 
-__device__ __forceinline__ gate_f gate_thresholds(float Nf, float pf)
+// sym: the bias also on the first power, P(n = N) = (1 - max(q, eps))^(N2
+// min(1, q/eps)) with q the negative side's probability computed on its own
+// (the printed algorithm takes p^N2, which float rounds to 1 when q < 2^-25).
+__device__ __forceinline__ gate_f gate_thresholds(float Nf, float pf, float qf, bool sym)
 {
 #pragma clang fp contract(off)
     const float eps = 2.8840315031266055e-04f; // 10^-3.54
@@ -420,7 +423,7 @@ __device__ __forceinline__ gate_f gate_thresholds(float Nf, float pf)
     const float cp = fmaxf(pf, eps);
     const float ex = N2 * fminf(1.0f, pf / eps);
     const float d1 = fmaxf(0.0f, 1.0f - fabsf(1.0f - Nf));
-    const float P_nN = cN * powf(pf, N2);
+    const float P_nN = cN * (sym ? powf(1.0f - fmaxf(qf, eps), N2 * fminf(1.0f, qf / eps)) : powf(pf, N2));
     const float P_nbN = cN * powf(1.0f - cp, ex);
     const float P_n1 = d1 * pf;
     const float P_nb1 = d1 * (1.0f - pf);
@@ -444,7 +447,8 @@ struct gate_d {
     bool nN, n1N, nbN, nb1N;
 };
 
-__device__ __forceinline__ gate_d gate_decide(float Nf, float pf, float xi1, bool exact_only = false)
+__device__ __forceinline__ gate_d gate_decide(float Nf, float pf, float qf, bool sym, float xi1,
+                                              bool exact_only = false)
 {
 #pragma clang fp contract(off)
     const float eps = 2.8840315031266055e-04f; // 10^-3.54
@@ -454,7 +458,9 @@ __device__ __forceinline__ gate_d gate_decide(float Nf, float pf, float xi1, boo
     const float ex = N2 * fminf(1.0f, pf / eps);
     const float d1 = fmaxf(0.0f, 1.0f - fabsf(1.0f - Nf));
     const float bN = 1.0f - cp;
-    const float P_nN = cN * __builtin_amdgcn_exp2f(N2 * __builtin_amdgcn_logf(pf));
+    const float bA = sym ? 1.0f - fmaxf(qf, eps) : pf;
+    const float eA = sym ? N2 * fminf(1.0f, qf / eps) : N2;
+    const float P_nN = cN * __builtin_amdgcn_exp2f(eA * __builtin_amdgcn_logf(bA));
     const float P_nbN = cN * __builtin_amdgcn_exp2f(ex * __builtin_amdgcn_logf(bN));
     const float P_n1 = d1 * pf;
     const float P_nb1 = d1 * (1.0f - pf);
@@ -471,7 +477,7 @@ __device__ __forceinline__ gate_d gate_decide(float Nf, float pf, float xi1, boo
         d.nbN = t_nbN <= xi1;
         d.nb1N = t_nb1N <= xi1;
     } else {
-        const gate_f g = gate_thresholds(Nf, pf);
+        const gate_f g = gate_thresholds(Nf, pf, qf, sym);
         d.nN = xi1 < g.th_nN;
         d.n1N = xi1 < g.th_n1N;
         d.nbN = g.th_nbN <= xi1;

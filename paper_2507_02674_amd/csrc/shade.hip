@@ -235,9 +235,9 @@ __device__ __forceinline__ void pyramid_trilinear(const Args &A, const d3 &dir, 
 // One dual-gated Gaussian draw (Alg. "Dual-gated Gaussian").
 // xi2 = (h9 + 1/2) 2^-23; qtail: the quantile's tail table (or null: the
 // tails are evaluated here).
-__device__ __forceinline__ void dual_gated(double N, double p, float xi1, float xi2, uint32_t h9,
-                                           const double *__restrict__ qtail, bool exact_gating, double &n,
-                                           double &nb, uint32_t &code)
+__device__ __forceinline__ void dual_gated(double N, double p, double q, bool sym, float xi1, float xi2,
+                                           uint32_t h9, const double *__restrict__ qtail, bool exact_gating,
+                                           double &n, double &nb, uint32_t &code)
 {
     // Rounded as written (no fused multiply-add): at N ~ 1e12 one ulp of mu
     // is ~1e-4, so every operation must round as in the definition for the
@@ -248,7 +248,7 @@ __device__ __forceinline__ void dual_gated(double N, double p, float xi1, float 
     const bool tail = tail_index(h9, tidx);
     double ztab = 0.0;
     if (qtail && tail) ztab = qtail[tidx];
-    const gate_d gd = gate_decide((float)N, (float)p, xi1, exact_gating);
+    const gate_d gd = gate_decide((float)N, (float)p, (float)q, sym, xi1, exact_gating);
     const bool BnN = gd.nN;
     const bool Bn1N = gd.n1N;
     const bool BnbN = gd.nbN;
@@ -305,13 +305,16 @@ __device__ __forceinline__ void single_gated(int form, double N, double p, float
 // SG: a single-gated form (`sampler` says which); else the dual gate.  A
 // compile-time switch, so the dual-gated kernels carry no trace of the
 // other forms (registers, code size).
+// q: the node's negative-side probability (1 - p in exact arithmetic),
+// used by GLINT_SAMPLER_DUAL_SYMMETRIC.
 template <bool SG>
-__device__ __forceinline__ void node_sample(int sampler, double N, double p, float xi1, float xi2, uint32_t h9,
-                                            const double *__restrict__ qtail, bool exact_gating, double &n,
-                                            double &nb, uint32_t &code)
+__device__ __forceinline__ void node_sample(int sampler, double N, double p, double q, float xi1, float xi2,
+                                            uint32_t h9, const double *__restrict__ qtail, bool exact_gating,
+                                            double &n, double &nb, uint32_t &code)
 {
     if constexpr (SG) single_gated(sampler, N, p, xi1, xi2, h9, qtail, exact_gating, n, nb, code);
-    else dual_gated(N, p, xi1, xi2, h9, qtail, exact_gating, n, nb, code);
+    else dual_gated(N, p, q, sampler == GLINT_SAMPLER_DUAL_SYMMETRIC, xi1, xi2, h9, qtail, exact_gating, n, nb,
+                    code);
 }
 
 // Hierarchical multinomial over K bins: balanced binary tree, nodes in
@@ -339,7 +342,7 @@ __device__ __forceinline__ void multinomial(double NP, const double (&p)[K], uin
 #pragma unroll
     for (int d = 0; (1 << d) < K; ++d) {
         const int nd = 1 << d, width = K >> d;
-        double P[K / 2]; // node probabilities of this depth, in node order
+        double P[K / 2], Qr[K / 2]; // node probabilities (left, right share) of this depth, in node order
 #pragma unroll
         for (int j = 0; j < nd; ++j) {
             const int lo = j * width, mid = lo + width / 2, hi = lo + width;
@@ -350,16 +353,18 @@ __device__ __forceinline__ void multinomial(double NP, const double (&p)[K], uin
             for (int k = mid; k < hi; ++k) sr += p[k];
             const double st = sl + sr;
             const double q = st > 0.0 ? sl / st : 0.0;
+            const double r = st > 0.0 ? sr / st : 0.0;
             P[j] = q > 1.0 ? 1.0 : q;
+            Qr[j] = r > 1.0 ? 1.0 : r;
         }
         double Rq[K];
 #pragma unroll
         for (int k = 0; k < K; ++k) Rq[k] = 0.0;
 #pragma unroll 1
         for (int j = 0; j < nd; ++j) {
-            const double N = Q[0], pj = P[0];
+            const double N = Q[0], pj = P[0], qj = Qr[0];
 #pragma unroll
-            for (int k = 0; k + 1 < nd; ++k) { Q[k] = Q[k + 1]; P[k] = P[k + 1]; }
+            for (int k = 0; k + 1 < nd; ++k) { Q[k] = Q[k + 1]; P[k] = P[k + 1]; Qr[k] = Qr[k + 1]; }
             const int node = nd - 1 + j;
             uint32_t hx, hy;
             if ((node & 1) == 0) {
@@ -375,7 +380,8 @@ __device__ __forceinline__ void multinomial(double NP, const double (&p)[K], uin
             }
             double n, nb;
             uint32_t code;
-            node_sample<SG>(sampler, N, pj, hash_unit(hx), hash_unit(hy), hy >> 9, qtail, exact_gating, n, nb, code);
+            node_sample<SG>(sampler, N, pj, qj, hash_unit(hx), hash_unit(hy), hy >> 9, qtail, exact_gating, n, nb,
+                            code);
             if (codes) codes[node] = (uint8_t)code;
 #pragma unroll
             for (int k = 0; k + 2 < 2 * nd; ++k) Rq[k] = Rq[k + 2];
@@ -405,11 +411,13 @@ __device__ __forceinline__ void multinomial_chain(double NP, const double (&p)[K
     S[K - 1] = p[K - 1];
 #pragma unroll
     for (int k = K - 2; k >= 0; --k) S[k] = p[k] + S[k + 1];
-    double P[K - 1];
+    double P[K - 1], Qr[K - 1]; // bin k's share of S_k and that of the bins after it
 #pragma unroll
     for (int k = 0; k < K - 1; ++k) {
         const double q = S[k] > 0.0 ? p[k] / S[k] : 0.0;
+        const double r = S[k] > 0.0 ? S[k + 1] / S[k] : 0.0;
         P[k] = q > 1.0 ? 1.0 : q;
+        Qr[k] = r > 1.0 ? 1.0 : r;
     }
     double Mq[K];
 #pragma unroll
@@ -418,9 +426,9 @@ __device__ __forceinline__ void multinomial_chain(double NP, const double (&p)[K
     uint32_t carry_z = 0, carry_w = 0;
 #pragma unroll 1
     for (int node = 0; node < K - 1; ++node) {
-        const double pj = P[0];
+        const double pj = P[0], qj = Qr[0];
 #pragma unroll
-        for (int k = 0; k + 1 < K - 1; ++k) P[k] = P[k + 1];
+        for (int k = 0; k + 1 < K - 1; ++k) { P[k] = P[k + 1]; Qr[k] = Qr[k + 1]; }
         uint32_t hx, hy;
         if ((node & 1) == 0) {
             const u4 h = pcg4d({(uint32_t)a, (uint32_t)b, key | ((uint32_t)node >> 1), seed_mix});
@@ -434,7 +442,7 @@ __device__ __forceinline__ void multinomial_chain(double NP, const double (&p)[K
         }
         double n, nb;
         uint32_t code;
-        node_sample<SG>(sampler, N, pj, hash_unit(hx), hash_unit(hy), hy >> 9, qtail, exact_gating, n, nb, code);
+        node_sample<SG>(sampler, N, pj, qj, hash_unit(hx), hash_unit(hy), hy >> 9, qtail, exact_gating, n, nb, code);
         if (codes) codes[node] = (uint8_t)code;
 #pragma unroll
         for (int k = 0; k + 1 < K; ++k) Mq[k] = Mq[k + 1];
@@ -815,7 +823,7 @@ static hipError_t launch_shade_kd(const ShadeArgs &a, int V, hipStream_t stream)
         }
         return hipErrorInvalidValue;
     }
-    if (a.sampler != GLINT_SAMPLER_DUAL) {
+    if (a.sampler == GLINT_SAMPLER_SINGLE || a.sampler == GLINT_SAMPLER_SINGLE_FLOOR) {
         // single-gated forms: float32 pyramids only (the API checks)
         if constexpr (DT == 0) {
             if (V == 1)
@@ -946,7 +954,7 @@ hipError_t launch_shade(const glint_gbuffer &g, int64_t P, const glint_env &env,
     if (sp.prob_mode == GLINT_PROBS_CONSTANT) {
         // two bins, indicator pyramid not read
         const unsigned blocks = (unsigned)((P + kShadeThreads - 1) / kShadeThreads);
-        const bool sg = sp.sampler != GLINT_SAMPLER_DUAL;
+        const bool sg = sp.sampler == GLINT_SAMPLER_SINGLE || sp.sampler == GLINT_SAMPLER_SINGLE_FLOOR;
         if (V == 1 && !sg)
             GLINT_LAUNCH("k_shade", (k_shade<2, 0, 1, false, false, true>), dim3(blocks), dim3(kShadeThreads), 0,
                          stream, a);
@@ -966,7 +974,7 @@ hipError_t launch_shade(const glint_gbuffer &g, int64_t P, const glint_env &env,
         const unsigned blocks = (unsigned)((P + kShadeThreads - 1) / kShadeThreads);
 #define GLINT_SF(KK)                                                                                        \
     if (K == KK) {                                                                                          \
-        if (sp.sampler != GLINT_SAMPLER_DUAL) {                                                             \
+        if (sp.sampler == GLINT_SAMPLER_SINGLE || sp.sampler == GLINT_SAMPLER_SINGLE_FLOOR) {               \
             if (V == 1)                                                                                     \
                 GLINT_LAUNCH("k_shade_surrogate", (k_shade<KK, 0, 1, true, true>), dim3(blocks),            \
                              dim3(kShadeThreads), 0, stream, a);                                            \
@@ -1013,12 +1021,12 @@ __global__ void __launch_bounds__(256) k_sample_binomial(int sampler, int exact_
     const uint32_t b = h2[i];
     double a, c;
     uint32_t cd;
-    if (sampler == GLINT_SAMPLER_DUAL)
-        node_sample<false>(sampler, N[i], p[i], hash_unit(h1[i]), hash_unit(b), b >> 9, qtail, exact_gating != 0, a, c,
-                           cd);
+    if (sampler == GLINT_SAMPLER_DUAL || sampler == GLINT_SAMPLER_DUAL_SYMMETRIC)
+        node_sample<false>(sampler, N[i], p[i], 1.0 - p[i], hash_unit(h1[i]), hash_unit(b), b >> 9, qtail,
+                           exact_gating != 0, a, c, cd);
     else
-        node_sample<true>(sampler, N[i], p[i], hash_unit(h1[i]), hash_unit(b), b >> 9, qtail, exact_gating != 0, a, c,
-                          cd);
+        node_sample<true>(sampler, N[i], p[i], 1.0 - p[i], hash_unit(h1[i]), hash_unit(b), b >> 9, qtail,
+                          exact_gating != 0, a, c, cd);
     n[i] = a;
     nb[i] = c;
     code[i] = (uint8_t)cd;

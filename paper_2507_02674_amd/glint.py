@@ -14,7 +14,7 @@ from . import build as _build
 
 GLINT_OK, GLINT_EINVAL, GLINT_EUNSUPPORTED, GLINT_EDEVICE, GLINT_ENOMEM, GLINT_ENOTTRAINED = 0, 1, 2, 3, 4, 5
 GLINT_F32, GLINT_F16, GLINT_BF16, GLINT_UNORM16 = 0, 1, 2, 3
-GLINT_SAMPLER_DUAL, GLINT_SAMPLER_SINGLE, GLINT_SAMPLER_SINGLE_FLOOR = 0, 1, 2
+GLINT_SAMPLER_DUAL, GLINT_SAMPLER_SINGLE, GLINT_SAMPLER_SINGLE_FLOOR, GLINT_SAMPLER_DUAL_SYMMETRIC = 0, 1, 2, 3
 GLINT_PROBS_ENV, GLINT_PROBS_CONSTANT = 0, 1
 GLINT_TREE_BALANCED, GLINT_TREE_CHAIN = 0, 1
 GLINT_NO_SURFACE = 0xFFFFFFFF

@@ -69,6 +69,53 @@ def uniform_env(R: int, value: float = 1.0) -> np.ndarray:
     return np.full((6, R, R, 3), value, np.float32)
 
 
+def disc_env(R: int, lights, background: float = 0.05) -> np.ndarray:
+    """Grey map of constant background luminance with constant-luminance
+    discs: lights = [(elevation_deg, azimuth_deg, radius_deg, luminance)];
+    a texel belongs to the first disc containing its centre direction."""
+    d = _face_dirs(R)
+    env = np.full(d.shape[:3], background, np.float64)
+    done = np.zeros(d.shape[:3], bool)
+    for (el, az, rad, lum) in lights:
+        e, a = math.radians(el), math.radians(az)
+        c = np.array([math.cos(e) * math.sin(a), math.sin(e), math.cos(e) * math.cos(a)])
+        inside = (d @ c >= math.cos(math.radians(rad))) & ~done
+        env[inside] = lum
+        done |= inside
+    return np.ascontiguousarray(np.repeat(env[..., None], 3, axis=-1).astype(np.float32))
+
+
+def sweep_plane(elevations_deg, np_rows, alpha: float, azimuth_deg: float = 0.0, area: float = 1e-4,
+                f0: float = 0.9) -> dict:
+    """A flat surface (normal +y) seen so that column c reflects towards
+    elevation elevations_deg[c] (azimuth azimuth_deg) and row r holds
+    np_rows[r] facets per footprint; isotropic roughness alpha, footprint
+    area `area`, uv spaced so that every pixel draws at its own lattice
+    vertex."""
+    el = np.radians(np.asarray(elevations_deg, np.float64))
+    NP = np.asarray(np_rows, np.float64)
+    W, H = len(el), len(NP)
+    a = math.radians(azimuth_deg)
+    wr = np.stack([np.cos(el) * math.sin(a), np.sin(el), np.cos(el) * math.cos(a)], -1)  # [W,3]
+    n = np.array([0.0, 1.0, 0.0])
+    v = 2.0 * (wr @ n)[:, None] * n[None] - wr
+    P = W * H
+    g = _empty_gbuf(P)
+    cols = np.tile(np.arange(W), H)
+    rows = np.repeat(np.arange(H), W)
+    g["nx"][:], g["ny"][:], g["nz"][:] = 0.0, 1.0, 0.0
+    g["vx"][:], g["vy"][:], g["vz"][:] = v[cols, 0], v[cols, 1], v[cols, 2]
+    step = 4.0 * math.sqrt(area)  # a few lattice spacings apart
+    g["u"][:], g["v"][:] = cols * step, rows * step
+    g["area"][:] = area
+    g["ax"][:] = alpha
+    g["ay"][:] = alpha
+    g["density"][:] = NP[rows] / area
+    g["f0r"][:] = g["f0g"][:] = g["f0b"][:] = f0
+    g["surf_id"][:] = 3
+    return _finish(g)
+
+
 # --- value noise ---------------------------------------------------------------
 
 def _splitmix64(x: np.ndarray) -> np.ndarray:

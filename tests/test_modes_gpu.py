@@ -16,7 +16,8 @@ from tests import gpu_util as U
 
 pytestmark = pytest.mark.gpu
 
-SAMPLERS = [G.GLINT_SAMPLER_DUAL, G.GLINT_SAMPLER_SINGLE, G.GLINT_SAMPLER_SINGLE_FLOOR]
+SAMPLERS = [G.GLINT_SAMPLER_DUAL, G.GLINT_SAMPLER_SINGLE, G.GLINT_SAMPLER_SINGLE_FLOOR,
+            G.GLINT_SAMPLER_DUAL_SYMMETRIC]
 
 
 @pytest.fixture(scope="module")
@@ -49,6 +50,8 @@ def inputs(m, seed):
     p = rng.random(m)
     tiny = rng.random(m) < 0.15
     p[tiny] = 10.0 ** rng.uniform(-14, -3, tiny.sum())
+    near1 = rng.random(m) < 0.1  # the other side tiny (the symmetric bias's case)
+    p[near1] = 1.0 - 10.0 ** rng.uniform(-14, -3, near1.sum())
     p[rng.random(m) < 0.02] = 0.0
     p[rng.random(m) < 0.02] = 1.0
     h1 = rng.integers(0, 2 ** 32, m, dtype=np.uint32)
@@ -85,7 +88,10 @@ def test_sample_binomial_matches_oracle(ctx, qtail, sampler, with_table):
     N, p, h1, h2 = inputs(200_003, 11 + sampler)
     gpu = gpu_draw(ctx, sampler, N, p, h1, h2, qtail if with_table else None)
     orc = oracle.sample_binomial(sampler, N, p, h1, h2)
-    check_draws(gpu, orc, f"sampler {sampler}")
+    # the prior form's floor makes near-integer values decisions (flagged)
+    # most often where p is near 1 and the count near N
+    check_draws(gpu, orc, f"sampler {sampler}",
+                max_flagged=5e-3 if sampler == G.GLINT_SAMPLER_SINGLE_FLOOR else 1e-3)
 
 
 @pytest.mark.parametrize("sampler", SAMPLERS)
@@ -96,7 +102,8 @@ def test_sample_binomial_exact_gating_path(ctx, qtail, sampler):
     a = gpu_draw(ctx, sampler, N, p, h1, h2, qtail, exact_gating=1)
     b = gpu_draw(ctx, sampler, N, p, h1, h2, qtail, exact_gating=0)
     orc = oracle.sample_binomial(sampler, N, p, h1, h2)
-    check_draws(a, orc, f"exact gating sampler {sampler}")
+    check_draws(a, orc, f"exact gating sampler {sampler}",
+                max_flagged=5e-3 if sampler == G.GLINT_SAMPLER_SINGLE_FLOOR else 1e-3)
     for k in ("n", "nb", "code"):
         assert np.array_equal(a[k], b[k]), k
 
@@ -113,7 +120,7 @@ def test_sample_binomial_edge_sizes_and_errors(ctx):
     w = torch.zeros(4, dtype=torch.int32, device="cuda")
     c = torch.zeros(4, dtype=torch.uint8, device="cuda")
     with pytest.raises(G.GlintError) as e:
-        G.glint_sample_binomial(ctx, 3, t, t, w, w, t, t, c)
+        G.glint_sample_binomial(ctx, 4, t, t, w, w, t, t, c)
     assert e.value.code == G.GLINT_EINVAL
 
 
@@ -173,6 +180,27 @@ def test_shade_with_single_gated_sampler(ctx, qtail, sampler, vertices):
                   sampler=sampler)
     orc = oracle.shade(g, ind, rgb, levels, S, E, R, K, M, 7, vertices, sampler=sampler)
     check_pixels(gpu, orc, f"sampler={sampler} V={vertices}")
+
+
+@pytest.mark.parametrize("vertices", [1, 6])
+def test_shade_with_symmetric_dual_gate(ctx, qtail, vertices):
+    """GLINT_SAMPLER_DUAL_SYMMETRIC in the tree (right shares S_right / S
+    passed to every node) against the oracle, on a 16-bit pyramid too."""
+    R, K, M = 16, 8, 5
+    U.log(f"shade symmetric dual gate V={vertices}")
+    env = synth.make_env(R, 6)
+    levels, ind, rgb = oracle_env(env, K, M)
+    S, E = oracle.lut_tables()
+    g = synth.scene_frame(96, 54, seed=3, density_decades=(-1.0, 11.0))
+    gpu = U.shade(ctx, g, ind, rgb, levels, S, E, R, K, M, seed=7, vertices=vertices, qtail=qtail,
+                  sampler=G.GLINT_SAMPLER_DUAL_SYMMETRIC)
+    orc = oracle.shade(g, ind, rgb, levels, S, E, R, K, M, 7, vertices, sampler=3)
+    check_pixels(gpu, orc, f"dual symmetric V={vertices}")
+    raw16 = U.encode(ind, G.GLINT_F16)
+    gpu16 = U.shade(ctx, g, raw16, rgb, levels, S, E, R, K, M, dtype=G.GLINT_F16, seed=7, vertices=vertices,
+                    qtail=qtail, sampler=G.GLINT_SAMPLER_DUAL_SYMMETRIC)
+    orc16 = oracle.shade(g, U.decode(raw16, G.GLINT_F16), rgb, levels, S, E, R, K, M, 7, vertices, sampler=3)
+    check_pixels(gpu16, orc16, f"dual symmetric f16 V={vertices}")
 
 
 def test_single_gated_sampler_needs_f32_pyramid(ctx):
