@@ -454,8 +454,8 @@ typedef struct glint_shade_params {
     int sampler;      /* binomial approximation at every tree node (see glint_sample_binomial):
                          GLINT_SAMPLER_DUAL (the paper's method), GLINT_SAMPLER_DUAL_SYMMETRIC,
                          GLINT_SAMPLER_SINGLE, GLINT_SAMPLER_SINGLE_FLOOR; the single-gated forms
-                         need a float32 pyramid and are not available in glint_frame_batched
-                         (GLINT_EUNSUPPORTED) */
+                         need a float32 pyramid; glint_frame_batched runs GLINT_SAMPLER_DUAL only
+                         (GLINT_EUNSUPPORTED for the others) */
     int prob_mode;    /* GLINT_PROBS_ENV: p_k from the map (the paper's method);
                          GLINT_PROBS_CONSTANT: every facet reflects with probability gamma,
                          independent of the map (the comparison of Sec. 7) */
@@ -593,7 +593,10 @@ size_t glint_batched_workspace_bytes(int n_views);
 /* GLINT_EINVAL for null pointers, n_env outside 1..64, n_views outside
  * 1..4096, an env_index out of range, or any per-environment or per-view
  * argument glint_partition_env / glint_prefilter / glint_shade would
- * reject.  All environments in one call share one pyramid dtype. */
+ * reject; GLINT_EUNSUPPORTED for a view whose shading parameters ask for
+ * another sampler than GLINT_SAMPLER_DUAL, constant probabilities, the
+ * anisotropic lookup, the footprint grid or the sequential chain.  All
+ * environments in one call share one pyramid dtype. */
 int glint_frame_batched(glint_ctx ctx, const glint_env_task *envs, int n_env, const glint_view *views,
                         int n_views, void *workspace, void *stream);
 

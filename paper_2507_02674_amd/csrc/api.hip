@@ -688,8 +688,8 @@ int glint_frame_batched(glint_ctx ctx, const glint_env_task *envs, int n_env, co
         if (w.num_pixels < 0 || w.num_pixels > ((int64_t)1 << 40))
             return fail(GLINT_EINVAL, "view %d: bad num_pixels", v);
         if (int rc = check_shade_params(w.shade, v)) return rc;
-        if (!dual_sampler(w.shade.sampler) || w.shade.prob_mode != GLINT_PROBS_ENV || w.shade.lobe_taps != 0 ||
-            w.shade.vertices == 12 || w.shade.tree != GLINT_TREE_BALANCED)
+        if (w.shade.sampler != GLINT_SAMPLER_DUAL || w.shade.prob_mode != GLINT_PROBS_ENV ||
+            w.shade.lobe_taps != 0 || w.shade.vertices == 12 || w.shade.tree != GLINT_TREE_BALANCED)
             return fail(GLINT_EUNSUPPORTED, "view %d: batched frames use the dual-gated sampler, the balanced tree "
                         "and the map's probabilities with one lookup", v);
         if (!w.radiance) return fail(GLINT_EINVAL, "view %d: null radiance", v);

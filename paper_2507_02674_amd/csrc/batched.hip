@@ -272,13 +272,13 @@ hipError_t frame_batched(BatchedCache &c, const glint_env_task *envs, int n_env,
     }
     err = hipStreamEndCapture(cs, &graph);
     if (cap != hipSuccess) {
-        if (graph) hipGraphDestroy(graph);
+        if (graph) (void)hipGraphDestroy(graph);
         return cap;
     }
     if (err != hipSuccess) return err;
     hipGraphExec_t exec = nullptr;
     err = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    hipGraphDestroy(graph);
+    (void)hipGraphDestroy(graph);
     if (err != hipSuccess) return err;
     if (c.graphs.size() >= 16) { // bounded cache: drop one entry
         (void)hipGraphExecDestroy(c.graphs.begin()->second.exec);

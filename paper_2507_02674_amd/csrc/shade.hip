@@ -302,19 +302,22 @@ __device__ __forceinline__ void single_gated(int form, double N, double p, float
     code = (uint32_t)hit | ((uint32_t)BG << 4);
 }
 
-// SG: a single-gated form (`sampler` says which); else the dual gate.  A
-// compile-time switch, so the dual-gated kernels carry no trace of the
-// other forms (registers, code size).
+// SG: a single-gated form (`sampler` says which); else the dual gate, with
+// the bias on both powers when SYM (GLINT_SAMPLER_DUAL_SYMMETRIC).  Both are
+// compile-time switches, so each kernel carries only its own form: a
+// runtime choice between the two dual forms keeps the right shares of a
+// whole tree depth live and costs the default kernel a third of its
+// occupancy (236 instead of 166 registers).
 // q: the node's negative-side probability (1 - p in exact arithmetic),
-// used by GLINT_SAMPLER_DUAL_SYMMETRIC.
-template <bool SG>
+// read only when SYM.
+template <bool SG, bool SYM = false>
 __device__ __forceinline__ void node_sample(int sampler, double N, double p, double q, float xi1, float xi2,
                                             uint32_t h9, const double *__restrict__ qtail, bool exact_gating,
                                             double &n, double &nb, uint32_t &code)
 {
+    static_assert(!(SG && SYM), "the symmetric bias is a form of the dual gate");
     if constexpr (SG) single_gated(sampler, N, p, xi1, xi2, h9, qtail, exact_gating, n, nb, code);
-    else dual_gated(N, p, q, sampler == GLINT_SAMPLER_DUAL_SYMMETRIC, xi1, xi2, h9, qtail, exact_gating, n, nb,
-                    code);
+    else dual_gated(N, p, q, SYM, xi1, xi2, h9, qtail, exact_gating, n, nb, code);
 }
 
 // Hierarchical multinomial over K bins: balanced binary tree, nodes in
@@ -327,7 +330,7 @@ __device__ __forceinline__ void node_sample(int sampler, double N, double p, dou
 // its inputs from the front of small register queues and appends the two
 // child counts at the back, shifting with static indices, so no register
 // array is indexed dynamically.
-template <int K, bool SG>
+template <int K, bool SG, bool SYM>
 __device__ __forceinline__ void multinomial(double NP, const double (&p)[K], uint32_t seed_mix, uint32_t key, int64_t a,
                                             int64_t b, const double *__restrict__ qtail, bool exact_gating,
                                             int sampler, double (&leaf)[K], uint8_t *codes)
@@ -353,9 +356,13 @@ __device__ __forceinline__ void multinomial(double NP, const double (&p)[K], uin
             for (int k = mid; k < hi; ++k) sr += p[k];
             const double st = sl + sr;
             const double q = st > 0.0 ? sl / st : 0.0;
-            const double r = st > 0.0 ? sr / st : 0.0;
             P[j] = q > 1.0 ? 1.0 : q;
-            Qr[j] = r > 1.0 ? 1.0 : r;
+            if constexpr (SYM) {
+                const double r = st > 0.0 ? sr / st : 0.0;
+                Qr[j] = r > 1.0 ? 1.0 : r;
+            } else {
+                Qr[j] = 0.0;
+            }
         }
         double Rq[K];
 #pragma unroll
@@ -380,8 +387,8 @@ __device__ __forceinline__ void multinomial(double NP, const double (&p)[K], uin
             }
             double n, nb;
             uint32_t code;
-            node_sample<SG>(sampler, N, pj, qj, hash_unit(hx), hash_unit(hy), hy >> 9, qtail, exact_gating, n, nb,
-                            code);
+            node_sample<SG, SYM>(sampler, N, pj, qj, hash_unit(hx), hash_unit(hy), hy >> 9, qtail, exact_gating, n,
+                                 nb, code);
             if (codes) codes[node] = (uint8_t)code;
 #pragma unroll
             for (int k = 0; k + 2 < 2 * nd; ++k) Rq[k] = Rq[k + 2];
@@ -402,7 +409,7 @@ __device__ __forceinline__ void multinomial(double NP, const double (&p)[K], uin
 // reaches it.  One copy of the sampler in a loop that is not unrolled; the
 // node probabilities and the bins' counts move through register queues with
 // static indices.
-template <int K, bool SG>
+template <int K, bool SG, bool SYM>
 __device__ __forceinline__ void multinomial_chain(double NP, const double (&p)[K], uint32_t seed_mix, uint32_t key,
                                                   int64_t a, int64_t b, const double *__restrict__ qtail,
                                                   bool exact_gating, int sampler, double (&leaf)[K], uint8_t *codes)
@@ -415,9 +422,13 @@ __device__ __forceinline__ void multinomial_chain(double NP, const double (&p)[K
 #pragma unroll
     for (int k = 0; k < K - 1; ++k) {
         const double q = S[k] > 0.0 ? p[k] / S[k] : 0.0;
-        const double r = S[k] > 0.0 ? S[k + 1] / S[k] : 0.0;
         P[k] = q > 1.0 ? 1.0 : q;
-        Qr[k] = r > 1.0 ? 1.0 : r;
+        if constexpr (SYM) {
+            const double r = S[k] > 0.0 ? S[k + 1] / S[k] : 0.0;
+            Qr[k] = r > 1.0 ? 1.0 : r;
+        } else {
+            Qr[k] = 0.0;
+        }
     }
     double Mq[K];
 #pragma unroll
@@ -442,7 +453,8 @@ __device__ __forceinline__ void multinomial_chain(double NP, const double (&p)[K
         }
         double n, nb;
         uint32_t code;
-        node_sample<SG>(sampler, N, pj, qj, hash_unit(hx), hash_unit(hy), hy >> 9, qtail, exact_gating, n, nb, code);
+        node_sample<SG, SYM>(sampler, N, pj, qj, hash_unit(hx), hash_unit(hy), hy >> 9, qtail, exact_gating, n, nb,
+                             code);
         if (codes) codes[node] = (uint8_t)code;
 #pragma unroll
         for (int k = 0; k + 1 < K; ++k) Mq[k] = Mq[k + 1];
@@ -525,7 +537,7 @@ __device__ __forceinline__ FootGrid footprint_grid(double j00, double j01, doubl
 // and only RGB is read from the pyramid.  PC: constant reflection
 // probability A.gamma (K = 2, levels (0, 1)), no indicator lookup.
 template <int K, int DT, int V, bool SURR = false, bool SG = false, bool PC = false, bool AN = false,
-          bool CH = false, class Args = ShadeArgs>
+          bool CH = false, bool SYM = false, class Args = ShadeArgs>
 __device__ __forceinline__ void shade_pixel(const Args &A, int64_t i)
 {
     static_assert(!PC || (K == 2 && !SURR), "constant probabilities use two bins");
@@ -731,10 +743,10 @@ __device__ __forceinline__ void shade_pixel(const Args &A, int64_t i)
         double Mv[K];
         uint8_t *cod = A.codes ? (uint8_t *)A.codes + (i * V + vi) * (K - 1) : nullptr;
         if constexpr (CH)
-            multinomial_chain<K, SG>(Nv, p, seed_mix, key, a, b, (const double *)A.qtail, A.exact_gating != 0,
+            multinomial_chain<K, SG, SYM>(Nv, p, seed_mix, key, a, b, (const double *)A.qtail, A.exact_gating != 0,
                                      A.sampler, Mv, cod);
         else
-            multinomial<K, SG>(Nv, p, seed_mix, key, a, b, (const double *)A.qtail, A.exact_gating != 0, A.sampler,
+            multinomial<K, SG, SYM>(Nv, p, seed_mix, key, a, b, (const double *)A.qtail, A.exact_gating != 0, A.sampler,
                                Mv, cod);
 #pragma unroll
         for (int k = 0; k < K; ++k) Msum[k] += w * Mv[k];
@@ -762,12 +774,12 @@ __device__ __forceinline__ void shade_pixel(const Args &A, int64_t i)
 // The footprint grid and the anisotropic lookup carry more state per lane;
 // asking for two waves per SIMD keeps them at <= 256 registers.
 template <int K, int DT, int V, bool SURR = false, bool SG = false, bool PC = false, bool AN = false,
-          bool CH = false>
+          bool CH = false, bool SYM = false>
 __global__ void __launch_bounds__(kShadeThreads, (V == 12 || AN) ? 2 : 1) k_shade(ShadeArgs A)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= A.P) return;
-    shade_pixel<K, DT, V, SURR, SG, PC, AN, CH>(A, i);
+    shade_pixel<K, DT, V, SURR, SG, PC, AN, CH, SYM>(A, i);
 }
 
 // All views of one (K, V) group in one launch: block b shades tile b of the
@@ -795,17 +807,20 @@ __global__ void __launch_bounds__(kShadeThreads, 1) k_shade_views(const ShadeArg
     const ShadeArgsG A = reinterpret_cast<const ShadeArgsG *>(views)[__builtin_amdgcn_readfirstlane(s_view)];
     const int64_t i = (b - tile0[s_view]) * blockDim.x + threadIdx.x;
     if (i >= A.P) return;
-    shade_pixel<K, DT, V, SURR, false, false, false, false, ShadeArgsG>(A, i);
+    shade_pixel<K, DT, V, SURR, false, false, false, false, false, ShadeArgsG>(A, i);
 }
 
-template <int K, int DT>
+// SYM: the dual gate with the bias on both powers (the sampler decides
+// which instantiation runs; the single-gated kernels exist once, SYM false).
+template <int K, int DT, bool SYM>
 static hipError_t launch_shade_kd(const ShadeArgs &a, int V, hipStream_t stream)
 {
     const unsigned blocks = (unsigned)((a.P + kShadeThreads - 1) / kShadeThreads);
     if (V == 12) {
         // footprint grid: float32 pyramid, dual gate, one lookup (the API checks)
         if constexpr (DT == 0) {
-            GLINT_LAUNCH("k_shade", (k_shade<K, 0, 12>), dim3(blocks), dim3(kShadeThreads), 0, stream, a);
+            GLINT_LAUNCH("k_shade", (k_shade<K, 0, 12, false, false, false, false, false, SYM>), dim3(blocks),
+                         dim3(kShadeThreads), 0, stream, a);
             return hipGetLastError();
         }
         return hipErrorInvalidValue;
@@ -814,10 +829,10 @@ static hipError_t launch_shade_kd(const ShadeArgs &a, int V, hipStream_t stream)
         // anisotropic lookups: float32 pyramid, dual gate (the API checks)
         if constexpr (DT == 0) {
             if (V == 1)
-                GLINT_LAUNCH("k_shade", (k_shade<K, 0, 1, false, false, false, true>), dim3(blocks),
+                GLINT_LAUNCH("k_shade", (k_shade<K, 0, 1, false, false, false, true, false, SYM>), dim3(blocks),
                              dim3(kShadeThreads), 0, stream, a);
             else
-                GLINT_LAUNCH("k_shade", (k_shade<K, 0, 6, false, false, false, true>), dim3(blocks),
+                GLINT_LAUNCH("k_shade", (k_shade<K, 0, 6, false, false, false, true, false, SYM>), dim3(blocks),
                              dim3(kShadeThreads), 0, stream, a);
             return hipGetLastError();
         }
@@ -825,7 +840,7 @@ static hipError_t launch_shade_kd(const ShadeArgs &a, int V, hipStream_t stream)
     }
     if (a.sampler == GLINT_SAMPLER_SINGLE || a.sampler == GLINT_SAMPLER_SINGLE_FLOOR) {
         // single-gated forms: float32 pyramids only (the API checks)
-        if constexpr (DT == 0) {
+        if constexpr (DT == 0 && !SYM) {
             if (V == 1)
                 GLINT_LAUNCH("k_shade", (k_shade<K, 0, 1, false, true>), dim3(blocks), dim3(kShadeThreads), 0, stream, a);
             else
@@ -834,8 +849,12 @@ static hipError_t launch_shade_kd(const ShadeArgs &a, int V, hipStream_t stream)
         }
         return hipErrorInvalidValue;
     }
-    if (V == 1) GLINT_LAUNCH("k_shade", (k_shade<K, DT, 1>), dim3(blocks), dim3(kShadeThreads), 0, stream, a);
-    else GLINT_LAUNCH("k_shade", (k_shade<K, DT, 6>), dim3(blocks), dim3(kShadeThreads), 0, stream, a);
+    if (V == 1)
+        GLINT_LAUNCH("k_shade", (k_shade<K, DT, 1, false, false, false, false, false, SYM>), dim3(blocks),
+                     dim3(kShadeThreads), 0, stream, a);
+    else
+        GLINT_LAUNCH("k_shade", (k_shade<K, DT, 6, false, false, false, false, false, SYM>), dim3(blocks),
+                     dim3(kShadeThreads), 0, stream, a);
     return hipGetLastError();
 }
 
@@ -930,18 +949,25 @@ hipError_t launch_shade(const glint_gbuffer &g, int64_t P, const glint_env &env,
     a.gamma = (double)sp.gamma;
     a.lobe_taps = sp.lobe_taps;
     const int K = env.K, DT = (int)env.dtype, V = sp.vertices;
+    const bool sym = sp.sampler == GLINT_SAMPLER_DUAL_SYMMETRIC;
     if (sp.tree == GLINT_TREE_CHAIN) {
         // sequential chain: float32 pyramid, dual gate, map probabilities, one
         // lookup, 1 or 6 vertices (the API checks)
         const unsigned blocks = (unsigned)((P + kShadeThreads - 1) / kShadeThreads);
 #define GLINT_CH(KK)                                                                                         \
     if (K == KK) {                                                                                           \
-        if (V == 1)                                                                                          \
+        if (V == 1 && !sym)                                                                                  \
             GLINT_LAUNCH("k_shade", (k_shade<KK, 0, 1, false, false, false, false, true>), dim3(blocks),     \
                          dim3(kShadeThreads), 0, stream, a);                                                 \
-        else                                                                                                 \
+        else if (V == 1)                                                                                     \
+            GLINT_LAUNCH("k_shade", (k_shade<KK, 0, 1, false, false, false, false, true, true>),             \
+                         dim3(blocks), dim3(kShadeThreads), 0, stream, a);                                   \
+        else if (!sym)                                                                                       \
             GLINT_LAUNCH("k_shade", (k_shade<KK, 0, 6, false, false, false, false, true>), dim3(blocks),     \
                          dim3(kShadeThreads), 0, stream, a);                                                 \
+        else                                                                                                 \
+            GLINT_LAUNCH("k_shade", (k_shade<KK, 0, 6, false, false, false, false, true, true>),             \
+                         dim3(blocks), dim3(kShadeThreads), 0, stream, a);                                   \
         return hipGetLastError();                                                                            \
     }
         GLINT_CH(2)
@@ -955,7 +981,13 @@ hipError_t launch_shade(const glint_gbuffer &g, int64_t P, const glint_env &env,
         // two bins, indicator pyramid not read
         const unsigned blocks = (unsigned)((P + kShadeThreads - 1) / kShadeThreads);
         const bool sg = sp.sampler == GLINT_SAMPLER_SINGLE || sp.sampler == GLINT_SAMPLER_SINGLE_FLOOR;
-        if (V == 1 && !sg)
+        if (V == 1 && sym)
+            GLINT_LAUNCH("k_shade", (k_shade<2, 0, 1, false, false, true, false, false, true>), dim3(blocks),
+                         dim3(kShadeThreads), 0, stream, a);
+        else if (V != 1 && sym)
+            GLINT_LAUNCH("k_shade", (k_shade<2, 0, 6, false, false, true, false, false, true>), dim3(blocks),
+                         dim3(kShadeThreads), 0, stream, a);
+        else if (V == 1 && !sg)
             GLINT_LAUNCH("k_shade", (k_shade<2, 0, 1, false, false, true>), dim3(blocks), dim3(kShadeThreads), 0,
                          stream, a);
         else if (V == 1)
@@ -981,7 +1013,13 @@ hipError_t launch_shade(const glint_gbuffer &g, int64_t P, const glint_env &env,
             else                                                                                            \
                 GLINT_LAUNCH("k_shade_surrogate", (k_shade<KK, 0, 6, true, true>), dim3(blocks),            \
                              dim3(kShadeThreads), 0, stream, a);                                            \
-        } else if (V == 1)                                                                                  \
+        } else if (sym && V == 1)                                                                           \
+            GLINT_LAUNCH("k_shade_surrogate", (k_shade<KK, 0, 1, true, false, false, false, false, true>),  \
+                         dim3(blocks), dim3(kShadeThreads), 0, stream, a);                                  \
+        else if (sym)                                                                                       \
+            GLINT_LAUNCH("k_shade_surrogate", (k_shade<KK, 0, 6, true, false, false, false, false, true>),  \
+                         dim3(blocks), dim3(kShadeThreads), 0, stream, a);                                  \
+        else if (V == 1)                                                                                    \
             GLINT_LAUNCH("k_shade_surrogate", (k_shade<KK, 0, 1, true>), dim3(blocks), dim3(kShadeThreads), \
                          0, stream, a);                                                                     \
         else                                                                                                \
@@ -997,7 +1035,8 @@ hipError_t launch_shade(const glint_gbuffer &g, int64_t P, const glint_env &env,
         return hipErrorInvalidValue;
     }
 #define GLINT_SH(KK, DD)                                                                                     \
-    if (K == KK && DT == DD) return launch_shade_kd<KK, DD>(a, V, stream);
+    if (K == KK && DT == DD)                                                                                 \
+        return sym ? launch_shade_kd<KK, DD, true>(a, V, stream) : launch_shade_kd<KK, DD, false>(a, V, stream);
 #define GLINT_SH_K(KK) GLINT_SH(KK, 0) GLINT_SH(KK, 1) GLINT_SH(KK, 2) GLINT_SH(KK, 3)
     GLINT_SH_K(2)
     GLINT_SH_K(4)
@@ -1021,9 +1060,12 @@ __global__ void __launch_bounds__(256) k_sample_binomial(int sampler, int exact_
     const uint32_t b = h2[i];
     double a, c;
     uint32_t cd;
-    if (sampler == GLINT_SAMPLER_DUAL || sampler == GLINT_SAMPLER_DUAL_SYMMETRIC)
+    if (sampler == GLINT_SAMPLER_DUAL)
         node_sample<false>(sampler, N[i], p[i], 1.0 - p[i], hash_unit(h1[i]), hash_unit(b), b >> 9, qtail,
                            exact_gating != 0, a, c, cd);
+    else if (sampler == GLINT_SAMPLER_DUAL_SYMMETRIC)
+        node_sample<false, true>(sampler, N[i], p[i], 1.0 - p[i], hash_unit(h1[i]), hash_unit(b), b >> 9, qtail,
+                                 exact_gating != 0, a, c, cd);
     else
         node_sample<true>(sampler, N[i], p[i], 1.0 - p[i], hash_unit(h1[i]), hash_unit(b), b >> 9, qtail,
                           exact_gating != 0, a, c, cd);

@@ -94,6 +94,15 @@ def test_batched_rejects_bad_arguments(ctx):
         G.glint_frame_batched(ctx, [bf.tasks[0], odd], bf.view_structs, bf.ws)
     with pytest.raises(G.GlintError):
         G.glint_frame_batched(ctx, bf.tasks, [], bf.ws)
+    # the batched graph runs the paper's dual gate only
+    for sampler in (G.GLINT_SAMPLER_DUAL_SYMMETRIC, G.GLINT_SAMPLER_SINGLE):
+        sp = type(bf.view_structs[0].shade).from_buffer_copy(bf.view_structs[0].shade)
+        sp.sampler = sampler
+        v0 = bf.view_structs[0]
+        other = G.View(v0.gbuf, v0.num_pixels, v0.env_index, sp, v0.radiance, None)
+        with pytest.raises(G.GlintError) as e:
+            G.glint_frame_batched(ctx, bf.tasks, [other], bf.ws)
+        assert e.value.code == G.GLINT_EUNSUPPORTED, sampler
 
 
 def test_batched_surrogate_form_equals_per_call_path(ctx):
