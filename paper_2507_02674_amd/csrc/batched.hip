@@ -118,14 +118,14 @@ size_t batched_workspace_bytes(int n_views)
 BatchedCache::~BatchedCache()
 {
     for (auto &kv : graphs) {
-        if (kv.second.exec) hipGraphExecDestroy(kv.second.exec);
+        if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
     }
     for (int i = 0; i < kSideStreams; ++i) {
-        if (side[i]) hipStreamDestroy(side[i]);
+        if (side[i]) (void)hipStreamDestroy(side[i]);
     }
-    if (capture) hipStreamDestroy(capture);
-    if (fork) hipEventDestroy(fork);
-    for (auto &ev : joins) hipEventDestroy(ev);
+    if (capture) (void)hipStreamDestroy(capture);
+    if (fork) (void)hipEventDestroy(fork);
+    for (auto &ev : joins) (void)hipEventDestroy(ev);
 }
 
 static hipError_t ensure_streams(BatchedCache &c, int n_env)
@@ -206,9 +206,18 @@ hipError_t frame_batched(BatchedCache &c, const glint_env_task *envs, int n_env,
         if ((err = launch_env(envs[e], stream)) != hipSuccess) return err;
     }
     // autotune the tile size per group (cached per K, dtype, V, size class)
-    hipEvent_t t0, t1;
-    if ((err = hipEventCreate(&t0)) != hipSuccess) return err;
-    if ((err = hipEventCreate(&t1)) != hipSuccess) return err;
+    // the timing events live until this scope ends, on every return path
+    struct TimingEvents {
+        hipEvent_t e[2] = {nullptr, nullptr};
+        ~TimingEvents()
+        {
+            for (hipEvent_t x : e)
+                if (x) (void)hipEventDestroy(x);
+        }
+    } tev;
+    if ((err = hipEventCreate(&tev.e[0])) != hipSuccess) return err;
+    if ((err = hipEventCreate(&tev.e[1])) != hipSuccess) return err;
+    hipEvent_t t0 = tev.e[0], t1 = tev.e[1];
     int64_t biggest = -1;
     for (auto &g : groups) {
         int64_t px_total = 0;
@@ -227,12 +236,12 @@ hipError_t frame_batched(BatchedCache &c, const glint_env_task *envs, int n_env,
                 if ((err = upload_group(g, envs, views, px, workspace, stream)) != hipSuccess) return err;
                 float ms_sum = 0.0f;
                 for (int rep = 0; rep < 3; ++rep) {
-                    hipEventRecord(t0, stream);
+                    if ((err = hipEventRecord(t0, stream)) != hipSuccess) return err;
                     if ((err = launch_group(g, dtype, workspace, stream)) != hipSuccess) return err;
-                    hipEventRecord(t1, stream);
+                    if ((err = hipEventRecord(t1, stream)) != hipSuccess) return err;
                     if ((err = hipEventSynchronize(t1)) != hipSuccess) return err;
                     float ms = 0.0f;
-                    hipEventElapsedTime(&ms, t0, t1);
+                    if ((err = hipEventElapsedTime(&ms, t0, t1)) != hipSuccess) return err;
                     if (rep > 0) ms_sum += ms; // first repetition warms caches
                 }
                 if (ms_sum < best) {
@@ -249,8 +258,6 @@ hipError_t frame_batched(BatchedCache &c, const glint_env_task *envs, int n_env,
             c.last_tile_px = g.tile_px;
         }
     }
-    hipEventDestroy(t0);
-    hipEventDestroy(t1);
 
     // capture on the context's own stream (the caller's may be the legacy
     // NULL stream, which cannot be captured): fork per environment, join,
