@@ -544,8 +544,11 @@ int glint_shade_given_F(glint_ctx ctx, const glint_gbuffer *gbuf, int64_t num_pi
  * form, size class) in the context, uploads the view descriptors into
  * `workspace`, and captures the frame into a HIP graph: one branch per
  * environment on the context's side streams (the maps are filtered
- * concurrently), joined before one shading launch per (K, vertices,
- * plain/surrogate) group that covers all views of the group.  The set-up
+ * concurrently) and one shading launch per (K, vertices, plain/surrogate)
+ * group, covering all views of the group, on a branch of its own that
+ * waits only for the environments those views are lit by (a group's
+ * shading overlaps the filtering of the other maps and the other groups'
+ * shading).  The set-up
  * call synchronises the stream and lets the HIP runtime allocate graph
  * objects.  Later calls with the same arguments enqueue exactly one
  * hipGraphLaunch and allocate nothing.  A workspace holds the descriptors of

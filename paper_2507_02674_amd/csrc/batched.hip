@@ -3,9 +3,11 @@
 // Set-up (first call per argument set): validate, upload per-view shading
 // descriptors and per-group tile tables into the caller's workspace, time
 // the shading launch for each candidate tile size, then capture the frame:
-// one fork per environment onto the context's side streams (partition ->
-// source chain -> prefilter), joined on the caller's stream before one
-// shading launch per (K, vertices) group.  Replays: one hipGraphLaunch.
+// one branch per environment on the context's side streams (partition ->
+// source chain -> prefilter) and one branch per (K, vertices, form) shading
+// group on the group streams, each group waiting only for the environments
+// its views are lit by, all joined on the capture stream.  Replays: one
+// hipGraphLaunch.
 #include <stdio.h>
 #include <string.h>
 
@@ -123,16 +125,27 @@ BatchedCache::~BatchedCache()
     for (int i = 0; i < kSideStreams; ++i) {
         if (side[i]) (void)hipStreamDestroy(side[i]);
     }
+    for (int i = 0; i < kGroupStreams; ++i) {
+        if (gside[i]) (void)hipStreamDestroy(gside[i]);
+    }
     if (capture) (void)hipStreamDestroy(capture);
     if (fork) (void)hipEventDestroy(fork);
     for (auto &ev : joins) (void)hipEventDestroy(ev);
+    for (auto &ev : gdone) (void)hipEventDestroy(ev);
 }
 
-static hipError_t ensure_streams(BatchedCache &c, int n_env)
+// Streams once per context; events grow to n_env environment joins and
+// n_groups group completions (the capture indexes each vector only below
+// its size, checked there).
+static hipError_t ensure_streams(BatchedCache &c, int n_env, int n_groups)
 {
     if (!c.side[0]) {
         for (int i = 0; i < BatchedCache::kSideStreams; ++i) {
             hipError_t err = hipStreamCreateWithFlags(&c.side[i], hipStreamNonBlocking);
+            if (err != hipSuccess) return err;
+        }
+        for (int i = 0; i < BatchedCache::kGroupStreams; ++i) {
+            hipError_t err = hipStreamCreateWithFlags(&c.gside[i], hipStreamNonBlocking);
             if (err != hipSuccess) return err;
         }
         hipError_t e2 = hipStreamCreateWithFlags(&c.capture, hipStreamNonBlocking);
@@ -145,6 +158,12 @@ static hipError_t ensure_streams(BatchedCache &c, int n_env)
         hipError_t err = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
         if (err != hipSuccess) return err;
         c.joins.push_back(ev);
+    }
+    while ((int)c.gdone.size() < n_groups) {
+        hipEvent_t ev;
+        hipError_t err = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (err != hipSuccess) return err;
+        c.gdone.push_back(ev);
     }
     return hipSuccess;
 }
@@ -160,8 +179,7 @@ hipError_t frame_batched(BatchedCache &c, const glint_env_task *envs, int n_env,
     auto it = c.graphs.find(key);
     if (it != c.graphs.end()) return hipGraphLaunch(it->second.exec, stream);
 
-    hipError_t err = ensure_streams(c, n_env);
-    if (err != hipSuccess) return err;
+    hipError_t err;
     const int dtype = (int)envs[0].prefilter.dtype;
 
     // A graph reads its descriptors and tile tables from the workspace, where
@@ -193,6 +211,7 @@ hipError_t frame_batched(BatchedCache &c, const glint_env_task *envs, int n_env,
         }
         g->views.push_back(v);
     }
+    if ((err = ensure_streams(c, n_env, (int)groups.size())) != hipSuccess) return err;
     size_t off = 0;
     for (auto &g : groups) {
         g.desc_off = off;
@@ -260,8 +279,11 @@ hipError_t frame_batched(BatchedCache &c, const glint_env_task *envs, int n_env,
     }
 
     // capture on the context's own stream (the caller's may be the legacy
-    // NULL stream, which cannot be captured): fork per environment, join,
-    // shade groups.  The graph is then launched on the caller's stream.
+    // NULL stream, which cannot be captured): a branch per environment, a
+    // branch per shading group after the environments it reads, all joined
+    // on the capture stream.  The graph is then launched on the caller's
+    // stream.
+    if ((int)c.joins.size() < n_env || (int)c.gdone.size() < (int)groups.size()) return hipErrorInvalidValue;
     hipGraph_t graph = nullptr;
     hipStream_t cs = c.capture;
     if ((err = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal)) != hipSuccess) return err;
@@ -271,12 +293,26 @@ hipError_t frame_batched(BatchedCache &c, const glint_env_task *envs, int n_env,
         cap = hipStreamWaitEvent(s, c.fork, 0);
         if (cap == hipSuccess) cap = launch_env(envs[e], s);
         if (cap == hipSuccess) cap = hipEventRecord(c.joins[e], s);
-        if (cap == hipSuccess) cap = hipStreamWaitEvent(cs, c.joins[e], 0);
     }
-    for (auto &g : groups) {
-        if (cap == hipSuccess) cap = launch_lookups(g, envs, views, cs);
-        if (cap == hipSuccess) cap = launch_group(g, dtype, workspace, cs);
+    for (size_t gi = 0; gi < groups.size() && cap == hipSuccess; ++gi) {
+        const Group &g = groups[gi];
+        hipStream_t s = c.gside[gi % BatchedCache::kGroupStreams];
+        std::vector<char> needs(n_env, 0);
+        for (int vi : g.views) {
+            const int e = views[vi].env_index;
+            if (e < 0 || e >= n_env) { cap = hipErrorInvalidValue; break; }
+            needs[e] = 1;
+        }
+        if (cap == hipSuccess) cap = hipStreamWaitEvent(s, c.fork, 0);
+        for (int e = 0; e < n_env && cap == hipSuccess; ++e)
+            if (needs[e]) cap = hipStreamWaitEvent(s, c.joins[e], 0);
+        if (cap == hipSuccess) cap = launch_lookups(g, envs, views, s);
+        if (cap == hipSuccess) cap = launch_group(g, dtype, workspace, s);
+        if (cap == hipSuccess) cap = hipEventRecord(c.gdone[gi], s);
     }
+    // every branch rejoins the capture stream (environments no view reads too)
+    for (int e = 0; e < n_env && cap == hipSuccess; ++e) cap = hipStreamWaitEvent(cs, c.joins[e], 0);
+    for (size_t gi = 0; gi < groups.size() && cap == hipSuccess; ++gi) cap = hipStreamWaitEvent(cs, c.gdone[gi], 0);
     err = hipStreamEndCapture(cs, &graph);
     if (cap != hipSuccess) {
         if (graph) (void)hipGraphDestroy(graph);
