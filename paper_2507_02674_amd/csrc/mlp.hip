@@ -32,6 +32,15 @@ constexpr int kLdW1 = 24, kLdX = 40, kLdH = 72, kLdO = 40;
 constexpr int sW1 = 0, sW2 = sW1 + kH * kLdW1, sW3 = sW2 + kH * kLdH, sW4 = sW3 + kH * kLdH,
               kWLds = sW4 + kOut * kLdH; // bf16 weights staged in LDS (no biases)
 
+// Biases staged in LDS by the inference kernels: b1, b2, b3 (64 each), b4 (32).
+constexpr int kBiasLds = 3 * kH + kOut;
+// Offset from b1 in the parameter layout of staged bias c (b1, b2, b3 and
+// b4 are separated by the weight matrices).
+__device__ __forceinline__ int bias_src(int c)
+{
+    return c < kH ? c : (c < 2 * kH ? (ob2 - ob1) + (c - kH) : (c < 3 * kH ? (ob3 - ob1) + (c - 2 * kH) : (ob4 - ob1) + (c - 3 * kH)));
+}
+
 constexpr int kInferWaves = 4;     // waves per block of the inference kernels
 constexpr int kInferMaxBlocks = 768; // one round at 3 blocks per CU (256 CUs)
 
@@ -540,11 +549,15 @@ __global__ void __launch_bounds__(64 * kInferWaves) k_mlp_infer(InferInput in, i
                                                                 float *__restrict__ out)
 {
     __shared__ __attribute__((aligned(16))) uint16_t s_w[kWLds];
+    __shared__ __attribute__((aligned(16))) float s_b[kBiasLds];
     __shared__ __attribute__((aligned(16))) InferTile s_t[kInferWaves];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     InferTile &t = s_t[wave];
     stage_weights(wb, s_w);
-    __syncthreads(); // the staged weights are shared by the block's waves
+    // the biases too: read from global memory they are 28 16-byte loads per
+    // lane and tile through the vector-memory path (the kernel's bound)
+    for (int c = threadIdx.x; c < kBiasLds; c += blockDim.x) s_b[c] = w[ob1 + bias_src(c)];
+    __syncthreads(); // the staged weights and biases are shared by the block's waves
     const uint16_t *W1 = s_w + sW1, *W2 = s_w + sW2, *W3 = s_w + sW3, *W4 = s_w + sW4;
     const int64_t tiles = (B + 31) / 32;
     const int64_t stride = (int64_t)gridDim.x * kInferWaves;
@@ -576,17 +589,17 @@ __global__ void __launch_bounds__(64 * kInferWaves) k_mlp_infer(InferInput in, i
         // network
         const bool active = __ballot(needed) != 0;
         wave_lds_sync();
-        if (active) dense_silu_inplace(t.h, kIn, W1, kLdW1, w + ob1);
+        if (active) dense_silu_inplace(t.h, kIn, W1, kLdW1, s_b);
         wave_lds_sync();
-        if (active) dense_silu_inplace(t.h, kH, W2, kLdH, w + ob2);
+        if (active) dense_silu_inplace(t.h, kH, W2, kLdH, s_b + kH);
         wave_lds_sync();
-        if (active) dense_silu_inplace(t.h, kH, W3, kLdH, w + ob3);
+        if (active) dense_silu_inplace(t.h, kH, W3, kLdH, s_b + 2 * kH);
         wave_lds_sync();
         float logit[16], y[16];
 #pragma unroll
         for (int j = 0; j < 16; ++j) y[j] = 0.0f;
         if (active) {
-            dense_out(t.h, W4, w + ob4, logit);
+            dense_out(t.h, W4, s_b + 3 * kH, logit);
             softmax_pair(logit, K, y);
         }
         const int64_t i = row0 + (lane & 31);
