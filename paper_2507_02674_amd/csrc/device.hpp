@@ -201,6 +201,77 @@ __device__ __forceinline__ int64_t reproject_edge(int face, int x, int y, int n)
     return ((int64_t)m.f2 * n + b) * n + a;
 }
 
+// The 24 edge maps packed 9 bits each, seven to a 64-bit word (f2: 3 bits,
+// a1 + 1: 2, an: 1, b1 + 1: 2, bn: 1), so a lane can decode its map from
+// four constants without a memory access.
+struct EdgeWords {
+    unsigned long long w[4];
+};
+
+constexpr EdgeWords pack_edge_maps()
+{
+    EdgeWords p{};
+    for (int i = 0; i < 24; ++i) {
+        const EdgeMap m = kEdgeMaps.m[i];
+        const unsigned long long v = (unsigned long long)m.f2 | (unsigned long long)(m.a1 + 1) << 3 |
+                                     (unsigned long long)m.an << 5 | (unsigned long long)(m.b1 + 1) << 6 |
+                                     (unsigned long long)m.bn << 8;
+        p.w[i / 7] |= v << (9 * (i % 7));
+    }
+    return p;
+}
+
+constexpr EdgeWords kEdgeWords = pack_edge_maps();
+
+constexpr bool edge_words_consistent()
+{
+    for (int i = 0; i < 24; ++i) {
+        const unsigned v = (unsigned)(kEdgeWords.w[i / 7] >> (9 * (i % 7))) & 511u;
+        const EdgeMap m = kEdgeMaps.m[i];
+        if ((int)(v & 7u) != m.f2 || (int)((v >> 3) & 3u) - 1 != m.a1 || (int)((v >> 5) & 1u) != m.an ||
+            (int)((v >> 6) & 3u) - 1 != m.b1 || (int)((v >> 8) & 1u) != m.bn)
+            return false;
+    }
+    return true;
+}
+static_assert(edge_words_consistent(), "edge map packing lost a field");
+
+// reproject_edge in 32-bit arithmetic with the maps decoded from kEdgeWords.
+__device__ __forceinline__ int reproject_edge_alu(int face, int x, int y, int n)
+{
+    const int e = x < 0 ? 0 : (x >= n ? 1 : (y < 0 ? 2 : 3));
+    const int i = e <= 1 ? y : x;
+    const int id = 4 * face + e, wi = id / 7;
+    const unsigned long long w = wi == 0 ? kEdgeWords.w[0]
+                                         : (wi == 1 ? kEdgeWords.w[1] : (wi == 2 ? kEdgeWords.w[2] : kEdgeWords.w[3]));
+    const unsigned v = (unsigned)(w >> (9 * (id - 7 * wi))) & 511u;
+    const int f2 = (int)(v & 7u), a1 = (int)((v >> 3) & 3u) - 1, an = (int)((v >> 5) & 1u);
+    const int b1 = (int)((v >> 6) & 3u) - 1, bn = (int)((v >> 8) & 1u);
+    const int a = a1 * i + an * (n - 1), b = b1 * i + bn * (n - 1);
+    return (f2 * n + b) * n + a;
+}
+
+// resolve_texel with the integer edge maps (the same texels as
+// reproject_edge), in 32-bit arithmetic without memory accesses (levels of
+// fewer than 2^31 / 6 texels per face).
+__device__ __forceinline__ int resolve_texel_edge(int face, int x, int y, int n, int (&idx)[3])
+{
+    const bool xin = (unsigned)x < (unsigned)n, yin = (unsigned)y < (unsigned)n;
+    if (xin && yin) {
+        idx[0] = (face * n + y) * n + x;
+        return 1;
+    }
+    if (xin || yin) {
+        idx[0] = reproject_edge_alu(face, x, y, n);
+        return 1;
+    }
+    const int xc = x < 0 ? 0 : n - 1, yc = y < 0 ? 0 : n - 1;
+    idx[0] = (face * n + yc) * n + xc;
+    idx[1] = reproject_edge_alu(face, x, yc, n);
+    idx[2] = reproject_edge_alu(face, xc, y, n);
+    return 3;
+}
+
 // Resolves texel (x, y), x and y in [-1, n], of `face` to 1 or 3 flat
 // indices within the level; returns the count.
 __device__ __forceinline__ int resolve_texel(int face, int x, int y, int n, int64_t (&idx)[3])
@@ -221,25 +292,6 @@ __device__ __forceinline__ int resolve_texel(int face, int x, int y, int n, int6
     return 3;
 }
 
-// resolve_texel with the integer edge maps (texels one step beyond an edge:
-// the same indices as reproject_one).
-__device__ __forceinline__ int resolve_texel_edge(int face, int x, int y, int n, int64_t (&idx)[3])
-{
-    const bool xin = (unsigned)x < (unsigned)n, yin = (unsigned)y < (unsigned)n;
-    if (xin && yin) {
-        idx[0] = ((int64_t)face * n + y) * n + x;
-        return 1;
-    }
-    if (xin || yin) {
-        idx[0] = reproject_edge(face, x, y, n);
-        return 1;
-    }
-    const int xc = x < 0 ? 0 : n - 1, yc = y < 0 ? 0 : n - 1;
-    idx[0] = ((int64_t)face * n + yc) * n + xc;
-    idx[1] = reproject_edge(face, x, yc, n);
-    idx[2] = reproject_edge(face, xc, y, n);
-    return 3;
-}
 
 // Footprint of a direction on one level: face coordinates are computed once
 // per direction (dir_face) and shared by every level.

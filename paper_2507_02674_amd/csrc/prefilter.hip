@@ -16,10 +16,10 @@
 //                   (alpha = 0, the dense level) and chain levels 1..5 via
 //                   LDS, each level the float-rounded 2x2 mean (double sums
 //                   in a fixed order) of the one above;
-//   k_chain_faces   the coarser levels of each face through LDS;
-//   k_chain_level   one level per launch (only for faces larger than 32
-//                   texels that the tiles did not reach, R >= 2048);
-//   k_chain_border  the border rings of every stored level;
+//   k_chain_level   one level per launch (levels the tiles did not reach
+//                   whose parent face is larger than 8 texels, R >= 512);
+//   k_chain_finish  the remaining coarse levels of all faces through LDS in
+//                   one block, and the border rings of every stored level;
 //   k_prefilter     mips >= 1: a group of G lanes per output texel splits
 //                   the T taps, sums each tap's trilinear corners in float
 //                   and the taps in double, reduces across the group with
@@ -76,12 +76,6 @@ __host__ __device__ inline int64_t chain_rec(int face, int x, int y, int n)
 __host__ __device__ inline int64_t chain_plane(int n)
 {
     return 6LL * (n + 2) * (n + 2) * 4;
-}
-
-// Element k of record `rec` in a stored level (planes of `plane` floats).
-__device__ __forceinline__ int64_t chain_elem(int64_t plane, int64_t rec, int k)
-{
-    return (k >> 2) * plane + rec * 4 + (k & 3);
 }
 
 // Writes the CP floats of record `rec`.
@@ -237,8 +231,8 @@ __global__ void __launch_bounds__(kChainThreads) k_chain_level(Level0<K> l0, con
 // fused chain: a block owns a T x T tile of level 0 (T = min(32, R)); it
 // writes mip 0 of the output pyramid for the tile and builds chain levels
 // 1..log2(T) through LDS (each level rounded to float before the next, sums
-// in double in a fixed order).  A second launch builds the coarser levels of
-// each face the same way from the last tile level.
+// in double in a fixed order).  The coarser levels are built the same way by
+// later launches.
 // ---------------------------------------------------------------------------
 constexpr int kTile = 32;
 
@@ -338,51 +332,10 @@ __global__ void __launch_bounds__(256) k_chain_tiles(Level0<K> l0, int R, int M,
     }
 }
 
-// Coarse levels: one block per face, from the last level the tiles built.
-template <int K>
-__global__ void __launch_bounds__(256) k_chain_faces(int R, int M, int first, float *__restrict__ chain)
+// Position `pos` in [0, 4n + 4) of a face's border ring -> texel (x, y), x or
+// y in {-1, n}: top row (x = -1..n), bottom row, left column, right column.
+__device__ __forceinline__ void ring_texel(int pos, int n, int &x, int &y)
 {
-    constexpr int CP = chain_stride(K);
-    extern __shared__ float s_dyn[];
-    const int face = blockIdx.x;
-    const int n0 = R >> (first - 1); // face size of the level the tiles finished
-    float *src = s_dyn, *dst = s_dyn + n0 * n0 * CP;
-    const float *lvl0 = chain + chain_level_base(R, first - 1) * CP;
-    for (int o = threadIdx.x; o < n0 * n0 * CP; o += blockDim.x) {
-        const int tex = o / CP, k = o % CP;
-        src[o] = lvl0[chain_elem(chain_plane(n0), chain_rec(face, tex % n0, tex / n0, n0), k)];
-    }
-    __syncthreads();
-    int side = n0;
-    for (int s = first; s < M; ++s) {
-        const int half = side / 2;
-        float *lvl = chain + chain_level_base(R, s) * CP;
-        reduce_lds_level<K>(src, dst, side, face, 0, 0, half, lvl);
-        __syncthreads();
-        float *t = src; src = dst; dst = t;
-        side = half;
-    }
-}
-
-// Border rings of stored levels 1..M-1: texel (x, y) with x or y in {-1, n}
-// gets the seam rule's value (one texel of the owning face, or at a corner
-// the float-rounded mean ((a + b) + c) / 3 of the three corner texels, sums
-// in double).  Thread i covers ring texel i of the concatenated rings.
-template <int K>
-__global__ void __launch_bounds__(256) k_chain_border(int R, int M, float *__restrict__ chain)
-{
-    constexpr int C = K + 3, CP = chain_stride(K);
-    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int s = 1, n = R >> 1;
-    while (s < M && r >= 6LL * (4 * n + 4)) {
-        r -= 6LL * (4 * n + 4);
-        ++s;
-        n = R >> s;
-    }
-    if (s >= M) return;
-    const int face = (int)(r / (4 * n + 4));
-    const int pos = (int)(r % (4 * n + 4));
-    int x, y;
     if (pos < n + 2) {
         x = pos - 1;
         y = -1;
@@ -396,33 +349,176 @@ __global__ void __launch_bounds__(256) k_chain_border(int R, int M, float *__res
         x = n;
         y = pos - 2 * (n + 2) - n;
     }
-    float *lvl = chain + chain_level_base(R, s) * CP;
-    int64_t idx[3];
-    const int cnt = resolve_texel_edge(face, x, y, n, idx);
-    int64_t rec[3];
-    const int64_t nn = (int64_t)n * n;
+}
+
+// The seam rule's value of a border texel from the interior texels it
+// resolves to (cnt = 1: one texel copied; cnt = 3: the float-rounded mean
+// ((a + b) + c) / 3 with sums in double).  Plane q of texel e is the float4
+// at p_e + q * ps: ps is the plane size in global memory, 4 in LDS records.
+// All three records are read whatever cnt is (p1 = p2 = p0 for an edge
+// texel), so the reads are issued together.
+template <int K>
+__device__ __forceinline__ void ring_value(int cnt, const float *p0, const float *p1, const float *p2, int64_t ps,
+                                           float (&out)[chain_stride(K)])
+{
+    constexpr int C = K + 3, CP = chain_stride(K);
+    float a[CP], b[CP], c[CP];
 #pragma unroll
-    for (int e = 0; e < 3; ++e) {
-        const int64_t i = e < cnt ? idx[e] : idx[0];
-        const int f = (int)(i / nn), rem = (int)(i % nn);
-        rec[e] = chain_rec(f, rem % n, rem / n, n);
+    for (int q = 0; q < CP / 4; ++q) {
+        const float4 u = *reinterpret_cast<const float4 *>(p0 + q * ps);
+        const float4 v = *reinterpret_cast<const float4 *>(p1 + q * ps);
+        const float4 w = *reinterpret_cast<const float4 *>(p2 + q * ps);
+        a[4 * q] = u.x; a[4 * q + 1] = u.y; a[4 * q + 2] = u.z; a[4 * q + 3] = u.w;
+        b[4 * q] = v.x; b[4 * q + 1] = v.y; b[4 * q + 2] = v.z; b[4 * q + 3] = v.w;
+        c[4 * q] = w.x; c[4 * q + 1] = w.y; c[4 * q + 2] = w.z; c[4 * q + 3] = w.w;
     }
-    const int64_t pl = chain_plane(n);
-    float out[CP];
     if (cnt == 1) {
 #pragma unroll
-        for (int k = 0; k < CP; ++k) out[k] = lvl[chain_elem(pl, rec[0], k)];
+        for (int k = 0; k < CP; ++k) out[k] = a[k];
     } else {
 #pragma clang fp contract(off)
 #pragma unroll
-        for (int k = 0; k < C; ++k)
-            out[k] = (float)((((double)lvl[chain_elem(pl, rec[0], k)] + (double)lvl[chain_elem(pl, rec[1], k)]) +
-                              (double)lvl[chain_elem(pl, rec[2], k)]) /
-                             3.0);
+        for (int k = 0; k < C; ++k) out[k] = (float)((((double)a[k] + (double)b[k]) + (double)c[k]) / 3.0);
 #pragma unroll
         for (int k = C; k < CP; ++k) out[k] = 0.0f;
     }
+}
+
+// Border ring texel r of stored level s (face size n) from the level's
+// interior in global memory.
+template <int K>
+__device__ __forceinline__ void border_from_global(int r, int s, int n, int R, float *__restrict__ chain)
+{
+    constexpr int CP = chain_stride(K);
+    const int face = r / (4 * n + 4);
+    int x, y;
+    ring_texel(r - face * (4 * n + 4), n, x, y);
+    float *lvl = chain + chain_level_base(R, s) * CP;
+    int idx[3];
+    const int cnt = resolve_texel_edge(face, x, y, n, idx);
+    const int lg = __builtin_ctz((unsigned)n);
+    const float *p[3];
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+        const int i = e < cnt ? idx[e] : idx[0];
+        const int f = i >> (2 * lg), rem = i & (n * n - 1);
+        p[e] = lvl + chain_rec(f, rem & (n - 1), rem >> lg, n) * 4;
+    }
+    const int64_t pl = chain_plane(n);
+    float out[CP];
+    ring_value<K>(cnt, p[0], p[1], p[2], pl, out);
     store_record<CP>(lvl, pl, chain_rec(face, x, y, n), out);
+}
+
+// Builds coarse level s (face size n = 2^lg, all six faces) from the level
+// above it in LDS (`src`, face size 2n, records of CP floats): texel
+// o = (f * n + y) * n + x is the float-rounded mean of its 2x2 texels,
+// ((a + b) + (c + d)) / 4 in double, kept in LDS (`dst`) and stored.  Thread
+// t of the block takes texels t', t' + 256, ... with t' = t, or with
+// t' = 255 - t when `reversed` (so the pass can share the block with a ring
+// pass on the low waves).
+template <int K>
+__device__ __forceinline__ void coarse_reduce(const float *src, float *dst, int lg, float *__restrict__ lvl,
+                                              bool reversed)
+{
+    constexpr int C = K + 3, CP = chain_stride(K);
+    const int n = 1 << lg, side = 2 * n;
+    const int t = reversed ? (int)blockDim.x - 1 - (int)threadIdx.x : (int)threadIdx.x;
+    for (int o = t; o < 6 * n * n; o += blockDim.x) {
+        const int f = o >> (2 * lg), rem = o & (n * n - 1), x = rem & (n - 1), y = rem >> lg;
+        const float *q = src + ((f * side + 2 * y) * side + 2 * x) * CP;
+        double a[C], b[C], c[C], d[C];
+        lds_texel<K>(q, a);
+        lds_texel<K>(q + CP, b);
+        lds_texel<K>(q + side * CP, c);
+        lds_texel<K>(q + (side + 1) * CP, d);
+        mean4_store<K>(a, b, c, d, dst + o * CP, lvl, chain_plane(n), chain_rec(f, x, y, n));
+    }
+}
+
+// Border rings of coarse level s (face size n = 2^lg) from its LDS copy.
+template <int K>
+__device__ __forceinline__ void coarse_rings(const float *lds, int lg, float *__restrict__ lvl)
+{
+    constexpr int CP = chain_stride(K);
+    const int n = 1 << lg;
+    const int64_t pl = chain_plane(n);
+    for (int r = threadIdx.x; r < 6 * (4 * n + 4); r += blockDim.x) {
+        const int face = r / (4 * n + 4);
+        int x, y;
+        ring_texel(r - face * (4 * n + 4), n, x, y);
+        int idx[3];
+        const int cnt = resolve_texel_edge(face, x, y, n, idx);
+        float out[CP];
+        ring_value<K>(cnt, lds + idx[0] * CP, lds + (cnt == 3 ? idx[1] : idx[0]) * CP,
+                      lds + (cnt == 3 ? idx[2] : idx[0]) * CP, 4, out);
+        store_record<CP>(lvl, pl, chain_rec(face, x, y, n), out);
+    }
+}
+
+// The rest of the chain after the tiles (and any per-level launches), in one
+// launch.  Block 0 (when first < M) loads level first - 1 of all six faces
+// (faces of <= 8 texels) into LDS and builds levels first..M-1 there; the
+// border rings of a level are written by the low waves while the high waves
+// build the next level.  Every other block covers the border rings of levels
+// 1..first-1, one ring texel per thread, read from the stored interiors.
+// The blocks do not depend on each other.
+template <int K>
+__global__ void __launch_bounds__(256) k_chain_finish(int R, int M, int first, float *__restrict__ chain)
+{
+    constexpr int CP = chain_stride(K);
+    extern __shared__ float s_dyn[];
+    const int coarse_blocks = first < M ? 1 : 0;
+    if ((int)blockIdx.x >= coarse_blocks) {
+        int r = (int)(blockIdx.x - coarse_blocks) * (int)blockDim.x + (int)threadIdx.x;
+        int s = 1, n = R >> 1;
+        while (s < first && r >= 6 * (4 * n + 4)) {
+            r -= 6 * (4 * n + 4);
+            ++s;
+            n = R >> s;
+        }
+        if (s < first) border_from_global<K>(r, s, n, R, chain);
+        return;
+    }
+    const int n0 = R >> (first - 1), lg0 = __builtin_ctz((unsigned)n0);
+    const int t0 = 6 * n0 * n0;
+    float *src = s_dyn, *dst = s_dyn + t0 * CP;
+    {
+        // level first-1 (<= 6 * 8 * 8 records) into LDS: every float4 of
+        // the thread's share is loaded before any is stored, so the loads
+        // are in flight together
+        constexpr int kPlanes = CP / 4, kLoads = (6 * 8 * 8 * kPlanes + 255) / 256;
+        const float *lvl0 = chain + chain_level_base(R, first - 1) * CP;
+        const int64_t pl0 = chain_plane(n0);
+        const int total = t0 * kPlanes; // float4 units: texel tex, plane q
+        float4 v[kLoads];
+        // past the end a lane repeats the last unit (the same value to the
+        // same place), so neither loop has a branch that a load could sink into
+#pragma unroll
+        for (int j = 0; j < kLoads; ++j) {
+            const int o = min((int)threadIdx.x + j * 256, total - 1);
+            const int tex = o / kPlanes, q = o - tex * kPlanes;
+            const int f = tex >> (2 * lg0), rem = tex & (n0 * n0 - 1);
+            v[j] = *reinterpret_cast<const float4 *>(lvl0 + q * pl0 + chain_rec(f, rem & (n0 - 1), rem >> lg0, n0) * 4);
+        }
+#pragma unroll
+        for (int j = 0; j < kLoads; ++j) {
+            const int o = min((int)threadIdx.x + j * 256, total - 1);
+            const int tex = o / kPlanes, q = o - tex * kPlanes;
+            *reinterpret_cast<float4 *>(src + tex * CP + q * 4) = v[j];
+        }
+    }
+    __syncthreads();
+    coarse_reduce<K>(src, dst, lg0 - 1, chain + chain_level_base(R, first) * CP, false);
+    __syncthreads();
+    for (int s = first, lg = lg0 - 1; s < M; ++s, --lg) {
+        float *t = src; src = dst; dst = t; // src: level s
+        coarse_rings<K>(src, lg, chain + chain_level_base(R, s) * CP);
+        // the next level reads level s too and writes the buffer of level
+        // s - 1, which nothing reads any more
+        if (s + 1 < M) coarse_reduce<K>(src, dst, lg - 1, chain + chain_level_base(R, s + 1) * CP, true);
+        __syncthreads();
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -782,13 +878,13 @@ static hipError_t launch_prefilter_t(const float *env, const uint8_t *ind_j, con
     int tile_levels = 0;
     while ((1 << (tile_levels + 1)) <= tile) ++tile_levels; // log2(tile)
     // levels the tiles did not build: per-level launches while the parent
-    // face is larger than a tile, then one per-face launch through LDS
+    // face is larger than 8 texels, then one launch that computes the rest
+    // and writes every border ring
+    int first = M;
     for (int s = tile_levels + 1; s < M; ++s) {
         const int parent = R >> (s - 1);
-        if (parent <= 16) { // (16^2 + 8^2) records of <= 20 floats: < 64 KB of LDS
-            const size_t shm =
-                sizeof(float) * (size_t)chain_stride(K) * (size_t)(parent * parent + (parent / 2) * (parent / 2));
-            GLINT_LAUNCH("k_chain_faces", k_chain_faces<K>, dim3(6), dim3(256), shm, stream, R, M, s, chain);
+        if (parent <= 8) { // 6 (8^2 + 4^2) records of <= 20 floats: 38 KB of LDS
+            first = s;
             break;
         }
         const int n = R >> s;
@@ -800,9 +896,14 @@ static hipError_t launch_prefilter_t(const float *env, const uint8_t *ind_j, con
     }
     if (M > 1) {
         int64_t ring = 0;
-        for (int s = 1; s < M; ++s) ring += 6LL * (4 * (R >> s) + 4);
-        GLINT_LAUNCH("k_chain_border", k_chain_border<K>, dim3((unsigned)((ring + 255) / 256)), dim3(256), 0, stream,
-                     R, M, chain);
+        for (int s = 1; s < first; ++s) ring += 6LL * (4 * (R >> s) + 4);
+        const int coarse_blocks = first < M ? 1 : 0;
+        const int n0 = R >> (first - 1);
+        const size_t shm = coarse_blocks ? sizeof(float) * (size_t)chain_stride(K) * 6 *
+                                               (size_t)(n0 * n0 + (n0 / 2) * (n0 / 2))
+                                         : 0;
+        GLINT_LAUNCH("k_chain_finish", k_chain_finish<K>, dim3((unsigned)(coarse_blocks + (ring + 255) / 256)),
+                     dim3(256), shm, stream, R, M, first, chain);
     }
     if (M > 1) {
         FilterLaunch fl{};

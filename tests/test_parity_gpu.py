@@ -221,10 +221,13 @@ def seam_texel(level, face, x, y, n):
     return ((level[face, yc, xc] + owner(x, yc)) + owner(xc, y)) / 3.0
 
 
-@pytest.mark.parametrize("R,K,M", [(32, 4, 6), (16, 8, 5)])
+@pytest.mark.parametrize("R,K,M", [(32, 4, 6), (16, 8, 5), (64, 16, 7), (256, 8, 8), (512, 4, 10)])
 def test_chain_borders_follow_seam_rule(ctx, R, K, M):
     """Every border texel of every stored chain level holds the seam rule's
-    value (edges bit-exact copies; corners the mean rounded once to float)."""
+    value (edges bit-exact copies; corners the mean rounded once to float).
+    R <= 32: every level comes from the tiles; R = 64 and 256: the coarse
+    levels (parent faces of 2 and 8 texels) and their rings come from the
+    one LDS block; R = 512: one per-level launch comes between them."""
     import torch
     from paper_2507_02674_amd.pipeline import EnvPipeline
     env = synth.make_env(R, 2)
@@ -285,7 +288,7 @@ def test_prefilter_degenerate_sizes(ctx, R, K, M, T):
 @pytest.mark.parametrize("R,K", [(1024, 8), (2048, 8), (4096, 4)])
 def test_prefilter_largest_faces_sampled(ctx, R, K):
     """Face sizes whose coarser chain levels are built one level per launch
-    (faces above 16 texels once the 32x32 tiles are done: R >= 1024), up to
+    (parent faces above 8 texels once the 32x32 tiles are done), up to
     the largest accepted face size R = 4096, all mips: partition, sampled
     chain records (bit-exact) and sampled pyramid texels against the oracle,
     gathered on the device."""
