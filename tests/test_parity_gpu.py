@@ -221,7 +221,7 @@ def seam_texel(level, face, x, y, n):
     return ((level[face, yc, xc] + owner(x, yc)) + owner(xc, y)) / 3.0
 
 
-@pytest.mark.parametrize("R,K,M", [(32, 4, 6), (16, 8, 5), (64, 16, 7), (256, 8, 8), (512, 4, 10)])
+@pytest.mark.parametrize("R,K,M", [(32, 4, 6), (16, 8, 5), (64, 16, 7), (256, 8, 8), (256, 16, 9), (512, 4, 10)])
 def test_chain_borders_follow_seam_rule(ctx, R, K, M):
     """Every border texel of every stored chain level holds the seam rule's
     value (edges bit-exact copies; corners the mean rounded once to float).
@@ -346,6 +346,19 @@ def test_prefilter_frame_size_sampled(ctx):
     U.log(f"  indicator ulp: max {d.max()}, mean {d.mean():.3f}, > 2: {(d > 2).mean():.4f}")
     assert d.max() <= PYR_ULP and d.mean() < 1.0
     assert U.ulp_diff(rgb[ids, :3], opyr[:, w.K:]).max() <= PYR_ULP
+
+
+@pytest.mark.parametrize("R,K,M", [(256, 16, 9), (128, 2, 8)])
+def test_chain_coarse_levels_match_oracle(ctx, R, K, M):
+    """Every stored chain level, the coarse ones built in one LDS block
+    (faces of 4, 2 and 1 texels; K = 16 fills the block's LDS, K = 2 the
+    narrowest records), bit for bit against the oracle's chain (one tap:
+    the pyramid is not the point here)."""
+    U.log(f"chain coarse levels R={R} K={K} M={M}")
+    env = synth.make_env(R, 9)
+    lv, ij, it = U.partition(ctx, env, K)
+    _, _, chain = U.prefilter(ctx, env, ij, it, K, M, 1)
+    assert np.array_equal(chain, oracle.mipchain(env, ij, it, K, M))
 
 
 def test_prefilter_rejects_bad_arguments(ctx):
