@@ -20,6 +20,13 @@ def hipcc_flags():
             "-I", os.path.join(ROOT, "include"), "-Wall", "-Wno-unused-function"]
 
 
+# Per-source additions: the network kernels keep their matrix-core
+# accumulators in ordinary vector registers (the backend's VGPR form of
+# MFMA), so the elementwise epilogue reads them without a copy out of the
+# accumulation registers per value.
+SOURCE_FLAGS = {"mlp.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=true"]}
+
+
 def build_library(verbose: bool = False, jobs: int = 8) -> str:
     out = library_path()
     objdir = os.path.join(HERE, "_build")
@@ -27,7 +34,7 @@ def build_library(verbose: bool = False, jobs: int = 8) -> str:
     objs, procs = [], []
     for src in SOURCES:
         obj = os.path.join(objdir, src.replace(".hip", ".o"))
-        cmd = ["hipcc", "-c", *hipcc_flags(), os.path.join(CSRC, src), "-o", obj]
+        cmd = ["hipcc", "-c", *hipcc_flags(), *SOURCE_FLAGS.get(src, []), os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd))
         procs.append((src, subprocess.Popen(cmd)))

@@ -49,12 +49,20 @@ __device__ __forceinline__ uint16_t to_bf16(float f)
     return __builtin_bit_cast(uint16_t, (__bf16)f); // round to nearest even (v_cvt_pk_bf16_f32)
 }
 
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+
+// Two floats to two packed bfloat16, a in the low half (one two-source
+// v_cvt_pk_bf16_f32, round to nearest even like to_bf16).
+__device__ __forceinline__ uint32_t pack_bf16x2(float a, float b)
+{
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2_t){a, b}, bf16x2_t));
+}
+
 // Four floats to four packed bfloat16 (two conversions of two).
 __device__ __forceinline__ uint2 pack_bf16x4(float a, float b, float c, float d)
 {
-    const uint32_t lo = (uint32_t)to_bf16(a) | ((uint32_t)to_bf16(b) << 16);
-    const uint32_t hi = (uint32_t)to_bf16(c) | ((uint32_t)to_bf16(d) << 16);
-    return make_uint2(lo, hi);
+    return make_uint2(pack_bf16x2(a, b), pack_bf16x2(c, d));
 }
 
 __device__ __forceinline__ float from_bf16(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
@@ -141,16 +149,40 @@ __device__ __forceinline__ void stage_weights(const uint16_t *__restrict__ wb, u
 // first operand and the activations the second, so both are read as
 // 16-byte rows, and each lane ends with four runs of four consecutive units
 // of one sample (stored as 8-byte bfloat16 quads).
-__device__ __forceinline__ void unit_tile(const uint16_t *W, int ldw, const uint16_t *in, int ldi, int Kd, int n0,
-                                          f32x16 &acc)
+__device__ __forceinline__ void unit_mma(const uint16_t *W, int ldw, const uint16_t *in, int ldi, int Kd, int n0,
+                                         f32x16 &acc)
 {
     const int l = threadIdx.x & 63, r = l & 31, kg = (l >> 5) * 8;
-    zero(acc);
     for (int k0 = 0; k0 < Kd; k0 += 16) {
         const bf16x8 a = *reinterpret_cast<const bf16x8 *>(W + (n0 + r) * ldw + k0 + kg);
         const bf16x8 b = *reinterpret_cast<const bf16x8 *>(in + r * ldi + k0 + kg);
         acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
     }
+}
+
+__device__ __forceinline__ void unit_tile(const uint16_t *W, int ldw, const uint16_t *in, int ldi, int Kd, int n0,
+                                          f32x16 &acc)
+{
+    zero(acc);
+    unit_mma(W, ldw, in, ldi, Kd, n0, acc);
+}
+
+// unit_tile with each accumulator starting at its unit's bias (bias in LDS,
+// indexed by unit): the pre-activation b + sum_k W x leaves the matrix cores
+// whole, with no separate additions.
+__device__ __forceinline__ void unit_tile_biased(const uint16_t *W, int ldw, const uint16_t *in, int ldi, int Kd,
+                                                 int n0, const float *bias, f32x16 &acc)
+{
+    const int h = (threadIdx.x & 63) >> 5;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const float4 b4 = *reinterpret_cast<const float4 *>(bias + n0 + 8 * q + 4 * h);
+        acc[4 * q] = b4.x;
+        acc[4 * q + 1] = b4.y;
+        acc[4 * q + 2] = b4.z;
+        acc[4 * q + 3] = b4.w;
+    }
+    unit_mma(W, ldw, in, ldi, Kd, n0, acc);
 }
 
 // out[r][n] = bf16(silu(in[r][:Kd] . W[n][:Kd] + bias[n])) for the 32 samples
@@ -181,17 +213,10 @@ __device__ __forceinline__ void dense_silu(const uint16_t *in, int ldi, int Kd, 
 __device__ __forceinline__ void dense_out(const uint16_t *hin, const uint16_t *W4, const float *__restrict__ b4,
                                           float (&logit)[16])
 {
-    const int h = (threadIdx.x & 63) >> 5;
     f32x16 acc;
-    unit_tile(W4, kLdH, hin, kLdH, kH, 0, acc);
+    unit_tile_biased(W4, kLdH, hin, kLdH, kH, 0, b4, acc);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const float4 b = *reinterpret_cast<const float4 *>(b4 + 8 * q + 4 * h);
-        logit[4 * q] = acc[4 * q] + b.x;
-        logit[4 * q + 1] = acc[4 * q + 1] + b.y;
-        logit[4 * q + 2] = acc[4 * q + 2] + b.z;
-        logit[4 * q + 3] = acc[4 * q + 3] + b.w;
-    }
+    for (int j = 0; j < 16; ++j) logit[j] = acc[j];
 }
 
 __device__ __forceinline__ int out_unit(int j) { return 8 * (j >> 2) + 4 * ((threadIdx.x & 63) >> 5) + (j & 3); }
@@ -233,17 +258,16 @@ __device__ __forceinline__ void dense_silu_inplace(uint16_t *buf, int Kd, const 
 {
     const int r = threadIdx.x & 31, h = (threadIdx.x & 63) >> 5;
     f32x16 acc[2];
-    unit_tile(W, ldw, buf, kLdH, Kd, 0, acc[0]);
-    unit_tile(W, ldw, buf, kLdH, Kd, 32, acc[1]);
+    unit_tile_biased(W, ldw, buf, kLdH, Kd, 0, bias, acc[0]);
+    unit_tile_biased(W, ldw, buf, kLdH, Kd, 32, bias, acc[1]);
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int n = 32 * t + 8 * q + 4 * h;
-            const float4 b4 = *reinterpret_cast<const float4 *>(bias + n);
-            const float z0 = acc[t][4 * q] + b4.x, z1 = acc[t][4 * q + 1] + b4.y, z2 = acc[t][4 * q + 2] + b4.z,
-                        z3 = acc[t][4 * q + 3] + b4.w;
-            *reinterpret_cast<uint2 *>(buf + r * kLdH + n) = pack_bf16x4(silu(z0), silu(z1), silu(z2), silu(z3));
+            *reinterpret_cast<uint2 *>(buf + r * kLdH + n) =
+                pack_bf16x4(silu(acc[t][4 * q]), silu(acc[t][4 * q + 1]), silu(acc[t][4 * q + 2]),
+                            silu(acc[t][4 * q + 3]));
         }
     }
 }
